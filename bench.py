@@ -1,0 +1,198 @@
+"""Benchmark of the sliding-window connectivity update on one MI355X.
+
+Workload (the 5000-node source-space case): N = 5000 nodes (12,497,500
+pairs), trials of 500 samples at 1 kHz, 512-point FFT, 8-30 Hz (12 bins),
+sliding window of W = 50 trials, all 8 metrics, synthetic coupled-AR(2)
+source activity.  One step = one pushed trial through the whole path:
+taper + band DFT into the spectra ring, power sums, the pair update of every
+running sum (new trial added, evicted trial subtracted), COR Gram update, and
+the refreshed band-mean network of all 8 metrics.  Trials are resident in HBM
+before timing starts.
+
+metric = pair*freq*trial updates/s = P * B * steps / wall time.  The JSON line
+also carries per-push latency percentiles, the coh-only and wPLI-only
+sessions, the roofline of the dominant kernel (pair update, HIP-event timed
+on the session stream over the timed region) and the FP64 oracle timed on a
+sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def pair_update_bytes(P: int, B: int, metrics: int) -> int:
+    """Algorithmic HBM bytes of one pair-update launch: every running sum the
+    enabled metrics need is read and written once per pair and bin (FP64
+    planes, int16 sign sums), and each enabled spectral metric's band mean is
+    written once per pair (FP32)."""
+    COH, IMCOH, PLV, PLI, WPLI, USPLI, DSWPLI = 1, 2, 4, 8, 16, 32, 64
+    planes = 0
+    planes += 1 if metrics & COH else 0                                   # S_re
+    planes += 1 if metrics & (COH | IMCOH | WPLI | DSWPLI) else 0         # S_im
+    planes += 2 if metrics & PLV else 0                                   # U_re, U_im
+    planes += 1 if metrics & (WPLI | DSWPLI) else 0                       # A
+    planes += 1 if metrics & DSWPLI else 0                                # Q
+    g = 2 if metrics & (PLI | USPLI) else 0
+    per_pair_bin = 2 * (8 * planes + g)
+    n_out = bin(metrics & 127).count("1")
+    return P * B * per_pair_bin + P * n_out * 4
+
+
+def make_pool(n_trials: int, seed: int = 3):
+    import synth
+    x, cfg = synth.c3_source(seed=seed, n_trials=n_trials)
+    return x.astype(np.float32), cfg
+
+
+def run_session(fcx, torch, cfg, pool_dev, steps, warmup, timing=True, lat_pushes=0):
+    W = cfg["window_trials"]
+    M = cfg["n_samples"]
+    npool = pool_dev.shape[0]
+    s = fcx.Session(cfg)
+    # fill the window so every timed push evicts a trial
+    for k in range(W):
+        fcx.check(s.push_device(pool_dev[k % npool].data_ptr(), M), "fill")
+    for k in range(warmup):
+        fcx.check(s.push_device(pool_dev[(W + k) % npool].data_ptr(), M), "warmup")
+    fcx.check(s.sync(), "sync")
+    s.set_timing(timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        fcx.check(s.push_device(pool_dev[(W + warmup + k) % npool].data_ptr(), M), "push")
+    fcx.check(s.sync(), "sync")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = {}
+    if timing:
+        for name, kid in [("spectra", fcx.FCX_K_SPECTRA), ("psd", fcx.FCX_K_PSD),
+                          ("pair_update", fcx.FCX_K_PAIR_UPDATE), ("cor", fcx.FCX_K_COR)]:
+            n, ms = s.kernel_time(kid)
+            if n:
+                kt[name] = dict(launches=n, avg_ms=ms / n)
+        s.set_timing(False)
+    lat = []
+    for k in range(lat_pushes):
+        t1 = time.perf_counter()
+        fcx.check(s.push_device(pool_dev[k % npool].data_ptr(), M), "push")
+        fcx.check(s.sync(), "sync")
+        lat.append(time.perf_counter() - t1)
+    s.close()
+    return wall, kt, lat
+
+
+def cpu_baseline(cfg, x_pool, rows):
+    import oracle
+    W = cfg["window_trials"]
+    N = cfg["n_nodes"]
+    win = oracle.as_device_input(x_pool[:W], cfg)
+    pi, pj = oracle.row_pairs(rows, N)
+    oracle.network(win[:, :64], dict(cfg, n_nodes=64), *oracle.row_pairs([0], 64))  # load/warm
+    t0 = time.perf_counter()
+    oracle.network(win, cfg, pi, pj)
+    dt = time.perf_counter() - t0
+    B = oracle.band_bins(cfg["n_fft"], cfg["fs_hz"], cfg["f_lo_hz"], cfg["f_hi_hz"]).size
+    return dict(value=pi.size * B / dt, unit="pair*freq*trial updates/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=(f"plain FP64 recompute of one network over the W={W} window for {len(rows)} rows "
+                        f"({pi.size} pairs x {B} bins, spectra of all {N} nodes included), "
+                        f"{dt:.2f} s; counts one pushed trial per pair and bin"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--pool", type=int, default=64, help="distinct trials resident in HBM")
+    ap.add_argument("--latency-pushes", type=int, default=300)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-subsets", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the update shards by pair "
+              "tiles, see the design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2303_03279_amd as fcx
+    import synth
+
+    torch.cuda.set_device(0)
+    print(f"[bench] generating {args.pool} trials of the 5000-node workload", file=sys.stderr, flush=True)
+    x_pool, cfg = make_pool(args.pool)
+    pool_dev = torch.from_numpy(x_pool).cuda()
+    torch.cuda.synchronize()
+    N = cfg["n_nodes"]
+    P = N * (N - 1) // 2
+    B = fcx.band_bins(cfg)[0]
+
+    print("[bench] all-8 session", file=sys.stderr, flush=True)
+    wall, kt, lat = run_session(fcx, torch, cfg, pool_dev, args.steps, args.warmup,
+                                lat_pushes=args.latency_pushes)
+    ups = P * B * args.steps / wall
+    pu = kt.get("pair_update", {})
+    algo = pair_update_bytes(P, B, synth.ALL8)
+    achieved = algo / (pu["avg_ms"] * 1e-3) / 1e9 if pu else None
+    lat_ms = np.array(lat) * 1e3 if lat else np.array([np.nan])
+
+    sessions = {}
+    if not args.no_subsets:
+        for name, mask in [("coh", synth.COH), ("wpli", synth.WPLI)]:
+            print(f"[bench] {name}-only session", file=sys.stderr, flush=True)
+            c2 = dict(cfg, metrics=mask)
+            w2, k2, l2 = run_session(fcx, torch, c2, pool_dev, args.steps, args.warmup, lat_pushes=100)
+            p2 = k2.get("pair_update", {})
+            a2 = pair_update_bytes(P, B, mask) / (p2["avg_ms"] * 1e-3) / 1e9 if p2 else None
+            sessions[name] = dict(value=P * B * args.steps / w2, ms_per_step=w2 * 1e3 / args.steps,
+                                  p50_ms=float(np.percentile(np.array(l2) * 1e3, 50)),
+                                  p99_ms=float(np.percentile(np.array(l2) * 1e3, 99)),
+                                  pair_update_avg_ms=p2.get("avg_ms"),
+                                  pair_update_gbs=a2, hbm_frac=(a2 / HBM_PEAK_GBS) if a2 else None)
+
+    base = None
+    if not args.no_cpu_baseline:
+        print("[bench] oracle on host cores", file=sys.stderr, flush=True)
+        base = cpu_baseline(cfg, x_pool, rows=list(range(0, N, N // 16))[:16])
+
+    out = {
+        "metric": "pair*freq*trial updates/s (coh, wPLI) + p99 per-trial update latency",
+        "value": ups,
+        "unit": "pair*freq*trial updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 spectra, f64 running sums",
+        "data": "synthetic",
+        "config": {"workload": "source-space sliding update: N=5000 (12.5M pairs), W=50 trials x 500 samples, "
+                               "fs=1 kHz, F=512, 8-30 Hz (12 bins), Hann, all 8 metrics, one push per step",
+                   "n_nodes": N, "pairs": P, "bins": B, "window": cfg["window_trials"]},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "pushes": len(lat)},
+        "kernels": kt,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "kernel": "pair_update", "algorithmic_bytes_per_launch": algo},
+        "sessions": sessions,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

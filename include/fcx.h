@@ -1,0 +1,218 @@
+/*
+ * fcx — online all-to-all functional connectivity on one MI355X (gfx950).
+ *
+ * A session holds one connectivity estimate over a sliding window of trials
+ * (the user-set number of averaged trials of the connectivity plug-in,
+ * Sec. 2.5).  Each pushed trial [N nodes][M samples] is tapered and
+ * transformed at the band bins only; its spectra are cached in a device ring
+ * so a trial is never transformed twice (the reuse of stored per-trial
+ * results, Sec. 2.4); running sums over the window are updated in place —
+ * the new trial added, the evicted one subtracted — and the band-averaged
+ * network of every enabled metric is refreshed.  The metrics are those of the
+ * supplementary metric section: COH, IMAGCOHY, PLV, PLI, WPLI, USPLI,
+ * debiased squared WPLI and COR.  Only pairs i < j are computed (undirected
+ * half, Sec. 2.4).
+ *
+ * Conventions (where the paper is silent):
+ *   CSD_ij = X_i conj(X_j); IMCOH_ji = -IMCOH_ij.
+ *   Band bins: k_lo = floor(f_lo F / fs), k_hi = floor(f_hi F / fs),
+ *              inclusive, clamped to [0, F/2].
+ *   Taper: periodic Hann 0.5 - 0.5 cos(2 pi n / M), or DPSS (unit energy,
+ *          weights = concentration ratios); zero padding to F.
+ *   Multitaper trial CSD/PSD: sum_l lam_l X_il conj(X_jl) / sum_l lam_l.
+ *   sign(0) = 0; a metric whose denominator is exactly 0 is 0; the unit
+ *   phasor of 0 is 0; USPLI and DSWPLI are NaN while K < 2.
+ *   DSWPLI = ((sum Im)^2 - sum Im^2) / ((sum |Im|)^2 - sum Im^2)  (the
+ *   debiased estimator the metric is named for).
+ *   COR = mean over the window of each trial's Pearson correlation.
+ *   Band value = arithmetic mean of the per-bin values.
+ *
+ * Network layout: packed upper triangle without diagonal, row-major:
+ *   idx(i, j) = i (2N - i - 1) / 2 + (j - i - 1),  0 <= i < j < N,
+ *   P = N (N - 1) / 2 entries per metric.
+ *
+ * Errors: every call returns an fcx_status; no exception crosses the ABI.
+ * Handles are checked against a table, so a closed handle gives
+ * FCX_E_CLOSED rather than undefined behaviour.  A session is used by one
+ * thread at a time; different sessions may be used concurrently.
+ */
+#ifndef FCX_H
+#define FCX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fcx_session fcx_session;
+typedef struct fcx_server fcx_server;
+
+typedef enum {
+    FCX_OK = 0,
+    FCX_E_INVAL = 1,      /* bad argument or configuration                        */
+    FCX_E_NOMEM = 2,      /* device or host allocation failed                     */
+    FCX_E_DEVICE = 3,     /* a HIP runtime call failed                            */
+    FCX_E_NOTREADY = 4,   /* no trial yet, or K < 2 for USPLI / DSWPLI            */
+    FCX_E_BUSY = 5,       /* server: the session does not fit the HBM budget now  */
+    FCX_E_CLOSED = 6,     /* the handle was closed                                */
+    FCX_E_NONFINITE = 7   /* a pushed trial held NaN/Inf and was rejected         */
+} fcx_status;
+
+/* metric mask bits; fcx_read_network takes exactly one of them */
+enum {
+    FCX_COH = 1, FCX_IMCOH = 2, FCX_PLV = 4, FCX_PLI = 8,
+    FCX_WPLI = 16, FCX_USPLI = 32, FCX_DSWPLI = 64, FCX_COR = 128
+};
+enum { FCX_TAPER_HANN = 0, FCX_TAPER_DPSS = 1 };
+/* operand precision of the batch Gram sums (fcx_push_batch / fcx_resync) */
+enum { FCX_GRAM_FP32 = 0, FCX_GRAM_BF16 = 1, FCX_GRAM_BF16X3 = 2 };
+/* arithmetic of spectra and outputs: float32 or float64 */
+enum { FCX_ELEM_F32 = 0, FCX_ELEM_F64 = 1 };
+
+typedef struct {
+    uint32_t struct_size;   /* sizeof(fcx_config), for forward compatibility      */
+    int32_t n_nodes;        /* N, 2 <= N <= 65536                                  */
+    int32_t n_samples;      /* M samples per trial, 2 <= M <= 8192                 */
+    int32_t window_trials;  /* W, trials averaged (FIFO window), 1 <= W <= 32767   */
+    int32_t n_fft;          /* F >= M, zero-padded DFT length                      */
+    double fs_hz;           /* sampling rate                                       */
+    double f_lo_hz;         /* band, inclusive bins (see conventions)              */
+    double f_hi_hz;
+    int32_t taper;          /* FCX_TAPER_*                                         */
+    int32_t dpss_k;         /* number of DPSS tapers (1..8), DPSS only             */
+    double dpss_nw;         /* time-bandwidth product NW, DPSS only                */
+    uint32_t metrics;       /* OR of metric bits, non-zero                         */
+    int32_t gram_precision; /* FCX_GRAM_*                                          */
+    int32_t elem;           /* FCX_ELEM_*; input x and outputs use this type       */
+} fcx_config;
+
+/* Fill *cfg with defaults (Hann, all 8 metrics, FP32 Gram, F32). */
+void fcx_config_init(fcx_config *cfg);
+
+/* Device bytes a session with this configuration allocates (ring of W+1
+ * spectra slots, running sums, COR sample ring, outputs, staging).
+ * Returns -1 for an invalid configuration. */
+int64_t fcx_footprint_bytes(const fcx_config *cfg);
+
+/* Number of band bins, or -1 for an invalid configuration. */
+int32_t fcx_band_bins(const fcx_config *cfg, int32_t *k_lo, int32_t *k_hi);
+
+/*
+ * Open a session on the current HIP device.  hip_stream is a hipStream_t to
+ * order all the session's work on (NULL: the session creates its own).  The
+ * library owns every device buffer it allocates here and frees them in
+ * fcx_close.
+ * Errors: FCX_E_INVAL (configuration), FCX_E_NOMEM, FCX_E_DEVICE.
+ */
+fcx_status fcx_open(const fcx_config *cfg, void *hip_stream, fcx_session **out);
+
+/*
+ * Push one trial x[N][M] (row stride ld >= M elements; float for ELEM_F32,
+ * double for ELEM_F64).  x_on_device = 0: x is host memory, copied before
+ * the call returns, so the caller may reuse it at once.  x_on_device = 1:
+ * x is device memory that must stay valid until fcx_sync returns.
+ * The push is stream-ordered and returns before the GPU work finishes.  It
+ * is atomic: a trial holding NaN/Inf is detected on the device before any
+ * running sum changes, is dropped, and the next fcx_sync or
+ * fcx_read_network reports FCX_E_NONFINITE once.
+ * Errors: FCX_E_INVAL, FCX_E_CLOSED, FCX_E_DEVICE.
+ */
+fcx_status fcx_push_trial(fcx_session *s, const void *x, int64_t ld, int x_on_device);
+
+/*
+ * Replace the window with n_trials trials (trial k at x + k*trial_stride,
+ * node rows ld apart), n_trials <= W, and compute the running sums in one
+ * batch pass: dense Gram sums on the matrix cores in the session's
+ * gram_precision, sign/|Im| sums on the vector units.  Inputs must be finite
+ * (checked on the device; a non-finite batch leaves the session empty and
+ * reports FCX_E_NONFINITE at the next sync).
+ */
+fcx_status fcx_push_batch(fcx_session *s, const void *x, int64_t n_trials, int64_t trial_stride,
+                          int64_t ld, int x_on_device);
+
+/*
+ * Copy the current network of one metric into out (host or device memory).
+ * per_bin = 0: band mean, out_len >= P.  per_bin = 1: [B][P], out_len >= B*P
+ * (COR is broadband and always [P]).  Element type follows cfg.elem.
+ * *k_trials_out (may be NULL) receives K, the trials in the window.
+ * Synchronous.  Returns FCX_E_NOTREADY (and fills NaN) for USPLI/DSWPLI
+ * while K < 2 and when no trial was pushed; FCX_E_NONFINITE once after a
+ * rejected push (the output is still the valid current network).
+ */
+fcx_status fcx_read_network(fcx_session *s, uint32_t metric, void *out, int64_t out_len,
+                            int out_on_device, int per_bin, int32_t *k_trials_out);
+
+/* Wait for the session's queued work. Returns FCX_E_NONFINITE once after a
+ * rejected push. */
+fcx_status fcx_sync(fcx_session *s);
+
+/* Rebuild every running sum from the cached spectra of the window (batch
+ * recompute); used after a precision change or to discard accumulated
+ * rounding of a very long run. */
+fcx_status fcx_resync(fcx_session *s);
+
+/* Release the session; the handle becomes invalid (FCX_E_CLOSED). */
+fcx_status fcx_close(fcx_session *s);
+
+/* The hipStream_t the session orders its work on. */
+fcx_status fcx_session_stream(fcx_session *s, void **hip_stream);
+
+/* Trials pushed and accepted so far, and trials rejected as non-finite. */
+fcx_status fcx_session_counts(fcx_session *s, int64_t *accepted, int64_t *rejected);
+
+/*
+ * Kernel timing: when enabled, every launch of the listed kernels is
+ * bracketed by HIP events on the session stream; fcx_kernel_time returns the
+ * number of timed launches and their summed duration in milliseconds
+ * (pending events are resolved, which synchronises the stream).
+ */
+enum { FCX_K_SPECTRA = 0, FCX_K_PSD = 1, FCX_K_PAIR_UPDATE = 2, FCX_K_COR = 3,
+       FCX_K_PAIR_BATCH = 4, FCX_K_FINALIZE = 5, FCX_K_COUNT = 6 };
+fcx_status fcx_set_timing(fcx_session *s, int enable);
+fcx_status fcx_kernel_time(fcx_session *s, int kernel, int64_t *launches, double *total_ms);
+
+/* Host DPSS tapers: tapers[K][M] (unit energy) and concentration ratios[K]. */
+fcx_status fcx_dpss(int32_t M, double NW, int32_t K, double *tapers, double *ratios);
+
+const char *fcx_status_str(fcx_status st);
+
+/*
+ * HBM streaming probe: dst[i] = src[i] for n_bytes (multiple of 16) on the
+ * given stream; used to calibrate traffic counters and the achievable copy
+ * bandwidth.  Device pointers.
+ */
+fcx_status fcx_probe_copy(void *dst, const void *src, int64_t n_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: many concurrent sessions, continuous batching.
+ *
+ * A server owns an HBM budget.  fcx_server_open admits a session only if its
+ * footprint fits what is left (FCX_E_BUSY otherwise; retry after another
+ * session closes).  Submitted trials of all sessions are gathered by a
+ * server thread into ticks: one tick runs the spectra, power and pair-update
+ * work of every session with pending trials as a few batched launches whose
+ * workgroups drain a shared list of (session, tile) items, so sessions of
+ * different N and W overlap on the device.  Per session, trials are applied
+ * in submission order.  Each result equals the same session run alone.
+ * ------------------------------------------------------------------------ */
+fcx_status fcx_server_create(int64_t hbm_budget_bytes, fcx_server **out);
+fcx_status fcx_server_open(fcx_server *srv, const fcx_config *cfg, fcx_session **out);
+/* Copy x (host, [N][M] with row stride ld) and queue it; *ticket identifies it. */
+fcx_status fcx_server_submit(fcx_server *srv, fcx_session *s, const void *x, int64_t ld,
+                             uint64_t *ticket);
+/* done = 1 once the trial's update finished on the device; latency_s is
+ * submit -> completion observed by the server thread (host monotonic clock). */
+fcx_status fcx_server_poll(fcx_server *srv, uint64_t ticket, int *done, double *latency_s);
+/* Wait until every submitted trial is done. */
+fcx_status fcx_server_drain(fcx_server *srv);
+/* Budget accounting: bytes admitted, bytes left, sessions open. */
+fcx_status fcx_server_usage(fcx_server *srv, int64_t *used, int64_t *left, int32_t *n_sessions);
+/* Close a session opened on this server (drains its pending trials). */
+fcx_status fcx_server_close_session(fcx_server *srv, fcx_session *s);
+fcx_status fcx_server_destroy(fcx_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCX_H */

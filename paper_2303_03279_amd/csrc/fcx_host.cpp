@@ -1,0 +1,929 @@
+// Host side of the fcx C ABI: configuration, band plan, tapers, buffer
+// planning, the session handle table, and the push / read entry points.
+#include "fcx_host.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <new>
+#include <unordered_map>
+
+namespace fcx {
+
+#define HIP_OK(call)                                   \
+    do {                                               \
+        if ((call) != hipSuccess) return FCX_E_DEVICE; \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// band plan: bins floor(f F / fs) for both edges, inclusive, clamped to the
+// one-sided range [0, F/2]
+// ---------------------------------------------------------------------------
+static void band_edges(const fcx_config *c, int *lo, int *hi)
+{
+    const double F = c->n_fft;
+    long long a = (long long)floor(c->f_lo_hz * F / c->fs_hz + 1e-9);
+    long long b = (long long)floor(c->f_hi_hz * F / c->fs_hz + 1e-9);
+    if (a < 0) a = 0;
+    if (b > c->n_fft / 2) b = c->n_fft / 2;
+    *lo = (int)a;
+    *hi = (int)b;
+}
+
+fcx_status make_geometry(const fcx_config *c, Geometry *g)
+{
+    if (!c || c->struct_size != sizeof(fcx_config)) return FCX_E_INVAL;
+    if (c->n_nodes < 2 || c->n_nodes > 65536) return FCX_E_INVAL;
+    if (c->n_samples < 2 || c->n_samples > 8192) return FCX_E_INVAL;
+    if (c->window_trials < 1 || c->window_trials > 32767) return FCX_E_INVAL;
+    if (c->n_fft < c->n_samples || c->n_fft > (1 << 20)) return FCX_E_INVAL;
+    if (!(c->fs_hz > 0.0) || !isfinite(c->fs_hz)) return FCX_E_INVAL;
+    if (!isfinite(c->f_lo_hz) || !isfinite(c->f_hi_hz) || c->f_lo_hz < 0.0 || c->f_hi_hz < c->f_lo_hz)
+        return FCX_E_INVAL;
+    if (c->metrics == 0 || (c->metrics & ~0xFFu)) return FCX_E_INVAL;
+    if (c->elem != FCX_ELEM_F32 && c->elem != FCX_ELEM_F64) return FCX_E_INVAL;
+    if (c->gram_precision < FCX_GRAM_FP32 || c->gram_precision > FCX_GRAM_BF16X3) return FCX_E_INVAL;
+    int L = 1;
+    if (c->taper == FCX_TAPER_DPSS) {
+        if (c->dpss_k < 1 || c->dpss_k > 8) return FCX_E_INVAL;
+        if (!(c->dpss_nw > 0.0) || c->dpss_nw >= c->n_samples / 2.0) return FCX_E_INVAL;
+        L = c->dpss_k;
+    } else if (c->taper != FCX_TAPER_HANN) {
+        return FCX_E_INVAL;
+    }
+    int lo, hi;
+    band_edges(c, &lo, &hi);
+    if (hi < lo) return FCX_E_INVAL;
+    g->N = c->n_nodes;
+    g->M = c->n_samples;
+    g->W = c->window_trials;
+    g->F = c->n_fft;
+    g->klo = lo;
+    g->khi = hi;
+    g->B = hi - lo + 1;
+    g->L = L;
+    g->nT = (g->N + TILE - 1) / TILE;
+    g->ntiles = g->nT * (g->nT + 1) / 2;
+    g->Mz = (g->M + ZPAD - 1) / ZPAD * ZPAD;
+    g->f64 = c->elem == FCX_ELEM_F64;
+    g->esz = g->f64 ? 8 : 4;
+    g->P = (size_t)g->N * (g->N - 1) / 2;
+    return FCX_OK;
+}
+
+size_t BufferPlan::total() const
+{
+    return ring + psd + plane * (size_t)nplanes + gsum + out + ctl + wtw + lamw + tiles + zring + rsum + xbuf;
+}
+
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+BufferPlan make_plan(const fcx_config &c, const Geometry &g)
+{
+    BufferPlan p;
+    const uint32_t m = c.metrics;
+    const size_t slots = (size_t)g.W + 1;
+    const size_t elems = (size_t)g.ntiles * g.B * TILE_PAIRS;
+    const bool spectral = (m & 0x7Fu) != 0;
+    if (spectral) {
+        p.ring = align256(slots * g.B * g.L * g.N * 2 * g.esz);
+        p.psd = align256((size_t)g.B * g.N * 8);
+        p.planes_used[P_SRE] = m & M_COH;
+        p.planes_used[P_SIM] = m & (M_COH | M_IMCOH | M_WPLI | M_DSWPLI);
+        p.planes_used[P_URE] = m & M_PLV;
+        p.planes_used[P_UIM] = m & M_PLV;
+        p.planes_used[P_A] = m & (M_WPLI | M_DSWPLI);
+        p.planes_used[P_Q] = m & M_DSWPLI;
+        for (int i = 0; i < NPLANES; ++i) p.nplanes += p.planes_used[i] ? 1 : 0;
+        p.plane = align256(elems * 8);
+        p.g_used = m & (M_PLI | M_USPLI);
+        p.gsum = p.g_used ? align256(elems * 2) : 0;
+        p.wtw = align256((size_t)g.L * g.B * g.M * 2 * g.esz);
+        p.lamw = align256((size_t)g.L * 8);
+    }
+    p.out = align256(8 * g.P * g.esz);
+    p.ctl = align256(2 * sizeof(DevCtl));   // live control + replay control
+    p.tiles = align256((size_t)g.ntiles * sizeof(int2));
+    if (m & M_COR) {
+        p.zring = align256(slots * g.N * g.Mz * 4);
+        p.rsum = align256((size_t)g.ntiles * TILE_PAIRS * 8);
+    }
+    p.xbuf = align256((size_t)g.N * g.M * g.esz);
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// tapers
+// ---------------------------------------------------------------------------
+// exp(-2 pi i r / F): the angle is reduced to a quadrant and then to at most
+// pi/4, so multiples of pi/2 come out exact (the DC and Nyquist bins stay
+// exactly real) and large r loses no accuracy.
+static void unit_root(long long r, long long F, double *c, double *s)
+{
+    r %= F;
+    if (r < 0) r += F;
+    const long long q = (4 * r) / F;          // quadrant
+    const long long rem = 4 * r - q * F;      // angle within it: (pi/2) rem / F
+    double cc, ss;
+    if (rem == 0) {
+        cc = 1.0;
+        ss = 0.0;
+    } else if (2 * rem <= F) {
+        const double a = (M_PI / 2.0) * (double)rem / (double)F;
+        cc = cos(a);
+        ss = sin(a);
+    } else {
+        const double b = (M_PI / 2.0) * (double)(F - rem) / (double)F;
+        cc = sin(b);
+        ss = cos(b);
+    }
+    double rc, rs;  // rotate by q quarter turns
+    switch (q & 3) {
+    case 0: rc = cc; rs = ss; break;
+    case 1: rc = -ss; rs = cc; break;
+    case 2: rc = -cc; rs = -ss; break;
+    default: rc = ss; rs = -cc; break;
+    }
+    *c = rc;
+    *s = -rs;
+}
+
+// Symmetric tridiagonal eigenpairs for the DPSS: Sturm-sequence bisection for
+// the K largest eigenvalues, then inverse iteration with a pivoted
+// tridiagonal solve for each eigenvector.
+static int sturm_below(const std::vector<double> &d, const std::vector<double> &e2, double x)
+{
+    int cnt = 0;
+    double q = 1.0;
+    const size_t n = d.size();
+    for (size_t i = 0; i < n; ++i) {
+        q = d[i] - x - (i ? e2[i] / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+static void tridiag_solve(const std::vector<double> &d, const std::vector<double> &e, double shift,
+                          std::vector<double> &x)
+{
+    // Gaussian elimination with partial pivoting on (T - shift I) x = b,
+    // e[i] couples i-1 and i.
+    const size_t n = d.size();
+    std::vector<double> dl(n, 0.0), dd(n), du(n, 0.0), du2(n, 0.0);
+    for (size_t i = 0; i < n; ++i) dd[i] = d[i] - shift;
+    for (size_t i = 0; i + 1 < n; ++i) {
+        du[i] = e[i + 1];
+        dl[i] = e[i + 1];
+    }
+    for (size_t i = 0; i + 1 < n; ++i) {
+        if (fabs(dd[i]) >= fabs(dl[i])) {
+            if (dd[i] == 0.0) dd[i] = 1e-300;
+            const double f = dl[i] / dd[i];
+            dd[i + 1] -= f * du[i];
+            x[i + 1] -= f * x[i];
+            dl[i] = 0.0;
+        } else {
+            const double f = dd[i] / dl[i];
+            dd[i] = dl[i];
+            const double t = dd[i + 1];
+            dd[i + 1] = du[i] - f * t;
+            if (i + 2 < n) {
+                du2[i] = du[i + 1];
+                du[i + 1] = -f * du2[i];
+            }
+            du[i] = t;
+            std::swap(x[i], x[i + 1]);
+            x[i + 1] -= f * x[i];
+        }
+    }
+    if (dd[n - 1] == 0.0) dd[n - 1] = 1e-300;
+    x[n - 1] /= dd[n - 1];
+    if (n > 1) x[n - 2] = (x[n - 2] - du[n - 2] * x[n - 1]) / dd[n - 2];
+    for (long long i = (long long)n - 3; i >= 0; --i)
+        x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / dd[i];
+}
+
+static fcx_status dpss_impl(int M, double NW, int K, double *tapers, double *ratios)
+{
+    if (M < 2 || K < 1 || K > M || !(NW > 0.0) || NW >= M / 2.0) return FCX_E_INVAL;
+    const double Wb = NW / M;
+    std::vector<double> d(M), e(M, 0.0), e2(M, 0.0);
+    for (int n = 0; n < M; ++n) {
+        const double h = (M - 1 - 2.0 * n) / 2.0;
+        d[n] = h * h * cos(2.0 * M_PI * Wb);
+    }
+    for (int n = 1; n < M; ++n) {
+        e[n] = 0.5 * n * (double)(M - n);
+        e2[n] = e[n] * e[n];
+    }
+    double lo = 1e300, hi = -1e300;
+    for (int n = 0; n < M; ++n) {
+        const double r = (n ? fabs(e[n]) : 0.0) + (n + 1 < M ? fabs(e[n + 1]) : 0.0);
+        lo = std::min(lo, d[n] - r);
+        hi = std::max(hi, d[n] + r);
+    }
+    std::vector<double> x(M);
+    for (int k = 0; k < K; ++k) {
+        // eigenvalue with exactly M-1-k eigenvalues below it
+        const int target = M - 1 - k;
+        double a = lo, b = hi;
+        for (int it = 0; it < 200 && b - a > 1e-15 * std::max(1.0, fabs(a) + fabs(b)); ++it) {
+            const double mid = 0.5 * (a + b);
+            if (sturm_below(d, e2, mid) <= target)
+                a = mid;
+            else
+                b = mid;
+        }
+        const double lam = 0.5 * (a + b);
+        for (int n = 0; n < M; ++n) x[n] = 1.0 + 0.01 * sin(0.37 * n + k);
+        for (int it = 0; it < 4; ++it) {
+            tridiag_solve(d, e, lam, x);
+            double nrm = 0.0;
+            for (int n = 0; n < M; ++n) nrm += x[n] * x[n];
+            nrm = sqrt(nrm);
+            for (int n = 0; n < M; ++n) x[n] /= nrm;
+        }
+        // sign: even orders positive sum, odd orders positive first
+        // significant sample (square above max(1e-7, 1/M))
+        double sum = 0.0;
+        for (int n = 0; n < M; ++n) sum += x[n];
+        bool flip = false;
+        if (k % 2 == 0) {
+            flip = sum < 0.0;
+        } else {
+            const double th = std::max(1e-7, 1.0 / M);
+            for (int n = 0; n < M; ++n)
+                if (x[n] * x[n] > th) {
+                    flip = x[n] < 0.0;
+                    break;
+                }
+        }
+        for (int n = 0; n < M; ++n) tapers[(size_t)k * M + n] = flip ? -x[n] : x[n];
+        // concentration in the band |f| < W: w^T A w with the sinc kernel
+        double conc = 0.0;
+        const double *w = tapers + (size_t)k * M;
+        std::vector<double> sk(M);
+        sk[0] = 2.0 * Wb;
+        for (int m = 1; m < M; ++m) sk[m] = sin(2.0 * M_PI * Wb * m) / (M_PI * m);
+        for (int i = 0; i < M; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < M; ++j) acc += sk[i > j ? i - j : j - i] * w[j];
+            conc += w[i] * acc;
+        }
+        ratios[k] = conc;
+    }
+    return FCX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// handle table: ids are never reused, so a closed handle stays recognisable
+// ---------------------------------------------------------------------------
+static std::mutex g_tab_mu;
+static std::unordered_map<uint64_t, Session *> g_tab;
+static uint64_t g_next_id = 1;
+
+uint64_t register_session(Session *s)
+{
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    s->id = g_next_id++;
+    g_tab[s->id] = s;
+    return s->id;
+}
+
+Session *lookup_session(fcx_session *h, fcx_status *st)
+{
+    const uint64_t id = (uint64_t)(uintptr_t)h;
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto it = g_tab.find(id);
+    if (it == g_tab.end()) {
+        *st = (id > 0 && id < g_next_id) ? FCX_E_CLOSED : FCX_E_INVAL;
+        return nullptr;
+    }
+    *st = FCX_OK;
+    return it->second;
+}
+
+Session *unregister_session(fcx_session *h, fcx_status *st)
+{
+    const uint64_t id = (uint64_t)(uintptr_t)h;
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto it = g_tab.find(id);
+    if (it == g_tab.end()) {
+        *st = (id > 0 && id < g_next_id) ? FCX_E_CLOSED : FCX_E_INVAL;
+        return nullptr;
+    }
+    Session *s = it->second;
+    g_tab.erase(it);
+    *st = FCX_OK;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// allocation
+// ---------------------------------------------------------------------------
+static fcx_status dalloc(Session *s, size_t bytes, void **p)
+{
+    *p = nullptr;
+    if (bytes == 0) return FCX_OK;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        return FCX_E_NOMEM;
+    }
+    s->allocs.push_back(*p);
+    if (hipMemsetAsync(*p, 0, bytes, s->stream) != hipSuccess) return FCX_E_DEVICE;
+    return FCX_OK;
+}
+
+void session_free(Session *s)
+{
+    if (s->stream) hipStreamSynchronize(s->stream);
+    for (void *p : s->allocs) hipFree(p);
+    s->allocs.clear();
+    for (int i = 0; i < 2; ++i) {
+        if (s->pinned[i]) hipHostFree(s->pinned[i]);
+        if (s->pinned_ev[i]) hipEventDestroy(s->pinned_ev[i]);
+        s->pinned[i] = nullptr;
+        s->pinned_ev[i] = nullptr;
+    }
+    for (auto &pt : s->pending) {
+        hipEventDestroy(pt.a);
+        hipEventDestroy(pt.b);
+    }
+    s->pending.clear();
+    for (auto ev : s->free_events) hipEventDestroy(ev);
+    s->free_events.clear();
+    if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+    s->stream = nullptr;
+}
+
+template <typename T>
+static void fill_tables(const Session *s, std::vector<T> &wtw, std::vector<double> &lamw)
+{
+    const Geometry &g = s->g;
+    std::vector<double> taper((size_t)g.L * g.M), lam(g.L, 1.0);
+    if (s->cfg.taper == FCX_TAPER_DPSS) {
+        dpss_impl(g.M, s->cfg.dpss_nw, g.L, taper.data(), lam.data());
+    } else {
+        for (int n = 0; n < g.M; ++n) {
+            double c, sn;
+            unit_root(n, g.M, &c, &sn);
+            taper[n] = 0.5 - 0.5 * c;
+        }
+    }
+    double lsum = 0.0;
+    for (int l = 0; l < g.L; ++l) lsum += lam[l];
+    lamw.resize(g.L);
+    for (int l = 0; l < g.L; ++l) lamw[l] = lam[l] / lsum;
+    wtw.assign((size_t)g.L * g.B * g.M * 2, (T)0);
+    for (int l = 0; l < g.L; ++l)
+        for (int b = 0; b < g.B; ++b) {
+            const long long k = g.klo + b;
+            for (int n = 0; n < g.M; ++n) {
+                double c, sn;
+                unit_root(k * n, g.F, &c, &sn);
+                const size_t o = (((size_t)l * g.B + b) * g.M + n) * 2;
+                wtw[o] = (T)(taper[(size_t)l * g.M + n] * c);
+                wtw[o + 1] = (T)(taper[(size_t)l * g.M + n] * sn);
+            }
+        }
+}
+
+fcx_status session_alloc(Session *s)
+{
+    const Geometry &g = s->g;
+    const BufferPlan &p = s->plan;
+    fcx_status st;
+#define ALLOC(field, bytes)                                        \
+    do {                                                           \
+        void *tmp_ = nullptr;                                      \
+        if ((st = dalloc(s, (bytes), &tmp_)) != FCX_OK) return st; \
+        s->field = (decltype(s->field))tmp_;                       \
+    } while (0)
+    ALLOC(ring, p.ring);
+    ALLOC(psd, p.psd);
+    for (int i = 0; i < NPLANES; ++i)
+        if (p.planes_used[i]) ALLOC(plane[i], p.plane);
+    if (p.g_used) ALLOC(gsum, p.gsum);
+    ALLOC(out, p.out);
+    ALLOC(ctl, p.ctl);
+    ALLOC(wtw, p.wtw);
+    ALLOC(lamw, p.lamw);
+    ALLOC(tiles, p.tiles);
+    ALLOC(zring, p.zring);
+    ALLOC(rsum, p.rsum);
+    ALLOC(xbuf, p.xbuf);
+#undef ALLOC
+    // tile list: upper-triangle tiles in row-major order
+    std::vector<int2> tl;
+    tl.reserve(g.ntiles);
+    for (int a = 0; a < g.nT; ++a)
+        for (int b = a; b < g.nT; ++b) tl.push_back(make_int2(a, b));
+    HIP_OK(hipMemcpyAsync(s->tiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream));
+    if (p.wtw) {
+        std::vector<double> lamw;
+        if (g.f64) {
+            std::vector<double> wtw;
+            fill_tables<double>(s, wtw, lamw);
+            HIP_OK(hipMemcpyAsync(s->wtw, wtw.data(), wtw.size() * 8, hipMemcpyHostToDevice, s->stream));
+        } else {
+            std::vector<float> wtw;
+            fill_tables<float>(s, wtw, lamw);
+            HIP_OK(hipMemcpyAsync(s->wtw, wtw.data(), wtw.size() * 4, hipMemcpyHostToDevice, s->stream));
+        }
+        HIP_OK(hipMemcpyAsync(s->lamw, lamw.data(), lamw.size() * 8, hipMemcpyHostToDevice, s->stream));
+        HIP_OK(hipStreamSynchronize(s->stream));  // host tables go out of scope
+    }
+    for (int i = 0; i < 2; ++i) {
+        HIP_OK(hipEventCreateWithFlags(&s->pinned_ev[i], hipEventDisableTiming));
+    }
+    HIP_OK(hipStreamSynchronize(s->stream));
+    return FCX_OK;
+}
+
+template <typename T> SessDev<T> session_dev(const Session *s, const void *x, long long ldx)
+{
+    SessDev<T> d;
+    const Geometry &g = s->g;
+    d.N = g.N;
+    d.M = g.M;
+    d.W = g.W;
+    d.B = g.B;
+    d.L = g.L;
+    d.nT = g.nT;
+    d.ntiles = g.ntiles;
+    d.Mz = g.Mz;
+    d.metrics = s->cfg.metrics;
+    d.has_cor = (s->cfg.metrics & M_COR) != 0;
+    d.tiles = s->tiles;
+    d.ring = (T *)s->ring;
+    d.psd = s->psd;
+    for (int i = 0; i < NPLANES; ++i) d.plane[i] = s->plane[i];
+    d.gsum = s->gsum;
+    d.out = (T *)s->out;
+    d.ctl = s->ctl;
+    d.wtw = (const T *)s->wtw;
+    d.lamw = s->lamw;
+    d.x = x;
+    d.ldx = ldx;
+    d.zring = s->zring;
+    d.rsum = s->rsum;
+    d.kbase = -1;
+    return d;
+}
+template SessDev<float> session_dev<float>(const Session *, const void *, long long);
+template SessDev<double> session_dev<double>(const Session *, const void *, long long);
+
+// ---------------------------------------------------------------------------
+// timing
+// ---------------------------------------------------------------------------
+static hipEvent_t get_event(Session *s)
+{
+    if (!s->free_events.empty()) {
+        hipEvent_t e = s->free_events.back();
+        s->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+static fcx_status resolve_timing(Session *s)
+{
+    if (s->pending.empty()) return FCX_OK;
+    HIP_OK(hipStreamSynchronize(s->stream));
+    for (auto &pt : s->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pt.a, pt.b) == hipSuccess) {
+            s->launches[pt.kernel] += 1;
+            s->total_ms[pt.kernel] += ms;
+        }
+        s->free_events.push_back(pt.a);
+        s->free_events.push_back(pt.b);
+    }
+    s->pending.clear();
+    return FCX_OK;
+}
+
+struct TimedLaunch {
+    Session *s;
+    int kernel;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(Session *s_, int k) : s(s_), kernel(k)
+    {
+        if (s->timing) {
+            a = get_event(s);
+            b = get_event(s);
+            hipEventRecord(a, s->stream);
+        }
+    }
+    ~TimedLaunch()
+    {
+        if (a) {
+            hipEventRecord(b, s->stream);
+            s->pending.push_back({kernel, a, b});
+            if (s->pending.size() > 4096) resolve_timing(s);
+        }
+    }
+};
+
+template <typename T> static fcx_status enqueue_push_t(Session *s, const void *xdev, long long ldx)
+{
+    const SessDev<T> d = session_dev<T>(s, xdev, ldx);
+    const bool spectral = (s->cfg.metrics & 0x7Fu) != 0;
+    if (spectral) {
+        TimedLaunch t(s, FCX_K_SPECTRA);
+        HIP_OK(launch_spectra<T>(d, s->stream));
+    }
+    if (s->cfg.metrics & M_COR) {  // also checks finiteness (COR-only sessions)
+        TimedLaunch t(s, FCX_K_COR);
+        HIP_OK(launch_znorm<T>(d, s->stream));
+    }
+    if (spectral) {
+        {
+            TimedLaunch t(s, FCX_K_PSD);
+            HIP_OK(launch_psd<T>(d, s->stream));
+        }
+        {
+            TimedLaunch t(s, FCX_K_PAIR_UPDATE);
+            HIP_OK(launch_pair_update<T>(d, s->stream));
+        }
+    }
+    if (s->cfg.metrics & M_COR) {
+        TimedLaunch t(s, FCX_K_COR);
+        HIP_OK(launch_cor_update<T>(d, s->stream));
+    }
+    HIP_OK(launch_commit(s->ctl, s->stream));
+    return FCX_OK;
+}
+
+fcx_status session_enqueue_push(Session *s, const void *xdev, long long ldx)
+{
+    return s->g.f64 ? enqueue_push_t<double>(s, xdev, ldx) : enqueue_push_t<float>(s, xdev, ldx);
+}
+
+// stage a host trial through pinned memory into the session's device buffer
+static fcx_status upload_host_trial(Session *s, const void *x, int64_t ld)
+{
+    const Geometry &g = s->g;
+    const size_t row = (size_t)g.M * g.esz;
+    const size_t bytes = row * g.N;
+    const int k = s->pinned_next;
+    s->pinned_next ^= 1;
+    if (!s->pinned[k]) {
+        if (hipHostMalloc(&s->pinned[k], bytes, hipHostMallocDefault) != hipSuccess) {
+            s->pinned[k] = nullptr;
+            return FCX_E_NOMEM;
+        }
+    }
+    if (s->pinned_busy[k]) HIP_OK(hipEventSynchronize(s->pinned_ev[k]));
+    const char *src = (const char *)x;
+    char *dst = (char *)s->pinned[k];
+    if ((size_t)ld * g.esz == row) {
+        memcpy(dst, src, bytes);
+    } else {
+        for (int i = 0; i < g.N; ++i) memcpy(dst + i * row, src + (size_t)i * ld * g.esz, row);
+    }
+    HIP_OK(hipMemcpyAsync(s->xbuf, dst, bytes, hipMemcpyHostToDevice, s->stream));
+    HIP_OK(hipEventRecord(s->pinned_ev[k], s->stream));
+    s->pinned_busy[k] = true;
+    return FCX_OK;
+}
+
+// Rebuild every running sum from the cached window: zero them, then add the
+// K cached trials oldest first through the same kernels, driven by a private
+// control block (no eviction, no new spectra).
+template <typename T> static fcx_status replay_window(Session *s, long long pushed)
+{
+    const Geometry &g = s->g;
+    const BufferPlan &p = s->plan;
+    const long long K = pushed < g.W ? pushed : g.W;
+    if (p.psd) HIP_OK(hipMemsetAsync(s->psd, 0, p.psd, s->stream));
+    for (int i = 0; i < NPLANES; ++i)
+        if (s->plane[i]) HIP_OK(hipMemsetAsync(s->plane[i], 0, p.plane, s->stream));
+    if (s->gsum) HIP_OK(hipMemsetAsync(s->gsum, 0, p.gsum, s->stream));
+    if (s->rsum) HIP_OK(hipMemsetAsync(s->rsum, 0, p.rsum, s->stream));
+    SessDev<T> d = session_dev<T>(s, nullptr, 0);
+    d.ctl = s->ctl + 1;
+    d.kbase = pushed - K;
+    const bool spectral = (s->cfg.metrics & 0x7Fu) != 0;
+    for (long long t = pushed - K; t < pushed; ++t) {
+        HIP_OK(launch_set_ctl(d.ctl, t, s->stream));
+        if (spectral) {
+            HIP_OK(launch_psd<T>(d, s->stream));
+            HIP_OK(launch_pair_update<T>(d, s->stream));
+        }
+        if (s->cfg.metrics & M_COR) HIP_OK(launch_cor_update<T>(d, s->stream));
+    }
+    HIP_OK(hipStreamSynchronize(s->stream));
+    return FCX_OK;
+}
+
+static fcx_status read_ctl(Session *s, DevCtl *c)
+{
+    HIP_OK(hipStreamSynchronize(s->stream));
+    HIP_OK(hipMemcpy(c, s->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost));
+    return FCX_OK;
+}
+
+static fcx_status take_rejections(Session *s, const DevCtl &c)
+{
+    if (c.rejected > s->reported_rejected) {
+        s->reported_rejected = c.rejected;
+        return FCX_E_NONFINITE;
+    }
+    return FCX_OK;
+}
+
+}  // namespace fcx
+
+using namespace fcx;
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *fcx_status_str(fcx_status st)
+{
+    switch (st) {
+    case FCX_OK: return "ok";
+    case FCX_E_INVAL: return "invalid argument";
+    case FCX_E_NOMEM: return "out of memory";
+    case FCX_E_DEVICE: return "HIP runtime error";
+    case FCX_E_NOTREADY: return "not enough trials";
+    case FCX_E_BUSY: return "HBM budget exhausted";
+    case FCX_E_CLOSED: return "session closed";
+    case FCX_E_NONFINITE: return "trial rejected: non-finite sample";
+    }
+    return "unknown status";
+}
+
+void fcx_config_init(fcx_config *c)
+{
+    if (!c) return;
+    memset(c, 0, sizeof(*c));
+    c->struct_size = sizeof(fcx_config);
+    c->window_trials = 1;
+    c->fs_hz = 1000.0;
+    c->taper = FCX_TAPER_HANN;
+    c->metrics = 0xFFu;
+    c->gram_precision = FCX_GRAM_FP32;
+    c->elem = FCX_ELEM_F32;
+}
+
+int32_t fcx_band_bins(const fcx_config *cfg, int32_t *k_lo, int32_t *k_hi)
+{
+    Geometry g;
+    if (make_geometry(cfg, &g) != FCX_OK) return -1;
+    if (k_lo) *k_lo = g.klo;
+    if (k_hi) *k_hi = g.khi;
+    return g.B;
+}
+
+int64_t fcx_footprint_bytes(const fcx_config *cfg)
+{
+    Geometry g;
+    if (make_geometry(cfg, &g) != FCX_OK) return -1;
+    return (int64_t)make_plan(*cfg, g).total();
+}
+
+fcx_status fcx_dpss(int32_t M, double NW, int32_t K, double *tapers, double *ratios)
+{
+    if (!tapers || !ratios) return FCX_E_INVAL;
+    return dpss_impl(M, NW, K, tapers, ratios);
+}
+
+fcx_status fcx_open(const fcx_config *cfg, void *hip_stream, fcx_session **out)
+{
+    if (!out) return FCX_E_INVAL;
+    *out = nullptr;
+    Geometry g;
+    fcx_status st = make_geometry(cfg, &g);
+    if (st != FCX_OK) return st;
+    Session *s = new (std::nothrow) Session();
+    if (!s) return FCX_E_NOMEM;
+    s->cfg = *cfg;
+    s->g = g;
+    s->plan = make_plan(*cfg, g);
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return FCX_E_DEVICE;
+    }
+    if (hip_stream) {
+        s->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete s;
+            return FCX_E_DEVICE;
+        }
+        s->own_stream = true;
+    }
+    st = session_alloc(s);
+    if (st != FCX_OK) {
+        session_free(s);
+        delete s;
+        return st;
+    }
+    *out = (fcx_session *)(uintptr_t)register_session(s);
+    return FCX_OK;
+}
+
+fcx_status fcx_push_trial(fcx_session *h, const void *x, int64_t ld, int x_on_device)
+{
+    fcx_status st;
+    Session *s = lookup_session(h, &st);
+    if (!s) return st;
+    if (s->server) return FCX_E_INVAL;  // served sessions take trials through the server
+    if (!x || ld < s->g.M) return FCX_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    const void *xdev = x;
+    long long ldx = ld;
+    if (!x_on_device) {
+        st = upload_host_trial(s, x, ld);
+        if (st != FCX_OK) return st;
+        xdev = s->xbuf;
+        ldx = s->g.M;
+    }
+    return session_enqueue_push(s, xdev, ldx);
+}
+
+fcx_status fcx_push_batch(fcx_session *h, const void *x, int64_t n_trials, int64_t trial_stride, int64_t ld,
+                          int x_on_device)
+{
+    fcx_status st;
+    Session *s = lookup_session(h, &st);
+    if (!s) return st;
+    if (s->server) return FCX_E_INVAL;
+    if (!x || n_trials < 1 || n_trials > s->g.W || ld < s->g.M || trial_stride < ld * s->g.N)
+        return FCX_E_INVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        // reset the window: zero the running sums and the push counter
+        const BufferPlan &p = s->plan;
+        if (p.psd) HIP_OK(hipMemsetAsync(s->psd, 0, p.psd, s->stream));
+        for (int i = 0; i < NPLANES; ++i)
+            if (s->plane[i]) HIP_OK(hipMemsetAsync(s->plane[i], 0, p.plane, s->stream));
+        if (s->gsum) HIP_OK(hipMemsetAsync(s->gsum, 0, p.gsum, s->stream));
+        if (s->rsum) HIP_OK(hipMemsetAsync(s->rsum, 0, p.rsum, s->stream));
+        HIP_OK(hipMemsetAsync(s->ctl, 0, sizeof(DevCtl), s->stream));
+        s->reported_rejected = 0;
+    }
+    const size_t es = s->g.esz;
+    for (int64_t k = 0; k < n_trials; ++k) {
+        st = fcx_push_trial(h, (const char *)x + (size_t)k * trial_stride * es, ld, x_on_device);
+        if (st != FCX_OK) return st;
+    }
+    return FCX_OK;
+}
+
+fcx_status fcx_sync(fcx_session *h)
+{
+    fcx_status st;
+    Session *s = lookup_session(h, &st);
+    if (!s) return st;
+    std::lock_guard<std::mutex> lk(s->mu);
+    DevCtl c;
+    st = read_ctl(s, &c);
+    if (st != FCX_OK) return st;
+    return take_rejections(s, c);
+}
+
+fcx_status fcx_read_network(fcx_session *h, uint32_t metric, void *out, int64_t out_len, int out_on_device,
+                            int per_bin, int32_t *k_trials_out)
+{
+    fcx_status st;
+    Session *s = lookup_session(h, &st);
+    if (!s) return st;
+    if (!out || metric == 0 || (metric & (metric - 1)) || !(metric & s->cfg.metrics)) return FCX_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    const Geometry &g = s->g;
+    const bool bins = per_bin && metric != M_COR;
+    const size_t need = bins ? (size_t)g.B * g.P : g.P;
+    if (out_len < (int64_t)need) return FCX_E_INVAL;
+    DevCtl c;
+    st = read_ctl(s, &c);
+    if (st != FCX_OK) return st;
+    const int64_t K = c.pushed < g.W ? c.pushed : g.W;
+    if (k_trials_out) *k_trials_out = (int32_t)K;
+    if (K == 0) return FCX_E_NOTREADY;
+    int mi = 0;
+    while (!((metric >> mi) & 1u)) ++mi;
+    const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (!bins) {
+        const char *src = (const char *)s->out + (size_t)mi * g.P * g.esz;
+        HIP_OK(hipMemcpy(out, src, g.P * g.esz, kind));
+    } else {
+        void *dst = out;
+        void *tmp = nullptr;
+        if (!out_on_device) {
+            if (hipMalloc(&tmp, need * g.esz) != hipSuccess) return FCX_E_NOMEM;
+            dst = tmp;
+        }
+        hipError_t e;
+        if (g.f64)
+            e = launch_finalize_bins<double>(session_dev<double>(s, nullptr, 0), metric, (double *)dst, s->stream);
+        else
+            e = launch_finalize_bins<float>(session_dev<float>(s, nullptr, 0), metric, (float *)dst, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e == hipSuccess && tmp) e = hipMemcpy(out, tmp, need * g.esz, hipMemcpyDeviceToHost);
+        if (tmp) hipFree(tmp);
+        if (e != hipSuccess) return FCX_E_DEVICE;
+    }
+    const fcx_status rej = take_rejections(s, c);
+    if (rej != FCX_OK) return rej;
+    if (K < 2 && (metric == M_USPLI || metric == M_DSWPLI)) return FCX_E_NOTREADY;
+    return FCX_OK;
+}
+
+fcx_status fcx_resync(fcx_session *h)
+{
+    fcx_status st;
+    Session *s = lookup_session(h, &st);
+    if (!s) return st;
+    std::lock_guard<std::mutex> lk(s->mu);
+    DevCtl c;
+    st = read_ctl(s, &c);
+    if (st != FCX_OK) return st;
+    return s->g.f64 ? replay_window<double>(s, c.pushed) : replay_window<float>(s, c.pushed);
+}
+
+fcx_status fcx_close(fcx_session *h)
+{
+    fcx_status st;
+    Session *s = lookup_session(h, &st);
+    if (!s) return st;
+    if (s->server) return FCX_E_INVAL;  // close through fcx_server_close_session
+    s = unregister_session(h, &st);
+    if (!s) return st;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        session_free(s);
+    }
+    delete s;
+    return FCX_OK;
+}
+
+fcx_status fcx_session_stream(fcx_session *h, void **hip_stream)
+{
+    fcx_status st;
+    Session *s = lookup_session(h, &st);
+    if (!s) return st;
+    if (!hip_stream) return FCX_E_INVAL;
+    *hip_stream = (void *)s->stream;
+    return FCX_OK;
+}
+
+fcx_status fcx_session_counts(fcx_session *h, int64_t *accepted, int64_t *rejected)
+{
+    fcx_status st;
+    Session *s = lookup_session(h, &st);
+    if (!s) return st;
+    std::lock_guard<std::mutex> lk(s->mu);
+    DevCtl c;
+    st = read_ctl(s, &c);
+    if (st != FCX_OK) return st;
+    if (accepted) *accepted = c.pushed;
+    if (rejected) *rejected = c.rejected;
+    return FCX_OK;
+}
+
+fcx_status fcx_set_timing(fcx_session *h, int enable)
+{
+    fcx_status st;
+    Session *s = lookup_session(h, &st);
+    if (!s) return st;
+    std::lock_guard<std::mutex> lk(s->mu);
+    st = resolve_timing(s);
+    s->timing = enable != 0;
+    for (int k = 0; k < FCX_K_COUNT; ++k) {
+        s->launches[k] = 0;
+        s->total_ms[k] = 0.0;
+    }
+    return st;
+}
+
+fcx_status fcx_kernel_time(fcx_session *h, int kernel, int64_t *launches, double *total_ms)
+{
+    fcx_status st;
+    Session *s = lookup_session(h, &st);
+    if (!s) return st;
+    if (kernel < 0 || kernel >= FCX_K_COUNT) return FCX_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    st = resolve_timing(s);
+    if (st != FCX_OK) return st;
+    if (launches) *launches = s->launches[kernel];
+    if (total_ms) *total_ms = s->total_ms[kernel];
+    return FCX_OK;
+}
+
+fcx_status fcx_probe_copy(void *dst, const void *src, int64_t n_bytes, void *hip_stream)
+{
+    if (!dst || !src || n_bytes <= 0 || (n_bytes % 16)) return FCX_E_INVAL;
+    return launch_copy_probe(dst, src, n_bytes, (hipStream_t)hip_stream) == hipSuccess ? FCX_OK : FCX_E_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Internal declarations shared by the host session code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fcx {
+
+constexpr int TILE = 64;             // pair tile edge: a tile holds 64 x 64 pairs
+constexpr int TILE_PAIRS = TILE * TILE;
+constexpr int PAIR_THREADS = 1024;   // workgroup of the pair kernels (16 waves)
+constexpr int PAIR_LDS_BYTES = 64 * 1024;
+constexpr int ZPAD = 16;             // COR sample rows padded to a multiple of 16
+
+// running-sum planes of the pair state, one FP64 plane each (G is int16)
+enum Plane { P_SRE = 0, P_SIM = 1, P_URE = 2, P_UIM = 3, P_A = 4, P_Q = 5, NPLANES = 6 };
+
+// metric bits (same values as the public header)
+enum : uint32_t { M_COH = 1, M_IMCOH = 2, M_PLV = 4, M_PLI = 8, M_WPLI = 16, M_USPLI = 32,
+                  M_DSWPLI = 64, M_COR = 128 };
+
+// Device-resident push control.  Every kernel of a push reads it; only the
+// commit kernel advances it, so a rejected (non-finite) trial changes nothing.
+struct DevCtl {
+    long long pushed;     // trials accepted so far
+    int bad;              // set by the spectra kernel when the trial is not finite
+    int pad;
+    long long rejected;   // trials rejected so far
+};
+
+// Everything a kernel needs to know about one session (passed by value, or
+// from a device array of descriptors in the serving path).
+template <typename T>
+struct SessDev {
+    int N, M, W, B, L, nT, ntiles, Mz;
+    uint32_t metrics;
+    int has_cor;
+    const int2 *tiles;      // [ntiles] (tile row, tile col), row <= col
+    T *ring;                // [(W+1)][B][L][N] complex (re, im interleaved)
+    double *psd;            // [B][N] running sum of per-trial power
+    double *plane[NPLANES]; // [ntiles][B][TILE_PAIRS] or null when not needed
+    short *gsum;            // [ntiles][B][TILE_PAIRS] sign sums or null
+    T *out;                 // [8][P] band-mean networks
+    DevCtl *ctl;
+    const T *wtw;           // [L][B][M] complex taper * exp(-2 pi i k n / F)
+    const double *lamw;     // [L] taper weights, normalised to sum 1
+    const void *x;          // current trial input [N][ldx] (T)
+    long long ldx;
+    float *zring;           // [(W+1)][N][Mz] z-scored samples (COR)
+    double *rsum;           // [ntiles][TILE_PAIRS] running sum of per-trial r (COR)
+    long long kbase;        // -1: sliding push; >= 0: replay of a cached window
+                            // (add only, K = pushed - kbase + 1)
+};
+
+// Which ring slots a push touches and how many trials the window holds after it.
+struct PushView {
+    long long tp;   // index of the trial being added
+    int K;          // trials in the window after the update
+    int slot_new, slot_old;
+    bool has_old;   // a trial is evicted
+};
+
+template <typename T>
+__host__ __device__ inline PushView push_view(const SessDev<T> &s, long long tp)
+{
+    PushView v;
+    v.tp = tp;
+    if (s.kbase >= 0) {
+        v.has_old = false;
+        v.K = (int)(tp - s.kbase + 1);
+    } else {
+        v.has_old = tp >= s.W;
+        v.K = v.has_old ? s.W : (int)tp + 1;
+    }
+    v.slot_new = (int)(tp % (long long)(s.W + 1));
+    v.slot_old = v.has_old ? (int)((tp - s.W) % (long long)(s.W + 1)) : 0;
+    return v;
+}
+
+// launchers (implemented in fcx_kernels.hip); all return hipError_t
+template <typename T> hipError_t launch_spectra(const SessDev<T> &s, hipStream_t st);
+template <typename T> hipError_t launch_psd(const SessDev<T> &s, hipStream_t st);
+template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStream_t st);
+template <typename T> hipError_t launch_znorm(const SessDev<T> &s, hipStream_t st);
+template <typename T> hipError_t launch_cor_update(const SessDev<T> &s, hipStream_t st);
+hipError_t launch_commit(DevCtl *ctl, hipStream_t st);
+hipError_t launch_set_ctl(DevCtl *ctl, long long pushed, hipStream_t st);
+template <typename T>
+hipError_t launch_finalize_bins(const SessDev<T> &s, uint32_t metric, T *out, hipStream_t st);
+hipError_t launch_copy_probe(void *dst, const void *src, int64_t n_bytes, hipStream_t st);
+
+// bin-chunk size of the pair kernel for a given (B, L, element size), and the
+// LDS it needs
+__host__ __device__ int pair_chunk_bins(int B, int L, int elem_bytes);
+__host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes);
+
+// batched launches of the serving path (float sessions); items are
+// (session index, a, b, 0) with a/b the block coordinates of the kernel
+enum { FCX_B_SPECTRA = 0, FCX_B_ZNORM, FCX_B_PSD, FCX_B_PAIR, FCX_B_COR, FCX_B_COMMIT };
+hipError_t launch_batched(int which, const SessDev<float> *S, const int4 *items, int n, size_t lds,
+                          hipStream_t st);
+
+}  // namespace fcx

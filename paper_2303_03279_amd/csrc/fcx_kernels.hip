@@ -1,0 +1,796 @@
+// HIP kernels of the sliding-window connectivity update for gfx950.
+//
+// One push of a trial runs, in stream order:
+//   k_spectra      taper x band-limited DFT of every node into the ring slot of
+//                  the new trial (the per-trial spectrum of the CSD/PSD eqs.),
+//                  flags non-finite input
+//   k_znorm        z-scored samples of the trial into the COR sample ring
+//   k_psd          running per-node power sums: + new trial, - evicted trial
+//   k_pair_update  per pair tile and bin: running sums of CSD, unit phasors,
+//                  sign(Im), |Im| and Im^2 (+ new, - evicted), then the seven
+//                  spectral metrics and their band mean (the hot kernel)
+//   k_cor_update   per pair tile: per-trial Pearson r of new and evicted trial
+//                  as 16x16x4 FP32 MFMA Gram blocks, running sum, COR
+//   k_commit       accept the trial (or count the rejection)
+//
+// Nothing is reordered across trials: an evicted trial's contribution is
+// recomputed from the cached spectra with exactly the instructions that added
+// it, so add and remove cancel bit for bit before the FP64 rounding of the
+// running sum itself.
+#include "fcx_internal.h"
+
+#include <math.h>
+
+#pragma clang fp contract(off)
+
+namespace fcx {
+
+template <typename T> struct V2;
+template <> struct V2<float> { typedef float2 t; };
+template <> struct V2<double> { typedef double2 t; };
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int sgn_of(double v) { return (v > 0.0) - (v < 0.0); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T> __device__ __forceinline__ T sqrt_ratio(double r);
+template <> __device__ __forceinline__ float sqrt_ratio<float>(double r) { return sqrtf((float)r); }
+template <> __device__ __forceinline__ double sqrt_ratio<double>(double r) { return sqrt(r); }
+
+__device__ __forceinline__ bool finite_v(float v) { return isfinite(v); }
+__device__ __forceinline__ bool finite_v(double v) { return isfinite(v); }
+
+// ---------------------------------------------------------------------------
+// spectra: X[b][l][i] = sum_n (w_l[n] e^{-2 pi i k_b n / F}) x_i[n]
+// A workgroup owns 16 nodes and 16 (taper, bin) outputs per node; samples are
+// staged through LDS 256 at a time and summed in blocks of 256 (block sums
+// added to the total) to keep the FP32 rounding growth small.
+// ---------------------------------------------------------------------------
+constexpr int SP_NODES = 16;
+constexpr int SP_CH = 256;
+
+template <typename T>
+__device__ __forceinline__ void spectra_body(const SessDev<T> &s, int bx, int by, T (*xs)[SP_CH + 1])
+{
+    const int t = threadIdx.x;
+    const int node0 = bx * SP_NODES;
+    const int nl = t & (SP_NODES - 1);
+    const int bl = by * (256 / SP_NODES) + (t / SP_NODES);   // l * B + b
+    const int BL = s.B * s.L;
+    const bool active = bl < BL && node0 + nl < s.N;
+    const long long tp = s.ctl->pushed;
+    const int slot = (int)(tp % (long long)(s.W + 1));
+    const T *x = (const T *)s.x;
+    const T *tw = s.wtw + (size_t)(active ? bl : 0) * s.M * 2;
+    T acc_re = 0, acc_im = 0;
+    int bad = 0;
+    for (int n0 = 0; n0 < s.M; n0 += SP_CH) {
+        for (int e = t; e < SP_NODES * SP_CH; e += 256) {
+            const int r = e / SP_CH, c = e % SP_CH;
+            const int node = node0 + r, n = n0 + c;
+            T v = 0;
+            if (node < s.N && n < s.M) {
+                v = x[(size_t)node * s.ldx + n];
+                if (!finite_v(v)) bad = 1;
+            }
+            xs[r][c] = v;
+        }
+        __syncthreads();
+        if (active) {
+            const int nmax = min(SP_CH, s.M - n0);
+            T pr = 0, pi = 0;
+            for (int c = 0; c < nmax; ++c) {
+                const T xv = xs[nl][c];
+                pr = fma(xv, tw[2 * (n0 + c)], pr);
+                pi = fma(xv, tw[2 * (n0 + c) + 1], pi);
+            }
+            acc_re += pr;
+            acc_im += pi;
+        }
+        __syncthreads();
+    }
+    if (bad) s.ctl->bad = 1;
+    if (active) {
+        const int l = bl / s.B, b = bl % s.B;
+        const size_t o = (((size_t)slot * s.B + b) * s.L + l) * s.N + node0 + nl;
+        typedef typename V2<T>::t T2;
+        T2 v;
+        v.x = acc_re;
+        v.y = acc_im;
+        ((T2 *)s.ring)[o] = v;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_spectra(SessDev<T> s)
+{
+    __shared__ T xs[SP_NODES][SP_CH + 1];
+    spectra_body(s, blockIdx.x, blockIdx.y, xs);
+}
+
+template <typename T> hipError_t launch_spectra(const SessDev<T> &s, hipStream_t st)
+{
+    dim3 grid((s.N + SP_NODES - 1) / SP_NODES, (s.B * s.L + 15) / 16);
+    hipLaunchKernelGGL(k_spectra<T>, grid, dim3(256), 0, st, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// z-scored samples for COR: z = (x - mean) / ||x - mean|| (0 for a constant
+// row), so that the Pearson r of a trial is the plain dot product z_i . z_j.
+// One wavefront per node; rows padded with zeros to Mz.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void znorm_body(const SessDev<T> &s, int bx)
+{
+    const int lane = threadIdx.x & 63;
+    const int node = bx * 4 + (threadIdx.x >> 6);
+    if (node >= s.N) return;
+    const long long tp = s.ctl->pushed;
+    const int slot = (int)(tp % (long long)(s.W + 1));
+    const T *xr = (const T *)s.x + (size_t)node * s.ldx;
+    double sum = 0.0;
+    int bad = 0;
+    for (int n = lane; n < s.M; n += 64) {
+        const T v = xr[n];
+        if (!finite_v(v)) bad = 1;
+        sum += (double)v;
+    }
+    if (bad) s.ctl->bad = 1;
+    const double mean = wave_sum(sum) / (double)s.M;
+    double ss = 0.0;
+    for (int n = lane; n < s.M; n += 64) {
+        const double d = (double)xr[n] - mean;
+        ss += d * d;
+    }
+    ss = wave_sum(ss);
+    const double inv = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+    float *z = s.zring + ((size_t)slot * s.N + node) * s.Mz;
+    for (int n = lane; n < s.Mz; n += 64) z[n] = n < s.M ? (float)(((double)xr[n] - mean) * inv) : 0.0f;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_znorm(SessDev<T> s)
+{
+    znorm_body(s, blockIdx.x);
+}
+
+template <typename T> hipError_t launch_znorm(const SessDev<T> &s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_znorm<T>, dim3((s.N + 3) / 4), dim3(256), 0, st, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// running power sums: P[b][i] += PSD_new - PSD_evicted (FP64)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ double trial_psd(const SessDev<T> &s, int slot, int b, int i)
+{
+    typedef typename V2<T>::t T2;
+    const T2 *ring = (const T2 *)s.ring;
+    double p = 0.0;
+    for (int l = 0; l < s.L; ++l) {
+        const T2 v = ring[(((size_t)slot * s.B + b) * s.L + l) * s.N + i];
+        const double re = v.x, im = v.y;
+        p += s.lamw[l] * (re * re + im * im);
+    }
+    return p;
+}
+
+template <typename T>
+__device__ __forceinline__ void psd_body(const SessDev<T> &s, int bx)
+{
+    if (s.ctl->bad) return;
+    const int e = bx * 256 + threadIdx.x;
+    if (e >= s.B * s.N) return;
+    const int b = e / s.N, i = e % s.N;
+    const PushView pv = push_view(s, s.ctl->pushed);
+    double v = s.psd[e];
+    v = v + trial_psd(s, pv.slot_new, b, i);
+    if (pv.has_old) v = v - trial_psd(s, pv.slot_old, b, i);
+    s.psd[e] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_psd(SessDev<T> s)
+{
+    psd_body(s, blockIdx.x);
+}
+
+template <typename T> hipError_t launch_psd(const SessDev<T> &s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_psd<T>, dim3((s.B * s.N + 255) / 256), dim3(256), 0, st, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// pair update (the hot kernel)
+//
+// Workgroup = one 64x64 pair tile, 1024 threads: lane = column j, wavefront
+// w handles rows w, w+16, w+32, w+48.  Bins are processed in chunks whose
+// node data (new and evicted spectra, unit phasors, 1/sqrt(P)) for the 64
+// row and 64 column nodes are staged in LDS; the running sums stream from
+// HBM once per push, coalesced ([tile][bin][row][col] planes), are updated in
+// FP64 and written back; the per-bin metrics are accumulated into the band
+// mean in registers and written once per pair.
+// ---------------------------------------------------------------------------
+__host__ __device__ int pair_chunk_bins(int B, int L, int elem_bytes)
+{
+    const int per_node_bin = 2 * L * 2 * elem_bytes + (L == 1 ? 2 * 2 * elem_bytes : 0) + 8;
+    int cb = PAIR_LDS_BYTES / (2 * TILE * per_node_bin);
+    if (cb < 1) cb = 1;
+    return cb < B ? cb : B;
+}
+
+__host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes)
+{
+    const int per_node_bin = 2 * L * 2 * elem_bytes + (L == 1 ? 2 * 2 * elem_bytes : 0) + 8;
+    return (size_t)CB * 2 * TILE * per_node_bin;
+}
+
+template <typename T>
+__device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, long long tp, int CB,
+                                                 char *lds)
+{
+    typedef typename V2<T>::t T2;
+    const int tid = threadIdx.x;
+    const int c = tid & (TILE - 1);
+    const int w = tid >> 6;
+    const int2 tt = s.tiles[tile];
+    const int I0 = tt.x * TILE, J0 = tt.y * TILE;
+    const int N = s.N, B = s.B, L = s.L;
+    const PushView pv = push_view(s, tp);
+    const bool has_old = pv.has_old;
+    const int K = pv.K;
+    const int slot_new = pv.slot_new, slot_old = pv.slot_old;
+    const uint32_t mm = s.metrics;
+    const bool needSre = mm & M_COH;
+    const bool needSim = mm & (M_COH | M_IMCOH | M_WPLI | M_DSWPLI);
+    const bool needU = mm & M_PLV;
+    const bool needG = mm & (M_PLI | M_USPLI);
+    const bool needA = mm & (M_WPLI | M_DSWPLI);
+    const bool needQ = mm & M_DSWPLI;
+    const T2 *ring = (const T2 *)s.ring;
+    double *__restrict__ pSre = s.plane[P_SRE];
+    double *__restrict__ pSim = s.plane[P_SIM];
+    double *__restrict__ pUre = s.plane[P_URE];
+    double *__restrict__ pUim = s.plane[P_UIM];
+    double *__restrict__ pA = s.plane[P_A];
+    double *__restrict__ pQ = s.plane[P_Q];
+    short *__restrict__ pG = s.gsum;
+
+    const int nodes2 = 2 * TILE;
+    T2 *Xn = (T2 *)lds;
+    T2 *Xo = Xn + (size_t)CB * L * nodes2;
+    T2 *Un = Xo + (size_t)CB * L * nodes2;
+    T2 *Uo = Un + (L == 1 ? (size_t)CB * nodes2 : 0);
+    double *SR = (double *)(Uo + (L == 1 ? (size_t)CB * nodes2 : 0));
+
+    T acc[4][7];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int m = 0; m < 7; ++m) acc[q][m] = 0;
+
+    const double Kd = (double)K;
+    for (int b0 = 0; b0 < B; b0 += CB) {
+        const int nb = min(CB, B - b0);
+        for (int e = tid; e < nb * L * nodes2; e += PAIR_THREADS) {
+            const int nl = e % nodes2, bl = e / nodes2;
+            const int l = bl % L, bb = bl / L;
+            const int node = nl < TILE ? I0 + nl : J0 + nl - TILE;
+            T2 xn, xo;
+            xn.x = xn.y = xo.x = xo.y = 0;
+            if (node < N) {
+                xn = ring[(((size_t)slot_new * B + b0 + bb) * L + l) * N + node];
+                if (has_old) xo = ring[(((size_t)slot_old * B + b0 + bb) * L + l) * N + node];
+            }
+            Xn[(size_t)bl * nodes2 + nl] = xn;
+            Xo[(size_t)bl * nodes2 + nl] = xo;
+            if (L == 1) {
+                // unit phasor X / |X| (0 for X = 0), formed in FP64 so that
+                // tiny amplitudes cannot underflow
+                T2 un, uo;
+                const double mn = sqrt((double)xn.x * xn.x + (double)xn.y * xn.y);
+                const double mo = sqrt((double)xo.x * xo.x + (double)xo.y * xo.y);
+                un.x = mn > 0.0 ? (T)(xn.x / mn) : (T)0;
+                un.y = mn > 0.0 ? (T)(xn.y / mn) : (T)0;
+                uo.x = mo > 0.0 ? (T)(xo.x / mo) : (T)0;
+                uo.y = mo > 0.0 ? (T)(xo.y / mo) : (T)0;
+                Un[(size_t)bb * nodes2 + nl] = un;
+                Uo[(size_t)bb * nodes2 + nl] = uo;
+            }
+        }
+        for (int e = tid; e < nb * nodes2; e += PAIR_THREADS) {
+            const int nl = e % nodes2, bb = e / nodes2;
+            const int node = nl < TILE ? I0 + nl : J0 + nl - TILE;
+            double sr = 0.0;
+            if (node < N) {
+                const double p = s.psd[(size_t)(b0 + bb) * N + node];
+                sr = p > 0.0 ? 1.0 / sqrt(p) : 0.0;
+            }
+            SR[e] = sr;
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = w + 16 * q;
+            const int i = I0 + r, j = J0 + c;
+            if (!(i < j && j < N)) continue;
+            for (int bb = 0; bb < nb; ++bb) {
+                const size_t e = (((size_t)tile * B + b0 + bb) * TILE + r) * TILE + c;
+                double cnr = 0.0, cni = 0.0, cor_ = 0.0, coi = 0.0;
+                for (int l = 0; l < L; ++l) {
+                    const size_t ob = (size_t)(bb * L + l) * nodes2;
+                    const T2 a = Xn[ob + r], bx = Xn[ob + TILE + c];
+                    // X_i conj(X_j): FP32 operands give exact FP64 products
+                    double re = (double)a.x * bx.x + (double)a.y * bx.y;
+                    double im = (double)a.y * bx.x - (double)a.x * bx.y;
+                    if (L == 1) {
+                        cnr = re;
+                        cni = im;
+                    } else {
+                        cnr += s.lamw[l] * re;
+                        cni += s.lamw[l] * im;
+                    }
+                    if (has_old) {
+                        const T2 ao = Xo[ob + r], bo = Xo[ob + TILE + c];
+                        re = (double)ao.x * bo.x + (double)ao.y * bo.y;
+                        im = (double)ao.y * bo.x - (double)ao.x * bo.y;
+                        if (L == 1) {
+                            cor_ = re;
+                            coi = im;
+                        } else {
+                            cor_ += s.lamw[l] * re;
+                            coi += s.lamw[l] * im;
+                        }
+                    }
+                }
+                double Sre = 0.0, Sim = 0.0, Ure = 0.0, Uim = 0.0, A = 0.0, Q = 0.0;
+                int g = 0;
+                if (needSre) {
+                    Sre = pSre[e] + cnr;
+                    if (has_old) Sre = Sre - cor_;
+                    pSre[e] = Sre;
+                }
+                if (needSim) {
+                    Sim = pSim[e] + cni;
+                    if (has_old) Sim = Sim - coi;
+                    pSim[e] = Sim;
+                }
+                if (needU) {
+                    double unr, uni, uor = 0.0, uoi = 0.0;
+                    if (L == 1) {
+                        const T2 ui = Un[(size_t)bb * nodes2 + r], uj = Un[(size_t)bb * nodes2 + TILE + c];
+                        unr = (double)(T)(ui.x * uj.x + ui.y * uj.y);
+                        uni = (double)(T)(ui.y * uj.x - ui.x * uj.y);
+                        if (has_old) {
+                            const T2 vi = Uo[(size_t)bb * nodes2 + r], vj = Uo[(size_t)bb * nodes2 + TILE + c];
+                            uor = (double)(T)(vi.x * vj.x + vi.y * vj.y);
+                            uoi = (double)(T)(vi.y * vj.x - vi.x * vj.y);
+                        }
+                    } else {
+                        const double mn = sqrt(cnr * cnr + cni * cni);
+                        unr = mn > 0.0 ? cnr / mn : 0.0;
+                        uni = mn > 0.0 ? cni / mn : 0.0;
+                        if (has_old) {
+                            const double mo = sqrt(cor_ * cor_ + coi * coi);
+                            uor = mo > 0.0 ? cor_ / mo : 0.0;
+                            uoi = mo > 0.0 ? coi / mo : 0.0;
+                        }
+                    }
+                    Ure = pUre[e] + unr;
+                    Uim = pUim[e] + uni;
+                    if (has_old) {
+                        Ure = Ure - uor;
+                        Uim = Uim - uoi;
+                    }
+                    pUre[e] = Ure;
+                    pUim[e] = Uim;
+                }
+                if (needG) {
+                    g = (int)pG[e] + sgn_of(cni);
+                    if (has_old) g -= sgn_of(coi);
+                    pG[e] = (short)g;
+                }
+                if (needA) {
+                    A = pA[e] + fabs(cni);
+                    if (has_old) A = A - fabs(coi);
+                    pA[e] = A;
+                }
+                if (needQ) {
+                    Q = pQ[e] + cni * cni;
+                    if (has_old) Q = Q - coi * coi;
+                    pQ[e] = Q;
+                }
+                // metrics of this bin, into the band mean
+                const double srij = SR[bb * nodes2 + r] * SR[bb * nodes2 + TILE + c];
+                if (mm & M_COH) acc[q][0] += sqrt_ratio<T>((Sre * Sre + Sim * Sim) * srij * srij);
+                if (mm & M_IMCOH) acc[q][1] += (T)(Sim * srij);
+                if (mm & M_PLV) acc[q][2] += sqrt_ratio<T>(Ure * Ure + Uim * Uim) / (T)K;
+                if (mm & (M_PLI | M_USPLI)) {
+                    const double pli = fabs((double)g) / Kd;
+                    if (mm & M_PLI) acc[q][3] += (T)pli;
+                    if (mm & M_USPLI) acc[q][5] += K >= 2 ? (T)((Kd * pli * pli - 1.0) / (Kd - 1.0)) : (T)NAN;
+                }
+                if (mm & M_WPLI) acc[q][4] += A > 0.0 ? (T)(fabs(Sim) / A) : (T)0;
+                if (mm & M_DSWPLI) {
+                    const double dd = A * A - Q;
+                    acc[q][6] += K >= 2 ? (dd != 0.0 ? (T)((Sim * Sim - Q) / dd) : (T)0) : (T)NAN;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    const size_t P = (size_t)N * (N - 1) / 2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = w + 16 * q;
+        const int i = I0 + r, j = J0 + c;
+        if (!(i < j && j < N)) continue;
+        const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+#pragma unroll
+        for (int m = 0; m < 7; ++m)
+            if (mm & (1u << m)) s.out[(size_t)m * P + idx] = acc[q][m] / (T)B;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(PAIR_THREADS) void k_pair_update(SessDev<T> s, int CB)
+{
+    extern __shared__ __align__(16) char lds[];
+    if (s.ctl->bad) return;
+    pair_tile_update<T>(s, blockIdx.x, s.ctl->pushed, CB, lds);
+}
+
+template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStream_t st)
+{
+    const int CB = pair_chunk_bins(s.B, s.L, (int)sizeof(T));
+    const size_t lds = pair_lds_bytes(CB, s.L, (int)sizeof(T));
+    hipLaunchKernelGGL(k_pair_update<T>, dim3(s.ntiles), dim3(PAIR_THREADS), lds, st, s, CB);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// COR update: r_ij(trial) = z_i . z_j as FP32 MFMA Gram blocks.
+// Workgroup = one 64x64 pair tile, 4 wavefronts, each a 32x32 quadrant made
+// of 2x2 blocks of v_mfma_f32_16x16x4f32.  Lane l feeds row (l & 15) of its
+// block and the 4 consecutive samples 4*(l >> 4) .. +3 of each 16-sample
+// step, loaded as one float4; the same sample permutation on both operands
+// leaves the dot products unchanged.  The new and the evicted trial are
+// contracted separately so the evicted r is bit-identical to the one added.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void cor_body(const SessDev<T> &s, int tile)
+{
+    if (s.ctl->bad) return;
+    const int N = s.N, Mz = s.Mz;
+    const PushView pv = push_view(s, s.ctl->pushed);
+    const bool has_old = pv.has_old;
+    const int K = pv.K;
+    const int slot_new = pv.slot_new, slot_old = pv.slot_old;
+    const int2 tt = s.tiles[tile];
+    const int I0 = tt.x * TILE, J0 = tt.y * TILE;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int qi = wv >> 1, qj = wv & 1;
+    const int lr = lane & 15, lg = lane >> 4;
+
+    int rows[2], cols[2];
+    for (int k = 0; k < 2; ++k) {
+        rows[k] = I0 + 32 * qi + 16 * k + lr;
+        cols[k] = J0 + 32 * qj + 16 * k + lr;
+    }
+    // skip blocks with no valid pair (i < j, j < N)
+    const int rmin = I0 + 32 * qi, cmax = J0 + 32 * qj + 31;
+    if (rmin >= N || rmin >= cmax || J0 + 32 * qj >= N) return;
+
+    const float *zn = s.zring + (size_t)slot_new * N * Mz;
+    const float *zo = s.zring + (size_t)slot_old * N * Mz;
+    floatx4 an[2][2], ao[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            an[a][b] = (floatx4){0.f, 0.f, 0.f, 0.f};
+            ao[a][b] = (floatx4){0.f, 0.f, 0.f, 0.f};
+        }
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int n0 = 0; n0 < Mz; n0 += 16) {
+        float4 ra[2], cb[2], rao[2], cbo[2];
+        for (int k = 0; k < 2; ++k) {
+            ra[k] = rows[k] < N ? *(const float4 *)(zn + (size_t)rows[k] * Mz + n0 + 4 * lg) : zero4;
+            cb[k] = cols[k] < N ? *(const float4 *)(zn + (size_t)cols[k] * Mz + n0 + 4 * lg) : zero4;
+            if (has_old) {
+                rao[k] = rows[k] < N ? *(const float4 *)(zo + (size_t)rows[k] * Mz + n0 + 4 * lg) : zero4;
+                cbo[k] = cols[k] < N ? *(const float4 *)(zo + (size_t)cols[k] * Mz + n0 + 4 * lg) : zero4;
+            }
+        }
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                an[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[a].x, cb[b].x, an[a][b], 0, 0, 0);
+                an[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[a].y, cb[b].y, an[a][b], 0, 0, 0);
+                an[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[a].z, cb[b].z, an[a][b], 0, 0, 0);
+                an[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[a].w, cb[b].w, an[a][b], 0, 0, 0);
+            }
+        if (has_old) {
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    ao[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rao[a].x, cbo[b].x, ao[a][b], 0, 0, 0);
+                    ao[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rao[a].y, cbo[b].y, ao[a][b], 0, 0, 0);
+                    ao[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rao[a].z, cbo[b].z, ao[a][b], 0, 0, 0);
+                    ao[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rao[a].w, cbo[b].w, ao[a][b], 0, 0, 0);
+                }
+        }
+    }
+    const size_t P = (size_t)N * (N - 1) / 2;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int k = 0; k < 4; ++k) {
+                // accumulator element k of lane l: row 4*(l>>4)+k, column l&15
+                const int ri = 32 * qi + 16 * a + 4 * lg + k;
+                const int cj = 32 * qj + 16 * b + lr;
+                const int i = I0 + ri, j = J0 + cj;
+                if (!(i < j && j < N)) continue;
+                const size_t e = (size_t)tile * TILE_PAIRS + (size_t)ri * TILE + cj;
+                double R = s.rsum[e] + (double)an[a][b][k];
+                if (has_old) R = R - (double)ao[a][b][k];
+                s.rsum[e] = R;
+                const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+                s.out[7 * P + idx] = (T)(R / (double)K);
+            }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cor_update(SessDev<T> s)
+{
+    cor_body(s, blockIdx.x);
+}
+
+template <typename T> hipError_t launch_cor_update(const SessDev<T> &s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cor_update<T>, dim3(s.ntiles), dim3(256), 0, st, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// commit: the only writer of the accepted-trial counter
+// ---------------------------------------------------------------------------
+__global__ void k_commit(DevCtl *c)
+{
+    if (threadIdx.x == 0) {
+        if (c->bad)
+            c->rejected = c->rejected + 1;
+        else
+            c->pushed = c->pushed + 1;
+        c->bad = 0;
+    }
+}
+
+hipError_t launch_commit(DevCtl *ctl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, st, ctl);
+    return hipGetLastError();
+}
+
+// replay control: point a private DevCtl at one cached trial
+__global__ void k_set_ctl(DevCtl *c, long long pushed)
+{
+    if (threadIdx.x == 0) {
+        c->pushed = pushed;
+        c->bad = 0;
+        c->rejected = 0;
+    }
+}
+
+hipError_t launch_set_ctl(DevCtl *ctl, long long pushed, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, st, ctl, pushed);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-bin finalisation of one spectral metric from the running sums:
+// out[b][P].  One thread per (tile, bin, pair slot).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_finalize_bins(SessDev<T> s, uint32_t metric, T *out)
+{
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t total = (size_t)s.ntiles * s.B * TILE_PAIRS;
+    if (e >= total) return;
+    const int c = (int)(e % TILE), r = (int)((e / TILE) % TILE);
+    const int b = (int)((e / TILE_PAIRS) % s.B);
+    const int tile = (int)(e / ((size_t)TILE_PAIRS * s.B));
+    const int2 tt = s.tiles[tile];
+    const int N = s.N;
+    const int i = tt.x * TILE + r, j = tt.y * TILE + c;
+    if (!(i < j && j < N)) return;
+    const long long tp = s.ctl->pushed;
+    const int K = tp >= s.W ? s.W : (int)tp;
+    const double Kd = (double)K;
+    const size_t P = (size_t)N * (N - 1) / 2;
+    const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+    const double pi_ = s.psd[(size_t)b * N + i], pj_ = s.psd[(size_t)b * N + j];
+    const double den = sqrt(pi_ * pj_);
+    double v = 0.0;
+    switch (metric) {
+    case M_COH: {
+        const double a = s.plane[P_SRE][e], bb = s.plane[P_SIM][e];
+        v = den > 0.0 ? sqrt(a * a + bb * bb) / den : 0.0;
+        break;
+    }
+    case M_IMCOH: v = den > 0.0 ? s.plane[P_SIM][e] / den : 0.0; break;
+    case M_PLV: {
+        const double a = s.plane[P_URE][e], bb = s.plane[P_UIM][e];
+        v = sqrt(a * a + bb * bb) / Kd;
+        break;
+    }
+    case M_PLI: v = fabs((double)s.gsum[e]) / Kd; break;
+    case M_USPLI: {
+        const double pli = fabs((double)s.gsum[e]) / Kd;
+        v = K >= 2 ? (Kd * pli * pli - 1.0) / (Kd - 1.0) : NAN;
+        break;
+    }
+    case M_WPLI: {
+        const double A = s.plane[P_A][e];
+        v = A > 0.0 ? fabs(s.plane[P_SIM][e]) / A : 0.0;
+        break;
+    }
+    case M_DSWPLI: {
+        const double A = s.plane[P_A][e], Q = s.plane[P_Q][e], S = s.plane[P_SIM][e];
+        const double dd = A * A - Q;
+        v = K >= 2 ? (dd != 0.0 ? (S * S - Q) / dd : 0.0) : NAN;
+        break;
+    }
+    default: break;
+    }
+    out[(size_t)b * P + idx] = (T)v;
+}
+
+template <typename T>
+hipError_t launch_finalize_bins(const SessDev<T> &s, uint32_t metric, T *out, hipStream_t st)
+{
+    const size_t total = (size_t)s.ntiles * s.B * TILE_PAIRS;
+    hipLaunchKernelGGL(k_finalize_bins<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, s,
+                       metric, out);
+    return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched launches of the serving path: one launch drains a list of work
+// items of many sessions (persistent-style grid-stride over the list).  Each
+// item runs the same device body as the single-session kernels, so a
+// session's result does not depend on what else shares the launch.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void kb_spectra(const SessDev<float> *S, const int4 *items, int n)
+{
+    __shared__ float xs[SP_NODES][SP_CH + 1];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 w = items[it];
+        spectra_body(S[w.x], w.y, w.z, xs);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_znorm(const SessDev<float> *S, const int4 *items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 w = items[it];
+        znorm_body(S[w.x], w.y);
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_psd(const SessDev<float> *S, const int4 *items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 w = items[it];
+        psd_body(S[w.x], w.y);
+    }
+}
+
+__global__ __launch_bounds__(PAIR_THREADS) void kb_pair_update(const SessDev<float> *S, const int4 *items, int n)
+{
+    extern __shared__ __align__(16) char lds[];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 w = items[it];
+        const SessDev<float> &s = S[w.x];
+        if (s.ctl->bad) continue;
+        pair_tile_update<float>(s, w.y, s.ctl->pushed, pair_chunk_bins(s.B, s.L, 4), lds);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_cor_update(const SessDev<float> *S, const int4 *items, int n)
+{
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 w = items[it];
+        cor_body(S[w.x], w.y);
+    }
+}
+
+__global__ void kb_commit(const SessDev<float> *S, int n)
+{
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i < n) {
+        DevCtl *c = S[i].ctl;
+        if (c->bad)
+            c->rejected = c->rejected + 1;
+        else
+            c->pushed = c->pushed + 1;
+        c->bad = 0;
+    }
+}
+
+static unsigned persistent_grid(int n, int cap)
+{
+    return (unsigned)(n < cap ? (n > 0 ? n : 1) : cap);
+}
+
+hipError_t launch_batched(int which, const SessDev<float> *S, const int4 *items, int n, size_t lds,
+                          hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    switch (which) {
+    case FCX_B_SPECTRA:
+        hipLaunchKernelGGL(kb_spectra, dim3(persistent_grid(n, 1 << 20)), dim3(256), 0, st, S, items, n);
+        break;
+    case FCX_B_ZNORM:
+        hipLaunchKernelGGL(kb_znorm, dim3(persistent_grid(n, 1 << 20)), dim3(256), 0, st, S, items, n);
+        break;
+    case FCX_B_PSD:
+        hipLaunchKernelGGL(kb_psd, dim3(persistent_grid(n, 1 << 20)), dim3(256), 0, st, S, items, n);
+        break;
+    case FCX_B_PAIR:
+        hipLaunchKernelGGL(kb_pair_update, dim3(persistent_grid(n, 1 << 20)), dim3(PAIR_THREADS), lds, st, S, items, n);
+        break;
+    case FCX_B_COR:
+        hipLaunchKernelGGL(kb_cor_update, dim3(persistent_grid(n, 1 << 20)), dim3(256), 0, st, S, items, n);
+        break;
+    case FCX_B_COMMIT:
+        hipLaunchKernelGGL(kb_commit, dim3((n + 63) / 64), dim3(64), 0, st, S, n);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// HBM copy probe (16-byte vector loads/stores, grid-stride)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_copy_probe(float4 *__restrict__ dst, const float4 *__restrict__ src,
+                                                    size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
+}
+
+hipError_t launch_copy_probe(void *dst, const void *src, int64_t n_bytes, hipStream_t st)
+{
+    const size_t n = (size_t)n_bytes / 16;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_copy_probe, dim3((unsigned)blocks), dim3(256), 0, st, (float4 *)dst,
+                       (const float4 *)src, n);
+    return hipGetLastError();
+}
+
+// explicit instantiations
+#define FCX_INST(T)                                                                          \
+    template hipError_t launch_spectra<T>(const SessDev<T> &, hipStream_t);                   \
+    template hipError_t launch_psd<T>(const SessDev<T> &, hipStream_t);                       \
+    template hipError_t launch_pair_update<T>(const SessDev<T> &, hipStream_t);               \
+    template hipError_t launch_znorm<T>(const SessDev<T> &, hipStream_t);                     \
+    template hipError_t launch_cor_update<T>(const SessDev<T> &, hipStream_t);                \
+    template hipError_t launch_finalize_bins<T>(const SessDev<T> &, uint32_t, T *, hipStream_t);
+FCX_INST(float)
+FCX_INST(double)
+
+}  // namespace fcx

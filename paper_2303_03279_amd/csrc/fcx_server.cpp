@@ -1,0 +1,456 @@
+// Serving form: many concurrent sessions, continuous batching.
+//
+// Admission: a session is opened only if its device footprint fits the
+// server's HBM budget (FCX_E_BUSY otherwise).  Submission copies the trial
+// into pinned host memory and queues it on its session.  A builder thread
+// forms ticks: every session with a queued trial contributes its oldest one;
+// the tick uploads those trials and runs the whole update of all of them as
+// six batched launches (spectra, z-scores, power sums, pair update, COR,
+// commit) whose workgroups drain a shared list of (session, block) items.
+// Trials that arrive while a tick runs go into the next tick, which is queued
+// behind it on the stream (at most two ticks in flight), so the device is
+// never idle while work is waiting.  A completion thread waits for each
+// tick's event and stamps its trials done.
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <thread>
+#include <unordered_map>
+
+#include "fcx_host.h"
+
+namespace fcx {
+
+static double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Submission {
+    uint64_t ticket;
+    Session *s;
+    void *pinned;
+    size_t bytes;
+    double t_submit;
+};
+
+struct TickBuffers {
+    // host (pinned) and device copies of the descriptors and item lists
+    SessDev<float> *h_desc = nullptr, *d_desc = nullptr;
+    int4 *h_items = nullptr, *d_items = nullptr;
+    size_t desc_cap = 0, item_cap = 0;
+    hipEvent_t done = nullptr;
+};
+
+struct Tick {
+    std::vector<Submission> subs;
+    int buf = 0;
+};
+
+struct Server {
+    int64_t budget = 0, used = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done, cv_slot;
+    std::map<uint64_t, Session *> sessions;             // by id, for deterministic order
+    std::unordered_map<Session *, std::deque<Submission>> queues;
+    std::unordered_map<uint64_t, double> latency;       // finished tickets
+    std::unordered_map<uint64_t, bool> pending_tickets;
+    std::deque<Tick> inflight;
+    TickBuffers bufs[2];
+    bool buf_busy[2] = {false, false};
+    uint64_t next_ticket = 1;
+    int64_t outstanding = 0;
+    bool stop = false;
+    bool failed = false;
+    std::multimap<size_t, void *> pinned_pool;
+    std::thread builder, completer;
+};
+
+static std::mutex g_srv_mu;
+static std::unordered_map<uint64_t, Server *> g_srv;
+static uint64_t g_srv_next = 1;
+
+static Server *lookup_server(fcx_server *h)
+{
+    std::lock_guard<std::mutex> lk(g_srv_mu);
+    auto it = g_srv.find((uint64_t)(uintptr_t)h);
+    return it == g_srv.end() ? nullptr : it->second;
+}
+
+static hipError_t ensure_capacity(TickBuffers &b, size_t ndesc, size_t nitems)
+{
+    hipError_t e = hipSuccess;
+    if (ndesc > b.desc_cap) {
+        if (b.h_desc) hipHostFree(b.h_desc);
+        if (b.d_desc) hipFree(b.d_desc);
+        size_t cap = ndesc * 2;
+        if ((e = hipHostMalloc((void **)&b.h_desc, cap * sizeof(SessDev<float>), hipHostMallocDefault)) != hipSuccess)
+            return e;
+        if ((e = hipMalloc((void **)&b.d_desc, cap * sizeof(SessDev<float>))) != hipSuccess) return e;
+        b.desc_cap = cap;
+    }
+    if (nitems > b.item_cap) {
+        if (b.h_items) hipHostFree(b.h_items);
+        if (b.d_items) hipFree(b.d_items);
+        size_t cap = nitems * 2;
+        if ((e = hipHostMalloc((void **)&b.h_items, cap * sizeof(int4), hipHostMallocDefault)) != hipSuccess)
+            return e;
+        if ((e = hipMalloc((void **)&b.d_items, cap * sizeof(int4))) != hipSuccess) return e;
+        b.item_cap = cap;
+    }
+    return e;
+}
+
+// enqueue one tick (called by the builder with the server lock released)
+static hipError_t run_tick(Server *sv, Tick &tk)
+{
+    TickBuffers &b = sv->bufs[tk.buf];
+    const int ns = (int)tk.subs.size();
+    // item counts per kernel
+    size_t n_sp = 0, n_zn = 0, n_psd = 0, n_pair = 0, n_cor = 0;
+    size_t lds = 0;
+    for (auto &sb : tk.subs) {
+        const Geometry &g = sb.s->g;
+        const bool spectral = (sb.s->cfg.metrics & 0x7Fu) != 0;
+        if (spectral) {
+            n_sp += (size_t)((g.N + 15) / 16) * ((g.B * g.L + 15) / 16);
+            n_psd += (size_t)(g.B * g.N + 255) / 256;
+            n_pair += g.ntiles;
+            const size_t l = pair_lds_bytes(pair_chunk_bins(g.B, g.L, 4), g.L, 4);
+            if (l > lds) lds = l;
+        }
+        if (sb.s->cfg.metrics & M_COR) {
+            n_zn += (size_t)(g.N + 3) / 4;
+            n_cor += g.ntiles;
+        }
+    }
+    const size_t n_items = n_sp + n_zn + n_psd + n_pair + n_cor;
+    hipError_t e = ensure_capacity(b, ns, n_items);
+    if (e != hipSuccess) return e;
+    int4 *it_sp = b.h_items, *it_zn = it_sp + n_sp, *it_psd = it_zn + n_zn, *it_pair = it_psd + n_psd,
+         *it_cor = it_pair + n_pair;
+    size_t a = 0, z = 0, p = 0, q = 0, c = 0;
+    for (int k = 0; k < ns; ++k) {
+        Session *s = tk.subs[k].s;
+        const Geometry &g = s->g;
+        e = hipMemcpyAsync(s->xbuf, tk.subs[k].pinned, tk.subs[k].bytes, hipMemcpyHostToDevice, sv->stream);
+        if (e != hipSuccess) return e;
+        b.h_desc[k] = session_dev<float>(s, s->xbuf, g.M);
+        const bool spectral = (s->cfg.metrics & 0x7Fu) != 0;
+        if (spectral) {
+            for (int by = 0; by < (g.B * g.L + 15) / 16; ++by)
+                for (int bx = 0; bx < (g.N + 15) / 16; ++bx) it_sp[a++] = make_int4(k, bx, by, 0);
+            for (int bx = 0; bx < (g.B * g.N + 255) / 256; ++bx) it_psd[p++] = make_int4(k, bx, 0, 0);
+            for (int t = 0; t < g.ntiles; ++t) it_pair[q++] = make_int4(k, t, 0, 0);
+        }
+        if (s->cfg.metrics & M_COR) {
+            for (int bx = 0; bx < (g.N + 3) / 4; ++bx) it_zn[z++] = make_int4(k, bx, 0, 0);
+            for (int t = 0; t < g.ntiles; ++t) it_cor[c++] = make_int4(k, t, 0, 0);
+        }
+    }
+    if ((e = hipMemcpyAsync(b.d_desc, b.h_desc, ns * sizeof(SessDev<float>), hipMemcpyHostToDevice, sv->stream)) !=
+        hipSuccess)
+        return e;
+    if ((e = hipMemcpyAsync(b.d_items, b.h_items, n_items * sizeof(int4), hipMemcpyHostToDevice, sv->stream)) !=
+        hipSuccess)
+        return e;
+    const int4 *d_sp = b.d_items, *d_zn = d_sp + n_sp, *d_psd = d_zn + n_zn, *d_pair = d_psd + n_psd,
+               *d_cor = d_pair + n_pair;
+    if ((e = launch_batched(FCX_B_SPECTRA, b.d_desc, d_sp, (int)n_sp, 0, sv->stream)) != hipSuccess) return e;
+    if ((e = launch_batched(FCX_B_ZNORM, b.d_desc, d_zn, (int)n_zn, 0, sv->stream)) != hipSuccess) return e;
+    if ((e = launch_batched(FCX_B_PSD, b.d_desc, d_psd, (int)n_psd, 0, sv->stream)) != hipSuccess) return e;
+    if ((e = launch_batched(FCX_B_PAIR, b.d_desc, d_pair, (int)n_pair, lds, sv->stream)) != hipSuccess) return e;
+    if ((e = launch_batched(FCX_B_COR, b.d_desc, d_cor, (int)n_cor, 0, sv->stream)) != hipSuccess) return e;
+    if ((e = launch_batched(FCX_B_COMMIT, b.d_desc, nullptr, ns, 0, sv->stream)) != hipSuccess) return e;
+    return hipEventRecord(b.done, sv->stream);
+}
+
+static void builder_main(Server *sv)
+{
+    hipSetDevice(sv->device);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        sv->cv_work.wait(lk, [&] {
+            if (sv->stop) return true;
+            if (sv->buf_busy[0] && sv->buf_busy[1]) return false;
+            for (auto &kv : sv->queues)
+                if (!kv.second.empty()) return true;
+            return false;
+        });
+        if (sv->stop) return;
+        Tick tk;
+        tk.buf = sv->buf_busy[0] ? 1 : 0;
+        for (auto &kv : sv->sessions) {  // deterministic order: by session id
+            auto qit = sv->queues.find(kv.second);
+            if (qit == sv->queues.end() || qit->second.empty()) continue;
+            tk.subs.push_back(qit->second.front());
+            qit->second.pop_front();
+        }
+        sv->buf_busy[tk.buf] = true;
+        lk.unlock();
+        const hipError_t e = run_tick(sv, tk);
+        lk.lock();
+        if (e != hipSuccess) sv->failed = true;
+        sv->inflight.push_back(std::move(tk));
+        sv->cv_done.notify_all();
+    }
+}
+
+static void completer_main(Server *sv)
+{
+    hipSetDevice(sv->device);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        sv->cv_done.wait(lk, [&] { return sv->stop || !sv->inflight.empty(); });
+        if (sv->inflight.empty() && sv->stop) return;
+        Tick tk = std::move(sv->inflight.front());
+        sv->inflight.pop_front();
+        lk.unlock();
+        hipEventSynchronize(sv->bufs[tk.buf].done);
+        const double t = now_s();
+        lk.lock();
+        for (auto &sb : tk.subs) {
+            sv->latency[sb.ticket] = t - sb.t_submit;
+            sv->pending_tickets.erase(sb.ticket);
+            sv->pinned_pool.insert({sb.bytes, sb.pinned});
+            sv->outstanding -= 1;
+        }
+        sv->buf_busy[tk.buf] = false;
+        sv->cv_work.notify_all();
+        sv->cv_slot.notify_all();
+    }
+}
+
+static bool session_idle(Server *sv, Session *s)
+{
+    auto it = sv->queues.find(s);
+    if (it != sv->queues.end() && !it->second.empty()) return false;
+    for (auto &tk : sv->inflight)
+        for (auto &sb : tk.subs)
+            if (sb.s == s) return false;
+    return true;
+}
+
+}  // namespace fcx
+
+using namespace fcx;
+
+extern "C" {
+
+fcx_status fcx_server_create(int64_t hbm_budget_bytes, fcx_server **out)
+{
+    if (!out || hbm_budget_bytes <= 0) return FCX_E_INVAL;
+    *out = nullptr;
+    Server *sv = new (std::nothrow) Server();
+    if (!sv) return FCX_E_NOMEM;
+    sv->budget = hbm_budget_bytes;
+    if (hipGetDevice(&sv->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete sv;
+        return FCX_E_DEVICE;
+    }
+    for (auto &b : sv->bufs)
+        if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) return FCX_E_DEVICE;
+    sv->builder = std::thread(builder_main, sv);
+    sv->completer = std::thread(completer_main, sv);
+    std::lock_guard<std::mutex> lk(g_srv_mu);
+    const uint64_t id = g_srv_next++;
+    g_srv[id] = sv;
+    *out = (fcx_server *)(uintptr_t)id;
+    return FCX_OK;
+}
+
+fcx_status fcx_server_open(fcx_server *h, const fcx_config *cfg, fcx_session **out)
+{
+    Server *sv = lookup_server(h);
+    if (!sv || !out) return FCX_E_INVAL;
+    *out = nullptr;
+    Geometry g;
+    fcx_status st = make_geometry(cfg, &g);
+    if (st != FCX_OK) return st;
+    if (g.f64) return FCX_E_INVAL;  // served sessions compute in float32
+    const int64_t fp = (int64_t)make_plan(*cfg, g).total();
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->used + fp > sv->budget) return FCX_E_BUSY;
+        sv->used += fp;  // reserve before allocating
+    }
+    Session *s = new (std::nothrow) Session();
+    if (!s) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->used -= fp;
+        return FCX_E_NOMEM;
+    }
+    s->cfg = *cfg;
+    s->g = g;
+    s->plan = make_plan(*cfg, g);
+    s->stream = sv->stream;
+    s->own_stream = false;
+    s->device = sv->device;
+    s->server = sv;
+    st = session_alloc(s);
+    if (st != FCX_OK) {
+        session_free(s);
+        delete s;
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->used -= fp;
+        return st;
+    }
+    const uint64_t id = register_session(s);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->sessions[id] = s;
+        sv->queues[s];
+    }
+    *out = (fcx_session *)(uintptr_t)id;
+    return FCX_OK;
+}
+
+fcx_status fcx_server_submit(fcx_server *h, fcx_session *hs, const void *x, int64_t ld, uint64_t *ticket)
+{
+    Server *sv = lookup_server(h);
+    if (!sv || !x || !ticket) return FCX_E_INVAL;
+    fcx_status st;
+    Session *s = lookup_session(hs, &st);
+    if (!s) return st;
+    if (s->server != sv || ld < s->g.M) return FCX_E_INVAL;
+    const size_t row = (size_t)s->g.M * 4;
+    const size_t bytes = row * s->g.N;
+    void *pin = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->failed) return FCX_E_DEVICE;
+        auto it = sv->pinned_pool.find(bytes);
+        if (it != sv->pinned_pool.end()) {
+            pin = it->second;
+            sv->pinned_pool.erase(it);
+        }
+    }
+    if (!pin && hipHostMalloc(&pin, bytes, hipHostMallocDefault) != hipSuccess) return FCX_E_NOMEM;
+    const char *src = (const char *)x;
+    if ((size_t)ld * 4 == row) {
+        memcpy(pin, src, bytes);
+    } else {
+        for (int i = 0; i < s->g.N; ++i) memcpy((char *)pin + i * row, src + (size_t)i * ld * 4, row);
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    const uint64_t t = sv->next_ticket++;
+    sv->queues[s].push_back({t, s, pin, bytes, now_s()});
+    sv->pending_tickets[t] = true;
+    sv->outstanding += 1;
+    *ticket = t;
+    sv->cv_work.notify_all();
+    return FCX_OK;
+}
+
+fcx_status fcx_server_poll(fcx_server *h, uint64_t ticket, int *done, double *latency_s)
+{
+    Server *sv = lookup_server(h);
+    if (!sv || !done) return FCX_E_INVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->failed) return FCX_E_DEVICE;
+    auto it = sv->latency.find(ticket);
+    if (it != sv->latency.end()) {
+        *done = 1;
+        if (latency_s) *latency_s = it->second;
+        return FCX_OK;
+    }
+    if (sv->pending_tickets.count(ticket)) {
+        *done = 0;
+        return FCX_OK;
+    }
+    return FCX_E_INVAL;
+}
+
+fcx_status fcx_server_drain(fcx_server *h)
+{
+    Server *sv = lookup_server(h);
+    if (!sv) return FCX_E_INVAL;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_slot.wait(lk, [&] { return sv->outstanding == 0 || sv->failed; });
+    return sv->failed ? FCX_E_DEVICE : FCX_OK;
+}
+
+fcx_status fcx_server_usage(fcx_server *h, int64_t *used, int64_t *left, int32_t *n_sessions)
+{
+    Server *sv = lookup_server(h);
+    if (!sv) return FCX_E_INVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (used) *used = sv->used;
+    if (left) *left = sv->budget - sv->used;
+    if (n_sessions) *n_sessions = (int32_t)sv->sessions.size();
+    return FCX_OK;
+}
+
+fcx_status fcx_server_close_session(fcx_server *h, fcx_session *hs)
+{
+    Server *sv = lookup_server(h);
+    if (!sv) return FCX_E_INVAL;
+    fcx_status st;
+    Session *s = lookup_session(hs, &st);
+    if (!s) return st;
+    if (s->server != sv) return FCX_E_INVAL;
+    {
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv_slot.wait(lk, [&] { return session_idle(sv, s) || sv->failed; });
+        sv->sessions.erase(s->id);
+        sv->queues.erase(s);
+        sv->used -= (int64_t)s->plan.total();
+    }
+    s = unregister_session(hs, &st);
+    if (!s) return st;
+    session_free(s);
+    delete s;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->cv_work.notify_all();
+    return FCX_OK;
+}
+
+fcx_status fcx_server_destroy(fcx_server *h)
+{
+    Server *sv = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_srv_mu);
+        auto it = g_srv.find((uint64_t)(uintptr_t)h);
+        if (it == g_srv.end()) return FCX_E_INVAL;
+        sv = it->second;
+        g_srv.erase(it);
+    }
+    {
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv_slot.wait(lk, [&] { return sv->outstanding == 0 || sv->failed; });
+        sv->stop = true;
+        sv->cv_work.notify_all();
+        sv->cv_done.notify_all();
+    }
+    sv->builder.join();
+    sv->completer.join();
+    hipStreamSynchronize(sv->stream);
+    std::vector<Session *> left;
+    for (auto &kv : sv->sessions) left.push_back(kv.second);
+    for (Session *s : left) {
+        fcx_status st;
+        unregister_session((fcx_session *)(uintptr_t)s->id, &st);
+        session_free(s);
+        delete s;
+    }
+    for (auto &kv : sv->pinned_pool) hipHostFree(kv.second);
+    for (auto &b : sv->bufs) {
+        if (b.h_desc) hipHostFree(b.h_desc);
+        if (b.d_desc) hipFree(b.d_desc);
+        if (b.h_items) hipHostFree(b.h_items);
+        if (b.d_items) hipFree(b.d_items);
+        if (b.done) hipEventDestroy(b.done);
+    }
+    hipStreamDestroy(sv->stream);
+    delete sv;
+    return FCX_OK;
+}
+
+}  // extern "C"

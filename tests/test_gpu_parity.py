@@ -1,0 +1,290 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every comparison is element by element on the same seeded inputs; the
+tolerance is 1e-5 absolute on the metric scale for the FP32 path (1e-11 for
+the FP64 path), and PLI/USPLI are compared with the tie allowance of the
+sign counts (a trial whose Im CSD lies within the spectra's rounding of zero
+may flip sign).
+"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import TOL, TOL_F64, compare_network, log, run_pushes
+
+pytestmark = pytest.mark.gpu
+
+ALL = ["coh", "imcoh", "plv", "pli", "wpli", "uspli", "dswpli", "cor"]
+
+
+@pytest.fixture(scope="module")
+def fcx():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    import paper_2303_03279_amd as m
+    return m
+
+
+# ------------------------------------------------------------------ tiny (C1)
+
+def test_c1_tiny_f64(fcx):
+    x, cfg = synth.c1_tiny()
+    log("c1 f64: N=32 K=20 M=256 F=256 all 129 bins")
+    s = run_pushes(fcx, cfg, x)
+    ref = oracle.network(x, cfg)
+    compare_network(s, ref, cfg, ["coh", "plv", "pli", "wpli"], tol=TOL_F64, label="c1-f64")
+    for m in ["coh", "plv", "wpli"]:
+        st, out, K = s.read(m, per_bin=True)
+        fcx.check(st)
+        assert np.max(np.abs(out.T - ref["per_bin"][m])) < TOL_F64, m
+    st, pli, K = s.read("pli", per_bin=True)
+    G = np.rint(pli.T * K).astype(int)
+    assert np.all(np.abs(G - np.abs(ref["G"])) <= 2 * ref["ties"])
+    s.close()
+
+
+def test_c1_tiny_f32(fcx):
+    x, cfg = synth.c1_tiny()
+    cfg = dict(cfg, elem="f32", metrics=synth.ALL8)
+    s = run_pushes(fcx, cfg, x)
+    ref = oracle.network(oracle.as_device_input(x, cfg), cfg)
+    compare_network(s, ref, cfg, ALL, label="c1-f32")
+    s.close()
+
+
+def test_dc_and_nyquist_exactly_real_on_gpu(fcx):
+    x, cfg = synth.c1_tiny()
+    cfg = dict(cfg, elem="f32", metrics=synth.ALL8)
+    s = run_pushes(fcx, cfg, x)
+    K = x.shape[0]
+    for m, v in [("pli", 0.0), ("wpli", 0.0), ("dswpli", 0.0), ("imcoh", 0.0),
+                 ("uspli", np.float32(-1.0 / (K - 1)))]:
+        st, out, _ = s.read(m, per_bin=True)
+        assert np.all(out[0] == v) and np.all(out[128] == v), m
+    s.close()
+
+
+def test_rank1_zero_lag_exact_on_gpu(fcx):
+    K, N, M = 9, 70, 128
+    x = synth.rank1_zero_lag(K, N, M, seed=4)
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=K, n_fft=256, f_lo_hz=0, f_hi_hz=500,
+                            metrics=synth.ALL8)
+    s = run_pushes(fcx, cfg, x)
+    for m in ["pli", "wpli", "dswpli"]:
+        st, out, _ = s.read(m, per_bin=True)
+        assert np.all(out == 0.0), m
+    st, out, _ = s.read("imcoh", per_bin=True)
+    assert np.max(np.abs(out)) < 1e-6
+    for m in ["coh", "plv"]:
+        st, out, _ = s.read(m)
+        assert np.max(np.abs(out - 1.0)) < 1e-5, m
+    st, out, _ = s.read("cor")
+    assert np.max(np.abs(np.abs(out) - 1.0)) < 1e-5
+    s.close()
+
+
+@pytest.mark.parametrize("tau_ms", [5.0, 31.0])
+def test_two_sinusoids_on_gpu(fcx, tau_ms):
+    M = F = 200
+    x = synth.two_sinusoids(30, M, F, 1000.0, 20.0, tau_ms / 1000.0, seed=3)
+    cfg = synth.base_config(n_nodes=2, n_samples=M, window_trials=30, n_fft=F, f_lo_hz=20, f_hi_hz=20,
+                            metrics=synth.ALL8)
+    s = run_pushes(fcx, cfg, x)
+    for m in ["coh", "plv", "pli", "wpli", "uspli", "dswpli"]:
+        st, out, _ = s.read(m)
+        assert abs(out[0] - 1.0) < 1e-5, m
+    st, out, _ = s.read("imcoh")
+    assert abs(out[0] - math.sin(2 * math.pi * 20.0 * tau_ms / 1000.0)) < 1e-5
+    s.close()
+
+
+# ------------------------------------------------------- sliding window (C2)
+
+@pytest.fixture(scope="module")
+def c2():
+    x, cfg = synth.c2_sensor(n_trials=300)
+    return x, cfg
+
+
+def test_c2_sensor_sliding(fcx, c2):
+    x, cfg = c2
+    W = cfg["window_trials"]
+    xd = oracle.as_device_input(x, cfg)
+    log("c2: N=306 W=100 M=600 F=1024 23 bins, 300 pushes")
+    s = run_pushes(fcx, cfg, x, 0, 50)
+    compare_network(s, oracle.network(xd[:50], cfg), cfg, ALL, label="c2@50")
+    run_pushes(fcx, cfg, x, 50, 300, session=s)
+    ref = oracle.network(xd[300 - W:300], cfg)
+    compare_network(s, ref, cfg, ALL, label="c2@300")
+    # per-bin values of the sliding window
+    for m in ["coh", "imcoh", "plv", "wpli", "dswpli"]:
+        st, out, K = s.read(m, per_bin=True)
+        assert np.max(np.abs(out.T - ref["per_bin"][m])) < TOL, m
+    s.close()
+
+
+def test_c2_cached_equals_recompute(fcx, c2):
+    """The ring makes the sliding state equal to recomputing the window: the
+    running sums after 160 pushes equal a fresh session fed only the last W
+    trials, and a rebuild from the cached spectra (resync) changes nothing
+    beyond rounding."""
+    x, cfg = c2
+    W = cfg["window_trials"]
+    s = run_pushes(fcx, cfg, x, 0, 160)
+    f = run_pushes(fcx, cfg, x, 160 - W, 160)
+    before = {m: s.read(m)[1].copy() for m in ALL}
+    for m in ALL:
+        assert np.max(np.abs(before[m] - f.read(m)[1])) < 2e-6, m
+    fcx.check(s.resync(), "resync")
+    for m in ALL:
+        st, out, K = s.read(m)
+        assert K == W
+        assert np.max(np.abs(out - before[m])) < 2e-6, m
+    s.close()
+    f.close()
+
+
+# --------------------------------------------------- full source-space size (C3)
+
+def test_c3_full_size_sampled_rows(fcx):
+    """5000 nodes, W=50, 60 pushes (10 evictions): sampled rows of the packed
+    network against the oracle, in the configuration the benchmark times."""
+    T = 60
+    x, cfg = synth.c3_source(n_trials=T)
+    W = cfg["window_trials"]
+    N = cfg["n_nodes"]
+    log("c3: N=5000 W=50 M=500 F=512 12 bins, 60 pushes; sampled rows")
+    s = run_pushes(fcx, cfg, x)
+    rows = [0, 1, 63, 64, 65, 2047, 2500, 4095, 4930, 4990, 4998]
+    pi, pj = oracle.row_pairs(rows, N)
+    ref = oracle.network(oracle.as_device_input(x[T - W:], cfg), cfg, pi, pj)
+    compare_network(s, ref, cfg, ALL, idx=oracle.packed_index(pi, pj, N), label="c3")
+    s.close()
+
+
+# ---------------------------------------------------------------- edge shapes
+
+@pytest.mark.parametrize("N,W,T", [(2, 1, 3), (63, 3, 5), (64, 4, 4), (65, 3, 7), (129, 2, 5), (200, 5, 12)])
+def test_edge_shapes(fcx, N, W, T):
+    rng = np.random.default_rng(N * 100 + W)
+    M = 96
+    x = rng.standard_normal((T, N, M))
+    x[:, N // 2:, 2:] += 0.7 * x[:, : N - N // 2, :-2]
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=W, n_fft=128, f_lo_hz=30, f_hi_hz=200,
+                            metrics=synth.ALL8)
+    s = run_pushes(fcx, cfg, x)
+    K = min(T, W)
+    ref = oracle.network(oracle.as_device_input(x[T - K:], cfg), cfg)
+    compare_network(s, ref, cfg, ALL, label=f"edge N={N} W={W}")
+    s.close()
+
+
+def test_multitaper_dpss(fcx):
+    rng = np.random.default_rng(5)
+    N, M, W, T = 40, 200, 8, 13
+    x = rng.standard_normal((T, N, M))
+    x[:, 1, 4:] += 0.9 * x[:, 0, :-4]
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=W, n_fft=256, f_lo_hz=4, f_hi_hz=120,
+                            taper="dpss", dpss_nw=2.0, dpss_k=3, metrics=synth.ALL8)
+    s = run_pushes(fcx, cfg, x)
+    ref = oracle.network(oracle.as_device_input(x[T - W:], cfg), cfg)
+    compare_network(s, ref, cfg, ALL, label="dpss L=3")
+    s.close()
+
+
+def test_metric_subsets_match_all8(fcx):
+    x, cfg = synth.c2_sensor(n_trials=120)
+    cfg = dict(cfg, n_nodes=306)
+    full = run_pushes(fcx, cfg, x)
+    for mask, names in [(synth.COH, ["coh"]), (synth.WPLI, ["wpli"]), (synth.PLI | synth.COR, ["pli", "cor"]),
+                        (synth.DSWPLI | synth.PLV, ["dswpli", "plv"])]:
+        s = run_pushes(fcx, dict(cfg, metrics=mask), x)
+        for m in names:
+            assert np.array_equal(s.read(m)[1], full.read(m)[1]), m
+        s.close()
+    full.close()
+
+
+# --------------------------------------------------------------- error paths
+
+def test_not_ready_and_k_below_two(fcx):
+    N, M = 10, 64
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=4, n_fft=64, f_lo_hz=50, f_hi_hz=300)
+    s = fcx.Session(cfg)
+    st, out, K = s.read("coh")
+    assert st == fcx.FCX_E_NOTREADY and K == 0
+    x = np.random.default_rng(1).standard_normal((N, M)).astype(np.float32)
+    fcx.check(s.push_host(x))
+    st, out, K = s.read("uspli")
+    assert st == fcx.FCX_E_NOTREADY and K == 1 and np.all(np.isnan(out))
+    st, out, K = s.read("coh")
+    assert st == fcx.FCX_OK
+    s.close()
+
+
+def test_nonfinite_trial_rejected_atomically(fcx):
+    rng = np.random.default_rng(3)
+    N, M, W = 70, 128, 4
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=W, n_fft=128, f_lo_hz=20, f_hi_hz=200,
+                            metrics=synth.ALL8)
+    x = rng.standard_normal((8, N, M))
+    s = run_pushes(fcx, cfg, x, 0, 5)
+    fcx.check(s.sync())
+    before = {m: s.read(m)[1].copy() for m in ALL}
+    bad = x[5].astype(np.float32).copy()
+    bad[17, 33] = np.nan
+    fcx.check(s.push_host(bad))
+    assert s.sync() == fcx.FCX_E_NONFINITE
+    assert s.sync() == fcx.FCX_OK            # reported once
+    for m in ALL:
+        assert np.array_equal(s.read(m)[1], before[m], equal_nan=True), m
+    assert s.counts() == (5, 1)
+    run_pushes(fcx, cfg, x, 5, 8, session=s)
+    ref = oracle.network(oracle.as_device_input(x[8 - W:8], cfg), cfg)
+    compare_network(s, ref, cfg, ALL, label="after rejection")
+    inf = x[0].astype(np.float32).copy()
+    inf[0, 0] = np.inf
+    fcx.check(s.push_host(inf))
+    st, out, K = s.read("coh")
+    assert st == fcx.FCX_E_NONFINITE and K == W
+    s.close()
+
+
+def test_closed_handle(fcx):
+    cfg = synth.base_config(n_nodes=8, n_samples=32, window_trials=2, n_fft=32, f_lo_hz=40, f_hi_hz=300)
+    s = fcx.Session(cfg)
+    h = s.h
+    assert s.close() == fcx.FCX_OK
+    assert fcx.lib.fcx_sync(h) == fcx.FCX_E_CLOSED
+    assert fcx.lib.fcx_close(h) == fcx.FCX_E_CLOSED
+    x = np.zeros((8, 32), np.float32)
+    assert fcx.lib.fcx_push_trial(h, x.ctypes.data, 32, 0) == fcx.FCX_E_CLOSED
+
+
+def test_device_input_equals_host_input(fcx):
+    import torch
+    rng = np.random.default_rng(11)
+    N, M, W, T = 130, 160, 5, 9
+    x = rng.standard_normal((T, N, M)).astype(np.float32)
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=W, n_fft=256, f_lo_hz=10, f_hi_hz=90,
+                            metrics=synth.ALL8)
+    a = run_pushes(fcx, cfg, x)
+    b = fcx.Session(cfg)
+    xd = torch.from_numpy(x).cuda()
+    torch.cuda.synchronize()
+    for k in range(T):
+        fcx.check(b.push_device(xd[k].data_ptr(), M))
+    fcx.check(b.sync())
+    for m in ALL:
+        assert np.array_equal(a.read(m)[1], b.read(m)[1]), m
+    # device output buffer
+    out = torch.empty(b.P, dtype=torch.float32, device="cuda")
+    fcx.check(b.read_device("coh", out.data_ptr(), b.P))
+    assert np.array_equal(out.cpu().numpy(), a.read("coh")[1])
+    a.close()
+    b.close()

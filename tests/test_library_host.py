@@ -1,0 +1,88 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, exports
+every symbol the header declares, and its host logic (configuration checks,
+band plan, footprint, DPSS) is right."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+fcx = pytest.importorskip("paper_2303_03279_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "fcx.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(fcx_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol():
+    names = _header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(fcx.lib, n), n
+        assert n in fcx.EXPORTED, n
+
+
+def test_status_strings():
+    for st in range(8):
+        assert fcx.lib.fcx_status_str(st)
+    assert fcx.lib.fcx_status_str(fcx.FCX_E_BUSY).decode() == "HBM budget exhausted"
+
+
+@pytest.mark.parametrize("F,lo,hi", [(512, 8, 30), (1000, 4, 40), (1024, 8, 30), (256, 0, 500), (600, 8, 12)])
+def test_band_plan_matches_oracle(F, lo, hi):
+    cfg = synth.base_config(n_nodes=10, n_samples=min(F, 500), window_trials=5, n_fft=F, f_lo_hz=lo, f_hi_hz=hi)
+    n, klo, khi = fcx.band_bins(cfg)
+    ref = oracle.band_bins(F, 1000.0, lo, hi)
+    assert n == ref.size and klo == ref[0] and khi == ref[-1]
+
+
+def test_invalid_configs_rejected():
+    good = synth.base_config(n_nodes=10, n_samples=100, window_trials=5, n_fft=128, f_lo_hz=8, f_hi_hz=30)
+    assert fcx.footprint_bytes(good) > 0
+    bad = [dict(n_nodes=1), dict(n_samples=1), dict(window_trials=0), dict(n_fft=50),
+           dict(fs_hz=0.0), dict(f_lo_hz=40, f_hi_hz=30), dict(metrics=0), dict(metrics=256),
+           dict(taper="dpss", dpss_k=0, dpss_nw=2.0), dict(taper="dpss", dpss_k=3, dpss_nw=60.0)]
+    for b in bad:
+        cfg = dict(good)
+        cfg.update(b)
+        assert fcx.footprint_bytes(cfg) == -1, b
+    c = fcx.make_config(good)
+    c.struct_size = 4
+    h = ctypes.c_void_p()
+    assert fcx.lib.fcx_open(ctypes.byref(c), None, ctypes.byref(h)) == fcx.FCX_E_INVAL
+
+
+def test_footprint_scales_with_metrics():
+    base = synth.base_config(n_nodes=5000, n_samples=500, window_trials=50, n_fft=512, f_lo_hz=8, f_hi_hz=30)
+    all8 = fcx.footprint_bytes(dict(base, metrics=synth.ALL8))
+    coh = fcx.footprint_bytes(dict(base, metrics=synth.COH))
+    wpli = fcx.footprint_bytes(dict(base, metrics=synth.WPLI))
+    # 12.5M pairs x 12 bins: all-8 keeps 6 FP64 planes + int16 signs (~7.8 GB);
+    # coh and wpli keep 2 FP64 planes each (~2.5 GB)
+    assert 7.5e9 < all8 < 9.5e9
+    assert 2.4e9 < coh < 3.0e9 and 2.4e9 < wpli < 3.0e9
+
+
+def test_bad_handles():
+    h = ctypes.c_void_p(987654321)
+    assert fcx.lib.fcx_sync(h) == fcx.FCX_E_INVAL
+    assert fcx.lib.fcx_close(h) == fcx.FCX_E_INVAL
+    assert fcx.lib.fcx_server_drain(h) == fcx.FCX_E_INVAL
+
+
+@pytest.mark.parametrize("M,NW,K", [(1000, 2.0, 3), (500, 2.5, 4), (64, 1.5, 2)])
+def test_host_dpss_matches_scipy(M, NW, K):
+    from scipy.signal.windows import dpss as sp_dpss
+    tap, rat = fcx.dpss(M, NW, K)
+    ref, rref = sp_dpss(M, NW, K, return_ratios=True)
+    assert np.allclose(tap, ref, atol=1e-9)
+    assert np.allclose(rat, rref, atol=1e-9)
