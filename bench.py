@@ -77,7 +77,8 @@ def run_session(fcx, torch, cfg, pool_dev, steps, warmup, timing=True, lat_pushe
     kt = {}
     if timing:
         for name, kid in [("spectra", fcx.FCX_K_SPECTRA), ("psd", fcx.FCX_K_PSD),
-                          ("pair_update", fcx.FCX_K_PAIR_UPDATE), ("cor", fcx.FCX_K_COR)]:
+                          ("pair_update", fcx.FCX_K_PAIR_UPDATE), ("znorm", fcx.FCX_K_ZNORM),
+                          ("cor_update", fcx.FCX_K_COR)]:
             n, ms = s.kernel_time(kid)
             if n:
                 kt[name] = dict(launches=n, avg_ms=ms / n)
@@ -119,6 +120,8 @@ def main():
     ap.add_argument("--latency-pushes", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-subsets", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=1024,
+                    help="size of the HBM copy probe (read + write), 0 to skip")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the update shards by pair "
@@ -137,6 +140,26 @@ def main():
     N = cfg["n_nodes"]
     P = N * (N - 1) // 2
     B = fcx.band_bins(cfg)[0]
+
+    probe = None
+    if args.copy_probe_mb > 0:
+        nbytes = args.copy_probe_mb << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        stream = torch.cuda.current_stream()
+        for _ in range(3):
+            fcx.check(fcx.lib.fcx_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream.cuda_stream))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        reps = 10
+        for _ in range(reps):
+            fcx.check(fcx.lib.fcx_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream.cuda_stream))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        probe = dict(bytes_per_launch=2 * nbytes, avg_ms=ms, gbs=2 * nbytes / (ms * 1e-3) / 1e9)
+        del src, dst
+        torch.cuda.empty_cache()
 
     print("[bench] all-8 session", file=sys.stderr, flush=True)
     wall, kt, lat = run_session(fcx, torch, cfg, pool_dev, args.steps, args.warmup,
@@ -188,6 +211,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
                      "kernel": "pair_update", "algorithmic_bytes_per_launch": algo},
+        "hbm_copy_probe": probe,
         "sessions": sessions,
         "cpu_baseline": base,
     }

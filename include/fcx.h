@@ -168,7 +168,7 @@ fcx_status fcx_session_counts(fcx_session *s, int64_t *accepted, int64_t *reject
  * (pending events are resolved, which synchronises the stream).
  */
 enum { FCX_K_SPECTRA = 0, FCX_K_PSD = 1, FCX_K_PAIR_UPDATE = 2, FCX_K_COR = 3,
-       FCX_K_PAIR_BATCH = 4, FCX_K_FINALIZE = 5, FCX_K_COUNT = 6 };
+       FCX_K_PAIR_BATCH = 4, FCX_K_ZNORM = 5, FCX_K_COUNT = 6 };
 fcx_status fcx_set_timing(fcx_session *s, int enable);
 fcx_status fcx_kernel_time(fcx_session *s, int kernel, int64_t *launches, double *total_ms);
 

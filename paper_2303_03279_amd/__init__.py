@@ -36,7 +36,7 @@ FCX_COH, FCX_IMCOH, FCX_PLV, FCX_PLI, FCX_WPLI, FCX_USPLI, FCX_DSWPLI, FCX_COR =
 FCX_TAPER_HANN, FCX_TAPER_DPSS = 0, 1
 FCX_GRAM_FP32, FCX_GRAM_BF16, FCX_GRAM_BF16X3 = 0, 1, 2
 FCX_ELEM_F32, FCX_ELEM_F64 = 0, 1
-(FCX_K_SPECTRA, FCX_K_PSD, FCX_K_PAIR_UPDATE, FCX_K_COR, FCX_K_PAIR_BATCH, FCX_K_FINALIZE,
+(FCX_K_SPECTRA, FCX_K_PSD, FCX_K_PAIR_UPDATE, FCX_K_COR, FCX_K_PAIR_BATCH, FCX_K_ZNORM,
  FCX_K_COUNT) = range(7)
 
 METRIC_BITS = dict(coh=FCX_COH, imcoh=FCX_IMCOH, plv=FCX_PLV, pli=FCX_PLI, wpli=FCX_WPLI,

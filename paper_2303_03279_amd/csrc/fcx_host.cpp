@@ -539,7 +539,7 @@ template <typename T> static fcx_status enqueue_push_t(Session *s, const void *x
         HIP_OK(launch_spectra<T>(d, s->stream));
     }
     if (s->cfg.metrics & M_COR) {  // also checks finiteness (COR-only sessions)
-        TimedLaunch t(s, FCX_K_COR);
+        TimedLaunch t(s, FCX_K_ZNORM);
         HIP_OK(launch_znorm<T>(d, s->stream));
     }
     if (spectral) {
