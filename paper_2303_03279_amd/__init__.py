@@ -238,3 +238,74 @@ class Session:
                 lib.fcx_close(self.h)
         except Exception:
             pass
+
+
+class Server:
+    """Owning wrapper of an fcx_server handle (marshalling only)."""
+
+    def __init__(self, hbm_budget_bytes: int):
+        h = ctypes.c_void_p()
+        check(lib.fcx_server_create(int(hbm_budget_bytes), ctypes.byref(h)), "fcx_server_create")
+        self.h = h
+
+    def open(self, cfg: dict):
+        """Returns (status, ServedSession or None)."""
+        c = make_config(cfg)
+        h = ctypes.c_void_p()
+        st = lib.fcx_server_open(self.h, ctypes.byref(c), ctypes.byref(h))
+        if st != FCX_OK:
+            return st, None
+        return st, ServedSession(self, cfg, h)
+
+    def submit(self, sess, x) -> int:
+        t = ctypes.c_uint64()
+        check(lib.fcx_server_submit(self.h, sess.h, x.ctypes.data, x.strides[0] // x.itemsize,
+                                    ctypes.byref(t)), "fcx_server_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        done, lat = ctypes.c_int(), ctypes.c_double()
+        check(lib.fcx_server_poll(self.h, ticket, ctypes.byref(done), ctypes.byref(lat)), "fcx_server_poll")
+        return bool(done.value), float(lat.value)
+
+    def drain(self):
+        check(lib.fcx_server_drain(self.h), "fcx_server_drain")
+
+    def usage(self):
+        u, l, n = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        check(lib.fcx_server_usage(self.h, ctypes.byref(u), ctypes.byref(l), ctypes.byref(n)), "fcx_server_usage")
+        return int(u.value), int(l.value), int(n.value)
+
+    def close_session(self, sess) -> int:
+        st = lib.fcx_server_close_session(self.h, sess.h)
+        sess.h = None
+        return st
+
+    def destroy(self) -> int:
+        if self.h is None:
+            return FCX_OK
+        st = lib.fcx_server_destroy(self.h)
+        self.h = None
+        return st
+
+
+class ServedSession(Session):
+    """A session owned by a server: trials go through Server.submit, reads are
+    the same as for a plain session."""
+
+    def __init__(self, server, cfg, h):  # noqa: D401 - no fcx_open here
+        self.cfg = dict(cfg)
+        self.h = h
+        self.server = server
+        self.N = int(cfg["n_nodes"])
+        self.P = self.N * (self.N - 1) // 2
+        self.B, self.klo, self.khi = band_bins(cfg)
+        self.f64 = False
+
+    def close(self) -> int:
+        if self.h is None:
+            return FCX_OK
+        return self.server.close_session(self)
+
+    def __del__(self):
+        pass

@@ -543,18 +543,13 @@ template <typename T> static fcx_status enqueue_push_t(Session *s, const void *x
         HIP_OK(launch_znorm<T>(d, s->stream));
     }
     if (spectral) {
-        {
-            TimedLaunch t(s, FCX_K_PSD);
-            HIP_OK(launch_psd<T>(d, s->stream));
-        }
-        {
-            TimedLaunch t(s, FCX_K_PAIR_UPDATE);
-            HIP_OK(launch_pair_update<T>(d, s->stream));
-        }
+        TimedLaunch t(s, FCX_K_PSD);
+        HIP_OK(launch_psd<T>(d, s->stream));
     }
-    if (s->cfg.metrics & M_COR) {
-        TimedLaunch t(s, FCX_K_COR);
-        HIP_OK(launch_cor_update<T>(d, s->stream));
+    {
+        // spectral running sums and COR Gram blocks of every pair tile
+        TimedLaunch t(s, FCX_K_PAIR_UPDATE);
+        HIP_OK(launch_pair_update<T>(d, s->stream));
     }
     HIP_OK(launch_commit(s->ctl, s->stream));
     return FCX_OK;
@@ -612,11 +607,8 @@ template <typename T> static fcx_status replay_window(Session *s, long long push
     const bool spectral = (s->cfg.metrics & 0x7Fu) != 0;
     for (long long t = pushed - K; t < pushed; ++t) {
         HIP_OK(launch_set_ctl(d.ctl, t, s->stream));
-        if (spectral) {
-            HIP_OK(launch_psd<T>(d, s->stream));
-            HIP_OK(launch_pair_update<T>(d, s->stream));
-        }
-        if (s->cfg.metrics & M_COR) HIP_OK(launch_cor_update<T>(d, s->stream));
+        if (spectral) HIP_OK(launch_psd<T>(d, s->stream));
+        HIP_OK(launch_pair_update<T>(d, s->stream));
     }
     HIP_OK(hipStreamSynchronize(s->stream));
     return FCX_OK;

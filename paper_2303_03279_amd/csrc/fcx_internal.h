@@ -82,7 +82,6 @@ template <typename T> hipError_t launch_spectra(const SessDev<T> &s, hipStream_t
 template <typename T> hipError_t launch_psd(const SessDev<T> &s, hipStream_t st);
 template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStream_t st);
 template <typename T> hipError_t launch_znorm(const SessDev<T> &s, hipStream_t st);
-template <typename T> hipError_t launch_cor_update(const SessDev<T> &s, hipStream_t st);
 hipError_t launch_commit(DevCtl *ctl, hipStream_t st);
 hipError_t launch_set_ctl(DevCtl *ctl, long long pushed, hipStream_t st);
 template <typename T>
@@ -96,7 +95,7 @@ __host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes);
 
 // batched launches of the serving path (float sessions); items are
 // (session index, a, b, 0) with a/b the block coordinates of the kernel
-enum { FCX_B_SPECTRA = 0, FCX_B_ZNORM, FCX_B_PSD, FCX_B_PAIR, FCX_B_COR, FCX_B_COMMIT };
+enum { FCX_B_SPECTRA = 0, FCX_B_ZNORM, FCX_B_PSD, FCX_B_PAIR, FCX_B_COMMIT };
 hipError_t launch_batched(int which, const SessDev<float> *S, const int4 *items, int n, size_t lds,
                           hipStream_t st);
 

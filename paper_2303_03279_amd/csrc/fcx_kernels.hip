@@ -6,11 +6,11 @@
 //                  flags non-finite input
 //   k_znorm        z-scored samples of the trial into the COR sample ring
 //   k_psd          running per-node power sums: + new trial, - evicted trial
-//   k_pair_update  per pair tile and bin: running sums of CSD, unit phasors,
-//                  sign(Im), |Im| and Im^2 (+ new, - evicted), then the seven
-//                  spectral metrics and their band mean (the hot kernel)
-//   k_cor_update   per pair tile: per-trial Pearson r of new and evicted trial
-//                  as 16x16x4 FP32 MFMA Gram blocks, running sum, COR
+//   k_pair_update  per pair tile: the per-trial Pearson r of the new and the
+//                  evicted trial as 16x16x4 FP32 MFMA Gram blocks into the COR
+//                  running sum; then per bin the running sums of CSD, unit
+//                  phasors, sign(Im), |Im| and Im^2 (+ new, - evicted), the
+//                  seven spectral metrics and their band mean (the hot kernel)
 //   k_commit       accept the trial (or count the rejection)
 //
 // Nothing is reordered across trials: an evicted trial's contribution is
@@ -235,7 +235,95 @@ __host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes)
     return (size_t)CB * 2 * TILE * per_node_bin;
 }
 
+// COR part of a pair tile: r_ij(trial) = z_i . z_j for the new and the
+// evicted trial as v_mfma_f32_16x16x4f32 blocks.  Wavefront w of the tile's
+// workgroup owns the 16x16 block (w / 4, w % 4).  Lane l feeds row (l & 15)
+// of its block with the 4 consecutive samples 4*(l >> 4) .. +3 of each
+// 16-sample step (one float4 load; the same sample permutation on both
+// operands leaves every dot product unchanged); the next step's operands are
+// loaded before the current step's MFMAs issue.  The new and the evicted trial
+// are contracted separately so the evicted r is bit-identical to the r added.
 template <typename T>
+__device__ __forceinline__ void cor_block(const SessDev<T> &s, const PushView &pv, int tile, int I0, int J0,
+                                          int w)
+{
+    const int N = s.N, Mz = s.Mz;
+    const int br = w >> 2, bc = w & 3;
+    const int R0 = I0 + 16 * br, C0 = J0 + 16 * bc;
+    if (R0 >= N || C0 >= N || R0 >= C0 + 15) return;   // no pair i < j < N in this block
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int row = R0 + lr, col = C0 + lr;
+    const bool rv = row < N, cv = col < N, old = pv.has_old;
+    const float4 *rn = (const float4 *)(s.zring + ((size_t)pv.slot_new * N + (rv ? row : 0)) * Mz) + lg;
+    const float4 *cn = (const float4 *)(s.zring + ((size_t)pv.slot_new * N + (cv ? col : 0)) * Mz) + lg;
+    const float4 *ro = (const float4 *)(s.zring + ((size_t)pv.slot_old * N + (rv ? row : 0)) * Mz) + lg;
+    const float4 *co = (const float4 *)(s.zring + ((size_t)pv.slot_old * N + (cv ? col : 0)) * Mz) + lg;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    floatx4 an = {0.f, 0.f, 0.f, 0.f}, ao = {0.f, 0.f, 0.f, 0.f};
+    const int steps = Mz / 16;
+    float4 a = rv ? rn[0] : z4, b = cv ? cn[0] : z4;
+    float4 a2 = (old && rv) ? ro[0] : z4, b2 = (old && cv) ? co[0] : z4;
+    for (int st = 0; st < steps; ++st) {
+        float4 na = z4, nb = z4, na2 = z4, nb2 = z4;
+        if (st + 1 < steps) {
+            const int o = 4 * (st + 1);
+            if (rv) na = rn[o];
+            if (cv) nb = cn[o];
+            if (old) {
+                if (rv) na2 = ro[o];
+                if (cv) nb2 = co[o];
+            }
+        }
+        an = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, an, 0, 0, 0);
+        an = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, an, 0, 0, 0);
+        an = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, an, 0, 0, 0);
+        an = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, an, 0, 0, 0);
+        if (old) {
+            ao = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.x, b2.x, ao, 0, 0, 0);
+            ao = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.y, b2.y, ao, 0, 0, 0);
+            ao = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.z, b2.z, ao, 0, 0, 0);
+            ao = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.w, b2.w, ao, 0, 0, 0);
+        }
+        a = na;
+        b = nb;
+        a2 = na2;
+        b2 = nb2;
+    }
+    const size_t P = (size_t)N * (N - 1) / 2;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        // accumulator element k of lane l: row 4*(l>>4)+k, column l&15
+        const int ri = 16 * br + 4 * lg + k, cj = 16 * bc + lr;
+        const int i = I0 + ri, j = J0 + cj;
+        if (!(i < j && j < N)) continue;
+        const size_t e = (size_t)tile * TILE_PAIRS + (size_t)ri * TILE + cj;
+        double R = s.rsum[e] + (double)an[k];
+        if (old) R = R - (double)ao[k];
+        s.rsum[e] = R;
+        const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+        s.out[7 * P + idx] = (T)(R / (double)pv.K);
+    }
+}
+
+// running sums of one (pair, bin) as held in the planes
+struct PairState {
+    double sre, sim, ure, uim, a, q;
+    int g;
+};
+
+// num / den for a metric in [-1, 1]: FP64 operands of any scale are brought
+// to den in [0.5, 1) by an exact power-of-two scaling, then divided in FP32
+// (the FP64 instantiation divides in FP64)
+template <typename T> __device__ __forceinline__ T ratio_t(double num, double den);
+template <> __device__ __forceinline__ float ratio_t<float>(double num, double den)
+{
+    int e;
+    const double dm = frexp(den, &e);
+    return __fdividef((float)ldexp(num, -e), (float)dm);
+}
+template <> __device__ __forceinline__ double ratio_t<double>(double num, double den) { return num / den; }
+
+template <typename T, bool ONE_CHUNK>
 __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, long long tp, int CB,
                                                  char *lds)
 {
@@ -273,15 +361,29 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
     T2 *Uo = Un + (L == 1 ? (size_t)CB * nodes2 : 0);
     double *SR = (double *)(Uo + (L == 1 ? (size_t)CB * nodes2 : 0));
 
-    T acc[4][7];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int m = 0; m < 7; ++m) acc[q][m] = 0;
-
     const double Kd = (double)K;
-    for (int b0 = 0; b0 < B; b0 += CB) {
+    const T invK = (T)1 / (T)K;
+    const size_t P = (size_t)N * (N - 1) / 2;
+
+    if (mm & M_COR) cor_block(s, pv, tile, I0, J0, w);
+    if (!(mm & 0x7Fu)) return;   // COR-only session: no spectral sums
+
+    auto load_state = [&](size_t e) {
+        PairState st;
+        st.sre = needSre ? pSre[e] : 0.0;
+        st.sim = needSim ? pSim[e] : 0.0;
+        st.ure = needU ? pUre[e] : 0.0;
+        st.uim = needU ? pUim[e] : 0.0;
+        st.a = needA ? pA[e] : 0.0;
+        st.q = needQ ? pQ[e] : 0.0;
+        st.g = needG ? (int)pG[e] : 0;
+        return st;
+    };
+
+    int ci = 0;
+    for (int b0 = 0; b0 < B; b0 += CB, ++ci) {
         const int nb = min(CB, B - b0);
+        const bool last_chunk = b0 + CB >= B;
         for (int e = tid; e < nb * L * nodes2; e += PAIR_THREADS) {
             const int nl = e % nodes2, bl = e / nodes2;
             const int l = bl % L, bb = bl / L;
@@ -320,13 +422,23 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
         }
         __syncthreads();
 
-#pragma unroll
+#pragma unroll 1
         for (int q = 0; q < 4; ++q) {
             const int r = w + 16 * q;
             const int i = I0 + r, j = J0 + c;
             if (!(i < j && j < N)) continue;
+            T acc[7];
+#pragma unroll
+            for (int m = 0; m < 7; ++m) acc[m] = 0;
+            const size_t e0 = (((size_t)tile * B + b0) * TILE + r) * TILE + c;
+            PairState cur = load_state(e0);
             for (int bb = 0; bb < nb; ++bb) {
-                const size_t e = (((size_t)tile * B + b0 + bb) * TILE + r) * TILE + c;
+                const size_t e = e0 + (size_t)bb * TILE_PAIRS;
+                // software pipelining: the next bin's sums are in flight
+                // while this bin is computed
+                PairState nxt = cur;
+                if (bb + 1 < nb) nxt = load_state(e + TILE_PAIRS);
+
                 double cnr = 0.0, cni = 0.0, cor_ = 0.0, coi = 0.0;
                 for (int l = 0; l < L; ++l) {
                     const size_t ob = (size_t)(bb * L + l) * nodes2;
@@ -354,17 +466,16 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
                         }
                     }
                 }
-                double Sre = 0.0, Sim = 0.0, Ure = 0.0, Uim = 0.0, A = 0.0, Q = 0.0;
-                int g = 0;
+                PairState st = cur;
                 if (needSre) {
-                    Sre = pSre[e] + cnr;
-                    if (has_old) Sre = Sre - cor_;
-                    pSre[e] = Sre;
+                    st.sre = st.sre + cnr;
+                    if (has_old) st.sre = st.sre - cor_;
+                    pSre[e] = st.sre;
                 }
                 if (needSim) {
-                    Sim = pSim[e] + cni;
-                    if (has_old) Sim = Sim - coi;
-                    pSim[e] = Sim;
+                    st.sim = st.sim + cni;
+                    if (has_old) st.sim = st.sim - coi;
+                    pSim[e] = st.sim;
                 }
                 if (needU) {
                     double unr, uni, uor = 0.0, uoi = 0.0;
@@ -387,61 +498,72 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
                             uoi = mo > 0.0 ? coi / mo : 0.0;
                         }
                     }
-                    Ure = pUre[e] + unr;
-                    Uim = pUim[e] + uni;
+                    st.ure = st.ure + unr;
+                    st.uim = st.uim + uni;
                     if (has_old) {
-                        Ure = Ure - uor;
-                        Uim = Uim - uoi;
+                        st.ure = st.ure - uor;
+                        st.uim = st.uim - uoi;
                     }
-                    pUre[e] = Ure;
-                    pUim[e] = Uim;
+                    pUre[e] = st.ure;
+                    pUim[e] = st.uim;
                 }
                 if (needG) {
-                    g = (int)pG[e] + sgn_of(cni);
-                    if (has_old) g -= sgn_of(coi);
-                    pG[e] = (short)g;
+                    st.g = st.g + sgn_of(cni);
+                    if (has_old) st.g -= sgn_of(coi);
+                    pG[e] = (short)st.g;
                 }
                 if (needA) {
-                    A = pA[e] + fabs(cni);
-                    if (has_old) A = A - fabs(coi);
-                    pA[e] = A;
+                    st.a = st.a + fabs(cni);
+                    if (has_old) st.a = st.a - fabs(coi);
+                    pA[e] = st.a;
                 }
                 if (needQ) {
-                    Q = pQ[e] + cni * cni;
-                    if (has_old) Q = Q - coi * coi;
-                    pQ[e] = Q;
+                    st.q = st.q + cni * cni;
+                    if (has_old) st.q = st.q - coi * coi;
+                    pQ[e] = st.q;
                 }
                 // metrics of this bin, into the band mean
                 const double srij = SR[bb * nodes2 + r] * SR[bb * nodes2 + TILE + c];
-                if (mm & M_COH) acc[q][0] += sqrt_ratio<T>((Sre * Sre + Sim * Sim) * srij * srij);
-                if (mm & M_IMCOH) acc[q][1] += (T)(Sim * srij);
-                if (mm & M_PLV) acc[q][2] += sqrt_ratio<T>(Ure * Ure + Uim * Uim) / (T)K;
+                if (mm & M_COH) acc[0] += sqrt_ratio<T>((st.sre * st.sre + st.sim * st.sim) * srij * srij);
+                if (mm & M_IMCOH) acc[1] += (T)(st.sim * srij);
+                if (mm & M_PLV) acc[2] += sqrt_ratio<T>(st.ure * st.ure + st.uim * st.uim) * invK;
                 if (mm & (M_PLI | M_USPLI)) {
-                    const double pli = fabs((double)g) / Kd;
-                    if (mm & M_PLI) acc[q][3] += (T)pli;
-                    if (mm & M_USPLI) acc[q][5] += K >= 2 ? (T)((Kd * pli * pli - 1.0) / (Kd - 1.0)) : (T)NAN;
+                    const double pli = fabs((double)st.g) / Kd;
+                    if (mm & M_PLI) acc[3] += (T)pli;
+                    if (mm & M_USPLI) acc[5] += K >= 2 ? (T)((Kd * pli * pli - 1.0) / (Kd - 1.0)) : (T)NAN;
                 }
-                if (mm & M_WPLI) acc[q][4] += A > 0.0 ? (T)(fabs(Sim) / A) : (T)0;
+                if (mm & M_WPLI) acc[4] += st.a > 0.0 ? ratio_t<T>(fabs(st.sim), st.a) : (T)0;
                 if (mm & M_DSWPLI) {
-                    const double dd = A * A - Q;
-                    acc[q][6] += K >= 2 ? (dd != 0.0 ? (T)((Sim * Sim - Q) / dd) : (T)0) : (T)NAN;
+                    const double dd = st.a * st.a - st.q;
+                    acc[6] += K >= 2 ? (dd != 0.0 ? ratio_t<T>(st.sim * st.sim - st.q, dd) : (T)0) : (T)NAN;
+                }
+                cur = nxt;
+            }
+            const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+#pragma unroll
+            for (int m = 0; m < 7; ++m) {
+                if (!(mm & (1u << m))) continue;
+                T *o = s.out + (size_t)m * P + idx;
+                if (ONE_CHUNK) {
+                    *o = acc[m] / (T)B;
+                } else {
+                    T v = ci == 0 ? acc[m] : *o + acc[m];
+                    if (last_chunk) v = v / (T)B;
+                    *o = v;
                 }
             }
         }
         __syncthreads();
     }
+}
 
-    const size_t P = (size_t)N * (N - 1) / 2;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int r = w + 16 * q;
-        const int i = I0 + r, j = J0 + c;
-        if (!(i < j && j < N)) continue;
-        const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
-#pragma unroll
-        for (int m = 0; m < 7; ++m)
-            if (mm & (1u << m)) s.out[(size_t)m * P + idx] = acc[q][m] / (T)B;
-    }
+template <typename T>
+__device__ __forceinline__ void pair_tile_dispatch(const SessDev<T> &s, int tile, long long tp, int CB, char *lds)
+{
+    if (CB >= s.B)
+        pair_tile_update<T, true>(s, tile, tp, CB, lds);
+    else
+        pair_tile_update<T, false>(s, tile, tp, CB, lds);
 }
 
 template <typename T>
@@ -449,113 +571,15 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_update(SessDev<T> s, int 
 {
     extern __shared__ __align__(16) char lds[];
     if (s.ctl->bad) return;
-    pair_tile_update<T>(s, blockIdx.x, s.ctl->pushed, CB, lds);
+    pair_tile_dispatch<T>(s, blockIdx.x, s.ctl->pushed, CB, lds);
 }
 
 template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStream_t st)
 {
     const int CB = pair_chunk_bins(s.B, s.L, (int)sizeof(T));
-    const size_t lds = pair_lds_bytes(CB, s.L, (int)sizeof(T));
+    const bool spectral = (s.metrics & 0x7Fu) != 0;
+    const size_t lds = spectral ? pair_lds_bytes(CB, s.L, (int)sizeof(T)) : 0;
     hipLaunchKernelGGL(k_pair_update<T>, dim3(s.ntiles), dim3(PAIR_THREADS), lds, st, s, CB);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// COR update: r_ij(trial) = z_i . z_j as FP32 MFMA Gram blocks.
-// Workgroup = one 64x64 pair tile, 4 wavefronts, each a 32x32 quadrant made
-// of 2x2 blocks of v_mfma_f32_16x16x4f32.  Lane l feeds row (l & 15) of its
-// block and the 4 consecutive samples 4*(l >> 4) .. +3 of each 16-sample
-// step, loaded as one float4; the same sample permutation on both operands
-// leaves the dot products unchanged.  The new and the evicted trial are
-// contracted separately so the evicted r is bit-identical to the one added.
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void cor_body(const SessDev<T> &s, int tile)
-{
-    if (s.ctl->bad) return;
-    const int N = s.N, Mz = s.Mz;
-    const PushView pv = push_view(s, s.ctl->pushed);
-    const bool has_old = pv.has_old;
-    const int K = pv.K;
-    const int slot_new = pv.slot_new, slot_old = pv.slot_old;
-    const int2 tt = s.tiles[tile];
-    const int I0 = tt.x * TILE, J0 = tt.y * TILE;
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int qi = wv >> 1, qj = wv & 1;
-    const int lr = lane & 15, lg = lane >> 4;
-
-    int rows[2], cols[2];
-    for (int k = 0; k < 2; ++k) {
-        rows[k] = I0 + 32 * qi + 16 * k + lr;
-        cols[k] = J0 + 32 * qj + 16 * k + lr;
-    }
-    // skip blocks with no valid pair (i < j, j < N)
-    const int rmin = I0 + 32 * qi, cmax = J0 + 32 * qj + 31;
-    if (rmin >= N || rmin >= cmax || J0 + 32 * qj >= N) return;
-
-    const float *zn = s.zring + (size_t)slot_new * N * Mz;
-    const float *zo = s.zring + (size_t)slot_old * N * Mz;
-    floatx4 an[2][2], ao[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-            an[a][b] = (floatx4){0.f, 0.f, 0.f, 0.f};
-            ao[a][b] = (floatx4){0.f, 0.f, 0.f, 0.f};
-        }
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int n0 = 0; n0 < Mz; n0 += 16) {
-        float4 ra[2], cb[2], rao[2], cbo[2];
-        for (int k = 0; k < 2; ++k) {
-            ra[k] = rows[k] < N ? *(const float4 *)(zn + (size_t)rows[k] * Mz + n0 + 4 * lg) : zero4;
-            cb[k] = cols[k] < N ? *(const float4 *)(zn + (size_t)cols[k] * Mz + n0 + 4 * lg) : zero4;
-            if (has_old) {
-                rao[k] = rows[k] < N ? *(const float4 *)(zo + (size_t)rows[k] * Mz + n0 + 4 * lg) : zero4;
-                cbo[k] = cols[k] < N ? *(const float4 *)(zo + (size_t)cols[k] * Mz + n0 + 4 * lg) : zero4;
-            }
-        }
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                an[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[a].x, cb[b].x, an[a][b], 0, 0, 0);
-                an[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[a].y, cb[b].y, an[a][b], 0, 0, 0);
-                an[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[a].z, cb[b].z, an[a][b], 0, 0, 0);
-                an[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[a].w, cb[b].w, an[a][b], 0, 0, 0);
-            }
-        if (has_old) {
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b) {
-                    ao[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rao[a].x, cbo[b].x, ao[a][b], 0, 0, 0);
-                    ao[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rao[a].y, cbo[b].y, ao[a][b], 0, 0, 0);
-                    ao[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rao[a].z, cbo[b].z, ao[a][b], 0, 0, 0);
-                    ao[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(rao[a].w, cbo[b].w, ao[a][b], 0, 0, 0);
-                }
-        }
-    }
-    const size_t P = (size_t)N * (N - 1) / 2;
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int k = 0; k < 4; ++k) {
-                // accumulator element k of lane l: row 4*(l>>4)+k, column l&15
-                const int ri = 32 * qi + 16 * a + 4 * lg + k;
-                const int cj = 32 * qj + 16 * b + lr;
-                const int i = I0 + ri, j = J0 + cj;
-                if (!(i < j && j < N)) continue;
-                const size_t e = (size_t)tile * TILE_PAIRS + (size_t)ri * TILE + cj;
-                double R = s.rsum[e] + (double)an[a][b][k];
-                if (has_old) R = R - (double)ao[a][b][k];
-                s.rsum[e] = R;
-                const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
-                s.out[7 * P + idx] = (T)(R / (double)K);
-            }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_cor_update(SessDev<T> s)
-{
-    cor_body(s, blockIdx.x);
-}
-
-template <typename T> hipError_t launch_cor_update(const SessDev<T> &s, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_cor_update<T>, dim3(s.ntiles), dim3(256), 0, st, s);
     return hipGetLastError();
 }
 
@@ -703,16 +727,8 @@ __global__ __launch_bounds__(PAIR_THREADS) void kb_pair_update(const SessDev<flo
         const int4 w = items[it];
         const SessDev<float> &s = S[w.x];
         if (s.ctl->bad) continue;
-        pair_tile_update<float>(s, w.y, s.ctl->pushed, pair_chunk_bins(s.B, s.L, 4), lds);
+        pair_tile_dispatch<float>(s, w.y, s.ctl->pushed, pair_chunk_bins(s.B, s.L, 4), lds);
         __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(256) void kb_cor_update(const SessDev<float> *S, const int4 *items, int n)
-{
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
-        const int4 w = items[it];
-        cor_body(S[w.x], w.y);
     }
 }
 
@@ -751,9 +767,6 @@ hipError_t launch_batched(int which, const SessDev<float> *S, const int4 *items,
     case FCX_B_PAIR:
         hipLaunchKernelGGL(kb_pair_update, dim3(persistent_grid(n, 1 << 20)), dim3(PAIR_THREADS), lds, st, S, items, n);
         break;
-    case FCX_B_COR:
-        hipLaunchKernelGGL(kb_cor_update, dim3(persistent_grid(n, 1 << 20)), dim3(256), 0, st, S, items, n);
-        break;
     case FCX_B_COMMIT:
         hipLaunchKernelGGL(kb_commit, dim3((n + 63) / 64), dim3(64), 0, st, S, n);
         break;
@@ -788,7 +801,6 @@ hipError_t launch_copy_probe(void *dst, const void *src, int64_t n_bytes, hipStr
     template hipError_t launch_psd<T>(const SessDev<T> &, hipStream_t);                       \
     template hipError_t launch_pair_update<T>(const SessDev<T> &, hipStream_t);               \
     template hipError_t launch_znorm<T>(const SessDev<T> &, hipStream_t);                     \
-    template hipError_t launch_cor_update<T>(const SessDev<T> &, hipStream_t);                \
     template hipError_t launch_finalize_bins<T>(const SessDev<T> &, uint32_t, T *, hipStream_t);
 FCX_INST(float)
 FCX_INST(double)

@@ -5,8 +5,8 @@
 // into pinned host memory and queues it on its session.  A builder thread
 // forms ticks: every session with a queued trial contributes its oldest one;
 // the tick uploads those trials and runs the whole update of all of them as
-// six batched launches (spectra, z-scores, power sums, pair update, COR,
-// commit) whose workgroups drain a shared list of (session, block) items.
+// five batched launches (spectra, z-scores, power sums, pair update
+// with its COR blocks, commit) whose workgroups drain a shared list of (session, block) items.
 // Trials that arrive while a tick runs go into the next tick, which is queued
 // behind it on the stream (at most two ticks in flight), so the device is
 // never idle while work is waiting.  A completion thread waits for each
@@ -113,7 +113,7 @@ static hipError_t run_tick(Server *sv, Tick &tk)
     TickBuffers &b = sv->bufs[tk.buf];
     const int ns = (int)tk.subs.size();
     // item counts per kernel
-    size_t n_sp = 0, n_zn = 0, n_psd = 0, n_pair = 0, n_cor = 0;
+    size_t n_sp = 0, n_zn = 0, n_psd = 0, n_pair = 0;
     size_t lds = 0;
     for (auto &sb : tk.subs) {
         const Geometry &g = sb.s->g;
@@ -121,21 +121,17 @@ static hipError_t run_tick(Server *sv, Tick &tk)
         if (spectral) {
             n_sp += (size_t)((g.N + 15) / 16) * ((g.B * g.L + 15) / 16);
             n_psd += (size_t)(g.B * g.N + 255) / 256;
-            n_pair += g.ntiles;
             const size_t l = pair_lds_bytes(pair_chunk_bins(g.B, g.L, 4), g.L, 4);
             if (l > lds) lds = l;
         }
-        if (sb.s->cfg.metrics & M_COR) {
-            n_zn += (size_t)(g.N + 3) / 4;
-            n_cor += g.ntiles;
-        }
+        if (sb.s->cfg.metrics & M_COR) n_zn += (size_t)(g.N + 3) / 4;
+        n_pair += g.ntiles;  // spectral sums and COR blocks of every tile
     }
-    const size_t n_items = n_sp + n_zn + n_psd + n_pair + n_cor;
+    const size_t n_items = n_sp + n_zn + n_psd + n_pair;
     hipError_t e = ensure_capacity(b, ns, n_items);
     if (e != hipSuccess) return e;
-    int4 *it_sp = b.h_items, *it_zn = it_sp + n_sp, *it_psd = it_zn + n_zn, *it_pair = it_psd + n_psd,
-         *it_cor = it_pair + n_pair;
-    size_t a = 0, z = 0, p = 0, q = 0, c = 0;
+    int4 *it_sp = b.h_items, *it_zn = it_sp + n_sp, *it_psd = it_zn + n_zn, *it_pair = it_psd + n_psd;
+    size_t a = 0, z = 0, p = 0, q = 0;
     for (int k = 0; k < ns; ++k) {
         Session *s = tk.subs[k].s;
         const Geometry &g = s->g;
@@ -147,12 +143,10 @@ static hipError_t run_tick(Server *sv, Tick &tk)
             for (int by = 0; by < (g.B * g.L + 15) / 16; ++by)
                 for (int bx = 0; bx < (g.N + 15) / 16; ++bx) it_sp[a++] = make_int4(k, bx, by, 0);
             for (int bx = 0; bx < (g.B * g.N + 255) / 256; ++bx) it_psd[p++] = make_int4(k, bx, 0, 0);
-            for (int t = 0; t < g.ntiles; ++t) it_pair[q++] = make_int4(k, t, 0, 0);
         }
-        if (s->cfg.metrics & M_COR) {
+        if (s->cfg.metrics & M_COR)
             for (int bx = 0; bx < (g.N + 3) / 4; ++bx) it_zn[z++] = make_int4(k, bx, 0, 0);
-            for (int t = 0; t < g.ntiles; ++t) it_cor[c++] = make_int4(k, t, 0, 0);
-        }
+        for (int t = 0; t < g.ntiles; ++t) it_pair[q++] = make_int4(k, t, 0, 0);
     }
     if ((e = hipMemcpyAsync(b.d_desc, b.h_desc, ns * sizeof(SessDev<float>), hipMemcpyHostToDevice, sv->stream)) !=
         hipSuccess)
@@ -160,13 +154,11 @@ static hipError_t run_tick(Server *sv, Tick &tk)
     if ((e = hipMemcpyAsync(b.d_items, b.h_items, n_items * sizeof(int4), hipMemcpyHostToDevice, sv->stream)) !=
         hipSuccess)
         return e;
-    const int4 *d_sp = b.d_items, *d_zn = d_sp + n_sp, *d_psd = d_zn + n_zn, *d_pair = d_psd + n_psd,
-               *d_cor = d_pair + n_pair;
+    const int4 *d_sp = b.d_items, *d_zn = d_sp + n_sp, *d_psd = d_zn + n_zn, *d_pair = d_psd + n_psd;
     if ((e = launch_batched(FCX_B_SPECTRA, b.d_desc, d_sp, (int)n_sp, 0, sv->stream)) != hipSuccess) return e;
     if ((e = launch_batched(FCX_B_ZNORM, b.d_desc, d_zn, (int)n_zn, 0, sv->stream)) != hipSuccess) return e;
     if ((e = launch_batched(FCX_B_PSD, b.d_desc, d_psd, (int)n_psd, 0, sv->stream)) != hipSuccess) return e;
     if ((e = launch_batched(FCX_B_PAIR, b.d_desc, d_pair, (int)n_pair, lds, sv->stream)) != hipSuccess) return e;
-    if ((e = launch_batched(FCX_B_COR, b.d_desc, d_cor, (int)n_cor, 0, sv->stream)) != hipSuccess) return e;
     if ((e = launch_batched(FCX_B_COMMIT, b.d_desc, nullptr, ns, 0, sv->stream)) != hipSuccess) return e;
     return hipEventRecord(b.done, sv->stream);
 }

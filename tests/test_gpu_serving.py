@@ -1,0 +1,130 @@
+"""Serving form: continuous batching of many sessions in one device stream.
+
+Each session's networks must be identical (bit for bit) whether it runs
+alone through the plain push path or mixed with other sessions in the
+server's batched launches; admission must respect the HBM budget."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import compare_network, log, run_pushes
+
+pytestmark = pytest.mark.gpu
+
+ALL = ["coh", "imcoh", "plv", "pli", "wpli", "uspli", "dswpli", "cor"]
+
+
+@pytest.fixture(scope="module")
+def fcx():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    import paper_2303_03279_amd as m
+    return m
+
+
+def _mix_configs():
+    base = dict(n_samples=500, n_fft=512, fs_hz=1000.0, f_lo_hz=8.0, f_hi_hz=30.0)
+    return [
+        synth.base_config(n_nodes=60, window_trials=10, metrics=synth.ALL8, **base),
+        synth.base_config(n_nodes=128, window_trials=7, metrics=synth.COH | synth.PLI, **base),
+        synth.base_config(n_nodes=306, window_trials=12, metrics=synth.WPLI | synth.DSWPLI, **base),
+        synth.base_config(n_nodes=200, window_trials=5, metrics=synth.COR, **base),
+        synth.base_config(n_nodes=97, window_trials=3, metrics=synth.PLV | synth.IMCOH | synth.USPLI, **base),
+    ]
+
+
+def test_alone_equals_mix(fcx):
+    cfgs = _mix_configs()
+    T = [14, 11, 16, 9, 8]
+    xs = [synth.c4_trials(c, 100 + k, T[k]).astype(np.float32) for k, c in enumerate(cfgs)]
+    alone = []
+    for c, x in zip(cfgs, xs):
+        s = run_pushes(fcx, c, x)
+        names = [m for m in ALL if c["metrics"] & synth.METRIC_BITS[m]]
+        alone.append({m: s.read(m)[1].copy() for m in names})
+        s.close()
+    srv = fcx.Server(1 << 36)
+    sess = []
+    for c in cfgs:
+        st, ss = srv.open(c)
+        fcx.check(st)
+        sess.append(ss)
+    # interleave submissions across sessions (per-session order preserved)
+    rng = np.random.default_rng(0)
+    cursor = [0] * len(cfgs)
+    tickets = []
+    while any(cursor[k] < T[k] for k in range(len(cfgs))):
+        k = int(rng.integers(len(cfgs)))
+        if cursor[k] < T[k]:
+            tickets.append(srv.submit(sess[k], np.ascontiguousarray(xs[k][cursor[k]])))
+            cursor[k] += 1
+    srv.drain()
+    lat = []
+    for t in tickets:
+        done, l = srv.poll(t)
+        assert done and l > 0
+        lat.append(l)
+    log(f"served {len(tickets)} trials, latency p50 {1e3 * np.median(lat):.2f} ms")
+    for k, c in enumerate(cfgs):
+        for m, ref in alone[k].items():
+            st, out, K = sess[k].read(m)
+            assert K == min(T[k], c["window_trials"])
+            assert np.array_equal(out, ref, equal_nan=True), (k, m)
+    # and one of them against the oracle
+    c, x = cfgs[0], xs[0]
+    W = c["window_trials"]
+    ref = oracle.network(x[T[0] - W:].astype(np.float64), c)
+    compare_network(sess[0], ref, c, ALL, label="served N=60")
+    for ss in sess:
+        fcx.check(ss.close())
+    fcx.check(srv.destroy())
+
+
+def test_admission_by_hbm_budget(fcx):
+    c = synth.base_config(n_nodes=1000, n_samples=500, window_trials=40, n_fft=512, f_lo_hz=8, f_hi_hz=30,
+                          metrics=synth.ALL8)
+    fp = fcx.footprint_bytes(c)
+    srv = fcx.Server(int(1.5 * fp))
+    st, a = srv.open(c)
+    fcx.check(st)
+    used, left, n = srv.usage()
+    assert used == fp and n == 1
+    st, b = srv.open(c)
+    assert st == fcx.FCX_E_BUSY and b is None
+    small = dict(c, n_nodes=60)
+    st, s2 = srv.open(small)
+    fcx.check(st)                               # a smaller session still fits
+    assert srv.usage()[0] == fp + fcx.footprint_bytes(small)
+    x = synth.c4_trials(c, 5, 3).astype(np.float32)
+    for k in range(3):
+        srv.submit(a, np.ascontiguousarray(x[k]))
+    fcx.check(a.close())                        # drains, then frees its memory
+    st, b = srv.open(c)
+    fcx.check(st)
+    assert srv.usage()[0] == fp + fcx.footprint_bytes(small)
+    fcx.check(b.close())
+    fcx.check(s2.close())
+    assert srv.usage()[0] == 0
+    fcx.check(srv.destroy())
+
+
+def test_served_nonfinite_rejected(fcx):
+    c = synth.base_config(n_nodes=64, n_samples=500, window_trials=4, n_fft=512, f_lo_hz=8, f_hi_hz=30,
+                          metrics=synth.ALL8)
+    x = synth.c4_trials(c, 9, 6).astype(np.float32)
+    srv = fcx.Server(1 << 34)
+    st, s = srv.open(c)
+    fcx.check(st)
+    for k in range(5):
+        srv.submit(s, np.ascontiguousarray(x[k]))
+    bad = x[5].copy()
+    bad[3, 7] = np.nan
+    srv.submit(s, bad)
+    srv.drain()
+    assert s.sync() == fcx.FCX_E_NONFINITE
+    ref = oracle.network(x[1:5].astype(np.float64), c)
+    compare_network(s, ref, c, ALL, label="served after rejection")
+    fcx.check(s.close())
+    fcx.check(srv.destroy())
