@@ -31,24 +31,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def pair_update_bytes(P: int, B: int, metrics: int) -> int:
-    """Algorithmic HBM bytes of one pair-update launch: every running sum the
-    enabled metrics need is read and written once per pair and bin (FP64
-    planes, int16 sign sums), and each enabled spectral metric's band mean is
-    written once per pair (FP32)."""
-    COH, IMCOH, PLV, PLI, WPLI, USPLI, DSWPLI = 1, 2, 4, 8, 16, 32, 64
-    planes = 0
-    planes += 1 if metrics & COH else 0                                   # S_re
-    planes += 1 if metrics & (COH | IMCOH | WPLI | DSWPLI) else 0         # S_im
-    planes += 2 if metrics & PLV else 0                                   # U_re, U_im
-    planes += 1 if metrics & (WPLI | DSWPLI) else 0                       # A
-    planes += 1 if metrics & DSWPLI else 0                                # Q
-    g = 2 if metrics & (PLI | USPLI) else 0
-    per_pair_bin = 2 * (8 * planes + g)
-    n_out = bin(metrics & 127).count("1")
-    return P * B * per_pair_bin + P * n_out * 4
-
-
 def make_pool(n_trials: int, seed: int = 3):
     import synth
     x, cfg = synth.c3_source(seed=seed, n_trials=n_trials)
@@ -166,7 +148,7 @@ def main():
                                 lat_pushes=args.latency_pushes)
     ups = P * B * args.steps / wall
     pu = kt.get("pair_update", {})
-    algo = pair_update_bytes(P, B, synth.ALL8)
+    algo = fcx.pair_update_bytes(cfg)
     achieved = algo / (pu["avg_ms"] * 1e-3) / 1e9 if pu else None
     lat_ms = np.array(lat) * 1e3 if lat else np.array([np.nan])
 
@@ -177,7 +159,7 @@ def main():
             c2 = dict(cfg, metrics=mask)
             w2, k2, l2 = run_session(fcx, torch, c2, pool_dev, args.steps, args.warmup, lat_pushes=100)
             p2 = k2.get("pair_update", {})
-            a2 = pair_update_bytes(P, B, mask) / (p2["avg_ms"] * 1e-3) / 1e9 if p2 else None
+            a2 = fcx.pair_update_bytes(c2) / (p2["avg_ms"] * 1e-3) / 1e9 if p2 else None
             sessions[name] = dict(value=P * B * args.steps / w2, ms_per_step=w2 * 1e3 / args.steps,
                                   p50_ms=float(np.percentile(np.array(l2) * 1e3, 50)),
                                   p99_ms=float(np.percentile(np.array(l2) * 1e3, 99)),

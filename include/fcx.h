@@ -95,6 +95,15 @@ void fcx_config_init(fcx_config *cfg);
  * Returns -1 for an invalid configuration. */
 int64_t fcx_footprint_bytes(const fcx_config *cfg);
 
+/* Algorithmic HBM bytes of the pair update of one push: every running sum the
+ * enabled metrics keep is read and written once per pair and bin (FP64 CSD,
+ * |Im| and Im^2 sums; unit-phasor sums as int32 fixed point for FP32 sessions
+ * with W <= 256, else FP64; sign sums as int8 for W <= 127, else int16), the
+ * COR sum (FP64) once per pair, and each enabled metric's band mean written
+ * once per pair.  Node data (spectra, power sums) are not counted.  Returns -1
+ * for an invalid configuration. */
+int64_t fcx_pair_update_bytes(const fcx_config *cfg);
+
 /* Number of band bins, or -1 for an invalid configuration. */
 int32_t fcx_band_bins(const fcx_config *cfg, int32_t *k_lo, int32_t *k_hi);
 

@@ -72,6 +72,7 @@ PP = ctypes.POINTER(ctypes.c_void_p)
 _SIGS = {
     "fcx_config_init": (None, [PCFG]),
     "fcx_footprint_bytes": (I64, [PCFG]),
+    "fcx_pair_update_bytes": (I64, [PCFG]),
     "fcx_band_bins": (I32, [PCFG, PI32, PI32]),
     "fcx_open": (ctypes.c_int, [PCFG, P, PP]),
     "fcx_push_trial": (ctypes.c_int, [P, P, I64, ctypes.c_int]),
@@ -143,6 +144,11 @@ def make_config(cfg: dict) -> fcx_config:
 def footprint_bytes(cfg: dict) -> int:
     c = make_config(cfg)
     return int(lib.fcx_footprint_bytes(ctypes.byref(c)))
+
+
+def pair_update_bytes(cfg: dict) -> int:
+    c = make_config(cfg)
+    return int(lib.fcx_pair_update_bytes(ctypes.byref(c)))
 
 
 def band_bins(cfg: dict):

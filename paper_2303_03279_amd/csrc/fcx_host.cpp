@@ -75,7 +75,20 @@ fcx_status make_geometry(const fcx_config *c, Geometry *g)
 
 size_t BufferPlan::total() const
 {
-    return ring + psd + plane * (size_t)nplanes + gsum + out + ctl + wtw + lamw + tiles + zring + rsum + xbuf;
+    size_t t = ring + psd + gsum + out + ctl + wtw + lamw + tiles + zring + rsum + xbuf;
+    for (int i = 0; i < NPLANES; ++i)
+        if (planes_used[i]) t += (i == P_URE || i == P_UIM) ? uplane : plane;
+    return t;
+}
+
+// Unit-phasor sums of FP32 sessions are kept as int32 multiples of 2^-k with
+// W * 2^k <= 2^30, exact under add/remove; FP64 sessions and windows longer
+// than 256 trials keep FP64 sums.
+static int ufix_bits_for(int W)
+{
+    int c = 0;
+    while ((1 << c) < W) ++c;   // ceil(log2 W)
+    return 30 - c;
 }
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -98,8 +111,12 @@ BufferPlan make_plan(const fcx_config &c, const Geometry &g)
         p.planes_used[P_Q] = m & M_DSWPLI;
         for (int i = 0; i < NPLANES; ++i) p.nplanes += p.planes_used[i] ? 1 : 0;
         p.plane = align256(elems * 8);
+        p.u_fixed = !g.f64 && g.W <= 256;
+        p.ufix_bits = p.u_fixed ? ufix_bits_for(g.W) : 0;
+        p.uplane = align256(elems * (p.u_fixed ? 4 : 8));
         p.g_used = m & (M_PLI | M_USPLI);
-        p.gsum = p.g_used ? align256(elems * 2) : 0;
+        p.g_narrow = g.W <= 127;
+        p.gsum = p.g_used ? align256(elems * (p.g_narrow ? 1 : 2)) : 0;
         p.wtw = align256((size_t)g.L * g.B * g.M * 2 * g.esz);
         p.lamw = align256((size_t)g.L * 8);
     }
@@ -405,7 +422,7 @@ fcx_status session_alloc(Session *s)
     ALLOC(ring, p.ring);
     ALLOC(psd, p.psd);
     for (int i = 0; i < NPLANES; ++i)
-        if (p.planes_used[i]) ALLOC(plane[i], p.plane);
+        if (p.planes_used[i]) ALLOC(plane[i], (i == P_URE || i == P_UIM) ? p.uplane : p.plane);
     if (p.g_used) ALLOC(gsum, p.gsum);
     ALLOC(out, p.out);
     ALLOC(ctl, p.ctl);
@@ -462,6 +479,9 @@ template <typename T> SessDev<T> session_dev(const Session *s, const void *x, lo
     d.psd = s->psd;
     for (int i = 0; i < NPLANES; ++i) d.plane[i] = s->plane[i];
     d.gsum = s->gsum;
+    d.u_fixed = s->plan.u_fixed ? 1 : 0;
+    d.ufix_bits = s->plan.ufix_bits;
+    d.g_narrow = s->plan.g_narrow ? 1 : 0;
     d.out = (T *)s->out;
     d.ctl = s->ctl;
     d.wtw = (const T *)s->wtw;
@@ -598,7 +618,8 @@ template <typename T> static fcx_status replay_window(Session *s, long long push
     const long long K = pushed < g.W ? pushed : g.W;
     if (p.psd) HIP_OK(hipMemsetAsync(s->psd, 0, p.psd, s->stream));
     for (int i = 0; i < NPLANES; ++i)
-        if (s->plane[i]) HIP_OK(hipMemsetAsync(s->plane[i], 0, p.plane, s->stream));
+        if (s->plane[i])
+            HIP_OK(hipMemsetAsync(s->plane[i], 0, (i == P_URE || i == P_UIM) ? p.uplane : p.plane, s->stream));
     if (s->gsum) HIP_OK(hipMemsetAsync(s->gsum, 0, p.gsum, s->stream));
     if (s->rsum) HIP_OK(hipMemsetAsync(s->rsum, 0, p.rsum, s->stream));
     SessDev<T> d = session_dev<T>(s, nullptr, 0);
@@ -683,6 +704,22 @@ int64_t fcx_footprint_bytes(const fcx_config *cfg)
     return (int64_t)make_plan(*cfg, g).total();
 }
 
+int64_t fcx_pair_update_bytes(const fcx_config *cfg)
+{
+    Geometry g;
+    if (make_geometry(cfg, &g) != FCX_OK) return -1;
+    const BufferPlan p = make_plan(*cfg, g);
+    int64_t per_pair_bin = 0;
+    for (int i = 0; i < NPLANES; ++i)
+        if (p.planes_used[i]) per_pair_bin += (i == P_URE || i == P_UIM) ? (p.u_fixed ? 4 : 8) : 8;
+    if (p.g_used) per_pair_bin += p.g_narrow ? 1 : 2;
+    int64_t per_pair = 0;
+    for (int m = 0; m < 7; ++m)
+        if (cfg->metrics & (1u << m)) per_pair += (int64_t)g.esz;
+    if (cfg->metrics & M_COR) per_pair += 2 * 8 + (int64_t)g.esz;
+    return (int64_t)g.P * (2 * per_pair_bin * g.B + per_pair);
+}
+
 fcx_status fcx_dpss(int32_t M, double NW, int32_t K, double *tapers, double *ratios)
 {
     if (!tapers || !ratios) return FCX_E_INVAL;
@@ -758,7 +795,8 @@ fcx_status fcx_push_batch(fcx_session *h, const void *x, int64_t n_trials, int64
         const BufferPlan &p = s->plan;
         if (p.psd) HIP_OK(hipMemsetAsync(s->psd, 0, p.psd, s->stream));
         for (int i = 0; i < NPLANES; ++i)
-            if (s->plane[i]) HIP_OK(hipMemsetAsync(s->plane[i], 0, p.plane, s->stream));
+            if (s->plane[i])
+                HIP_OK(hipMemsetAsync(s->plane[i], 0, (i == P_URE || i == P_UIM) ? p.uplane : p.plane, s->stream));
         if (s->gsum) HIP_OK(hipMemsetAsync(s->gsum, 0, p.gsum, s->stream));
         if (s->rsum) HIP_OK(hipMemsetAsync(s->rsum, 0, p.rsum, s->stream));
         HIP_OK(hipMemsetAsync(s->ctl, 0, sizeof(DevCtl), s->stream));

@@ -19,6 +19,9 @@ struct BufferPlan {
     int nplanes = 0;
     bool planes_used[NPLANES] = {false, false, false, false, false, false};
     bool g_used = false;
+    bool u_fixed = false, g_narrow = false;
+    int ufix_bits = 0;
+    size_t uplane = 0;   // bytes of each unit-phasor plane
     size_t total() const;
 };
 
@@ -46,8 +49,8 @@ struct Session {
     // device buffers
     void *ring = nullptr;
     double *psd = nullptr;
-    double *plane[NPLANES] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    short *gsum = nullptr;
+    void *plane[NPLANES] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    void *gsum = nullptr;
     void *out = nullptr;
     DevCtl *ctl = nullptr;
     void *wtw = nullptr;

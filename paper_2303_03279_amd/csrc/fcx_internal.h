@@ -8,11 +8,15 @@ namespace fcx {
 
 constexpr int TILE = 64;             // pair tile edge: a tile holds 64 x 64 pairs
 constexpr int TILE_PAIRS = TILE * TILE;
-constexpr int PAIR_THREADS = 1024;   // workgroup of the pair kernels (16 waves)
-constexpr int PAIR_LDS_BYTES = 64 * 1024;
+constexpr int PAIR_THREADS = 256;    // workgroup of the pair kernels (4 waves)
+constexpr int SLICE_ROWS = 16;       // a workgroup owns a 16-row slice of a tile
+constexpr int SLICES = TILE / SLICE_ROWS;
+constexpr int PAIR_NODES = SLICE_ROWS + TILE;   // row + column nodes staged per slice
+constexpr int PAIR_LDS_BYTES = 40 * 1024;
 constexpr int ZPAD = 16;             // COR sample rows padded to a multiple of 16
 
-// running-sum planes of the pair state, one FP64 plane each (G is int16)
+// running-sum planes of the pair state: FP64, except the unit-phasor sums of
+// FP32 sessions (int32 fixed point) and the sign sums (int8 or int16)
 enum Plane { P_SRE = 0, P_SIM = 1, P_URE = 2, P_UIM = 3, P_A = 4, P_Q = 5, NPLANES = 6 };
 
 // metric bits (same values as the public header)
@@ -38,8 +42,11 @@ struct SessDev {
     const int2 *tiles;      // [ntiles] (tile row, tile col), row <= col
     T *ring;                // [(W+1)][B][L][N] complex (re, im interleaved)
     double *psd;            // [B][N] running sum of per-trial power
-    double *plane[NPLANES]; // [ntiles][B][TILE_PAIRS] or null when not needed
-    short *gsum;            // [ntiles][B][TILE_PAIRS] sign sums or null
+    void *plane[NPLANES];   // [ntiles][B][TILE_PAIRS] or null when not needed
+    void *gsum;             // [ntiles][B][TILE_PAIRS] sign sums (int8 or int16) or null
+    int u_fixed;            // unit-phasor planes hold int32 multiples of 2^-ufix_bits
+    int ufix_bits;
+    int g_narrow;           // sign sums are int8
     T *out;                 // [8][P] band-mean networks
     DevCtl *ctl;
     const T *wtw;           // [L][B][M] complex taper * exp(-2 pi i k n / F)

@@ -213,18 +213,26 @@ template <typename T> hipError_t launch_psd(const SessDev<T> &s, hipStream_t st)
 // ---------------------------------------------------------------------------
 // pair update (the hot kernel)
 //
-// Workgroup = one 64x64 pair tile, 1024 threads: lane = column j, wavefront
-// w handles rows w, w+16, w+32, w+48.  Bins are processed in chunks whose
-// node data (new and evicted spectra, unit phasors, 1/sqrt(P)) for the 64
-// row and 64 column nodes are staged in LDS; the running sums stream from
-// HBM once per push, coalesced ([tile][bin][row][col] planes), are updated in
-// FP64 and written back; the per-bin metrics are accumulated into the band
-// mean in registers and written once per pair.
+// The pair state of a session is stored per 64x64 tile of the upper triangle,
+// as planes [tile][bin][row][col].  A workgroup of 256 threads (4 wavefronts)
+// owns one 16-row slice of a tile: lane = column j, wavefront w handles rows
+// w, w+4, w+8, w+12 of the slice.  For each chunk of bins, the node data of
+// the 16 row and 64 column nodes (new and evicted spectra, unit phasors,
+// 1/sqrt(P)) are staged in LDS; the running sums stream from HBM once per
+// push (the next bin's sums are loaded while the current bin is computed),
+// are updated, written back, and the per-bin metrics are accumulated into the
+// band mean, written once per pair.  Several slices share a CU, so one slice's
+// MFMA (COR) phase overlaps the others' streaming.
+//
+// Storage of the running sums: CSD (re, im), |Im| and Im^2 sums in FP64; the
+// unit-phasor sums of FP32 sessions in 32-bit fixed point with 2^-k resolution
+// (u_fixed), so that adding and later removing a trial's phasor cancels
+// exactly; sign sums in int8 when W <= 127, else int16.
 // ---------------------------------------------------------------------------
 __host__ __device__ int pair_chunk_bins(int B, int L, int elem_bytes)
 {
     const int per_node_bin = 2 * L * 2 * elem_bytes + (L == 1 ? 2 * 2 * elem_bytes : 0) + 8;
-    int cb = PAIR_LDS_BYTES / (2 * TILE * per_node_bin);
+    int cb = PAIR_LDS_BYTES / (PAIR_NODES * per_node_bin);
     if (cb < 1) cb = 1;
     return cb < B ? cb : B;
 }
@@ -232,24 +240,23 @@ __host__ __device__ int pair_chunk_bins(int B, int L, int elem_bytes)
 __host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes)
 {
     const int per_node_bin = 2 * L * 2 * elem_bytes + (L == 1 ? 2 * 2 * elem_bytes : 0) + 8;
-    return (size_t)CB * 2 * TILE * per_node_bin;
+    return (size_t)CB * PAIR_NODES * per_node_bin;
 }
 
-// COR part of a pair tile: r_ij(trial) = z_i . z_j for the new and the
-// evicted trial as v_mfma_f32_16x16x4f32 blocks.  Wavefront w of the tile's
-// workgroup owns the 16x16 block (w / 4, w % 4).  Lane l feeds row (l & 15)
-// of its block with the 4 consecutive samples 4*(l >> 4) .. +3 of each
-// 16-sample step (one float4 load; the same sample permutation on both
+// COR part of a slice: r_ij(trial) = z_i . z_j for the new and the evicted
+// trial as v_mfma_f32_16x16x4f32 blocks.  Wavefront w owns the 16x16 block of
+// the slice's rows and columns 16w..16w+15 of the tile.  Lane l feeds row
+// (l & 15) of its block with the 4 consecutive samples 4*(l >> 4) .. +3 of
+// each 16-sample step (one float4 load; the same sample permutation on both
 // operands leaves every dot product unchanged); the next step's operands are
 // loaded before the current step's MFMAs issue.  The new and the evicted trial
 // are contracted separately so the evicted r is bit-identical to the r added.
 template <typename T>
-__device__ __forceinline__ void cor_block(const SessDev<T> &s, const PushView &pv, int tile, int I0, int J0,
-                                          int w)
+__device__ __forceinline__ void cor_block(const SessDev<T> &s, const PushView &pv, int tile, int sub, int J0,
+                                          int R0, int w)
 {
     const int N = s.N, Mz = s.Mz;
-    const int br = w >> 2, bc = w & 3;
-    const int R0 = I0 + 16 * br, C0 = J0 + 16 * bc;
+    const int C0 = J0 + 16 * w;
     if (R0 >= N || C0 >= N || R0 >= C0 + 15) return;   // no pair i < j < N in this block
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
     const int row = R0 + lr, col = C0 + lr;
@@ -293,8 +300,8 @@ __device__ __forceinline__ void cor_block(const SessDev<T> &s, const PushView &p
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         // accumulator element k of lane l: row 4*(l>>4)+k, column l&15
-        const int ri = 16 * br + 4 * lg + k, cj = 16 * bc + lr;
-        const int i = I0 + ri, j = J0 + cj;
+        const int ri = 16 * sub + 4 * lg + k, cj = 16 * w + lr;
+        const int i = R0 + 4 * lg + k, j = C0 + lr;
         if (!(i < j && j < N)) continue;
         const size_t e = (size_t)tile * TILE_PAIRS + (size_t)ri * TILE + cj;
         double R = s.rsum[e] + (double)an[k];
@@ -308,7 +315,7 @@ __device__ __forceinline__ void cor_block(const SessDev<T> &s, const PushView &p
 // running sums of one (pair, bin) as held in the planes
 struct PairState {
     double sre, sim, ure, uim, a, q;
-    int g;
+    int uqr, uqi, g;
 };
 
 // num / den for a metric in [-1, 1]: FP64 operands of any scale are brought
@@ -324,16 +331,18 @@ template <> __device__ __forceinline__ float ratio_t<float>(double num, double d
 template <> __device__ __forceinline__ double ratio_t<double>(double num, double den) { return num / den; }
 
 template <typename T, bool ONE_CHUNK>
-__device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, long long tp, int CB,
-                                                 char *lds)
+__device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item, long long tp, int CB, char *lds)
 {
     typedef typename V2<T>::t T2;
+    const int tile = item / SLICES, sub = item % SLICES;
     const int tid = threadIdx.x;
     const int c = tid & (TILE - 1);
     const int w = tid >> 6;
     const int2 tt = s.tiles[tile];
     const int I0 = tt.x * TILE, J0 = tt.y * TILE;
+    const int R0 = I0 + SLICE_ROWS * sub;
     const int N = s.N, B = s.B, L = s.L;
+    if (R0 >= N || R0 >= min(J0 + TILE - 1, N - 1)) return;   // no pair i < j < N in this slice
     const PushView pv = push_view(s, tp);
     const bool has_old = pv.has_old;
     const int K = pv.K;
@@ -345,38 +354,45 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
     const bool needG = mm & (M_PLI | M_USPLI);
     const bool needA = mm & (M_WPLI | M_DSWPLI);
     const bool needQ = mm & M_DSWPLI;
+    const bool ufix = s.u_fixed != 0, g8 = s.g_narrow != 0;
+    const float uscale = ldexpf(1.0f, s.ufix_bits);
+    const double uinv = ldexp(1.0, -s.ufix_bits);
     const T2 *ring = (const T2 *)s.ring;
-    double *__restrict__ pSre = s.plane[P_SRE];
-    double *__restrict__ pSim = s.plane[P_SIM];
-    double *__restrict__ pUre = s.plane[P_URE];
-    double *__restrict__ pUim = s.plane[P_UIM];
-    double *__restrict__ pA = s.plane[P_A];
-    double *__restrict__ pQ = s.plane[P_Q];
-    short *__restrict__ pG = s.gsum;
-
-    const int nodes2 = 2 * TILE;
-    T2 *Xn = (T2 *)lds;
-    T2 *Xo = Xn + (size_t)CB * L * nodes2;
-    T2 *Un = Xo + (size_t)CB * L * nodes2;
-    T2 *Uo = Un + (L == 1 ? (size_t)CB * nodes2 : 0);
-    double *SR = (double *)(Uo + (L == 1 ? (size_t)CB * nodes2 : 0));
+    double *__restrict__ pSre = (double *)s.plane[P_SRE];
+    double *__restrict__ pSim = (double *)s.plane[P_SIM];
+    double *__restrict__ pUre = (double *)s.plane[P_URE];
+    double *__restrict__ pUim = (double *)s.plane[P_UIM];
+    int *__restrict__ qUre = (int *)s.plane[P_URE];
+    int *__restrict__ qUim = (int *)s.plane[P_UIM];
+    double *__restrict__ pA = (double *)s.plane[P_A];
+    double *__restrict__ pQ = (double *)s.plane[P_Q];
+    short *__restrict__ pG16 = (short *)s.gsum;
+    signed char *__restrict__ pG8 = (signed char *)s.gsum;
 
     const double Kd = (double)K;
     const T invK = (T)1 / (T)K;
     const size_t P = (size_t)N * (N - 1) / 2;
 
-    if (mm & M_COR) cor_block(s, pv, tile, I0, J0, w);
+    if (mm & M_COR) cor_block(s, pv, tile, sub, J0, R0, w);
     if (!(mm & 0x7Fu)) return;   // COR-only session: no spectral sums
+
+    T2 *Xn = (T2 *)lds;
+    T2 *Xo = Xn + (size_t)CB * L * PAIR_NODES;
+    T2 *Un = Xo + (size_t)CB * L * PAIR_NODES;
+    T2 *Uo = Un + (L == 1 ? (size_t)CB * PAIR_NODES : 0);
+    double *SR = (double *)(Uo + (L == 1 ? (size_t)CB * PAIR_NODES : 0));
 
     auto load_state = [&](size_t e) {
         PairState st;
         st.sre = needSre ? pSre[e] : 0.0;
         st.sim = needSim ? pSim[e] : 0.0;
-        st.ure = needU ? pUre[e] : 0.0;
-        st.uim = needU ? pUim[e] : 0.0;
+        st.ure = (needU && !ufix) ? pUre[e] : 0.0;
+        st.uim = (needU && !ufix) ? pUim[e] : 0.0;
+        st.uqr = (needU && ufix) ? qUre[e] : 0;
+        st.uqi = (needU && ufix) ? qUim[e] : 0;
         st.a = needA ? pA[e] : 0.0;
         st.q = needQ ? pQ[e] : 0.0;
-        st.g = needG ? (int)pG[e] : 0;
+        st.g = needG ? (g8 ? (int)pG8[e] : (int)pG16[e]) : 0;
         return st;
     };
 
@@ -384,18 +400,19 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
     for (int b0 = 0; b0 < B; b0 += CB, ++ci) {
         const int nb = min(CB, B - b0);
         const bool last_chunk = b0 + CB >= B;
-        for (int e = tid; e < nb * L * nodes2; e += PAIR_THREADS) {
-            const int nl = e % nodes2, bl = e / nodes2;
+        // node index nl: 0..15 the slice's rows, 16..79 the tile's columns
+        for (int e = tid; e < nb * L * PAIR_NODES; e += PAIR_THREADS) {
+            const int nl = e % PAIR_NODES, bl = e / PAIR_NODES;
             const int l = bl % L, bb = bl / L;
-            const int node = nl < TILE ? I0 + nl : J0 + nl - TILE;
+            const int node = nl < SLICE_ROWS ? R0 + nl : J0 + nl - SLICE_ROWS;
             T2 xn, xo;
             xn.x = xn.y = xo.x = xo.y = 0;
             if (node < N) {
                 xn = ring[(((size_t)slot_new * B + b0 + bb) * L + l) * N + node];
                 if (has_old) xo = ring[(((size_t)slot_old * B + b0 + bb) * L + l) * N + node];
             }
-            Xn[(size_t)bl * nodes2 + nl] = xn;
-            Xo[(size_t)bl * nodes2 + nl] = xo;
+            Xn[(size_t)bl * PAIR_NODES + nl] = xn;
+            Xo[(size_t)bl * PAIR_NODES + nl] = xo;
             if (L == 1) {
                 // unit phasor X / |X| (0 for X = 0), formed in FP64 so that
                 // tiny amplitudes cannot underflow
@@ -406,13 +423,13 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
                 un.y = mn > 0.0 ? (T)(xn.y / mn) : (T)0;
                 uo.x = mo > 0.0 ? (T)(xo.x / mo) : (T)0;
                 uo.y = mo > 0.0 ? (T)(xo.y / mo) : (T)0;
-                Un[(size_t)bb * nodes2 + nl] = un;
-                Uo[(size_t)bb * nodes2 + nl] = uo;
+                Un[(size_t)bb * PAIR_NODES + nl] = un;
+                Uo[(size_t)bb * PAIR_NODES + nl] = uo;
             }
         }
-        for (int e = tid; e < nb * nodes2; e += PAIR_THREADS) {
-            const int nl = e % nodes2, bb = e / nodes2;
-            const int node = nl < TILE ? I0 + nl : J0 + nl - TILE;
+        for (int e = tid; e < nb * PAIR_NODES; e += PAIR_THREADS) {
+            const int nl = e % PAIR_NODES, bb = e / PAIR_NODES;
+            const int node = nl < SLICE_ROWS ? R0 + nl : J0 + nl - SLICE_ROWS;
             double sr = 0.0;
             if (node < N) {
                 const double p = s.psd[(size_t)(b0 + bb) * N + node];
@@ -423,14 +440,15 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
         __syncthreads();
 
 #pragma unroll 1
-        for (int q = 0; q < 4; ++q) {
-            const int r = w + 16 * q;
-            const int i = I0 + r, j = J0 + c;
+        for (int q = 0; q < SLICE_ROWS / 4; ++q) {
+            const int r = 4 * q + w;                 // row within the slice
+            const int rt = SLICE_ROWS * sub + r;     // row within the tile
+            const int i = R0 + r, j = J0 + c;
             if (!(i < j && j < N)) continue;
             T acc[7];
 #pragma unroll
             for (int m = 0; m < 7; ++m) acc[m] = 0;
-            const size_t e0 = (((size_t)tile * B + b0) * TILE + r) * TILE + c;
+            const size_t e0 = (((size_t)tile * B + b0) * TILE + rt) * TILE + c;
             PairState cur = load_state(e0);
             for (int bb = 0; bb < nb; ++bb) {
                 const size_t e = e0 + (size_t)bb * TILE_PAIRS;
@@ -441,8 +459,8 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
 
                 double cnr = 0.0, cni = 0.0, cor_ = 0.0, coi = 0.0;
                 for (int l = 0; l < L; ++l) {
-                    const size_t ob = (size_t)(bb * L + l) * nodes2;
-                    const T2 a = Xn[ob + r], bx = Xn[ob + TILE + c];
+                    const size_t ob = (size_t)(bb * L + l) * PAIR_NODES;
+                    const T2 a = Xn[ob + r], bx = Xn[ob + SLICE_ROWS + c];
                     // X_i conj(X_j): FP32 operands give exact FP64 products
                     double re = (double)a.x * bx.x + (double)a.y * bx.y;
                     double im = (double)a.y * bx.x - (double)a.x * bx.y;
@@ -454,7 +472,7 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
                         cni += s.lamw[l] * im;
                     }
                     if (has_old) {
-                        const T2 ao = Xo[ob + r], bo = Xo[ob + TILE + c];
+                        const T2 ao = Xo[ob + r], bo = Xo[ob + SLICE_ROWS + c];
                         re = (double)ao.x * bo.x + (double)ao.y * bo.y;
                         im = (double)ao.y * bo.x - (double)ao.x * bo.y;
                         if (L == 1) {
@@ -477,14 +495,17 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
                     if (has_old) st.sim = st.sim - coi;
                     pSim[e] = st.sim;
                 }
+                double ure = 0.0, uim = 0.0;
                 if (needU) {
                     double unr, uni, uor = 0.0, uoi = 0.0;
                     if (L == 1) {
-                        const T2 ui = Un[(size_t)bb * nodes2 + r], uj = Un[(size_t)bb * nodes2 + TILE + c];
+                        const T2 ui = Un[(size_t)bb * PAIR_NODES + r];
+                        const T2 uj = Un[(size_t)bb * PAIR_NODES + SLICE_ROWS + c];
                         unr = (double)(T)(ui.x * uj.x + ui.y * uj.y);
                         uni = (double)(T)(ui.y * uj.x - ui.x * uj.y);
                         if (has_old) {
-                            const T2 vi = Uo[(size_t)bb * nodes2 + r], vj = Uo[(size_t)bb * nodes2 + TILE + c];
+                            const T2 vi = Uo[(size_t)bb * PAIR_NODES + r];
+                            const T2 vj = Uo[(size_t)bb * PAIR_NODES + SLICE_ROWS + c];
                             uor = (double)(T)(vi.x * vj.x + vi.y * vj.y);
                             uoi = (double)(T)(vi.y * vj.x - vi.x * vj.y);
                         }
@@ -498,19 +519,39 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
                             uoi = mo > 0.0 ? coi / mo : 0.0;
                         }
                     }
-                    st.ure = st.ure + unr;
-                    st.uim = st.uim + uni;
-                    if (has_old) {
-                        st.ure = st.ure - uor;
-                        st.uim = st.uim - uoi;
+                    if (ufix) {
+                        // u * 2^k is exact in FP32; the rounded integer of
+                        // the evicted trial equals the one it added
+                        st.uqr += (int)rintf((float)unr * uscale);
+                        st.uqi += (int)rintf((float)uni * uscale);
+                        if (has_old) {
+                            st.uqr -= (int)rintf((float)uor * uscale);
+                            st.uqi -= (int)rintf((float)uoi * uscale);
+                        }
+                        qUre[e] = st.uqr;
+                        qUim[e] = st.uqi;
+                        ure = (double)st.uqr * uinv;
+                        uim = (double)st.uqi * uinv;
+                    } else {
+                        st.ure = st.ure + unr;
+                        st.uim = st.uim + uni;
+                        if (has_old) {
+                            st.ure = st.ure - uor;
+                            st.uim = st.uim - uoi;
+                        }
+                        pUre[e] = st.ure;
+                        pUim[e] = st.uim;
+                        ure = st.ure;
+                        uim = st.uim;
                     }
-                    pUre[e] = st.ure;
-                    pUim[e] = st.uim;
                 }
                 if (needG) {
                     st.g = st.g + sgn_of(cni);
                     if (has_old) st.g -= sgn_of(coi);
-                    pG[e] = (short)st.g;
+                    if (g8)
+                        pG8[e] = (signed char)st.g;
+                    else
+                        pG16[e] = (short)st.g;
                 }
                 if (needA) {
                     st.a = st.a + fabs(cni);
@@ -523,10 +564,10 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
                     pQ[e] = st.q;
                 }
                 // metrics of this bin, into the band mean
-                const double srij = SR[bb * nodes2 + r] * SR[bb * nodes2 + TILE + c];
+                const double srij = SR[bb * PAIR_NODES + r] * SR[bb * PAIR_NODES + SLICE_ROWS + c];
                 if (mm & M_COH) acc[0] += sqrt_ratio<T>((st.sre * st.sre + st.sim * st.sim) * srij * srij);
                 if (mm & M_IMCOH) acc[1] += (T)(st.sim * srij);
-                if (mm & M_PLV) acc[2] += sqrt_ratio<T>(st.ure * st.ure + st.uim * st.uim) * invK;
+                if (mm & M_PLV) acc[2] += sqrt_ratio<T>(ure * ure + uim * uim) * invK;
                 if (mm & (M_PLI | M_USPLI)) {
                     const double pli = fabs((double)st.g) / Kd;
                     if (mm & M_PLI) acc[3] += (T)pli;
@@ -558,12 +599,12 @@ __device__ __forceinline__ void pair_tile_update(const SessDev<T> &s, int tile, 
 }
 
 template <typename T>
-__device__ __forceinline__ void pair_tile_dispatch(const SessDev<T> &s, int tile, long long tp, int CB, char *lds)
+__device__ __forceinline__ void pair_item(const SessDev<T> &s, int item, long long tp, int CB, char *lds)
 {
     if (CB >= s.B)
-        pair_tile_update<T, true>(s, tile, tp, CB, lds);
+        pair_slice_update<T, true>(s, item, tp, CB, lds);
     else
-        pair_tile_update<T, false>(s, tile, tp, CB, lds);
+        pair_slice_update<T, false>(s, item, tp, CB, lds);
 }
 
 template <typename T>
@@ -571,7 +612,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_update(SessDev<T> s, int 
 {
     extern __shared__ __align__(16) char lds[];
     if (s.ctl->bad) return;
-    pair_tile_dispatch<T>(s, blockIdx.x, s.ctl->pushed, CB, lds);
+    pair_item<T>(s, blockIdx.x, s.ctl->pushed, CB, lds);
 }
 
 template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStream_t st)
@@ -579,7 +620,7 @@ template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStre
     const int CB = pair_chunk_bins(s.B, s.L, (int)sizeof(T));
     const bool spectral = (s.metrics & 0x7Fu) != 0;
     const size_t lds = spectral ? pair_lds_bytes(CB, s.L, (int)sizeof(T)) : 0;
-    hipLaunchKernelGGL(k_pair_update<T>, dim3(s.ntiles), dim3(PAIR_THREADS), lds, st, s, CB);
+    hipLaunchKernelGGL(k_pair_update<T>, dim3(s.ntiles * SLICES), dim3(PAIR_THREADS), lds, st, s, CB);
     return hipGetLastError();
 }
 
@@ -643,32 +684,40 @@ __global__ __launch_bounds__(256) void k_finalize_bins(SessDev<T> s, uint32_t me
     const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
     const double pi_ = s.psd[(size_t)b * N + i], pj_ = s.psd[(size_t)b * N + j];
     const double den = sqrt(pi_ * pj_);
+    const double *pl[NPLANES];
+    for (int k = 0; k < NPLANES; ++k) pl[k] = (const double *)s.plane[k];
+    auto usum = [&](int k) {
+        return s.u_fixed ? (double)((const int *)s.plane[k])[e] * ldexp(1.0, -s.ufix_bits) : pl[k][e];
+    };
+    auto gsum = [&]() {
+        return s.g_narrow ? (double)((const signed char *)s.gsum)[e] : (double)((const short *)s.gsum)[e];
+    };
     double v = 0.0;
     switch (metric) {
     case M_COH: {
-        const double a = s.plane[P_SRE][e], bb = s.plane[P_SIM][e];
+        const double a = pl[P_SRE][e], bb = pl[P_SIM][e];
         v = den > 0.0 ? sqrt(a * a + bb * bb) / den : 0.0;
         break;
     }
-    case M_IMCOH: v = den > 0.0 ? s.plane[P_SIM][e] / den : 0.0; break;
+    case M_IMCOH: v = den > 0.0 ? pl[P_SIM][e] / den : 0.0; break;
     case M_PLV: {
-        const double a = s.plane[P_URE][e], bb = s.plane[P_UIM][e];
+        const double a = usum(P_URE), bb = usum(P_UIM);
         v = sqrt(a * a + bb * bb) / Kd;
         break;
     }
-    case M_PLI: v = fabs((double)s.gsum[e]) / Kd; break;
+    case M_PLI: v = fabs(gsum()) / Kd; break;
     case M_USPLI: {
-        const double pli = fabs((double)s.gsum[e]) / Kd;
+        const double pli = fabs(gsum()) / Kd;
         v = K >= 2 ? (Kd * pli * pli - 1.0) / (Kd - 1.0) : NAN;
         break;
     }
     case M_WPLI: {
-        const double A = s.plane[P_A][e];
-        v = A > 0.0 ? fabs(s.plane[P_SIM][e]) / A : 0.0;
+        const double A = pl[P_A][e];
+        v = A > 0.0 ? fabs(pl[P_SIM][e]) / A : 0.0;
         break;
     }
     case M_DSWPLI: {
-        const double A = s.plane[P_A][e], Q = s.plane[P_Q][e], S = s.plane[P_SIM][e];
+        const double A = pl[P_A][e], Q = pl[P_Q][e], S = pl[P_SIM][e];
         const double dd = A * A - Q;
         v = K >= 2 ? (dd != 0.0 ? (S * S - Q) / dd : 0.0) : NAN;
         break;
@@ -727,7 +776,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void kb_pair_update(const SessDev<flo
         const int4 w = items[it];
         const SessDev<float> &s = S[w.x];
         if (s.ctl->bad) continue;
-        pair_tile_dispatch<float>(s, w.y, s.ctl->pushed, pair_chunk_bins(s.B, s.L, 4), lds);
+        pair_item<float>(s, w.y, s.ctl->pushed, pair_chunk_bins(s.B, s.L, 4), lds);
         __syncthreads();
     }
 }

@@ -125,7 +125,7 @@ static hipError_t run_tick(Server *sv, Tick &tk)
             if (l > lds) lds = l;
         }
         if (sb.s->cfg.metrics & M_COR) n_zn += (size_t)(g.N + 3) / 4;
-        n_pair += g.ntiles;  // spectral sums and COR blocks of every tile
+        n_pair += (size_t)g.ntiles * SLICES;  // spectral sums and COR blocks of every tile slice
     }
     const size_t n_items = n_sp + n_zn + n_psd + n_pair;
     hipError_t e = ensure_capacity(b, ns, n_items);
@@ -146,7 +146,7 @@ static hipError_t run_tick(Server *sv, Tick &tk)
         }
         if (s->cfg.metrics & M_COR)
             for (int bx = 0; bx < (g.N + 3) / 4; ++bx) it_zn[z++] = make_int4(k, bx, 0, 0);
-        for (int t = 0; t < g.ntiles; ++t) it_pair[q++] = make_int4(k, t, 0, 0);
+        for (int t = 0; t < g.ntiles * SLICES; ++t) it_pair[q++] = make_int4(k, t, 0, 0);
     }
     if ((e = hipMemcpyAsync(b.d_desc, b.h_desc, ns * sizeof(SessDev<float>), hipMemcpyHostToDevice, sv->stream)) !=
         hipSuccess)

@@ -169,8 +169,11 @@ def test_c3_full_size_sampled_rows(fcx):
 
 # ---------------------------------------------------------------- edge shapes
 
-@pytest.mark.parametrize("N,W,T", [(2, 1, 3), (63, 3, 5), (64, 4, 4), (65, 3, 7), (129, 2, 5), (200, 5, 12)])
+@pytest.mark.parametrize("N,W,T", [(2, 1, 3), (63, 3, 5), (64, 4, 4), (65, 3, 7), (129, 2, 5), (200, 5, 12),
+                                   (70, 130, 137), (70, 300, 306)])
 def test_edge_shapes(fcx, N, W, T):
+    """Ragged and minimal node counts, W = 1, and the storage variants: int16
+    sign sums (W > 127) and FP64 phasor sums (W > 256)."""
     rng = np.random.default_rng(N * 100 + W)
     M = 96
     x = rng.standard_normal((T, N, M))

@@ -66,10 +66,25 @@ def test_footprint_scales_with_metrics():
     all8 = fcx.footprint_bytes(dict(base, metrics=synth.ALL8))
     coh = fcx.footprint_bytes(dict(base, metrics=synth.COH))
     wpli = fcx.footprint_bytes(dict(base, metrics=synth.WPLI))
-    # 12.5M pairs x 12 bins: all-8 keeps 6 FP64 planes + int16 signs (~7.8 GB);
-    # coh and wpli keep 2 FP64 planes each (~2.5 GB)
-    assert 7.5e9 < all8 < 9.5e9
+    # 3160 tiles x 12 bins x 4096 slots: all-8 keeps 4 FP64 planes, 2 int32
+    # fixed-point phasor planes and int8 signs (~6.4 GB) plus the COR sample
+    # ring, spectra ring and outputs (~1 GB); coh and wpli keep 2 FP64 planes
+    slots = 3160 * 12 * 4096
+    assert abs(all8 - (slots * (4 * 8 + 2 * 4 + 1) + 1.0e9)) < 0.1e9
     assert 2.4e9 < coh < 3.0e9 and 2.4e9 < wpli < 3.0e9
+
+
+def test_pair_update_bytes():
+    base = synth.base_config(n_nodes=5000, n_samples=500, window_trials=50, n_fft=512, f_lo_hz=8, f_hi_hz=30)
+    P, B = 5000 * 4999 // 2, 12
+    # all 8: per pair and bin 2 x (4 x 8 + 2 x 4 + 1) bytes; per pair 7 band means,
+    # the COR sum read and written and the COR output
+    assert fcx.pair_update_bytes(dict(base, metrics=synth.ALL8)) == P * (2 * 41 * B + 7 * 4 + 16 + 4)
+    assert fcx.pair_update_bytes(dict(base, metrics=synth.COH)) == P * (2 * 16 * B + 4)
+    assert fcx.pair_update_bytes(dict(base, metrics=synth.WPLI)) == P * (2 * 16 * B + 4)
+    # long windows keep FP64 phasor sums and int16 signs
+    assert fcx.pair_update_bytes(dict(base, metrics=synth.PLV | synth.PLI, window_trials=300)) == \
+        P * (2 * 18 * B + 8)
 
 
 def test_bad_handles():
