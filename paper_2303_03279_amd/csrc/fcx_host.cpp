@@ -642,6 +642,18 @@ static fcx_status read_ctl(Session *s, DevCtl *c)
     return FCX_OK;
 }
 
+// running sums of the current window rebuilt from the ring (after a batch
+// pass, or on request)
+static fcx_status rebuild_sums(Session *s)
+{
+    DevCtl c;
+    fcx_status st = read_ctl(s, &c);
+    if (st != FCX_OK) return st;
+    st = s->g.f64 ? replay_window<double>(s, c.pushed) : replay_window<float>(s, c.pushed);
+    if (st == FCX_OK) s->stale = false;
+    return st;
+}
+
 static fcx_status take_rejections(Session *s, const DevCtl &c)
 {
     if (c.rejected > s->reported_rejected) {
@@ -769,6 +781,7 @@ fcx_status fcx_push_trial(fcx_session *h, const void *x, int64_t ld, int x_on_de
     if (s->server) return FCX_E_INVAL;  // served sessions take trials through the server
     if (!x || ld < s->g.M) return FCX_E_INVAL;
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stale && (st = rebuild_sums(s)) != FCX_OK) return st;
     const void *xdev = x;
     long long ldx = ld;
     if (!x_on_device) {
@@ -789,24 +802,64 @@ fcx_status fcx_push_batch(fcx_session *h, const void *x, int64_t n_trials, int64
     if (s->server) return FCX_E_INVAL;
     if (!x || n_trials < 1 || n_trials > s->g.W || ld < s->g.M || trial_stride < ld * s->g.N)
         return FCX_E_INVAL;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        // reset the window: zero the running sums and the push counter
-        const BufferPlan &p = s->plan;
+    std::lock_guard<std::mutex> lk(s->mu);
+    const BufferPlan &p = s->plan;
+    const Geometry &g = s->g;
+    const size_t es = g.esz;
+    // empty window: the batch trials go to ring slots 0 .. n_trials-1
+    HIP_OK(hipMemsetAsync(s->ctl, 0, sizeof(DevCtl), s->stream));
+    s->reported_rejected = 0;
+    if (g.f64) {
+        // FP64 sessions: zero the sums and add the trials one by one
         if (p.psd) HIP_OK(hipMemsetAsync(s->psd, 0, p.psd, s->stream));
         for (int i = 0; i < NPLANES; ++i)
             if (s->plane[i])
                 HIP_OK(hipMemsetAsync(s->plane[i], 0, (i == P_URE || i == P_UIM) ? p.uplane : p.plane, s->stream));
         if (s->gsum) HIP_OK(hipMemsetAsync(s->gsum, 0, p.gsum, s->stream));
         if (s->rsum) HIP_OK(hipMemsetAsync(s->rsum, 0, p.rsum, s->stream));
-        HIP_OK(hipMemsetAsync(s->ctl, 0, sizeof(DevCtl), s->stream));
-        s->reported_rejected = 0;
+        for (int64_t k = 0; k < n_trials; ++k) {
+            const void *xk = (const char *)x + (size_t)k * trial_stride * es;
+            long long ldk = ld;
+            if (!x_on_device) {
+                if ((st = upload_host_trial(s, xk, ld)) != FCX_OK) return st;
+                xk = s->xbuf;
+                ldk = g.M;
+            }
+            if ((st = session_enqueue_push(s, xk, ldk)) != FCX_OK) return st;
+        }
+        s->stale = false;
+        return FCX_OK;
     }
-    const size_t es = s->g.esz;
+    // FP32 sessions: spectra of every trial into the ring, then one batch
+    // pass with the Gram sums on the matrix cores
+    SessDev<float> d = session_dev<float>(s, nullptr, 0);
+    const bool spectral = (s->cfg.metrics & 0x7Fu) != 0, cor = (s->cfg.metrics & M_COR) != 0;
     for (int64_t k = 0; k < n_trials; ++k) {
-        st = fcx_push_trial(h, (const char *)x + (size_t)k * trial_stride * es, ld, x_on_device);
-        if (st != FCX_OK) return st;
+        const void *xk = (const char *)x + (size_t)k * trial_stride * es;
+        long long ldk = ld;
+        if (!x_on_device) {
+            if ((st = upload_host_trial(s, xk, ld)) != FCX_OK) return st;
+            xk = s->xbuf;
+            ldk = g.M;
+        }
+        d.x = xk;
+        d.ldx = ldk;
+        HIP_OK(launch_set_pushed(s->ctl, k, s->stream));
+        if (spectral) HIP_OK(launch_spectra<float>(d, s->stream));
+        if (cor) HIP_OK(launch_znorm<float>(d, s->stream));
     }
+    const int prec = s->cfg.gram_precision;
+    if (spectral) {
+        HIP_OK(launch_psd_batch(d, (int)n_trials, s->stream));
+        TimedLaunch t(s, FCX_K_PAIR_BATCH);
+        HIP_OK(launch_pair_batch(d, (int)n_trials, prec, s->stream));
+    }
+    if (cor) {
+        TimedLaunch t(s, FCX_K_COR);
+        HIP_OK(launch_cor_batch(d, (int)n_trials, prec, s->stream));
+    }
+    HIP_OK(launch_batch_commit(s->ctl, n_trials, s->stream));
+    s->stale = true;  // the running sums do not hold this window yet
     return FCX_OK;
 }
 
@@ -847,6 +900,7 @@ fcx_status fcx_read_network(fcx_session *h, uint32_t metric, void *out, int64_t 
         const char *src = (const char *)s->out + (size_t)mi * g.P * g.esz;
         HIP_OK(hipMemcpy(out, src, g.P * g.esz, kind));
     } else {
+        if (s->stale && (st = rebuild_sums(s)) != FCX_OK) return st;
         void *dst = out;
         void *tmp = nullptr;
         if (!out_on_device) {
@@ -875,10 +929,7 @@ fcx_status fcx_resync(fcx_session *h)
     Session *s = lookup_session(h, &st);
     if (!s) return st;
     std::lock_guard<std::mutex> lk(s->mu);
-    DevCtl c;
-    st = read_ctl(s, &c);
-    if (st != FCX_OK) return st;
-    return s->g.f64 ? replay_window<double>(s, c.pushed) : replay_window<float>(s, c.pushed);
+    return rebuild_sums(s);
 }
 
 fcx_status fcx_close(fcx_session *h)

@@ -69,6 +69,7 @@ struct Session {
     int pinned_next = 0;
 
     int64_t reported_rejected = 0;
+    bool stale = false;   // running sums not yet built for the window (after a batch pass)
 
     // timing
     bool timing = false;

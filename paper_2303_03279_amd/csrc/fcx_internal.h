@@ -13,11 +13,14 @@ constexpr int SLICE_ROWS = 16;       // a workgroup owns a 16-row slice of a til
 constexpr int SLICES = TILE / SLICE_ROWS;
 constexpr int PAIR_NODES = SLICE_ROWS + TILE;   // row + column nodes staged per slice
 constexpr int PAIR_LDS_BYTES = 40 * 1024;
-constexpr int ZPAD = 16;             // COR sample rows padded to a multiple of 16
+constexpr int ZPAD = 32;             // COR sample rows padded to a multiple of 32
 
 // running-sum planes of the pair state: FP64, except the unit-phasor sums of
 // FP32 sessions (int32 fixed point) and the sign sums (int8 or int16)
 enum Plane { P_SRE = 0, P_SIM = 1, P_URE = 2, P_UIM = 3, P_A = 4, P_Q = 5, NPLANES = 6 };
+
+// Gram precisions (same values as the public header)
+enum { FCX_GRAM_FP32_ID = 0, FCX_GRAM_BF16_ID = 1, FCX_GRAM_BF16X3_ID = 2 };
 
 // metric bits (same values as the public header)
 enum : uint32_t { M_COH = 1, M_IMCOH = 2, M_PLV = 4, M_PLI = 8, M_WPLI = 16, M_USPLI = 32,
@@ -94,6 +97,13 @@ hipError_t launch_set_ctl(DevCtl *ctl, long long pushed, hipStream_t st);
 template <typename T>
 hipError_t launch_finalize_bins(const SessDev<T> &s, uint32_t metric, T *out, hipStream_t st);
 hipError_t launch_copy_probe(void *dst, const void *src, int64_t n_bytes, hipStream_t st);
+
+// batch (window recompute) path, float sessions (fcx_batch.hip)
+hipError_t launch_set_pushed(DevCtl *ctl, long long pushed, hipStream_t st);
+hipError_t launch_batch_commit(DevCtl *ctl, long long K, hipStream_t st);
+hipError_t launch_psd_batch(const SessDev<float> &s, int K, hipStream_t st);
+hipError_t launch_pair_batch(const SessDev<float> &s, int K, int prec, hipStream_t st);
+hipError_t launch_cor_batch(const SessDev<float> &s, int K, int prec, hipStream_t st);
 
 // bin-chunk size of the pair kernel for a given (B, L, element size), and the
 // LDS it needs

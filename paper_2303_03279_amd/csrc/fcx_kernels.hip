@@ -17,34 +17,13 @@
 // recomputed from the cached spectra with exactly the instructions that added
 // it, so add and remove cancel bit for bit before the FP64 rounding of the
 // running sum itself.
-#include "fcx_internal.h"
+#include "fcx_device.h"
 
 #include <math.h>
 
 #pragma clang fp contract(off)
 
 namespace fcx {
-
-template <typename T> struct V2;
-template <> struct V2<float> { typedef float2 t; };
-template <> struct V2<double> { typedef double2 t; };
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ int sgn_of(double v) { return (v > 0.0) - (v < 0.0); }
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-template <typename T> __device__ __forceinline__ T sqrt_ratio(double r);
-template <> __device__ __forceinline__ float sqrt_ratio<float>(double r) { return sqrtf((float)r); }
-template <> __device__ __forceinline__ double sqrt_ratio<double>(double r) { return sqrt(r); }
-
-__device__ __forceinline__ bool finite_v(float v) { return isfinite(v); }
-__device__ __forceinline__ bool finite_v(double v) { return isfinite(v); }
 
 // ---------------------------------------------------------------------------
 // spectra: X[b][l][i] = sum_n (w_l[n] e^{-2 pi i k_b n / F}) x_i[n]
@@ -318,18 +297,6 @@ struct PairState {
     int uqr, uqi, g;
 };
 
-// num / den for a metric in [-1, 1]: FP64 operands of any scale are brought
-// to den in [0.5, 1) by an exact power-of-two scaling, then divided in FP32
-// (the FP64 instantiation divides in FP64)
-template <typename T> __device__ __forceinline__ T ratio_t(double num, double den);
-template <> __device__ __forceinline__ float ratio_t<float>(double num, double den)
-{
-    int e;
-    const double dm = frexp(den, &e);
-    return __fdividef((float)ldexp(num, -e), (float)dm);
-}
-template <> __device__ __forceinline__ double ratio_t<double>(double num, double den) { return num / den; }
-
 template <typename T, bool ONE_CHUNK>
 __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item, long long tp, int CB, char *lds)
 {
@@ -369,8 +336,10 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
     short *__restrict__ pG16 = (short *)s.gsum;
     signed char *__restrict__ pG8 = (signed char *)s.gsum;
 
-    const double Kd = (double)K;
-    const T invK = (T)1 / (T)K;
+    const T Kt = (T)K;
+    const T invK = (T)(1.0 / (double)K);
+    const T invKm1 = K >= 2 ? (T)(1.0 / (double)(K - 1)) : (T)0;
+    const T uinvT = (T)uinv;
     const size_t P = (size_t)N * (N - 1) / 2;
 
     if (mm & M_COR) cor_block(s, pv, tile, sub, J0, R0, w);
@@ -413,29 +382,33 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
             }
             Xn[(size_t)bl * PAIR_NODES + nl] = xn;
             Xo[(size_t)bl * PAIR_NODES + nl] = xo;
-            if (L == 1) {
-                // unit phasor X / |X| (0 for X = 0), formed in FP64 so that
-                // tiny amplitudes cannot underflow
+            if (L == 1 && needU) {
+                // unit phasor X / |X| (0 for X = 0); the magnitude is formed
+                // in FP64 so that tiny amplitudes cannot underflow
                 T2 un, uo;
-                const double mn = sqrt((double)xn.x * xn.x + (double)xn.y * xn.y);
-                const double mo = sqrt((double)xo.x * xo.x + (double)xo.y * xo.y);
-                un.x = mn > 0.0 ? (T)(xn.x / mn) : (T)0;
-                un.y = mn > 0.0 ? (T)(xn.y / mn) : (T)0;
-                uo.x = mo > 0.0 ? (T)(xo.x / mo) : (T)0;
-                uo.y = mo > 0.0 ? (T)(xo.y / mo) : (T)0;
+                const double m2n = (double)xn.x * xn.x + (double)xn.y * xn.y;
+                const double m2o = (double)xo.x * xo.x + (double)xo.y * xo.y;
+                const double rn = m2n > 0.0 ? rsqrt(m2n) : 0.0;
+                const double ro = m2o > 0.0 ? rsqrt(m2o) : 0.0;
+                un.x = (T)(xn.x * rn);
+                un.y = (T)(xn.y * rn);
+                uo.x = (T)(xo.x * ro);
+                uo.y = (T)(xo.y * ro);
                 Un[(size_t)bb * PAIR_NODES + nl] = un;
                 Uo[(size_t)bb * PAIR_NODES + nl] = uo;
             }
         }
-        for (int e = tid; e < nb * PAIR_NODES; e += PAIR_THREADS) {
-            const int nl = e % PAIR_NODES, bb = e / PAIR_NODES;
-            const int node = nl < SLICE_ROWS ? R0 + nl : J0 + nl - SLICE_ROWS;
-            double sr = 0.0;
-            if (node < N) {
-                const double p = s.psd[(size_t)(b0 + bb) * N + node];
-                sr = p > 0.0 ? 1.0 / sqrt(p) : 0.0;
+        if (mm & (M_COH | M_IMCOH)) {
+            for (int e = tid; e < nb * PAIR_NODES; e += PAIR_THREADS) {
+                const int nl = e % PAIR_NODES, bb = e / PAIR_NODES;
+                const int node = nl < SLICE_ROWS ? R0 + nl : J0 + nl - SLICE_ROWS;
+                double sr = 0.0;
+                if (node < N) {
+                    const double p = s.psd[(size_t)(b0 + bb) * N + node];
+                    sr = p > 0.0 ? rsqrt(p) : 0.0;
+                }
+                SR[e] = sr;
             }
-            SR[e] = sr;
         }
         __syncthreads();
 
@@ -530,8 +503,6 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                         }
                         qUre[e] = st.uqr;
                         qUim[e] = st.uqi;
-                        ure = (double)st.uqr * uinv;
-                        uim = (double)st.uqi * uinv;
                     } else {
                         st.ure = st.ure + unr;
                         st.uim = st.uim + uni;
@@ -564,14 +535,21 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                     pQ[e] = st.q;
                 }
                 // metrics of this bin, into the band mean
-                const double srij = SR[bb * PAIR_NODES + r] * SR[bb * PAIR_NODES + SLICE_ROWS + c];
-                if (mm & M_COH) acc[0] += sqrt_ratio<T>((st.sre * st.sre + st.sim * st.sim) * srij * srij);
-                if (mm & M_IMCOH) acc[1] += (T)(st.sim * srij);
-                if (mm & M_PLV) acc[2] += sqrt_ratio<T>(ure * ure + uim * uim) * invK;
+                if (mm & (M_COH | M_IMCOH)) {
+                    const double srij = SR[bb * PAIR_NODES + r] * SR[bb * PAIR_NODES + SLICE_ROWS + c];
+                    if (mm & M_COH) acc[0] += sqrt_ratio<T>((st.sre * st.sre + st.sim * st.sim) * srij * srij);
+                    if (mm & M_IMCOH) acc[1] += (T)(st.sim * srij);
+                }
+                if (mm & M_PLV) {
+                    // |U| <= K: safe in the session's precision
+                    const T ur = ufix ? (T)st.uqr * uinvT : (T)ure;
+                    const T ui = ufix ? (T)st.uqi * uinvT : (T)uim;
+                    acc[2] += sqrt(ur * ur + ui * ui) * invK;
+                }
                 if (mm & (M_PLI | M_USPLI)) {
-                    const double pli = fabs((double)st.g) / Kd;
-                    if (mm & M_PLI) acc[3] += (T)pli;
-                    if (mm & M_USPLI) acc[5] += K >= 2 ? (T)((Kd * pli * pli - 1.0) / (Kd - 1.0)) : (T)NAN;
+                    const T pli = (T)abs(st.g) * invK;
+                    if (mm & M_PLI) acc[3] += pli;
+                    if (mm & M_USPLI) acc[5] += K >= 2 ? (Kt * pli * pli - (T)1) * invKm1 : (T)NAN;
                 }
                 if (mm & M_WPLI) acc[4] += st.a > 0.0 ? ratio_t<T>(fabs(st.sim), st.a) : (T)0;
                 if (mm & M_DSWPLI) {

@@ -1,0 +1,145 @@
+"""Batch pass (fcx_push_batch): the network of K trials with the Gram sums on
+the matrix cores in FP32, BF16 or split BF16x3, against the FP64 oracle.
+
+FP32 must meet the 1e-5 bound; the BF16 forms have the error the operand
+rounding gives, stated per metric here (the sign counts, |Im| and Im^2 sums
+do not go through the Gram and keep their FP32 accuracy)."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import TOL, compare_network, log, tie_bounds
+
+pytestmark = pytest.mark.gpu
+
+ALL = ["coh", "imcoh", "plv", "pli", "wpli", "uspli", "dswpli", "cor"]
+# stated bounds (absolute, on the metric scale) per Gram precision
+BOUND = {"fp32": dict.fromkeys(ALL, TOL),
+         "bf16x3": dict(coh=5e-5, imcoh=5e-5, plv=5e-5, pli=TOL, wpli=5e-5, uspli=TOL, dswpli=1e-4, cor=5e-5),
+         "bf16": dict(coh=2e-2, imcoh=2e-2, plv=2e-2, pli=TOL, wpli=2e-2, uspli=TOL, dswpli=5e-2, cor=2e-2)}
+
+
+@pytest.fixture(scope="module")
+def fcx():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    import paper_2303_03279_amd as m
+    return m
+
+
+def _batch(fcx, cfg, x):
+    import torch
+    s = fcx.Session(cfg)
+    xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    torch.cuda.synchronize()
+    K, N, M = x.shape
+    fcx.check(s.push_batch_device(xd.data_ptr(), K, N * M, M), "push_batch")
+    fcx.check(s.sync(), "sync")
+    return s, xd
+
+
+def _errors(s, ref, metrics, idx=None):
+    K = ref["K"]
+    dpli, dus = tie_bounds(ref, K)
+    out = {}
+    for m in metrics:
+        st, got, k = s.read(m)
+        assert k == K
+        got = got.astype(np.float64)
+        if idx is not None:
+            got = got[idx]
+        err = np.abs(got - ref["band"][m])
+        if m == "pli":
+            err = np.maximum(err - dpli, 0.0)
+        if m == "uspli":
+            err = np.maximum(err - dus, 0.0)
+        out[m] = float(err.max())
+    return out
+
+
+@pytest.fixture(scope="module")
+def mid():
+    x = synth.source_space(31, 300, 24, 500, 20)
+    cfg = synth.base_config(n_nodes=300, n_samples=500, window_trials=30, n_fft=512, fs_hz=1000.0,
+                            f_lo_hz=8.0, f_hi_hz=30.0, metrics=synth.ALL8)
+    return x, cfg
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+def test_batch_precision_vs_oracle(fcx, mid, prec):
+    x, cfg = mid
+    cfg = dict(cfg, gram=prec)
+    s, _ = _batch(fcx, cfg, x)
+    ref = oracle.network(oracle.as_device_input(x, cfg), cfg)
+    err = _errors(s, ref, ALL)
+    log(f"batch {prec} N=300 K=24 max abs error per metric: " + json.dumps({k: f"{v:.2e}" for k, v in err.items()}))
+    for m in ALL:
+        assert err[m] <= BOUND[prec][m], (prec, m, err[m])
+    s.close()
+
+
+def test_batch_then_slide(fcx, mid):
+    """After a batch the session keeps sliding: the running sums are rebuilt
+    from the cached spectra and later pushes add and evict as usual."""
+    x, cfg = mid
+    W = 10
+    cfg = dict(cfg, window_trials=W)
+    s, _ = _batch(fcx, cfg, x[:W])
+    st, pb, K = s.read("coh", per_bin=True)       # per-bin read rebuilds the sums
+    fcx.check(st)
+    ref0 = oracle.network(oracle.as_device_input(x[:W], cfg), cfg)
+    assert np.max(np.abs(pb.T - ref0["per_bin"]["coh"])) < TOL
+    for k in range(W, W + 7):
+        fcx.check(s.push_host(np.ascontiguousarray(x[k], dtype=np.float32)))
+    ref = oracle.network(oracle.as_device_input(x[7:W + 7], cfg), cfg)
+    compare_network(s, ref, cfg, ALL, label="batch then slide")
+    s.close()
+
+
+def test_batch_multitaper(fcx):
+    rng = np.random.default_rng(8)
+    N, M, K = 90, 200, 12
+    x = rng.standard_normal((K, N, M))
+    x[:, 1, 3:] += 0.9 * x[:, 0, :-3]
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=K, n_fft=256, f_lo_hz=4, f_hi_hz=120,
+                            taper="dpss", dpss_nw=2.0, dpss_k=3, metrics=synth.ALL8, gram="fp32")
+    s, _ = _batch(fcx, cfg, x)
+    ref = oracle.network(oracle.as_device_input(x, cfg), cfg)
+    err = _errors(s, ref, ALL)
+    log("batch dpss L=3 fp32: " + json.dumps({k: f"{v:.2e}" for k, v in err.items()}))
+    assert max(err.values()) <= TOL
+    s.close()
+
+
+def test_batch_rejects_nonfinite(fcx, mid):
+    x, cfg = mid
+    bad = np.array(x[:5], dtype=np.float32)
+    bad[3, 10, 20] = np.inf
+    s = fcx.Session(dict(cfg, window_trials=5))
+    import torch
+    xd = torch.from_numpy(bad).cuda()
+    torch.cuda.synchronize()
+    fcx.check(s.push_batch_device(xd.data_ptr(), 5, bad.shape[1] * bad.shape[2], bad.shape[2]))
+    assert s.sync() == fcx.FCX_E_NONFINITE
+    st, out, K = s.read("coh")
+    assert st == fcx.FCX_E_NOTREADY and K == 0
+    s.close()
+
+
+def test_batch_full_source_size_sampled(fcx):
+    """5000 nodes, K = 50 trials in one batch pass (FP32 Gram), sampled rows."""
+    x, cfg = synth.c3_source(n_trials=50)
+    N = cfg["n_nodes"]
+    log("batch c3: N=5000 K=50, fp32")
+    s, _ = _batch(fcx, cfg, x)
+    rows = [0, 77, 2500, 4990]
+    pi, pj = oracle.row_pairs(rows, N)
+    ref = oracle.network(oracle.as_device_input(x, cfg), cfg, pi, pj)
+    err = _errors(s, ref, ALL, idx=oracle.packed_index(pi, pj, N))
+    log("batch c3 fp32: " + json.dumps({k: f"{v:.2e}" for k, v in err.items()}))
+    assert max(err.values()) <= TOL
+    s.close()
