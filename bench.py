@@ -75,6 +75,149 @@ def run_session(fcx, torch, cfg, pool_dev, steps, warmup, timing=True, lat_pushe
     return wall, kt, lat
 
 
+def run_batch(fcx, torch, cfg, pool_dev, reps):
+    """One batch pass over the window (fcx_push_batch) per repetition, Gram
+    sums in the session's precision; returns wall time per pass and the
+    HIP-event kernel times."""
+    K = cfg["window_trials"]
+    N, M = cfg["n_nodes"], cfg["n_samples"]
+    s = fcx.Session(cfg)
+    fcx.check(s.push_batch_device(pool_dev.data_ptr(), K, N * M, M), "batch")   # warm
+    fcx.check(s.sync(), "sync")
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fcx.check(s.push_batch_device(pool_dev.data_ptr(), K, N * M, M), "batch")
+    fcx.check(s.sync(), "sync")
+    wall = (time.perf_counter() - t0) / reps
+    n1, ms1 = s.kernel_time(fcx.FCX_K_PAIR_BATCH)
+    n2, ms2 = s.kernel_time(fcx.FCX_K_COR)
+    s.close()
+    return wall, (ms1 / n1 if n1 else None), (ms2 / n2 if n2 else None)
+
+
+class _Completion:
+    """Stamps the completion time of HIP events recorded after plain-path
+    pushes (a host thread polling event.query())."""
+
+    def __init__(self):
+        import threading
+        self.pending = []
+        self.done = []
+        self.lock = threading.Lock()
+        self.stop = False
+        self.t = threading.Thread(target=self._run, daemon=True)
+        self.t.start()
+
+    def add(self, ev, t_submit, updates):
+        with self.lock:
+            self.pending.append((ev, t_submit, updates))
+
+    def _run(self):
+        while True:
+            with self.lock:
+                items = list(self.pending)
+            now = time.perf_counter()
+            finished = [it for it in items if it[0].query()]
+            if finished:
+                with self.lock:
+                    for it in finished:
+                        self.pending.remove(it)
+                        self.done.append((now - it[1], it[2]))
+            if self.stop and not items:
+                return
+            time.sleep(0.0002)
+
+    def close(self):
+        self.stop = True
+        self.t.join()
+
+
+def _wait_until(t0, t_arr):
+    """Sleep (releasing the GIL) until shortly before t0 + t_arr, then spin."""
+    while True:
+        dt = t_arr - (time.perf_counter() - t0)
+        if dt <= 0:
+            return
+        if dt > 0.0006:
+            time.sleep(dt - 0.0004)
+
+
+def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
+    """The serving mix: 64 sessions (N in {60,128,306,1000,2000}, W ~U{10..100},
+    random metric subsets), Poisson arrivals at 10 trials/s per session.  The
+    same arrival trace runs through (a) the plain path, one stream and one
+    push per trial per session, and (b) the server's continuous batching.
+    Latency = submit -> update finished on the device (host clock)."""
+    import synth
+    sys.setswitchinterval(1e-4)
+    sess = synth.c4_sessions(seed)
+    trials = [np.ascontiguousarray(synth.c4_trials(c, sd, pool_per_session), dtype=np.float32) for c, sd in sess]
+    ts, ss = synth.c4_arrivals(np.random.default_rng(seed + 1), len(sess), duration_s)
+    upd = [fcx.band_bins(c)[0] * c["n_nodes"] * (c["n_nodes"] - 1) // 2 for c, _ in sess]
+    fp = sum(fcx.footprint_bytes(c) for c, _ in sess)
+    out = {"sessions": len(sess), "arrivals": int(ts.size), "duration_s": duration_s, "footprint_gb": fp / 1e9}
+
+    # (a) plain per-session path
+    plain = [fcx.Session(c) for c, _ in sess]
+    streams = [torch.cuda.ExternalStream(p.stream()) for p in plain]
+    for k, p in enumerate(plain):                 # fill the windows
+        for t in range(sess[k][0]["window_trials"]):
+            fcx.check(p.push_host(trials[k][t % pool_per_session]))
+    for p in plain:
+        fcx.check(p.sync())
+    comp = _Completion()
+    cursor = [0] * len(sess)
+    t0 = time.perf_counter()
+    for t_arr, k in zip(ts, ss):
+        _wait_until(t0, t_arr)
+        ts_sub = time.perf_counter()
+        fcx.check(plain[k].push_host(trials[k][cursor[k] % pool_per_session]))
+        cursor[k] += 1
+        ev = torch.cuda.Event()
+        ev.record(streams[k])
+        comp.add(ev, ts_sub, upd[k])
+    for p in plain:
+        fcx.check(p.sync())
+    wall_a = time.perf_counter() - t0
+    comp.close()
+    lat = np.array([d for d, _ in comp.done]) * 1e3
+    out["plain"] = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                        updates_per_s=float(sum(upd[k] for k in ss) / wall_a), wall_s=wall_a)
+    for p in plain:
+        p.close()
+    torch.cuda.synchronize()
+
+    # (b) server, continuous batching
+    srv = fcx.Server(int(fp * 1.2))
+    served = []
+    for c, _ in sess:
+        st, h = srv.open(c)
+        fcx.check(st, "server open")
+        served.append(h)
+    for k, h in enumerate(served):
+        for t in range(sess[k][0]["window_trials"]):
+            srv.submit(h, trials[k][t % pool_per_session])
+    srv.drain()
+    cursor = [0] * len(sess)
+    tickets = []
+    t0 = time.perf_counter()
+    for t_arr, k in zip(ts, ss):
+        _wait_until(t0, t_arr)
+        tickets.append(srv.submit(served[k], trials[k][cursor[k] % pool_per_session]))
+        cursor[k] += 1
+    srv.drain()
+    wall_b = time.perf_counter() - t0
+    lat = np.array([srv.poll(t)[1] for t in tickets]) * 1e3
+    out["server"] = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                         updates_per_s=float(sum(upd[k] for k in ss) / wall_b), wall_s=wall_b)
+    for h in served:
+        h.close()
+    srv.destroy()
+    return out
+
+
 def cpu_baseline(cfg, x_pool, rows):
     import oracle
     W = cfg["window_trials"]
@@ -104,6 +247,8 @@ def main():
     ap.add_argument("--no-subsets", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=1024,
                     help="size of the HBM copy probe (read + write), 0 to skip")
+    ap.add_argument("--batch-reps", type=int, default=2, help="batch passes per Gram precision, 0 to skip")
+    ap.add_argument("--serving-seconds", type=float, default=5.0, help="serving-mix arrival window, 0 to skip")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the update shards by pair "
@@ -166,6 +311,25 @@ def main():
                                   pair_update_avg_ms=p2.get("avg_ms"),
                                   pair_update_gbs=a2, hbm_frac=(a2 / HBM_PEAK_GBS) if a2 else None)
 
+    batch = {}
+    if args.batch_reps > 0:
+        K = cfg["window_trials"]
+        M = cfg["n_samples"]
+        gram_flops = 16.0 * P * B * K              # S and U complex Grams: 2 x 4 real MACs
+        cor_flops = 2.0 * P * K * M
+        for prec in ["fp32", "bf16x3", "bf16"]:
+            print(f"[bench] batch pass, {prec} Gram", file=sys.stderr, flush=True)
+            w, pms, cms = run_batch(fcx, torch, dict(cfg, gram=prec), pool_dev, args.batch_reps)
+            batch[prec] = dict(ms_per_batch=w * 1e3, updates_per_s=P * B * K / w,
+                               pair_batch_ms=pms, cor_batch_ms=cms,
+                               gram_tflops=gram_flops / (pms * 1e-3) / 1e12 if pms else None,
+                               cor_tflops=cor_flops / (cms * 1e-3) / 1e12 if cms else None)
+
+    serving = None
+    if args.serving_seconds > 0:
+        print("[bench] serving mix", file=sys.stderr, flush=True)
+        serving = run_serving(fcx, torch, args.serving_seconds)
+
     base = None
     if not args.no_cpu_baseline:
         print("[bench] oracle on host cores", file=sys.stderr, flush=True)
@@ -195,6 +359,8 @@ def main():
                      "kernel": "pair_update", "algorithmic_bytes_per_launch": algo},
         "hbm_copy_probe": probe,
         "sessions": sessions,
+        "batch": batch,
+        "serving": serving,
         "cpu_baseline": base,
     }
     print(json.dumps(out))
