@@ -212,26 +212,60 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
     lat = np.array([srv.poll(t)[1] for t in tickets]) * 1e3
     out["server"] = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                          updates_per_s=float(sum(upd[k] for k in ss) / wall_b), wall_s=wall_b)
+    # (c) burst: every session submits `burst` trials at once; time to drain
+    burst = 8
+    t0 = time.perf_counter()
+    for r in range(burst):
+        for k, h in enumerate(served):
+            srv.submit(h, trials[k][r % pool_per_session])
+    srv.drain()
+    wall_c = time.perf_counter() - t0
+    out["server_burst"] = dict(trials=burst * len(sess), wall_s=wall_c,
+                               updates_per_s=float(burst * sum(upd) / wall_c))
     for h in served:
         h.close()
     srv.destroy()
+    plain = [fcx.Session(c) for c, _ in sess]
+    for k, p in enumerate(plain):
+        for t in range(sess[k][0]["window_trials"]):
+            fcx.check(p.push_host(trials[k][t % pool_per_session]))
+    for p in plain:
+        fcx.check(p.sync())
+    t0 = time.perf_counter()
+    for r in range(burst):
+        for k, p in enumerate(plain):
+            fcx.check(p.push_host(trials[k][r % pool_per_session]))
+    for p in plain:
+        fcx.check(p.sync())
+    wall_d = time.perf_counter() - t0
+    out["plain_burst"] = dict(trials=burst * len(sess), wall_s=wall_d,
+                              updates_per_s=float(burst * sum(upd) / wall_d))
+    for p in plain:
+        p.close()
     return out
 
 
-def cpu_baseline(cfg, x_pool, rows):
+def cpu_baseline(cfg, x_pool, target_s=10.0):
+    """The FP64 oracle on the host cores: one network of the window for a
+    sample of rows, sized from a short probe to take about target_s."""
     import oracle
     W = cfg["window_trials"]
     N = cfg["n_nodes"]
     win = oracle.as_device_input(x_pool[:W], cfg)
+    probe_rows = list(range(0, N, N // 16))[:16]
+    t0 = time.perf_counter()
+    oracle.network(win, cfg, *oracle.row_pairs(probe_rows, N))
+    dt0 = time.perf_counter() - t0
+    n_rows = int(min(N - 1, max(16, 16 * target_s / max(dt0, 1e-3))))
+    rows = list(np.linspace(0, N - 2, n_rows).astype(int))
     pi, pj = oracle.row_pairs(rows, N)
-    oracle.network(win[:, :64], dict(cfg, n_nodes=64), *oracle.row_pairs([0], 64))  # load/warm
     t0 = time.perf_counter()
     oracle.network(win, cfg, pi, pj)
     dt = time.perf_counter() - t0
     B = oracle.band_bins(cfg["n_fft"], cfg["fs_hz"], cfg["f_lo_hz"], cfg["f_hi_hz"]).size
     return dict(value=pi.size * B / dt, unit="pair*freq*trial updates/s", cores=oracle.num_threads(),
                 kind="oracle",
-                sample=(f"plain FP64 recompute of one network over the W={W} window for {len(rows)} rows "
+                sample=(f"plain FP64 recompute of one network over the W={W} window for {len(rows)} evenly spaced rows "
                         f"({pi.size} pairs x {B} bins, spectra of all {N} nodes included), "
                         f"{dt:.2f} s; counts one pushed trial per pair and bin"))
 
@@ -333,7 +367,7 @@ def main():
     base = None
     if not args.no_cpu_baseline:
         print("[bench] oracle on host cores", file=sys.stderr, flush=True)
-        base = cpu_baseline(cfg, x_pool, rows=list(range(0, N, N // 16))[:16])
+        base = cpu_baseline(cfg, x_pool)
 
     out = {
         "metric": "pair*freq*trial updates/s (coh, wPLI) + p99 per-trial update latency",
