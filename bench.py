@@ -29,6 +29,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "pair_update_n5000_all8_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per pair-update launch from the committed rocprofv3 counter
+    record (FETCH_SIZE + WRITE_SIZE scaled by the copy-probe calibration),
+    or None when the record is missing or the kernel sources changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+        h = hashlib.sha256()
+        for p in rec["source_files"]:
+            h.update(open(os.path.join(ROOT, p), "rb").read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return rec["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def make_pool(n_trials: int, seed: int = 3):
@@ -389,7 +407,7 @@ def main():
                        "pushes": len(lat)},
         "kernels": kt,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(),
                      "kernel": "pair_update", "algorithmic_bytes_per_launch": algo},
         "hbm_copy_probe": probe,
         "sessions": sessions,
