@@ -301,6 +301,8 @@ def main():
                     help="size of the HBM copy probe (read + write), 0 to skip")
     ap.add_argument("--batch-reps", type=int, default=2, help="batch passes per Gram precision, 0 to skip")
     ap.add_argument("--serving-seconds", type=float, default=5.0, help="serving-mix arrival window, 0 to skip")
+    ap.add_argument("--large-steps", type=int, default=5,
+                    help="timed pushes of the 10000-node multitaper session, 0 to skip")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the update shards by pair "
@@ -377,6 +379,29 @@ def main():
                                gram_tflops=gram_flops / (pms * 1e-3) / 1e12 if pms else None,
                                cor_tflops=cor_flops / (cms * 1e-3) / 1e12 if cms else None)
 
+    large = None
+    if args.large_steps > 0:
+        print("[bench] 10000-node multitaper session", file=sys.stderr, flush=True)
+        del pool_dev
+        torch.cuda.empty_cache()
+        xl, cl = synth.c5_multitaper(n_trials=16)
+        pool_l = torch.from_numpy(xl).cuda()
+        del xl
+        wl, kl, _ = run_session(fcx, torch, cl, pool_l, args.large_steps, 1)
+        Nl = cl["n_nodes"]
+        Pl = Nl * (Nl - 1) // 2
+        Bl = fcx.band_bins(cl)[0]
+        pl = kl.get("pair_update", {})
+        gl = fcx.pair_update_bytes(cl) / (pl["avg_ms"] * 1e-3) / 1e9 if pl else None
+        large = dict(workload="N=10000 (50M pairs), DPSS NW=2 x 3 tapers, 4-40 Hz (37 bins), W=200 x 1000 "
+                              "samples, all 8 metrics, one push per step",
+                     value=Pl * Bl * args.large_steps / wl, ms_per_step=wl * 1e3 / args.large_steps,
+                     pair_update_avg_ms=pl.get("avg_ms"), pair_update_gbs=gl,
+                     hbm_frac=(gl / HBM_PEAK_GBS) if gl else None,
+                     footprint_gb=fcx.footprint_bytes(cl) / 1e9)
+        del pool_l
+        torch.cuda.empty_cache()
+
     serving = None
     if args.serving_seconds > 0:
         print("[bench] serving mix", file=sys.stderr, flush=True)
@@ -412,6 +437,7 @@ def main():
         "hbm_copy_probe": probe,
         "sessions": sessions,
         "batch": batch,
+        "large_multitaper": large,
         "serving": serving,
         "cpu_baseline": base,
     }

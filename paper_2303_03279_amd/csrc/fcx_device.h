@@ -44,4 +44,16 @@ template <> __device__ __forceinline__ double ratio_t<double>(double num, double
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  This bijection on [0, n) gives the workgroups of one XCD a contiguous
+// run of work items, so neighbouring items (slices of one tile, tiles of one
+// row) share that XCD's L2.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_item(int b, int n)
+{
+    const int q = n / NUM_XCD, rem = n % NUM_XCD;
+    const int x = b % NUM_XCD, r = b / NUM_XCD;
+    return x * q + min(x, rem) + r;
+}
+
 }  // namespace fcx

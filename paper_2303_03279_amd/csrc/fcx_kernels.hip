@@ -590,7 +590,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_update(SessDev<T> s, int 
 {
     extern __shared__ __align__(16) char lds[];
     if (s.ctl->bad) return;
-    pair_item<T>(s, blockIdx.x, s.ctl->pushed, CB, lds);
+    pair_item<T>(s, xcd_item(blockIdx.x, gridDim.x), s.ctl->pushed, CB, lds);
 }
 
 template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStream_t st)

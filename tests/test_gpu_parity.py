@@ -291,3 +291,23 @@ def test_device_input_equals_host_input(fcx):
     assert np.array_equal(out.cpu().numpy(), a.read("coh")[1])
     a.close()
     b.close()
+
+
+def test_long_run_no_drift(fcx, c2):
+    """3000 pushes (30 full window turnovers): the running sums still match
+    the plain recompute of the final window, i.e. add/remove does not drift
+    (FP64 sums, exact fixed-point phasor and integer sign sums)."""
+    import torch
+    x, cfg = c2
+    W, M = cfg["window_trials"], cfg["n_samples"]
+    xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    torch.cuda.synchronize()
+    T = 3000
+    order = [(7 * k) % x.shape[0] for k in range(T)]
+    s = fcx.Session(cfg)
+    for k in order:
+        fcx.check(s.push_device(xd[k].data_ptr(), M))
+    fcx.check(s.sync())
+    ref = oracle.network(oracle.as_device_input(x[order[T - W:]], cfg), cfg)
+    compare_network(s, ref, cfg, ALL, label="after 3000 pushes")
+    s.close()
