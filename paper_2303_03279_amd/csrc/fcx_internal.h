@@ -107,8 +107,9 @@ hipError_t launch_cor_batch(const SessDev<float> &s, int K, int prec, hipStream_
 
 // bin-chunk size of the pair kernel for a given (B, L, element size), and the
 // LDS it needs
-__host__ __device__ int pair_chunk_bins(int B, int L, int elem_bytes);
-__host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes);
+__host__ __device__ int pair_node_bytes(int L, int elem_bytes, uint32_t metrics);
+__host__ __device__ int pair_chunk_bins(int B, int L, int elem_bytes, uint32_t metrics);
+__host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes, uint32_t metrics);
 
 // batched launches of the serving path (float sessions); items are
 // (session index, a, b, 0) with a/b the block coordinates of the kernel

@@ -208,18 +208,24 @@ template <typename T> hipError_t launch_psd(const SessDev<T> &s, hipStream_t st)
 // (u_fixed), so that adding and later removing a trial's phasor cancels
 // exactly; sign sums in int8 when W <= 127, else int16.
 // ---------------------------------------------------------------------------
-__host__ __device__ int pair_chunk_bins(int B, int L, int elem_bytes)
+// LDS per staged node and bin: new and evicted spectra (all tapers), their
+// unit phasors (single taper with PLV) and 1/sqrt(P) (COH, IMCOH)
+__host__ __device__ int pair_node_bytes(int L, int elem_bytes, uint32_t metrics)
 {
-    const int per_node_bin = 2 * L * 2 * elem_bytes + (L == 1 ? 2 * 2 * elem_bytes : 0) + 8;
-    int cb = PAIR_LDS_BYTES / (PAIR_NODES * per_node_bin);
+    return 2 * L * 2 * elem_bytes + ((L == 1 && (metrics & M_PLV)) ? 2 * 2 * elem_bytes : 0) +
+           ((metrics & (M_COH | M_IMCOH)) ? 8 : 0);
+}
+
+__host__ __device__ int pair_chunk_bins(int B, int L, int elem_bytes, uint32_t metrics)
+{
+    int cb = PAIR_LDS_BYTES / (PAIR_NODES * pair_node_bytes(L, elem_bytes, metrics));
     if (cb < 1) cb = 1;
     return cb < B ? cb : B;
 }
 
-__host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes)
+__host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes, uint32_t metrics)
 {
-    const int per_node_bin = 2 * L * 2 * elem_bytes + (L == 1 ? 2 * 2 * elem_bytes : 0) + 8;
-    return (size_t)CB * PAIR_NODES * per_node_bin;
+    return (size_t)CB * PAIR_NODES * pair_node_bytes(L, elem_bytes, metrics);
 }
 
 // COR part of a slice: r_ij(trial) = z_i . z_j for the new and the evicted
@@ -297,7 +303,10 @@ struct PairState {
     int uqr, uqi, g;
 };
 
-template <typename T, bool ONE_CHUNK>
+// SPEC != 0 fixes the spectral metric set at compile time (the branches on
+// it fold away); LT = 1 fixes a single taper.  SPEC = 0, LT = 0 is the
+// general kernel.
+template <typename T, bool ONE_CHUNK, uint32_t SPEC, int LT>
 __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item, long long tp, int CB, char *lds)
 {
     typedef typename V2<T>::t T2;
@@ -308,13 +317,13 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
     const int2 tt = s.tiles[tile];
     const int I0 = tt.x * TILE, J0 = tt.y * TILE;
     const int R0 = I0 + SLICE_ROWS * sub;
-    const int N = s.N, B = s.B, L = s.L;
+    const int N = s.N, B = s.B, L = LT ? LT : s.L;
     if (R0 >= N || R0 >= min(J0 + TILE - 1, N - 1)) return;   // no pair i < j < N in this slice
     const PushView pv = push_view(s, tp);
     const bool has_old = pv.has_old;
     const int K = pv.K;
     const int slot_new = pv.slot_new, slot_old = pv.slot_old;
-    const uint32_t mm = s.metrics;
+    const uint32_t mm = SPEC ? SPEC : (s.metrics & 0x7Fu);   // spectral metrics
     const bool needSre = mm & M_COH;
     const bool needSim = mm & (M_COH | M_IMCOH | M_WPLI | M_DSWPLI);
     const bool needU = mm & M_PLV;
@@ -325,16 +334,19 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
     const float uscale = ldexpf(1.0f, s.ufix_bits);
     const double uinv = ldexp(1.0, -s.ufix_bits);
     const T2 *ring = (const T2 *)s.ring;
-    double *__restrict__ pSre = (double *)s.plane[P_SRE];
-    double *__restrict__ pSim = (double *)s.plane[P_SIM];
-    double *__restrict__ pUre = (double *)s.plane[P_URE];
-    double *__restrict__ pUim = (double *)s.plane[P_UIM];
-    int *__restrict__ qUre = (int *)s.plane[P_URE];
-    int *__restrict__ qUim = (int *)s.plane[P_UIM];
-    double *__restrict__ pA = (double *)s.plane[P_A];
-    double *__restrict__ pQ = (double *)s.plane[P_Q];
-    short *__restrict__ pG16 = (short *)s.gsum;
-    signed char *__restrict__ pG8 = (signed char *)s.gsum;
+    // Per-workgroup base of this tile in every plane (uniform); pair slots
+    // are then addressed by 32-bit byte offsets within the tile.
+    const size_t tb = (size_t)tile * B * TILE_PAIRS;
+    const int usz = ufix ? 4 : 8, gsz = g8 ? 1 : 2;
+    char *__restrict__ bSre = needSre ? (char *)s.plane[P_SRE] + tb * 8 : nullptr;
+    char *__restrict__ bSim = needSim ? (char *)s.plane[P_SIM] + tb * 8 : nullptr;
+    char *__restrict__ bUre = needU ? (char *)s.plane[P_URE] + tb * usz : nullptr;
+    char *__restrict__ bUim = needU ? (char *)s.plane[P_UIM] + tb * usz : nullptr;
+    char *__restrict__ bA = needA ? (char *)s.plane[P_A] + tb * 8 : nullptr;
+    char *__restrict__ bQ = needQ ? (char *)s.plane[P_Q] + tb * 8 : nullptr;
+    char *__restrict__ bG = needG ? (char *)s.gsum + tb * gsz : nullptr;
+#define D8(base, le) (*(double *)((base) + (le) * 8u))
+#define I4(base, le) (*(int *)((base) + (le) * 4u))
 
     const T Kt = (T)K;
     const T invK = (T)(1.0 / (double)K);
@@ -342,26 +354,28 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
     const T uinvT = (T)uinv;
     const size_t P = (size_t)N * (N - 1) / 2;
 
-    if (mm & M_COR) cor_block(s, pv, tile, sub, J0, R0, w);
-    if (!(mm & 0x7Fu)) return;   // COR-only session: no spectral sums
+    if (s.metrics & M_COR) cor_block(s, pv, tile, sub, J0, R0, w);
+    if (!mm) return;   // COR-only session: no spectral sums
 
+    // LDS layout as sized by pair_node_bytes
+    const bool stageU = L == 1 && needU;
     T2 *Xn = (T2 *)lds;
     T2 *Xo = Xn + (size_t)CB * L * PAIR_NODES;
     T2 *Un = Xo + (size_t)CB * L * PAIR_NODES;
-    T2 *Uo = Un + (L == 1 ? (size_t)CB * PAIR_NODES : 0);
-    double *SR = (double *)(Uo + (L == 1 ? (size_t)CB * PAIR_NODES : 0));
+    T2 *Uo = Un + (stageU ? (size_t)CB * PAIR_NODES : 0);
+    double *SR = (double *)(Uo + (stageU ? (size_t)CB * PAIR_NODES : 0));
 
-    auto load_state = [&](size_t e) {
+    auto load_state = [&](uint32_t e) {
         PairState st;
-        st.sre = needSre ? pSre[e] : 0.0;
-        st.sim = needSim ? pSim[e] : 0.0;
-        st.ure = (needU && !ufix) ? pUre[e] : 0.0;
-        st.uim = (needU && !ufix) ? pUim[e] : 0.0;
-        st.uqr = (needU && ufix) ? qUre[e] : 0;
-        st.uqi = (needU && ufix) ? qUim[e] : 0;
-        st.a = needA ? pA[e] : 0.0;
-        st.q = needQ ? pQ[e] : 0.0;
-        st.g = needG ? (g8 ? (int)pG8[e] : (int)pG16[e]) : 0;
+        st.sre = needSre ? D8(bSre, e) : 0.0;
+        st.sim = needSim ? D8(bSim, e) : 0.0;
+        st.ure = (needU && !ufix) ? D8(bUre, e) : 0.0;
+        st.uim = (needU && !ufix) ? D8(bUim, e) : 0.0;
+        st.uqr = (needU && ufix) ? I4(bUre, e) : 0;
+        st.uqi = (needU && ufix) ? I4(bUim, e) : 0;
+        st.a = needA ? D8(bA, e) : 0.0;
+        st.q = needQ ? D8(bQ, e) : 0.0;
+        st.g = needG ? (g8 ? (int)*(signed char *)(bG + e) : (int)*(short *)(bG + e * 2u)) : 0;
         return st;
     };
 
@@ -382,7 +396,7 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
             }
             Xn[(size_t)bl * PAIR_NODES + nl] = xn;
             Xo[(size_t)bl * PAIR_NODES + nl] = xo;
-            if (L == 1 && needU) {
+            if (stageU) {
                 // unit phasor X / |X| (0 for X = 0); the magnitude is formed
                 // in FP64 so that tiny amplitudes cannot underflow
                 T2 un, uo;
@@ -418,13 +432,17 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
             const int rt = SLICE_ROWS * sub + r;     // row within the tile
             const int i = R0 + r, j = J0 + c;
             if (!(i < j && j < N)) continue;
+            const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+            // band sums accumulate in bin order; a later bin chunk resumes the
+            // partial sum the previous chunk stored, so the result does not
+            // depend on how the band is split into chunks
             T acc[7];
 #pragma unroll
-            for (int m = 0; m < 7; ++m) acc[m] = 0;
-            const size_t e0 = (((size_t)tile * B + b0) * TILE + rt) * TILE + c;
+            for (int m = 0; m < 7; ++m) acc[m] = (!ONE_CHUNK && ci > 0 && (mm & (1u << m))) ? s.out[(size_t)m * P + idx] : (T)0;
+            const uint32_t e0 = (uint32_t)((b0 * TILE + rt) * TILE + c);   // slot within the tile
             PairState cur = load_state(e0);
             for (int bb = 0; bb < nb; ++bb) {
-                const size_t e = e0 + (size_t)bb * TILE_PAIRS;
+                const uint32_t e = e0 + (uint32_t)bb * TILE_PAIRS;
                 // software pipelining: the next bin's sums are in flight
                 // while this bin is computed
                 PairState nxt = cur;
@@ -461,12 +479,12 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                 if (needSre) {
                     st.sre = st.sre + cnr;
                     if (has_old) st.sre = st.sre - cor_;
-                    pSre[e] = st.sre;
+                    D8(bSre, e) = st.sre;
                 }
                 if (needSim) {
                     st.sim = st.sim + cni;
                     if (has_old) st.sim = st.sim - coi;
-                    pSim[e] = st.sim;
+                    D8(bSim, e) = st.sim;
                 }
                 double ure = 0.0, uim = 0.0;
                 if (needU) {
@@ -474,14 +492,18 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                     if (L == 1) {
                         const T2 ui = Un[(size_t)bb * PAIR_NODES + r];
                         const T2 uj = Un[(size_t)bb * PAIR_NODES + SLICE_ROWS + c];
-                        unr = (double)(T)(ui.x * uj.x + ui.y * uj.y);
-                        uni = (double)(T)(ui.y * uj.x - ui.x * uj.y);
+                        const T nr = ui.x * uj.x + ui.y * uj.y, ni = ui.y * uj.x - ui.x * uj.y;
+                        T orr = 0, oi = 0;
                         if (has_old) {
                             const T2 vi = Uo[(size_t)bb * PAIR_NODES + r];
                             const T2 vj = Uo[(size_t)bb * PAIR_NODES + SLICE_ROWS + c];
-                            uor = (double)(T)(vi.x * vj.x + vi.y * vj.y);
-                            uoi = (double)(T)(vi.y * vj.x - vi.x * vj.y);
+                            orr = vi.x * vj.x + vi.y * vj.y;
+                            oi = vi.y * vj.x - vi.x * vj.y;
                         }
+                        unr = nr;
+                        uni = ni;
+                        uor = orr;
+                        uoi = oi;
                     } else {
                         const double mn = sqrt(cnr * cnr + cni * cni);
                         unr = mn > 0.0 ? cnr / mn : 0.0;
@@ -501,8 +523,8 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                             st.uqr -= (int)rintf((float)uor * uscale);
                             st.uqi -= (int)rintf((float)uoi * uscale);
                         }
-                        qUre[e] = st.uqr;
-                        qUim[e] = st.uqi;
+                        I4(bUre, e) = st.uqr;
+                        I4(bUim, e) = st.uqi;
                     } else {
                         st.ure = st.ure + unr;
                         st.uim = st.uim + uni;
@@ -510,8 +532,8 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                             st.ure = st.ure - uor;
                             st.uim = st.uim - uoi;
                         }
-                        pUre[e] = st.ure;
-                        pUim[e] = st.uim;
+                        D8(bUre, e) = st.ure;
+                        D8(bUim, e) = st.uim;
                         ure = st.ure;
                         uim = st.uim;
                     }
@@ -520,19 +542,19 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                     st.g = st.g + sgn_of(cni);
                     if (has_old) st.g -= sgn_of(coi);
                     if (g8)
-                        pG8[e] = (signed char)st.g;
+                        *(signed char *)(bG + e) = (signed char)st.g;
                     else
-                        pG16[e] = (short)st.g;
+                        *(short *)(bG + e * 2u) = (short)st.g;
                 }
                 if (needA) {
                     st.a = st.a + fabs(cni);
                     if (has_old) st.a = st.a - fabs(coi);
-                    pA[e] = st.a;
+                    D8(bA, e) = st.a;
                 }
                 if (needQ) {
                     st.q = st.q + cni * cni;
                     if (has_old) st.q = st.q - coi * coi;
-                    pQ[e] = st.q;
+                    D8(bQ, e) = st.q;
                 }
                 // metrics of this bin, into the band mean
                 if (mm & (M_COH | M_IMCOH)) {
@@ -558,47 +580,50 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                 }
                 cur = nxt;
             }
-            const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
 #pragma unroll
             for (int m = 0; m < 7; ++m) {
                 if (!(mm & (1u << m))) continue;
-                T *o = s.out + (size_t)m * P + idx;
-                if (ONE_CHUNK) {
-                    *o = acc[m] / (T)B;
-                } else {
-                    T v = ci == 0 ? acc[m] : *o + acc[m];
-                    if (last_chunk) v = v / (T)B;
-                    *o = v;
-                }
+                s.out[(size_t)m * P + idx] = (ONE_CHUNK || last_chunk) ? acc[m] / (T)B : acc[m];
             }
         }
         __syncthreads();
     }
 }
 
-template <typename T>
+template <typename T, uint32_t SPEC, int LT>
 __device__ __forceinline__ void pair_item(const SessDev<T> &s, int item, long long tp, int CB, char *lds)
 {
     if (CB >= s.B)
-        pair_slice_update<T, true>(s, item, tp, CB, lds);
+        pair_slice_update<T, true, SPEC, LT>(s, item, tp, CB, lds);
     else
-        pair_slice_update<T, false>(s, item, tp, CB, lds);
+        pair_slice_update<T, false, SPEC, LT>(s, item, tp, CB, lds);
 }
 
-template <typename T>
+template <typename T, uint32_t SPEC, int LT>
 __global__ __launch_bounds__(PAIR_THREADS) void k_pair_update(SessDev<T> s, int CB)
 {
     extern __shared__ __align__(16) char lds[];
     if (s.ctl->bad) return;
-    pair_item<T>(s, xcd_item(blockIdx.x, gridDim.x), s.ctl->pushed, CB, lds);
+    pair_item<T, SPEC, LT>(s, xcd_item(blockIdx.x, gridDim.x), s.ctl->pushed, CB, lds);
 }
 
 template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStream_t st)
 {
-    const int CB = pair_chunk_bins(s.B, s.L, (int)sizeof(T));
-    const bool spectral = (s.metrics & 0x7Fu) != 0;
-    const size_t lds = spectral ? pair_lds_bytes(CB, s.L, (int)sizeof(T)) : 0;
-    hipLaunchKernelGGL(k_pair_update<T>, dim3(s.ntiles * SLICES), dim3(PAIR_THREADS), lds, st, s, CB);
+    const uint32_t spec = s.metrics & 0x7Fu;
+    const int CB = pair_chunk_bins(s.B, s.L, (int)sizeof(T), spec);
+    const size_t lds = spec ? pair_lds_bytes(CB, s.L, (int)sizeof(T), spec) : 0;
+    const dim3 grid(s.ntiles * SLICES), blk(PAIR_THREADS);
+    // compile-time metric sets for the common sessions, the general kernel otherwise
+    if (sizeof(T) == 4 && s.L == 1 && spec == 0x7Fu)
+        hipLaunchKernelGGL((k_pair_update<T, 0x7Fu, 1>), grid, blk, lds, st, s, CB);
+    else if (sizeof(T) == 4 && s.L == 1 && spec == M_COH)
+        hipLaunchKernelGGL((k_pair_update<T, M_COH, 1>), grid, blk, lds, st, s, CB);
+    else if (sizeof(T) == 4 && s.L == 1 && spec == M_WPLI)
+        hipLaunchKernelGGL((k_pair_update<T, M_WPLI, 1>), grid, blk, lds, st, s, CB);
+    else if (sizeof(T) == 4 && spec == 0x7Fu)
+        hipLaunchKernelGGL((k_pair_update<T, 0x7Fu, 0>), grid, blk, lds, st, s, CB);
+    else
+        hipLaunchKernelGGL((k_pair_update<T, 0u, 0>), grid, blk, lds, st, s, CB);
     return hipGetLastError();
 }
 
@@ -754,7 +779,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void kb_pair_update(const SessDev<flo
         const int4 w = items[it];
         const SessDev<float> &s = S[w.x];
         if (s.ctl->bad) continue;
-        pair_item<float>(s, w.y, s.ctl->pushed, pair_chunk_bins(s.B, s.L, 4), lds);
+        pair_item<float, 0u, 0>(s, w.y, s.ctl->pushed, pair_chunk_bins(s.B, s.L, 4, s.metrics & 0x7Fu), lds);
         __syncthreads();
     }
 }

@@ -121,7 +121,8 @@ static hipError_t run_tick(Server *sv, Tick &tk)
         if (spectral) {
             n_sp += (size_t)((g.N + 15) / 16) * ((g.B * g.L + 15) / 16);
             n_psd += (size_t)(g.B * g.N + 255) / 256;
-            const size_t l = pair_lds_bytes(pair_chunk_bins(g.B, g.L, 4), g.L, 4);
+            const uint32_t sm = sb.s->cfg.metrics & 0x7Fu;
+            const size_t l = pair_lds_bytes(pair_chunk_bins(g.B, g.L, 4, sm), g.L, 4, sm);
             if (l > lds) lds = l;
         }
         if (sb.s->cfg.metrics & M_COR) n_zn += (size_t)(g.N + 3) / 4;
