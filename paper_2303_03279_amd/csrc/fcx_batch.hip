@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_psd_batch(SessDev<float> s, int K)
 }
 
 // ---------------------------------------------------------------- pairs
-template <int PREC>
+template <int PREC, int LT>
 __global__ __launch_bounds__(BT_THREADS) void k_pair_batch(SessDev<float> s, int K)
 {
     __shared__ float2 Xs[64 * BT_LD];
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_pair_batch(SessDev<float> s, int
     const int tile = blockIdx.x >> 2, qd = blockIdx.x & 3;
     const int2 tt = s.tiles[tile];
     const int R0 = tt.x * TILE + 32 * (qd >> 1), C0 = tt.y * TILE + 32 * (qd & 1);
-    const int N = s.N, B = s.B, L = s.L;
+    const int N = s.N, B = s.B, L = LT ? LT : s.L;
     if (R0 >= N || R0 >= min(C0 + 31, N - 1)) return;   // no pair i < j < N here
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
     const int wr = w >> 1, wc = w & 1;
@@ -191,6 +191,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_pair_batch(SessDev<float> s, int
             if (mfmaU) Gram<PREC>::chunk(Us, arow, bcol, lg, ure, uim);
             // per-trial sums of this lane's four pairs (FP32, no contraction)
             float Ap[4] = {0.f, 0.f, 0.f, 0.f}, Qp[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
             for (int t = 0; t < nk; ++t) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -205,10 +206,11 @@ __global__ __launch_bounds__(BT_THREADS) void k_pair_batch(SessDev<float> s, int
                     Ap[k] += fabsf(ci);
                     Qp[k] += ci * ci;
                     if (needU && L > 1) {
-                        const double m = sqrt((double)cr * cr + (double)ci * ci);
-                        if (m > 0.0) {
-                            VUr[k] += cr / m;
-                            VUi[k] += ci / m;
+                        const double m2 = (double)cr * cr + (double)ci * ci;
+                        if (m2 > 0.0) {
+                            const double rm = rsqrt(m2);
+                            VUr[k] += cr * rm;
+                            VUi[k] += ci * rm;
                         }
                     }
                 }
@@ -400,16 +402,22 @@ hipError_t launch_psd_batch(const SessDev<float> &s, int K, hipStream_t st)
     return hipGetLastError();
 }
 
+template <int LT> static void launch_pair_batch_l(const SessDev<float> &s, int K, int prec, hipStream_t st)
+{
+    const dim3 grid(s.ntiles * 4), blk(BT_THREADS);
+    switch (prec) {
+    case FCX_GRAM_BF16_ID: hipLaunchKernelGGL((k_pair_batch<FCX_GRAM_BF16_ID, LT>), grid, blk, 0, st, s, K); break;
+    case FCX_GRAM_BF16X3_ID: hipLaunchKernelGGL((k_pair_batch<FCX_GRAM_BF16X3_ID, LT>), grid, blk, 0, st, s, K); break;
+    default: hipLaunchKernelGGL((k_pair_batch<FCX_GRAM_FP32_ID, LT>), grid, blk, 0, st, s, K); break;
+    }
+}
+
 hipError_t launch_pair_batch(const SessDev<float> &s, int K, int prec, hipStream_t st)
 {
-    const dim3 grid(s.ntiles * 4);
-    switch (prec) {
-    case FCX_GRAM_BF16_ID: hipLaunchKernelGGL(k_pair_batch<FCX_GRAM_BF16_ID>, grid, dim3(BT_THREADS), 0, st, s, K); break;
-    case FCX_GRAM_BF16X3_ID:
-        hipLaunchKernelGGL(k_pair_batch<FCX_GRAM_BF16X3_ID>, grid, dim3(BT_THREADS), 0, st, s, K);
-        break;
-    default: hipLaunchKernelGGL(k_pair_batch<FCX_GRAM_FP32_ID>, grid, dim3(BT_THREADS), 0, st, s, K); break;
-    }
+    if (s.L == 1)
+        launch_pair_batch_l<1>(s, K, prec, st);
+    else
+        launch_pair_batch_l<0>(s, K, prec, st);
     return hipGetLastError();
 }
 

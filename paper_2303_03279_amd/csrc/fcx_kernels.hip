@@ -505,13 +505,16 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                         uor = orr;
                         uoi = oi;
                     } else {
-                        const double mn = sqrt(cnr * cnr + cni * cni);
-                        unr = mn > 0.0 ? cnr / mn : 0.0;
-                        uni = mn > 0.0 ? cni / mn : 0.0;
+                        // unit phasor of the taper-combined CSD (0 for 0)
+                        const double m2n = cnr * cnr + cni * cni;
+                        const double rn = m2n > 0.0 ? rsqrt(m2n) : 0.0;
+                        unr = cnr * rn;
+                        uni = cni * rn;
                         if (has_old) {
-                            const double mo = sqrt(cor_ * cor_ + coi * coi);
-                            uor = mo > 0.0 ? cor_ / mo : 0.0;
-                            uoi = mo > 0.0 ? coi / mo : 0.0;
+                            const double m2o = cor_ * cor_ + coi * coi;
+                            const double ro = m2o > 0.0 ? rsqrt(m2o) : 0.0;
+                            uor = cor_ * ro;
+                            uoi = coi * ro;
                         }
                     }
                     if (ufix) {
