@@ -301,6 +301,8 @@ def main():
                     help="size of the HBM copy probe (read + write), 0 to skip")
     ap.add_argument("--batch-reps", type=int, default=2, help="batch passes per Gram precision, 0 to skip")
     ap.add_argument("--serving-seconds", type=float, default=5.0, help="serving-mix arrival window, 0 to skip")
+    ap.add_argument("--sensor-pushes", type=int, default=300,
+                    help="latency pushes of the 306-sensor session (host input), 0 to skip")
     ap.add_argument("--large-steps", type=int, default=5,
                     help="timed pushes of the 10000-node multitaper session, 0 to skip")
     args = ap.parse_args()
@@ -379,6 +381,36 @@ def main():
                                gram_tflops=gram_flops / (pms * 1e-3) / 1e12 if pms else None,
                                cor_tflops=cor_flops / (cms * 1e-3) / 1e12 if cms else None)
 
+    sensor = None
+    if args.sensor_pushes > 0:
+        # sensor-space session: 306 channels, W=100 trials of 600 samples, 1024-point
+        # FFT, 8-30 Hz (23 bins), all 8 metrics; trials pushed from host memory
+        print("[bench] sensor-space session", file=sys.stderr, flush=True)
+        xs, cs = synth.c2_sensor(n_trials=64)
+        xs = np.ascontiguousarray(xs, dtype=np.float32)
+        ss = fcx.Session(cs)
+        for k in range(cs["window_trials"]):
+            fcx.check(ss.push_host(xs[k % 64]))
+        fcx.check(ss.sync())
+        lat = []
+        for k in range(args.sensor_pushes):
+            t1 = time.perf_counter()
+            fcx.check(ss.push_host(xs[k % 64]))
+            fcx.check(ss.sync())
+            lat.append(time.perf_counter() - t1)
+        t0 = time.perf_counter()
+        for k in range(args.sensor_pushes):
+            fcx.check(ss.push_host(xs[k % 64]))
+        fcx.check(ss.sync())
+        ws = (time.perf_counter() - t0) / args.sensor_pushes
+        ss.close()
+        Ps = cs["n_nodes"] * (cs["n_nodes"] - 1) // 2
+        sensor = dict(workload="N=306 sensors, W=100 x 600 samples, F=1024, 8-30 Hz (23 bins), all 8 metrics, "
+                               "host-resident trials (PCIe upload included)",
+                      p50_ms=float(np.percentile(np.array(lat) * 1e3, 50)),
+                      p99_ms=float(np.percentile(np.array(lat) * 1e3, 99)),
+                      pipelined_ms_per_push=ws * 1e3, updates_per_s=Ps * 23 / ws)
+
     large = None
     if args.large_steps > 0:
         print("[bench] 10000-node multitaper session", file=sys.stderr, flush=True)
@@ -438,6 +470,7 @@ def main():
         "sessions": sessions,
         "batch": batch,
         "large_multitaper": large,
+        "sensor_space": sensor,
         "serving": serving,
         "cpu_baseline": base,
     }

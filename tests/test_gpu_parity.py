@@ -187,13 +187,14 @@ def test_edge_shapes(fcx, N, W, T):
     s.close()
 
 
-def test_multitaper_dpss(fcx):
+@pytest.mark.parametrize("k", [3, 1])
+def test_multitaper_dpss(fcx, k):
     rng = np.random.default_rng(5)
     N, M, W, T = 40, 200, 8, 13
     x = rng.standard_normal((T, N, M))
     x[:, 1, 4:] += 0.9 * x[:, 0, :-4]
     cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=W, n_fft=256, f_lo_hz=4, f_hi_hz=120,
-                            taper="dpss", dpss_nw=2.0, dpss_k=3, metrics=synth.ALL8)
+                            taper="dpss", dpss_nw=2.0, dpss_k=k, metrics=synth.ALL8)
     s = run_pushes(fcx, cfg, x)
     ref = oracle.network(oracle.as_device_input(x[T - W:], cfg), cfg)
     compare_network(s, ref, cfg, ALL, label="dpss L=3")
@@ -285,10 +286,15 @@ def test_device_input_equals_host_input(fcx):
     fcx.check(b.sync())
     for m in ALL:
         assert np.array_equal(a.read(m)[1], b.read(m)[1]), m
-    # device output buffer
+    # device output buffers, band mean and per bin
     out = torch.empty(b.P, dtype=torch.float32, device="cuda")
     fcx.check(b.read_device("coh", out.data_ptr(), b.P))
     assert np.array_equal(out.cpu().numpy(), a.read("coh")[1])
+    outb = torch.empty(b.B * b.P, dtype=torch.float32, device="cuda")
+    fcx.check(b.read_device("wpli", outb.data_ptr(), b.B * b.P, per_bin=True))
+    assert np.array_equal(outb.cpu().numpy().reshape(b.B, b.P), a.read("wpli", per_bin=True)[1])
+    # too small an output buffer is rejected
+    assert b.read_device("coh", out.data_ptr(), b.P - 1) == fcx.FCX_E_INVAL
     a.close()
     b.close()
 
