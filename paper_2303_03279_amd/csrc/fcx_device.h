@@ -15,6 +15,50 @@ template <> struct V2<double> { typedef double2 t; };
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Raw buffer access (vector memory instructions through a buffer resource):
+// a uniform base and byte range in scalar registers, a 32-bit per-lane byte
+// offset.  An offset outside the range reads 0 and drops the store.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int RSRC_WORD3 = 0x00020000;   // untyped 32-bit data, gfx9 family
+
+__device__ __forceinline__ Rsrc tile_rsrc(void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, RSRC_WORD3);
+}
+__device__ __forceinline__ double buf_ld_f64(Rsrc r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st_f64(Rsrc r, uint32_t off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ int buf_ld_i32(Rsrc r, uint32_t off)
+{
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st_i32(Rsrc r, uint32_t off, int v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, r, off, 0, 0);
+}
+__device__ __forceinline__ int buf_ld_i8(Rsrc r, uint32_t off)
+{
+    return (int)(signed char)__builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st_i8(Rsrc r, uint32_t off, int v)
+{
+    __builtin_amdgcn_raw_buffer_store_b8((unsigned char)v, r, off, 0, 0);
+}
+__device__ __forceinline__ int buf_ld_i16(Rsrc r, uint32_t off)
+{
+    return (int)(short)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st_i16(Rsrc r, uint32_t off, int v)
+{
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, off, 0, 0);
+}
+
 __device__ __forceinline__ int sgn_of(double v) { return (v > 0.0) - (v < 0.0); }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -23,22 +67,30 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Finalisation arithmetic of a metric in [-1, 1] (or [0, 1]) in the
+// session's precision.  FP32 uses the hardware square root and reciprocal
+// (about 1 ulp, far inside the 1e-5 metric tolerance) instead of the
+// correctly rounded library sequences; FP64 stays exact IEEE.
+template <typename T> __device__ __forceinline__ T sqrt_t(T v);
+template <> __device__ __forceinline__ float sqrt_t<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
+template <> __device__ __forceinline__ double sqrt_t<double>(double v) { return sqrt(v); }
+
 template <typename T> __device__ __forceinline__ T sqrt_ratio(double r);
-template <> __device__ __forceinline__ float sqrt_ratio<float>(double r) { return sqrtf((float)r); }
+template <> __device__ __forceinline__ float sqrt_ratio<float>(double r) { return __builtin_amdgcn_sqrtf((float)r); }
 template <> __device__ __forceinline__ double sqrt_ratio<double>(double r) { return sqrt(r); }
 
 __device__ __forceinline__ bool finite_v(float v) { return isfinite(v); }
 __device__ __forceinline__ bool finite_v(double v) { return isfinite(v); }
 
-// num / den for a metric in [-1, 1]: FP64 operands of any scale are brought
-// to den in [0.5, 1) by an exact power-of-two scaling, then divided in FP32
-// (the FP64 instantiation divides in FP64)
+// num / den: FP64 operands of any scale are brought to den in [0.5, 1) by an
+// exact power-of-two scaling, then the FP32 quotient is num * rcp(den) (the
+// FP64 instantiation divides in FP64)
 template <typename T> __device__ __forceinline__ T ratio_t(double num, double den);
 template <> __device__ __forceinline__ float ratio_t<float>(double num, double den)
 {
     int e;
     const double dm = frexp(den, &e);
-    return __fdividef((float)ldexp(num, -e), (float)dm);
+    return (float)ldexp(num, -e) * __builtin_amdgcn_rcpf((float)dm);
 }
 template <> __device__ __forceinline__ double ratio_t<double>(double num, double den) { return num / den; }
 

@@ -233,9 +233,16 @@ __host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes, uint32_
 // the slice's rows and columns 16w..16w+15 of the tile.  Lane l feeds row
 // (l & 15) of its block with the 4 consecutive samples 4*(l >> 4) .. +3 of
 // each 16-sample step (one float4 load; the same sample permutation on both
-// operands leaves every dot product unchanged); the next step's operands are
-// loaded before the current step's MFMAs issue.  The new and the evicted trial
-// are contracted separately so the evicted r is bit-identical to the r added.
+// operands leaves every dot product unchanged).  The operands of the next
+// COR_DEPTH steps are in flight while a step's MFMAs issue, so the chain of
+// dependent L2 round trips is COR_DEPTH times shorter than the step count.
+// The new and the evicted trial are contracted separately so the evicted r is
+// bit-identical to the r added.
+#ifndef FCX_COR_DEPTH
+#define FCX_COR_DEPTH 4
+#endif
+constexpr int COR_DEPTH = FCX_COR_DEPTH;
+
 template <typename T>
 __device__ __forceinline__ void cor_block(const SessDev<T> &s, const PushView &pv, int tile, int sub, int J0,
                                           int R0, int w)
@@ -250,36 +257,40 @@ __device__ __forceinline__ void cor_block(const SessDev<T> &s, const PushView &p
     const float4 *cn = (const float4 *)(s.zring + ((size_t)pv.slot_new * N + (cv ? col : 0)) * Mz) + lg;
     const float4 *ro = (const float4 *)(s.zring + ((size_t)pv.slot_old * N + (rv ? row : 0)) * Mz) + lg;
     const float4 *co = (const float4 *)(s.zring + ((size_t)pv.slot_old * N + (cv ? col : 0)) * Mz) + lg;
-    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
     floatx4 an = {0.f, 0.f, 0.f, 0.f}, ao = {0.f, 0.f, 0.f, 0.f};
     const int steps = Mz / 16;
-    float4 a = rv ? rn[0] : z4, b = cv ? cn[0] : z4;
-    float4 a2 = (old && rv) ? ro[0] : z4, b2 = (old && cv) ? co[0] : z4;
-    for (int st = 0; st < steps; ++st) {
-        float4 na = z4, nb = z4, na2 = z4, nb2 = z4;
-        if (st + 1 < steps) {
-            const int o = 4 * (st + 1);
-            if (rv) na = rn[o];
-            if (cv) nb = cn[o];
+    // Loads are unconditional: a lane past N reads row 0 of the slot (its
+    // pointer is clamped above), which only feeds output rows / columns that
+    // are never stored, and a step past the end re-reads the last step.
+    float4 a[COR_DEPTH], b[COR_DEPTH], a2[COR_DEPTH] = {}, b2[COR_DEPTH] = {};   // slot d: step st + d
+    auto fetch = [&](int d, int stp) {
+        const int o = 4 * min(stp, steps - 1);
+        a[d] = rn[o];
+        b[d] = cn[o];
+        if (old) {
+            a2[d] = ro[o];
+            b2[d] = co[o];
+        }
+    };
+#pragma unroll
+    for (int d = 0; d < COR_DEPTH; ++d) fetch(d, d);
+    for (int st = 0; st < steps; st += COR_DEPTH) {
+#pragma unroll
+        for (int d = 0; d < COR_DEPTH; ++d) {
+            if (st + d >= steps) break;
+            const float4 x = a[d], y = b[d], x2 = a2[d], y2 = b2[d];
+            fetch(d, st + d + COR_DEPTH);   // refill the slot with the step COR_DEPTH ahead
+            an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, y.x, an, 0, 0, 0);
+            an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, y.y, an, 0, 0, 0);
+            an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, y.z, an, 0, 0, 0);
+            an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, y.w, an, 0, 0, 0);
             if (old) {
-                if (rv) na2 = ro[o];
-                if (cv) nb2 = co[o];
+                ao = __builtin_amdgcn_mfma_f32_16x16x4f32(x2.x, y2.x, ao, 0, 0, 0);
+                ao = __builtin_amdgcn_mfma_f32_16x16x4f32(x2.y, y2.y, ao, 0, 0, 0);
+                ao = __builtin_amdgcn_mfma_f32_16x16x4f32(x2.z, y2.z, ao, 0, 0, 0);
+                ao = __builtin_amdgcn_mfma_f32_16x16x4f32(x2.w, y2.w, ao, 0, 0, 0);
             }
         }
-        an = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, an, 0, 0, 0);
-        an = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, an, 0, 0, 0);
-        an = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, an, 0, 0, 0);
-        an = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, an, 0, 0, 0);
-        if (old) {
-            ao = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.x, b2.x, ao, 0, 0, 0);
-            ao = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.y, b2.y, ao, 0, 0, 0);
-            ao = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.z, b2.z, ao, 0, 0, 0);
-            ao = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.w, b2.w, ao, 0, 0, 0);
-        }
-        a = na;
-        b = nb;
-        a2 = na2;
-        b2 = nb2;
     }
     const size_t P = (size_t)N * (N - 1) / 2;
 #pragma unroll
@@ -297,6 +308,13 @@ __device__ __forceinline__ void cor_block(const SessDev<T> &s, const PushView &p
     }
 }
 
+// Bins of a pair whose running-sum loads are issued together (1: the next
+// bin's loads are in flight while the current bin is computed).
+#ifndef FCX_BIN_GROUP
+#define FCX_BIN_GROUP 2
+#endif
+constexpr int BIN_GROUP = FCX_BIN_GROUP;
+
 // running sums of one (pair, bin) as held in the planes
 struct PairState {
     double sre, sim, ure, uim, a, q;
@@ -304,10 +322,11 @@ struct PairState {
 };
 
 // SPEC != 0 fixes the spectral metric set at compile time (the branches on
-// it fold away); LT = 1 fixes a single taper.  SPEC = 0, LT = 0 is the
-// general kernel.
-template <typename T, bool ONE_CHUNK, uint32_t SPEC, int LT>
-__device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item, long long tp, int CB, char *lds)
+// it fold away); LT = 1 fixes a single taper; COR = 1 / 0 compiles the COR
+// part in / out (-1: decided by the session's metric bits).  SPEC = 0, LT = 0,
+// COR = -1 is the general kernel.  The COR part runs after the spectral sums.
+template <typename T, uint32_t SPEC, int LT, int COR, int UG, bool OLD>
+__device__ __forceinline__ void pair_slice_body(const SessDev<T> &s, const PushView &pv, int item, int CB, char *lds)
 {
     typedef typename V2<T>::t T2;
     const int tile = item / SLICES, sub = item % SLICES;
@@ -318,9 +337,7 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
     const int I0 = tt.x * TILE, J0 = tt.y * TILE;
     const int R0 = I0 + SLICE_ROWS * sub;
     const int N = s.N, B = s.B, L = LT ? LT : s.L;
-    if (R0 >= N || R0 >= min(J0 + TILE - 1, N - 1)) return;   // no pair i < j < N in this slice
-    const PushView pv = push_view(s, tp);
-    const bool has_old = pv.has_old;
+    constexpr bool has_old = OLD;
     const int K = pv.K;
     const int slot_new = pv.slot_new, slot_old = pv.slot_old;
     const uint32_t mm = SPEC ? SPEC : (s.metrics & 0x7Fu);   // spectral metrics
@@ -330,23 +347,28 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
     const bool needG = mm & (M_PLI | M_USPLI);
     const bool needA = mm & (M_WPLI | M_DSWPLI);
     const bool needQ = mm & M_DSWPLI;
-    const bool ufix = s.u_fixed != 0, g8 = s.g_narrow != 0;
+    const bool ufix = UG >= 0 ? (UG & 1) != 0 : s.u_fixed != 0;
+    const bool g8 = UG >= 0 ? (UG & 2) != 0 : s.g_narrow != 0;
     const float uscale = ldexpf(1.0f, s.ufix_bits);
     const double uinv = ldexp(1.0, -s.ufix_bits);
     const T2 *ring = (const T2 *)s.ring;
-    // Per-workgroup base of this tile in every plane (uniform); pair slots
-    // are then addressed by 32-bit byte offsets within the tile.
+    // Per-workgroup buffer resources over this tile of every plane (uniform
+    // base, range = the tile); pair slots are addressed by 32-bit byte
+    // offsets within the tile, so no per-lane 64-bit address arithmetic.
     const size_t tb = (size_t)tile * B * TILE_PAIRS;
     const int usz = ufix ? 4 : 8, gsz = g8 ? 1 : 2;
-    char *__restrict__ bSre = needSre ? (char *)s.plane[P_SRE] + tb * 8 : nullptr;
-    char *__restrict__ bSim = needSim ? (char *)s.plane[P_SIM] + tb * 8 : nullptr;
-    char *__restrict__ bUre = needU ? (char *)s.plane[P_URE] + tb * usz : nullptr;
-    char *__restrict__ bUim = needU ? (char *)s.plane[P_UIM] + tb * usz : nullptr;
-    char *__restrict__ bA = needA ? (char *)s.plane[P_A] + tb * 8 : nullptr;
-    char *__restrict__ bQ = needQ ? (char *)s.plane[P_Q] + tb * 8 : nullptr;
-    char *__restrict__ bG = needG ? (char *)s.gsum + tb * gsz : nullptr;
-#define D8(base, le) (*(double *)((base) + (le) * 8u))
-#define I4(base, le) (*(int *)((base) + (le) * 4u))
+    const uint32_t tpairs = (uint32_t)B * TILE_PAIRS;
+    // a plane the metric set does not use gets an empty range
+    auto plane_rsrc = [&](bool need, void *plane, int esz) {
+        return tile_rsrc(need ? (char *)plane + tb * esz : nullptr, need ? tpairs * (uint32_t)esz : 0u);
+    };
+    const Rsrc rSre = plane_rsrc(needSre, s.plane[P_SRE], 8);
+    const Rsrc rSim = plane_rsrc(needSim, s.plane[P_SIM], 8);
+    const Rsrc rUre = plane_rsrc(needU, s.plane[P_URE], usz);
+    const Rsrc rUim = plane_rsrc(needU, s.plane[P_UIM], usz);
+    const Rsrc rA = plane_rsrc(needA, s.plane[P_A], 8);
+    const Rsrc rQ = plane_rsrc(needQ, s.plane[P_Q], 8);
+    const Rsrc rG = plane_rsrc(needG, s.gsum, gsz);
 
     const T Kt = (T)K;
     const T invK = (T)(1.0 / (double)K);
@@ -354,8 +376,11 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
     const T uinvT = (T)uinv;
     const size_t P = (size_t)N * (N - 1) / 2;
 
-    if (s.metrics & M_COR) cor_block(s, pv, tile, sub, J0, R0, w);
-    if (!mm) return;   // COR-only session: no spectral sums
+    const bool with_cor = COR > 0 || (COR < 0 && (s.metrics & M_COR));
+    if (!mm) {   // COR-only session: no spectral sums
+        if (with_cor) cor_block(s, pv, tile, sub, J0, R0, w);
+        return;
+    }
 
     // LDS layout as sized by pair_node_bytes
     const bool stageU = L == 1 && needU;
@@ -367,15 +392,15 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
 
     auto load_state = [&](uint32_t e) {
         PairState st;
-        st.sre = needSre ? D8(bSre, e) : 0.0;
-        st.sim = needSim ? D8(bSim, e) : 0.0;
-        st.ure = (needU && !ufix) ? D8(bUre, e) : 0.0;
-        st.uim = (needU && !ufix) ? D8(bUim, e) : 0.0;
-        st.uqr = (needU && ufix) ? I4(bUre, e) : 0;
-        st.uqi = (needU && ufix) ? I4(bUim, e) : 0;
-        st.a = needA ? D8(bA, e) : 0.0;
-        st.q = needQ ? D8(bQ, e) : 0.0;
-        st.g = needG ? (g8 ? (int)*(signed char *)(bG + e) : (int)*(short *)(bG + e * 2u)) : 0;
+        st.sre = needSre ? buf_ld_f64(rSre, e * 8u) : 0.0;
+        st.sim = needSim ? buf_ld_f64(rSim, e * 8u) : 0.0;
+        st.ure = (needU && !ufix) ? buf_ld_f64(rUre, e * 8u) : 0.0;
+        st.uim = (needU && !ufix) ? buf_ld_f64(rUim, e * 8u) : 0.0;
+        st.uqr = (needU && ufix) ? buf_ld_i32(rUre, e * 4u) : 0;
+        st.uqi = (needU && ufix) ? buf_ld_i32(rUim, e * 4u) : 0;
+        st.a = needA ? buf_ld_f64(rA, e * 8u) : 0.0;
+        st.q = needQ ? buf_ld_f64(rQ, e * 8u) : 0.0;
+        st.g = needG ? (g8 ? buf_ld_i8(rG, e) : buf_ld_i16(rG, e * 2u)) : 0;
         return st;
     };
 
@@ -438,16 +463,12 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
             // depend on how the band is split into chunks
             T acc[7];
 #pragma unroll
-            for (int m = 0; m < 7; ++m) acc[m] = (!ONE_CHUNK && ci > 0 && (mm & (1u << m))) ? s.out[(size_t)m * P + idx] : (T)0;
+            for (int m = 0; m < 7; ++m) acc[m] = (ci > 0 && (mm & (1u << m))) ? s.out[(size_t)m * P + idx] : (T)0;
             const uint32_t e0 = (uint32_t)((b0 * TILE + rt) * TILE + c);   // slot within the tile
-            PairState cur = load_state(e0);
-            for (int bb = 0; bb < nb; ++bb) {
+            // one bin of the pair: update its running sums from the loaded
+            // state, store them, add the bin's metrics to the band sums
+            auto bin_step = [&](int bb, PairState st) {
                 const uint32_t e = e0 + (uint32_t)bb * TILE_PAIRS;
-                // software pipelining: the next bin's sums are in flight
-                // while this bin is computed
-                PairState nxt = cur;
-                if (bb + 1 < nb) nxt = load_state(e + TILE_PAIRS);
-
                 double cnr = 0.0, cni = 0.0, cor_ = 0.0, coi = 0.0;
                 for (int l = 0; l < L; ++l) {
                     const size_t ob = (size_t)(bb * L + l) * PAIR_NODES;
@@ -475,16 +496,15 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                         }
                     }
                 }
-                PairState st = cur;
                 if (needSre) {
                     st.sre = st.sre + cnr;
                     if (has_old) st.sre = st.sre - cor_;
-                    D8(bSre, e) = st.sre;
+                    buf_st_f64(rSre, e * 8u, st.sre);
                 }
                 if (needSim) {
                     st.sim = st.sim + cni;
                     if (has_old) st.sim = st.sim - coi;
-                    D8(bSim, e) = st.sim;
+                    buf_st_f64(rSim, e * 8u, st.sim);
                 }
                 double ure = 0.0, uim = 0.0;
                 if (needU) {
@@ -526,8 +546,8 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                             st.uqr -= (int)rintf((float)uor * uscale);
                             st.uqi -= (int)rintf((float)uoi * uscale);
                         }
-                        I4(bUre, e) = st.uqr;
-                        I4(bUim, e) = st.uqi;
+                        buf_st_i32(rUre, e * 4u, st.uqr);
+                        buf_st_i32(rUim, e * 4u, st.uqi);
                     } else {
                         st.ure = st.ure + unr;
                         st.uim = st.uim + uni;
@@ -535,8 +555,8 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                             st.ure = st.ure - uor;
                             st.uim = st.uim - uoi;
                         }
-                        D8(bUre, e) = st.ure;
-                        D8(bUim, e) = st.uim;
+                        buf_st_f64(rUre, e * 8u, st.ure);
+                        buf_st_f64(rUim, e * 8u, st.uim);
                         ure = st.ure;
                         uim = st.uim;
                     }
@@ -545,19 +565,19 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                     st.g = st.g + sgn_of(cni);
                     if (has_old) st.g -= sgn_of(coi);
                     if (g8)
-                        *(signed char *)(bG + e) = (signed char)st.g;
+                        buf_st_i8(rG, e, st.g);
                     else
-                        *(short *)(bG + e * 2u) = (short)st.g;
+                        buf_st_i16(rG, e * 2u, st.g);
                 }
                 if (needA) {
                     st.a = st.a + fabs(cni);
                     if (has_old) st.a = st.a - fabs(coi);
-                    D8(bA, e) = st.a;
+                    buf_st_f64(rA, e * 8u, st.a);
                 }
                 if (needQ) {
                     st.q = st.q + cni * cni;
                     if (has_old) st.q = st.q - coi * coi;
-                    D8(bQ, e) = st.q;
+                    buf_st_f64(rQ, e * 8u, st.q);
                 }
                 // metrics of this bin, into the band mean
                 if (mm & (M_COH | M_IMCOH)) {
@@ -569,7 +589,7 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                     // |U| <= K: safe in the session's precision
                     const T ur = ufix ? (T)st.uqr * uinvT : (T)ure;
                     const T ui = ufix ? (T)st.uqi * uinvT : (T)uim;
-                    acc[2] += sqrt(ur * ur + ui * ui) * invK;
+                    acc[2] += sqrt_t<T>(ur * ur + ui * ui) * invK;
                 }
                 if (mm & (M_PLI | M_USPLI)) {
                     const T pli = (T)abs(st.g) * invK;
@@ -581,33 +601,85 @@ __device__ __forceinline__ void pair_slice_update(const SessDev<T> &s, int item,
                     const double dd = st.a * st.a - st.q;
                     acc[6] += K >= 2 ? (dd != 0.0 ? ratio_t<T>(st.sim * st.sim - st.q, dd) : (T)0) : (T)NAN;
                 }
-                cur = nxt;
+            };
+            if constexpr (BIN_GROUP <= 1) {
+                // software pipelining: the next bin's sums are in flight
+                // while this bin is computed
+                PairState cur = load_state(e0);
+                for (int bb = 0; bb < nb; ++bb) {
+                    PairState nxt = cur;
+                    if (bb + 1 < nb) nxt = load_state(e0 + (uint32_t)(bb + 1) * TILE_PAIRS);
+                    bin_step(bb, cur);
+                    cur = nxt;
+                }
+            } else {
+                // groups of bins: all loads of a group are issued before its
+                // first bin is computed
+                for (int g0 = 0; g0 < nb; g0 += BIN_GROUP) {
+                    PairState st[BIN_GROUP];
+#pragma unroll
+                    for (int k = 0; k < BIN_GROUP; ++k)
+                        if (g0 + k < nb) st[k] = load_state(e0 + (uint32_t)(g0 + k) * TILE_PAIRS);
+#pragma unroll
+                    for (int k = 0; k < BIN_GROUP; ++k)
+                        if (g0 + k < nb) bin_step(g0 + k, st[k]);
+                }
             }
 #pragma unroll
             for (int m = 0; m < 7; ++m) {
                 if (!(mm & (1u << m))) continue;
-                s.out[(size_t)m * P + idx] = (ONE_CHUNK || last_chunk) ? acc[m] / (T)B : acc[m];
+                s.out[(size_t)m * P + idx] = last_chunk ? acc[m] / (T)B : acc[m];
             }
         }
         __syncthreads();
     }
+    if (with_cor) cor_block(s, pv, tile, sub, J0, R0, w);
 }
 
-template <typename T, uint32_t SPEC, int LT>
+// One slice of a pair tile: the evicting and the non-evicting push are
+// separate compile-time bodies (the choice is uniform across the launch).
+template <typename T, uint32_t SPEC, int LT, int COR, int UG>
 __device__ __forceinline__ void pair_item(const SessDev<T> &s, int item, long long tp, int CB, char *lds)
 {
-    if (CB >= s.B)
-        pair_slice_update<T, true, SPEC, LT>(s, item, tp, CB, lds);
+    const int tile = item / SLICES, sub = item % SLICES;
+    const int2 tt = s.tiles[tile];
+    const int R0 = tt.x * TILE + SLICE_ROWS * sub, J0 = tt.y * TILE;
+    if (R0 >= s.N || R0 >= min(J0 + TILE - 1, s.N - 1)) return;   // no pair i < j < N in this slice
+    const PushView pv = push_view(s, tp);
+    if (pv.has_old)
+        pair_slice_body<T, SPEC, LT, COR, UG, true>(s, pv, item, CB, lds);
     else
-        pair_slice_update<T, false, SPEC, LT>(s, item, tp, CB, lds);
+        pair_slice_body<T, SPEC, LT, COR, UG, false>(s, pv, item, CB, lds);
 }
 
-template <typename T, uint32_t SPEC, int LT>
+template <typename T, uint32_t SPEC, int LT, int COR, int UG>
 __global__ __launch_bounds__(PAIR_THREADS) void k_pair_update(SessDev<T> s, int CB)
 {
     extern __shared__ __align__(16) char lds[];
     if (s.ctl->bad) return;
-    pair_item<T, SPEC, LT>(s, xcd_item(blockIdx.x, gridDim.x), s.ctl->pushed, CB, lds);
+    pair_item<T, SPEC, LT, COR, UG>(s, xcd_item(blockIdx.x, gridDim.x), s.ctl->pushed, CB, lds);
+}
+
+// Kernel choice for a metric set: COR part in or out, and (FP32 sessions
+// with fixed-point phasor sums and 8-bit sign sums, the common case) the
+// storage widths fixed at compile time.
+template <typename T, uint32_t SPEC, int LT>
+static void launch_pair_spec(const SessDev<T> &s, dim3 grid, size_t lds, hipStream_t st, int CB)
+{
+    const bool cor = (s.metrics & M_COR) != 0;
+    if constexpr (sizeof(T) == 4) {
+        if (s.u_fixed && s.g_narrow) {
+            if (cor)
+                hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 1, 3>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
+            else
+                hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 0, 3>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
+            return;
+        }
+    }
+    if (cor)
+        hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 1, -1>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
+    else
+        hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 0, -1>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
 }
 
 template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStream_t st)
@@ -615,18 +687,18 @@ template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStre
     const uint32_t spec = s.metrics & 0x7Fu;
     const int CB = pair_chunk_bins(s.B, s.L, (int)sizeof(T), spec);
     const size_t lds = spec ? pair_lds_bytes(CB, s.L, (int)sizeof(T), spec) : 0;
-    const dim3 grid(s.ntiles * SLICES), blk(PAIR_THREADS);
+    const dim3 grid(s.ntiles * SLICES);
     // compile-time metric sets for the common sessions, the general kernel otherwise
     if (sizeof(T) == 4 && s.L == 1 && spec == 0x7Fu)
-        hipLaunchKernelGGL((k_pair_update<T, 0x7Fu, 1>), grid, blk, lds, st, s, CB);
+        launch_pair_spec<T, 0x7Fu, 1>(s, grid, lds, st, CB);
     else if (sizeof(T) == 4 && s.L == 1 && spec == M_COH)
-        hipLaunchKernelGGL((k_pair_update<T, M_COH, 1>), grid, blk, lds, st, s, CB);
+        launch_pair_spec<T, M_COH, 1>(s, grid, lds, st, CB);
     else if (sizeof(T) == 4 && s.L == 1 && spec == M_WPLI)
-        hipLaunchKernelGGL((k_pair_update<T, M_WPLI, 1>), grid, blk, lds, st, s, CB);
+        launch_pair_spec<T, M_WPLI, 1>(s, grid, lds, st, CB);
     else if (sizeof(T) == 4 && spec == 0x7Fu)
-        hipLaunchKernelGGL((k_pair_update<T, 0x7Fu, 0>), grid, blk, lds, st, s, CB);
+        launch_pair_spec<T, 0x7Fu, 0>(s, grid, lds, st, CB);
     else
-        hipLaunchKernelGGL((k_pair_update<T, 0u, 0>), grid, blk, lds, st, s, CB);
+        launch_pair_spec<T, 0u, 0>(s, grid, lds, st, CB);
     return hipGetLastError();
 }
 
@@ -782,7 +854,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void kb_pair_update(const SessDev<flo
         const int4 w = items[it];
         const SessDev<float> &s = S[w.x];
         if (s.ctl->bad) continue;
-        pair_item<float, 0u, 0>(s, w.y, s.ctl->pushed, pair_chunk_bins(s.B, s.L, 4, s.metrics & 0x7Fu), lds);
+        pair_item<float, 0u, 0, -1, -1>(s, w.y, s.ctl->pushed, pair_chunk_bins(s.B, s.L, 4, s.metrics & 0x7Fu), lds);
         __syncthreads();
     }
 }
