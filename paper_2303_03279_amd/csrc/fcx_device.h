@@ -22,9 +22,15 @@ typedef __amdgpu_buffer_rsrc_t Rsrc;
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 constexpr int RSRC_WORD3 = 0x00020000;   // untyped 32-bit data, gfx9 family
 
+// base and bytes must be uniform; they are read from the first lane so the
+// resource always lives in scalar registers
 __device__ __forceinline__ Rsrc tile_rsrc(void *base, uint32_t bytes)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, RSRC_WORD3);
+    const uint64_t a = (uint64_t)base;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    void *ub = (void *)(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), RSRC_WORD3);
 }
 __device__ __forceinline__ double buf_ld_f64(Rsrc r, uint32_t off)
 {
@@ -74,6 +80,13 @@ __device__ __forceinline__ double wave_sum(double v)
 template <typename T> __device__ __forceinline__ T sqrt_t(T v);
 template <> __device__ __forceinline__ float sqrt_t<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
 template <> __device__ __forceinline__ double sqrt_t<double>(double v) { return sqrt(v); }
+
+// 1/sqrt(x) of an FP64 x > 0 feeding an FP32 session's unit phasor: the
+// hardware estimate (no Newton step) is far finer than the phasor's FP32
+// rounding; FP64 sessions keep the refined library value.
+template <typename T> __device__ __forceinline__ double rsqrt_t(double x);
+template <> __device__ __forceinline__ double rsqrt_t<float>(double x) { return __builtin_amdgcn_rsq(x); }
+template <> __device__ __forceinline__ double rsqrt_t<double>(double x) { return rsqrt(x); }
 
 template <typename T> __device__ __forceinline__ T sqrt_ratio(double r);
 template <> __device__ __forceinline__ float sqrt_ratio<float>(double r) { return __builtin_amdgcn_sqrtf((float)r); }

@@ -322,7 +322,7 @@ struct PairState {
 };
 
 // SPEC != 0 fixes the spectral metric set at compile time (the branches on
-// it fold away); LT = 1 fixes a single taper; COR = 1 / 0 compiles the COR
+// it fold away); LT != 0 fixes the taper count; COR = 1 / 0 compiles the COR
 // part in / out (-1: decided by the session's metric bits).  SPEC = 0, LT = 0,
 // COR = -1 is the general kernel.  The COR part runs after the spectral sums.
 template <typename T, uint32_t SPEC, int LT, int COR, int UG, bool OLD>
@@ -527,12 +527,12 @@ __device__ __forceinline__ void pair_slice_body(const SessDev<T> &s, const PushV
                     } else {
                         // unit phasor of the taper-combined CSD (0 for 0)
                         const double m2n = cnr * cnr + cni * cni;
-                        const double rn = m2n > 0.0 ? rsqrt(m2n) : 0.0;
+                        const double rn = m2n > 0.0 ? rsqrt_t<T>(m2n) : 0.0;
                         unr = cnr * rn;
                         uni = cni * rn;
                         if (has_old) {
                             const double m2o = cor_ * cor_ + coi * coi;
-                            const double ro = m2o > 0.0 ? rsqrt(m2o) : 0.0;
+                            const double ro = m2o > 0.0 ? rsqrt_t<T>(m2o) : 0.0;
                             uor = cor_ * ro;
                             uoi = coi * ro;
                         }
@@ -660,6 +660,13 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_update(SessDev<T> s, int 
     pair_item<T, SPEC, LT, COR, UG>(s, xcd_item(blockIdx.x, gridDim.x), s.ctl->pushed, CB, lds);
 }
 
+#ifndef FCX_WIDE_G_KERNELS
+#define FCX_WIDE_G_KERNELS 1
+#endif
+#ifndef FCX_L3_KERNELS
+#define FCX_L3_KERNELS 1
+#endif
+
 // Kernel choice for a metric set: COR part in or out, and (FP32 sessions
 // with fixed-point phasor sums and 8-bit sign sums, the common case) the
 // storage widths fixed at compile time.
@@ -673,6 +680,13 @@ static void launch_pair_spec(const SessDev<T> &s, dim3 grid, size_t lds, hipStre
                 hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 1, 3>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
             else
                 hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 0, 3>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
+            return;
+        }
+        if (s.u_fixed && FCX_WIDE_G_KERNELS) {   // 128 <= W <= 256: 16-bit sign sums
+            if (cor)
+                hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 1, 1>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
+            else
+                hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 0, 1>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
             return;
         }
     }
@@ -695,6 +709,8 @@ template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStre
         launch_pair_spec<T, M_COH, 1>(s, grid, lds, st, CB);
     else if (sizeof(T) == 4 && s.L == 1 && spec == M_WPLI)
         launch_pair_spec<T, M_WPLI, 1>(s, grid, lds, st, CB);
+    else if (sizeof(T) == 4 && s.L == 3 && spec == 0x7Fu && FCX_L3_KERNELS)
+        launch_pair_spec<T, 0x7Fu, 3>(s, grid, lds, st, CB);
     else if (sizeof(T) == 4 && spec == 0x7Fu)
         launch_pair_spec<T, 0x7Fu, 0>(s, grid, lds, st, CB);
     else
