@@ -198,7 +198,9 @@ fcx_status fcx_probe_copy(void *dst, const void *src, int64_t n_bytes, void *hip
  *
  * A server owns an HBM budget.  fcx_server_open admits a session only if its
  * footprint fits what is left (FCX_E_BUSY otherwise; retry after another
- * session closes).  Submitted trials of all sessions are gathered by a
+ * session closes).  A served session's footprint is fcx_footprint_bytes plus
+ * one more N x M float32 input buffer (256-byte aligned): the uploads of one
+ * tick run on a copy stream while the previous tick computes.  Submitted trials of all sessions are gathered by a
  * server thread into ticks: one tick runs the spectra, power and pair-update
  * work of every session with pending trials as a few batched launches whose
  * workgroups drain a shared list of (session, tile) items, so sessions of

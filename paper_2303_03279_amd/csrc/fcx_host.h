@@ -59,6 +59,7 @@ struct Session {
     float *zring = nullptr;
     double *rsum = nullptr;
     void *xbuf = nullptr;
+    void *xbuf2 = nullptr;   // served sessions: input of the other tick buffer
     std::vector<void *> allocs;
 
     // pinned host staging for host-resident trials (two buffers, each

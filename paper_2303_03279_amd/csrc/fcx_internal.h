@@ -113,8 +113,15 @@ __host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes, uint32_
 
 // batched launches of the serving path (float sessions); items are
 // (session index, a, b, 0) with a/b the block coordinates of the kernel
-enum { FCX_B_SPECTRA = 0, FCX_B_ZNORM, FCX_B_PSD, FCX_B_PAIR, FCX_B_COMMIT };
+enum { FCX_B_SPECTRA = 0, FCX_B_ZNORM, FCX_B_PSD, FCX_B_COMMIT };
 hipError_t launch_batched(int which, const SessDev<float> *S, const int4 *items, int n, size_t lds,
                           hipStream_t st);
+
+// compile-time variant (class) of an FP32 session's pair update, and the
+// batched pair launch over items (session, tile slice) of sessions of one class
+constexpr int PAIR_CLASSES = 36;
+int pair_kernel_class(const SessDev<float> &s);
+hipError_t launch_batched_pair(int cls, const SessDev<float> *S, const int4 *items, int n, size_t lds,
+                               hipStream_t st);
 
 }  // namespace fcx

@@ -660,40 +660,66 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_update(SessDev<T> s, int 
     pair_item<T, SPEC, LT, COR, UG>(s, xcd_item(blockIdx.x, gridDim.x), s.ctl->pushed, CB, lds);
 }
 
-#ifndef FCX_WIDE_G_KERNELS
-#define FCX_WIDE_G_KERNELS 1
-#endif
-#ifndef FCX_L3_KERNELS
-#define FCX_L3_KERNELS 1
-#endif
+// Compile-time variants of the pair update.  An FP32 session maps to one
+// class: its metric set (all spectral metrics with one or three tapers, COH
+// only, WPLI only, all spectral metrics with any taper count, or any set),
+// COR in or out, and its storage widths (fixed-point phasor sums with 8- or
+// 16-bit sign sums, or decided at run time).  The single-session launch and
+// the batched serving launch use the same class, so a session's result does
+// not depend on the path that ran it.
+#define FCX_PAIR_SPECS(X) X(0, 0x7Fu, 1) X(1, M_COH, 1) X(2, M_WPLI, 1) X(3, 0x7Fu, 3) X(4, 0x7Fu, 0) X(5, 0u, 0)
 
-// Kernel choice for a metric set: COR part in or out, and (FP32 sessions
-// with fixed-point phasor sums and 8-bit sign sums, the common case) the
-// storage widths fixed at compile time.
-template <typename T, uint32_t SPEC, int LT>
-static void launch_pair_spec(const SessDev<T> &s, dim3 grid, size_t lds, hipStream_t st, int CB)
+template <uint32_t SPEC, int LT, int COR, int UG> struct PairVariant {
+    static constexpr uint32_t spec = SPEC;
+    static constexpr int lt = LT, cor = COR, ug = UG;
+};
+
+int pair_kernel_class(const SessDev<float> &s)
 {
-    const bool cor = (s.metrics & M_COR) != 0;
-    if constexpr (sizeof(T) == 4) {
-        if (s.u_fixed && s.g_narrow) {
-            if (cor)
-                hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 1, 3>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
-            else
-                hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 0, 3>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
-            return;
-        }
-        if (s.u_fixed && FCX_WIDE_G_KERNELS) {   // 128 <= W <= 256: 16-bit sign sums
-            if (cor)
-                hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 1, 1>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
-            else
-                hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 0, 1>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
-            return;
-        }
-    }
-    if (cor)
-        hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 1, -1>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
+    const uint32_t spec = s.metrics & 0x7Fu;
+    int si;
+    if (s.L == 1 && spec == 0x7Fu)
+        si = 0;
+    else if (s.L == 1 && spec == M_COH)
+        si = 1;
+    else if (s.L == 1 && spec == M_WPLI)
+        si = 2;
+    else if (s.L == 3 && spec == 0x7Fu)
+        si = 3;
+    else if (spec == 0x7Fu)
+        si = 4;
     else
-        hipLaunchKernelGGL((k_pair_update<T, SPEC, LT, 0, -1>), grid, dim3(PAIR_THREADS), lds, st, s, CB);
+        si = 5;
+    const int cor = (s.metrics & M_COR) ? 1 : 0;
+    const int ug = (s.u_fixed && s.g_narrow) ? 0 : (s.u_fixed ? 1 : 2);
+    return (si * 2 + cor) * 3 + ug;
+}
+
+// calls f(PairVariant<...>{}) for class cls; false for an unknown class
+template <typename F> static bool dispatch_pair_class(int cls, F &&f)
+{
+    if (cls < 0 || cls >= PAIR_CLASSES) return false;
+    const int ugi = cls % 3, cor = (cls / 3) % 2, si = cls / 6;
+#define FCX_UG(SPEC, LT, C)                       \
+    if (ugi == 0)                                 \
+        f(PairVariant<SPEC, LT, C, 3>{});         \
+    else if (ugi == 1)                            \
+        f(PairVariant<SPEC, LT, C, 1>{});         \
+    else                                          \
+        f(PairVariant<SPEC, LT, C, -1>{});
+#define FCX_SPEC(I, SPEC, LT)   \
+    if (si == I) {              \
+        if (cor) {              \
+            FCX_UG(SPEC, LT, 1) \
+        } else {                \
+            FCX_UG(SPEC, LT, 0) \
+        }                       \
+        return true;            \
+    }
+    FCX_PAIR_SPECS(FCX_SPEC)
+#undef FCX_SPEC
+#undef FCX_UG
+    return false;
 }
 
 template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStream_t st)
@@ -701,20 +727,19 @@ template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStre
     const uint32_t spec = s.metrics & 0x7Fu;
     const int CB = pair_chunk_bins(s.B, s.L, (int)sizeof(T), spec);
     const size_t lds = spec ? pair_lds_bytes(CB, s.L, (int)sizeof(T), spec) : 0;
-    const dim3 grid(s.ntiles * SLICES);
-    // compile-time metric sets for the common sessions, the general kernel otherwise
-    if (sizeof(T) == 4 && s.L == 1 && spec == 0x7Fu)
-        launch_pair_spec<T, 0x7Fu, 1>(s, grid, lds, st, CB);
-    else if (sizeof(T) == 4 && s.L == 1 && spec == M_COH)
-        launch_pair_spec<T, M_COH, 1>(s, grid, lds, st, CB);
-    else if (sizeof(T) == 4 && s.L == 1 && spec == M_WPLI)
-        launch_pair_spec<T, M_WPLI, 1>(s, grid, lds, st, CB);
-    else if (sizeof(T) == 4 && s.L == 3 && spec == 0x7Fu && FCX_L3_KERNELS)
-        launch_pair_spec<T, 0x7Fu, 3>(s, grid, lds, st, CB);
-    else if (sizeof(T) == 4 && spec == 0x7Fu)
-        launch_pair_spec<T, 0x7Fu, 0>(s, grid, lds, st, CB);
-    else
-        launch_pair_spec<T, 0u, 0>(s, grid, lds, st, CB);
+    const dim3 grid(s.ntiles * SLICES), blk(PAIR_THREADS);
+    if constexpr (sizeof(T) == 4) {
+        dispatch_pair_class(pair_kernel_class(s), [&](auto v) {
+            using V = decltype(v);
+            hipLaunchKernelGGL((k_pair_update<float, V::spec, V::lt, V::cor, V::ug>), grid, blk, lds, st, s, CB);
+        });
+    } else {
+        // FP64 sessions: the general kernel, COR in or out
+        if (s.metrics & M_COR)
+            hipLaunchKernelGGL((k_pair_update<T, 0u, 0, 1, -1>), grid, blk, lds, st, s, CB);
+        else
+            hipLaunchKernelGGL((k_pair_update<T, 0u, 0, 0, -1>), grid, blk, lds, st, s, CB);
+    }
     return hipGetLastError();
 }
 
@@ -863,6 +888,7 @@ __global__ __launch_bounds__(256) void kb_psd(const SessDev<float> *S, const int
     }
 }
 
+template <uint32_t SPEC, int LT, int COR, int UG>
 __global__ __launch_bounds__(PAIR_THREADS) void kb_pair_update(const SessDev<float> *S, const int4 *items, int n)
 {
     extern __shared__ __align__(16) char lds[];
@@ -870,7 +896,8 @@ __global__ __launch_bounds__(PAIR_THREADS) void kb_pair_update(const SessDev<flo
         const int4 w = items[it];
         const SessDev<float> &s = S[w.x];
         if (s.ctl->bad) continue;
-        pair_item<float, 0u, 0, -1, -1>(s, w.y, s.ctl->pushed, pair_chunk_bins(s.B, s.L, 4, s.metrics & 0x7Fu), lds);
+        pair_item<float, SPEC, LT, COR, UG>(s, w.y, s.ctl->pushed, pair_chunk_bins(s.B, s.L, 4, s.metrics & 0x7Fu),
+                                            lds);
         __syncthreads();
     }
 }
@@ -907,15 +934,24 @@ hipError_t launch_batched(int which, const SessDev<float> *S, const int4 *items,
     case FCX_B_PSD:
         hipLaunchKernelGGL(kb_psd, dim3(persistent_grid(n, 1 << 20)), dim3(256), 0, st, S, items, n);
         break;
-    case FCX_B_PAIR:
-        hipLaunchKernelGGL(kb_pair_update, dim3(persistent_grid(n, 1 << 20)), dim3(PAIR_THREADS), lds, st, S, items, n);
-        break;
     case FCX_B_COMMIT:
         hipLaunchKernelGGL(kb_commit, dim3((n + 63) / 64), dim3(64), 0, st, S, n);
         break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_batched_pair(int cls, const SessDev<float> *S, const int4 *items, int n, size_t lds,
+                               hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const bool ok = dispatch_pair_class(cls, [&](auto v) {
+        using V = decltype(v);
+        hipLaunchKernelGGL((kb_pair_update<V::spec, V::lt, V::cor, V::ug>), dim3(persistent_grid(n, 1 << 20)),
+                           dim3(PAIR_THREADS), lds, st, S, items, n);
+    });
+    return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

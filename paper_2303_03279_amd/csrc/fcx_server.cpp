@@ -19,6 +19,7 @@
 #include <map>
 #include <thread>
 #include <unordered_map>
+#include <vector>
 
 #include "fcx_host.h"
 
@@ -43,6 +44,7 @@ struct TickBuffers {
     SessDev<float> *h_desc = nullptr, *d_desc = nullptr;
     int4 *h_items = nullptr, *d_items = nullptr;
     size_t desc_cap = 0, item_cap = 0;
+    hipEvent_t uploaded = nullptr;   // inputs, descriptors and items of the tick are on the device
     hipEvent_t done = nullptr;
 };
 
@@ -54,7 +56,8 @@ struct Tick {
 struct Server {
     int64_t budget = 0, used = 0;
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;        // kernels
+    hipStream_t copy_stream = nullptr;   // host-to-device uploads, overlapping the previous tick
     std::mutex mu;
     std::condition_variable cv_work, cv_done, cv_slot;
     std::map<uint64_t, Session *> sessions;             // by id, for deterministic order
@@ -71,6 +74,13 @@ struct Server {
     std::multimap<size_t, void *> pinned_pool;
     std::thread builder, completer;
 };
+
+// device bytes a served session holds: the plain session plus a second
+// input buffer (uploads of one tick overlap the other tick's kernels)
+static int64_t served_footprint(const BufferPlan &p)
+{
+    return (int64_t)p.total() + (int64_t)p.xbuf;
+}
 
 static std::mutex g_srv_mu;
 static std::unordered_map<uint64_t, Server *> g_srv;
@@ -114,31 +124,45 @@ static hipError_t run_tick(Server *sv, Tick &tk)
     const int ns = (int)tk.subs.size();
     // item counts per kernel
     size_t n_sp = 0, n_zn = 0, n_psd = 0, n_pair = 0;
-    size_t lds = 0;
-    for (auto &sb : tk.subs) {
-        const Geometry &g = sb.s->g;
-        const bool spectral = (sb.s->cfg.metrics & 0x7Fu) != 0;
-        if (spectral) {
+    // pair items are grouped by the session's kernel class: one batched
+    // launch per class present, with that class's LDS
+    std::vector<int> cls(ns);
+    size_t cls_n[PAIR_CLASSES] = {}, cls_lds[PAIR_CLASSES] = {};
+    for (int k = 0; k < ns; ++k) {
+        Session *s = tk.subs[k].s;
+        const Geometry &g = s->g;
+        cls[k] = pair_kernel_class(session_dev<float>(s, s->xbuf, g.M));
+        const uint32_t sm = s->cfg.metrics & 0x7Fu;
+        if (sm) {
             n_sp += (size_t)((g.N + 15) / 16) * ((g.B * g.L + 15) / 16);
             n_psd += (size_t)(g.B * g.N + 255) / 256;
-            const uint32_t sm = sb.s->cfg.metrics & 0x7Fu;
             const size_t l = pair_lds_bytes(pair_chunk_bins(g.B, g.L, 4, sm), g.L, 4, sm);
-            if (l > lds) lds = l;
+            if (l > cls_lds[cls[k]]) cls_lds[cls[k]] = l;
         }
-        if (sb.s->cfg.metrics & M_COR) n_zn += (size_t)(g.N + 3) / 4;
-        n_pair += (size_t)g.ntiles * SLICES;  // spectral sums and COR blocks of every tile slice
+        if (s->cfg.metrics & M_COR) n_zn += (size_t)(g.N + 3) / 4;
+        const size_t np = (size_t)g.ntiles * SLICES;  // spectral sums and COR blocks of every tile slice
+        cls_n[cls[k]] += np;
+        n_pair += np;
     }
     const size_t n_items = n_sp + n_zn + n_psd + n_pair;
     hipError_t e = ensure_capacity(b, ns, n_items);
     if (e != hipSuccess) return e;
     int4 *it_sp = b.h_items, *it_zn = it_sp + n_sp, *it_psd = it_zn + n_zn, *it_pair = it_psd + n_psd;
-    size_t a = 0, z = 0, p = 0, q = 0;
+    size_t cls_off[PAIR_CLASSES + 1] = {};
+    for (int c = 0; c < PAIR_CLASSES; ++c) cls_off[c + 1] = cls_off[c] + cls_n[c];
+    size_t cls_fill[PAIR_CLASSES];
+    for (int c = 0; c < PAIR_CLASSES; ++c) cls_fill[c] = cls_off[c];
+    size_t a = 0, z = 0, p = 0;
     for (int k = 0; k < ns; ++k) {
         Session *s = tk.subs[k].s;
         const Geometry &g = s->g;
-        e = hipMemcpyAsync(s->xbuf, tk.subs[k].pinned, tk.subs[k].bytes, hipMemcpyHostToDevice, sv->stream);
+        // each tick buffer has its own device input per session; the last
+        // tick that used this buffer has finished, so the upload can run
+        // while the other buffer's tick computes
+        void *xb = tk.buf ? s->xbuf2 : s->xbuf;
+        e = hipMemcpyAsync(xb, tk.subs[k].pinned, tk.subs[k].bytes, hipMemcpyHostToDevice, sv->copy_stream);
         if (e != hipSuccess) return e;
-        b.h_desc[k] = session_dev<float>(s, s->xbuf, g.M);
+        b.h_desc[k] = session_dev<float>(s, xb, g.M);
         const bool spectral = (s->cfg.metrics & 0x7Fu) != 0;
         if (spectral) {
             for (int by = 0; by < (g.B * g.L + 15) / 16; ++by)
@@ -147,19 +171,25 @@ static hipError_t run_tick(Server *sv, Tick &tk)
         }
         if (s->cfg.metrics & M_COR)
             for (int bx = 0; bx < (g.N + 3) / 4; ++bx) it_zn[z++] = make_int4(k, bx, 0, 0);
-        for (int t = 0; t < g.ntiles * SLICES; ++t) it_pair[q++] = make_int4(k, t, 0, 0);
+        for (int t = 0; t < g.ntiles * SLICES; ++t) it_pair[cls_fill[cls[k]]++] = make_int4(k, t, 0, 0);
     }
-    if ((e = hipMemcpyAsync(b.d_desc, b.h_desc, ns * sizeof(SessDev<float>), hipMemcpyHostToDevice, sv->stream)) !=
-        hipSuccess)
+    if ((e = hipMemcpyAsync(b.d_desc, b.h_desc, ns * sizeof(SessDev<float>), hipMemcpyHostToDevice,
+                            sv->copy_stream)) != hipSuccess)
         return e;
-    if ((e = hipMemcpyAsync(b.d_items, b.h_items, n_items * sizeof(int4), hipMemcpyHostToDevice, sv->stream)) !=
-        hipSuccess)
+    if ((e = hipMemcpyAsync(b.d_items, b.h_items, n_items * sizeof(int4), hipMemcpyHostToDevice,
+                            sv->copy_stream)) != hipSuccess)
         return e;
+    if ((e = hipEventRecord(b.uploaded, sv->copy_stream)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(sv->stream, b.uploaded, 0)) != hipSuccess) return e;
     const int4 *d_sp = b.d_items, *d_zn = d_sp + n_sp, *d_psd = d_zn + n_zn, *d_pair = d_psd + n_psd;
     if ((e = launch_batched(FCX_B_SPECTRA, b.d_desc, d_sp, (int)n_sp, 0, sv->stream)) != hipSuccess) return e;
     if ((e = launch_batched(FCX_B_ZNORM, b.d_desc, d_zn, (int)n_zn, 0, sv->stream)) != hipSuccess) return e;
     if ((e = launch_batched(FCX_B_PSD, b.d_desc, d_psd, (int)n_psd, 0, sv->stream)) != hipSuccess) return e;
-    if ((e = launch_batched(FCX_B_PAIR, b.d_desc, d_pair, (int)n_pair, lds, sv->stream)) != hipSuccess) return e;
+    for (int c = 0; c < PAIR_CLASSES; ++c)
+        if (cls_n[c] &&
+            (e = launch_batched_pair(c, b.d_desc, d_pair + cls_off[c], (int)cls_n[c], cls_lds[c], sv->stream)) !=
+                hipSuccess)
+            return e;
     if ((e = launch_batched(FCX_B_COMMIT, b.d_desc, nullptr, ns, 0, sv->stream)) != hipSuccess) return e;
     return hipEventRecord(b.done, sv->stream);
 }
@@ -248,8 +278,15 @@ fcx_status fcx_server_create(int64_t hbm_budget_bytes, fcx_server **out)
         delete sv;
         return FCX_E_DEVICE;
     }
+    if (hipStreamCreateWithFlags(&sv->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(sv->stream);
+        delete sv;
+        return FCX_E_DEVICE;
+    }
     for (auto &b : sv->bufs)
-        if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) return FCX_E_DEVICE;
+        if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b.uploaded, hipEventDisableTiming) != hipSuccess)
+            return FCX_E_DEVICE;
     sv->builder = std::thread(builder_main, sv);
     sv->completer = std::thread(completer_main, sv);
     std::lock_guard<std::mutex> lk(g_srv_mu);
@@ -268,7 +305,7 @@ fcx_status fcx_server_open(fcx_server *h, const fcx_config *cfg, fcx_session **o
     fcx_status st = make_geometry(cfg, &g);
     if (st != FCX_OK) return st;
     if (g.f64) return FCX_E_INVAL;  // served sessions compute in float32
-    const int64_t fp = (int64_t)make_plan(*cfg, g).total();
+    const int64_t fp = served_footprint(make_plan(*cfg, g));
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         if (sv->used + fp > sv->budget) return FCX_E_BUSY;
@@ -288,6 +325,12 @@ fcx_status fcx_server_open(fcx_server *h, const fcx_config *cfg, fcx_session **o
     s->device = sv->device;
     s->server = sv;
     st = session_alloc(s);
+    if (st == FCX_OK) {
+        if (hipMalloc(&s->xbuf2, s->plan.xbuf) == hipSuccess)
+            s->allocs.push_back(s->xbuf2);
+        else
+            st = FCX_E_NOMEM;
+    }
     if (st != FCX_OK) {
         session_free(s);
         delete s;
@@ -394,7 +437,7 @@ fcx_status fcx_server_close_session(fcx_server *h, fcx_session *hs)
         sv->cv_slot.wait(lk, [&] { return session_idle(sv, s) || sv->failed; });
         sv->sessions.erase(s->id);
         sv->queues.erase(s);
-        sv->used -= (int64_t)s->plan.total();
+        sv->used -= served_footprint(s->plan);
     }
     s = unregister_session(hs, &st);
     if (!s) return st;
@@ -424,7 +467,8 @@ fcx_status fcx_server_destroy(fcx_server *h)
     }
     sv->builder.join();
     sv->completer.join();
-    hipStreamSynchronize(sv->stream);
+    (void)hipStreamSynchronize(sv->copy_stream);
+    (void)hipStreamSynchronize(sv->stream);
     std::vector<Session *> left;
     for (auto &kv : sv->sessions) left.push_back(kv.second);
     for (Session *s : left) {
@@ -439,9 +483,11 @@ fcx_status fcx_server_destroy(fcx_server *h)
         if (b.d_desc) hipFree(b.d_desc);
         if (b.h_items) hipHostFree(b.h_items);
         if (b.d_items) hipFree(b.d_items);
-        if (b.done) hipEventDestroy(b.done);
+        if (b.done) (void)hipEventDestroy(b.done);
+        if (b.uploaded) (void)hipEventDestroy(b.uploaded);
     }
-    hipStreamDestroy(sv->stream);
+    (void)hipStreamDestroy(sv->copy_stream);
+    (void)hipStreamDestroy(sv->stream);
     delete sv;
     return FCX_OK;
 }

@@ -82,10 +82,17 @@ def test_alone_equals_mix(fcx):
     fcx.check(srv.destroy())
 
 
+def _served_bytes(fcx, c):
+    # a served session holds the plain session's buffers plus a second
+    # device input buffer (N x M float32, 256-byte aligned)
+    xb = c["n_nodes"] * c["n_samples"] * 4
+    return fcx.footprint_bytes(c) + (xb + 255) // 256 * 256
+
+
 def test_admission_by_hbm_budget(fcx):
     c = synth.base_config(n_nodes=1000, n_samples=500, window_trials=40, n_fft=512, f_lo_hz=8, f_hi_hz=30,
                           metrics=synth.ALL8)
-    fp = fcx.footprint_bytes(c)
+    fp = _served_bytes(fcx, c)
     srv = fcx.Server(int(1.5 * fp))
     st, a = srv.open(c)
     fcx.check(st)
@@ -96,14 +103,14 @@ def test_admission_by_hbm_budget(fcx):
     small = dict(c, n_nodes=60)
     st, s2 = srv.open(small)
     fcx.check(st)                               # a smaller session still fits
-    assert srv.usage()[0] == fp + fcx.footprint_bytes(small)
+    assert srv.usage()[0] == fp + _served_bytes(fcx, small)
     x = synth.c4_trials(c, 5, 3).astype(np.float32)
     for k in range(3):
         srv.submit(a, np.ascontiguousarray(x[k]))
     fcx.check(a.close())                        # drains, then frees its memory
     st, b = srv.open(c)
     fcx.check(st)
-    assert srv.usage()[0] == fp + fcx.footprint_bytes(small)
+    assert srv.usage()[0] == fp + _served_bytes(fcx, small)
     fcx.check(b.close())
     fcx.check(s2.close())
     assert srv.usage()[0] == 0
