@@ -174,6 +174,9 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
     trials = [np.ascontiguousarray(synth.c4_trials(c, sd, pool_per_session), dtype=np.float32) for c, sd in sess]
     ts, ss = synth.c4_arrivals(np.random.default_rng(seed + 1), len(sess), duration_s)
     upd = [fcx.band_bins(c)[0] * c["n_nodes"] * (c["n_nodes"] - 1) // 2 for c, _ in sess]
+    # algorithmic HBM bytes of one push of each session (its pair update)
+    pbytes = [fcx.pair_update_bytes(c) for c, _ in sess]
+    offered = float(sum(pbytes[k] for k in ss))
     fp = sum(fcx.footprint_bytes(c) for c, _ in sess)
     out = {"sessions": len(sess), "arrivals": int(ts.size), "duration_s": duration_s, "footprint_gb": fp / 1e9}
 
@@ -202,7 +205,8 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
     comp.close()
     lat = np.array([d for d, _ in comp.done]) * 1e3
     out["plain"] = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                        updates_per_s=float(sum(upd[k] for k in ss) / wall_a), wall_s=wall_a)
+                        updates_per_s=float(sum(upd[k] for k in ss) / wall_a), wall_s=wall_a,
+                        hbm_frac=offered / wall_a / (HBM_PEAK_GBS * 1e9))
     for p in plain:
         p.close()
     torch.cuda.synchronize()
@@ -229,7 +233,8 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
     wall_b = time.perf_counter() - t0
     lat = np.array([srv.poll(t)[1] for t in tickets]) * 1e3
     out["server"] = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                         updates_per_s=float(sum(upd[k] for k in ss) / wall_b), wall_s=wall_b)
+                         updates_per_s=float(sum(upd[k] for k in ss) / wall_b), wall_s=wall_b,
+                         hbm_frac=offered / wall_b / (HBM_PEAK_GBS * 1e9))
     # (c) burst: every session submits `burst` trials at once; time to drain
     burst = 8
     t0 = time.perf_counter()
@@ -239,7 +244,8 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
     srv.drain()
     wall_c = time.perf_counter() - t0
     out["server_burst"] = dict(trials=burst * len(sess), wall_s=wall_c,
-                               updates_per_s=float(burst * sum(upd) / wall_c))
+                               updates_per_s=float(burst * sum(upd) / wall_c),
+                               hbm_frac=burst * sum(pbytes) / wall_c / (HBM_PEAK_GBS * 1e9))
     for h in served:
         h.close()
     srv.destroy()
@@ -257,7 +263,8 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
         fcx.check(p.sync())
     wall_d = time.perf_counter() - t0
     out["plain_burst"] = dict(trials=burst * len(sess), wall_s=wall_d,
-                              updates_per_s=float(burst * sum(upd) / wall_d))
+                              updates_per_s=float(burst * sum(upd) / wall_d),
+                              hbm_frac=burst * sum(pbytes) / wall_d / (HBM_PEAK_GBS * 1e9))
     for p in plain:
         p.close()
     return out
@@ -294,13 +301,15 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--pool", type=int, default=64, help="distinct trials resident in HBM")
-    ap.add_argument("--latency-pushes", type=int, default=300)
+    ap.add_argument("--latency-pushes", type=int, default=10000,
+                    help="pushes timed one by one (submit to device completion) for p50/p99")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-subsets", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=1024,
                     help="size of the HBM copy probe (read + write), 0 to skip")
     ap.add_argument("--batch-reps", type=int, default=2, help="batch passes per Gram precision, 0 to skip")
-    ap.add_argument("--serving-seconds", type=float, default=5.0, help="serving-mix arrival window, 0 to skip")
+    ap.add_argument("--serving-seconds", type=float, default=16.0,
+                    help="serving-mix arrival window (about 650 arrivals/s), 0 to skip")
     ap.add_argument("--sensor-pushes", type=int, default=300,
                     help="latency pushes of the 306-sensor session (host input), 0 to skip")
     ap.add_argument("--large-steps", type=int, default=5,

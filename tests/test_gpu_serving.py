@@ -32,12 +32,21 @@ def _mix_configs():
         synth.base_config(n_nodes=306, window_trials=12, metrics=synth.WPLI | synth.DSWPLI, **base),
         synth.base_config(n_nodes=200, window_trials=5, metrics=synth.COR, **base),
         synth.base_config(n_nodes=97, window_trials=3, metrics=synth.PLV | synth.IMCOH | synth.USPLI, **base),
+        # one session of each remaining compile-time kernel class: COH only,
+        # WPLI only, three DPSS tapers, 16-bit sign sums (W > 127) and
+        # FP64 phasor sums (W > 256)
+        synth.base_config(n_nodes=150, window_trials=20, metrics=synth.COH, **base),
+        synth.base_config(n_nodes=90, window_trials=8, metrics=synth.WPLI, **base),
+        synth.base_config(n_nodes=80, window_trials=6, metrics=synth.ALL8, taper="dpss", dpss_nw=2.0, dpss_k=3,
+                          **base),
+        synth.base_config(n_nodes=70, window_trials=140, metrics=synth.ALL8, **base),
+        synth.base_config(n_nodes=66, window_trials=300, metrics=synth.ALL8 & ~synth.COR, **base),
     ]
 
 
 def test_alone_equals_mix(fcx):
     cfgs = _mix_configs()
-    T = [14, 11, 16, 9, 8]
+    T = [14, 11, 16, 9, 8, 30, 12, 10, 150, 310]
     xs = [synth.c4_trials(c, 100 + k, T[k]).astype(np.float32) for k, c in enumerate(cfgs)]
     alone = []
     for c, x in zip(cfgs, xs):
@@ -72,11 +81,12 @@ def test_alone_equals_mix(fcx):
             st, out, K = sess[k].read(m)
             assert K == min(T[k], c["window_trials"])
             assert np.array_equal(out, ref, equal_nan=True), (k, m)
-    # and one of them against the oracle
-    c, x = cfgs[0], xs[0]
-    W = c["window_trials"]
-    ref = oracle.network(x[T[0] - W:].astype(np.float64), c)
-    compare_network(sess[0], ref, c, ALL, label="served N=60")
+    # and some of them against the oracle
+    for k in (0, 7, 8):
+        c, x = cfgs[k], xs[k]
+        W = c["window_trials"]
+        ref = oracle.network(oracle.as_device_input(x[T[k] - W:], c), c)
+        compare_network(sess[k], ref, c, ALL, label=f"served N={c['n_nodes']} W={W} L={c.get('dpss_k', 1)}")
     for ss in sess:
         fcx.check(ss.close())
     fcx.check(srv.destroy())
