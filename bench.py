@@ -270,6 +270,45 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
     return out
 
 
+def run_netsel(fcx, torch, cfg, pool_dev, reps, fraction=0.05):
+    """fcx_network_select on the COH network of a short 5000-node session:
+    HIP-event time per call on the calling stream, and its algorithmic HBM
+    bytes: the network is read once for the maximum, once per radix pass (4),
+    twice by the per-node pass (each edge from both ends) and once by the
+    final pass, which writes the normalised network and the flags:
+    P * (4 * 9 + 4 + 1) bytes."""
+    N, M = cfg["n_nodes"], cfg["n_samples"]
+    P = N * (N - 1) // 2
+    s = fcx.Session(dict(cfg, metrics=fcx.FCX_COH, window_trials=3))
+    for k in range(3):
+        fcx.check(s.push_device(pool_dev[k].data_ptr(), M))
+    w = torch.empty(P, dtype=torch.float32, device="cuda")
+    fcx.check(s.read_device("coh", w.data_ptr(), P))
+    s.close()
+    wn = torch.empty_like(w)
+    sel = torch.empty(P, dtype=torch.uint8, device="cuda")
+    deg = torch.empty(N, dtype=torch.int32, device="cuda")
+    st = torch.empty(N, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    args = (N, w.data_ptr(), fraction, wn.data_ptr(), sel.data_ptr(), deg.data_ptr(), st.data_ptr(),
+            stream.cuda_stream)
+    fcx.check(fcx.network_select(*args)[0])
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        status, info = fcx.network_select(*args)
+        e1.record(stream)
+        fcx.check(status)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    algo = P * (4 * 9 + 4 + 1)
+    return dict(workload=f"N={N} COH network (P={P}), strongest {fraction:.0%}", ms=ms,
+                algorithmic_bytes=algo, gbs=algo / (ms * 1e-3) / 1e9,
+                hbm_frac=algo / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), k=info["k"], n_selected=info["n_selected"])
+
+
 def cpu_baseline(cfg, x_pool, target_s=10.0):
     """The FP64 oracle on the host cores: one network of the window for a
     sample of rows, sized from a short probe to take about target_s."""
@@ -312,6 +351,8 @@ def main():
                     help="serving-mix arrival window (about 650 arrivals/s), 0 to skip")
     ap.add_argument("--sensor-pushes", type=int, default=300,
                     help="latency pushes of the 306-sensor session (host input), 0 to skip")
+    ap.add_argument("--netsel-reps", type=int, default=5,
+                    help="timed calls of the network post-processing on a 5000-node network, 0 to skip")
     ap.add_argument("--large-steps", type=int, default=5,
                     help="timed pushes of the 10000-node multitaper session, 0 to skip")
     args = ap.parse_args()
@@ -420,6 +461,13 @@ def main():
                       p99_ms=float(np.percentile(np.array(lat) * 1e3, 99)),
                       pipelined_ms_per_push=ws * 1e3, updates_per_s=Ps * 23 / ws)
 
+    netsel = None
+    if args.netsel_reps > 0:
+        # display post-processing of a 5000-node network: max-edge normalisation,
+        # strongest 5% of the edges, node degree and strength
+        print("[bench] network post-processing", file=sys.stderr, flush=True)
+        netsel = run_netsel(fcx, torch, cfg, pool_dev, args.netsel_reps)
+
     large = None
     if args.large_steps > 0:
         print("[bench] 10000-node multitaper session", file=sys.stderr, flush=True)
@@ -480,6 +528,7 @@ def main():
         "batch": batch,
         "large_multitaper": large,
         "sensor_space": sensor,
+        "network_select": netsel,
         "serving": serving,
         "cpu_baseline": base,
     }

@@ -194,6 +194,45 @@ const char *fcx_status_str(fcx_status st);
 fcx_status fcx_probe_copy(void *dst, const void *src, int64_t n_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Network post-processing for display (results sections and the online
+ * pipeline: every network is normalised by its maximum edge weight, only the
+ * strongest fraction of its edges is drawn, and nodes are sized by their
+ * degree in that thresholded network).
+ *
+ * w is one packed upper-triangle FP32 network of n_nodes nodes (P =
+ * n(n-1)/2 edges, pair (i, j), i < j, at i(2n-i-1)/2 + j-i-1), e.g. the
+ * device output of fcx_read_network.  Over its finite edges E (USPLI and
+ * DSWPLI are NaN below two trials):
+ *   max_abs     = max |w_e|
+ *   w_norm_e    = w_e / max_abs  (FP32 division; 0 when max_abs = 0;
+ *                 non-finite edges copied)
+ *   k           = min(ceil(fraction * P), |E|)
+ *   threshold   = |w| of the k-th strongest edge (+inf when k = 0)
+ *   selected_e  = 1 iff e in E and |w_e| >= threshold (ties are all kept,
+ *                 so n_selected >= k; equal when the weights are distinct)
+ *   degree_i    = selected edges at node i
+ *   strength_i  = sum of |w_norm_e| over them (FP64 sum, stored as FP32)
+ * Strength is taken on |w| so that signed ImCoh keeps its strongest negative
+ * edges.  w, w_norm [P], selected [P] (bytes), degree and strength [n] are
+ * device pointers; any output may be NULL; w_norm may equal w (in place).
+ * The call enqueues its kernels on hip_stream (NULL: the default stream),
+ * waits for them and fills *info (may be NULL).  Errors: FCX_E_INVAL for
+ * n_nodes outside [2, 65536], a NULL w or a fraction outside [0, 1];
+ * FCX_E_NOMEM / FCX_E_DEVICE from HIP.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    float max_abs;
+    float threshold;
+    int64_t k;
+    int64_t n_finite;
+    int64_t n_selected;
+} fcx_select_info;
+
+fcx_status fcx_network_select(int32_t n_nodes, const float *w, double fraction, float *w_norm,
+                              uint8_t *selected, int32_t *degree, float *strength, fcx_select_info *info,
+                              void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Serving: many concurrent sessions, continuous batching.
  *
  * A server owns an HBM budget.  fcx_server_open admits a session only if its

@@ -62,6 +62,16 @@ class fcx_config(ctypes.Structure):
     ]
 
 
+class fcx_select_info(ctypes.Structure):
+    _fields_ = [
+        ("max_abs", ctypes.c_float),
+        ("threshold", ctypes.c_float),
+        ("k", ctypes.c_int64),
+        ("n_finite", ctypes.c_int64),
+        ("n_selected", ctypes.c_int64),
+    ]
+
+
 P = ctypes.c_void_p
 I32, I64, U32, U64, D = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
 PI32, PI64, PD, PU64 = (ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
@@ -88,6 +98,7 @@ _SIGS = {
     "fcx_dpss": (ctypes.c_int, [I32, D, I32, P, P]),
     "fcx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "fcx_probe_copy": (ctypes.c_int, [P, P, I64, P]),
+    "fcx_network_select": (ctypes.c_int, [I32, P, D, P, P, P, P, ctypes.POINTER(fcx_select_info), P]),
     "fcx_server_create": (ctypes.c_int, [I64, PP]),
     "fcx_server_open": (ctypes.c_int, [P, PCFG, PP]),
     "fcx_server_submit": (ctypes.c_int, [P, P, P, I64, PU64]),
@@ -117,6 +128,17 @@ def check(status: int, where: str = "fcx") -> int:
     if status != FCX_OK:
         raise FcxError(status, where)
     return status
+
+
+def network_select(n_nodes: int, w_ptr: int, fraction: float, w_norm_ptr: int = 0, selected_ptr: int = 0,
+                   degree_ptr: int = 0, strength_ptr: int = 0, stream: int = 0):
+    """fcx_network_select on device buffers (pointers as ints, 0 = not
+    wanted).  Returns (status, info dict)."""
+    info = fcx_select_info()
+    st = lib.fcx_network_select(int(n_nodes), w_ptr, float(fraction), w_norm_ptr or None, selected_ptr or None,
+                                degree_ptr or None, strength_ptr or None, ctypes.byref(info), stream or None)
+    return st, dict(max_abs=info.max_abs, threshold=info.threshold, k=info.k, n_finite=info.n_finite,
+                    n_selected=info.n_selected)
 
 
 def make_config(cfg: dict) -> fcx_config:

@@ -101,3 +101,16 @@ def test_host_dpss_matches_scipy(M, NW, K):
     ref, rref = sp_dpss(M, NW, K, return_ratios=True)
     assert np.allclose(tap, ref, atol=1e-9)
     assert np.allclose(rat, rref, atol=1e-9)
+
+
+def test_network_select_rejects_bad_arguments():
+    """Argument checks run before any device work (no GPU needed)."""
+    st, _ = fcx.network_select(1, 0x1000, 0.1)
+    assert st == fcx.FCX_E_INVAL
+    st, _ = fcx.network_select(10, 0, 0.1)          # NULL network
+    assert st == fcx.FCX_E_INVAL
+    for f in (-0.01, 1.5, float("nan")):
+        st, _ = fcx.network_select(10, 0x1000, f)
+        assert st == fcx.FCX_E_INVAL, f
+    st, _ = fcx.network_select(70000, 0x1000, 0.1)
+    assert st == fcx.FCX_E_INVAL
