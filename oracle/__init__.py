@@ -63,6 +63,8 @@ def _load():
         lib.orc_pairs.restype = None
         lib.orc_cor.argtypes = [P, I64, I64, I64, I64, P, P, I64, P]
         lib.orc_cor.restype = None
+        lib.orc_xcor.argtypes = [P, I64, I64, I64, I64, I64, P, P, I64, P, P]
+        lib.orc_xcor.restype = None
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -238,6 +240,23 @@ def cor(x: np.ndarray, pi, pj) -> np.ndarray:
     out = np.empty(a.size)
     lib.orc_cor(_ptr(x), K, N * M, M, M, _ptr(a), _ptr(b), a.size, _ptr(out))
     return out
+
+
+def xcor(x: np.ndarray, pi, pj, max_lag: int | None = None, with_lag: bool = False):
+    """Trial-averaged maximum cross-correlation of pairs (pi, pj) over the
+    lags -L..L (L = max_lag, default M-1); see orc_xcor.  x: [K][N][M].
+    with_lag: also the lag of the maximum in the last trial (positive: the
+    first node advanced against the second)."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    K, N, M = x.shape
+    L = M - 1 if max_lag is None else int(max_lag)
+    a = np.ascontiguousarray(pi, dtype=np.int32)
+    b = np.ascontiguousarray(pj, dtype=np.int32)
+    out = np.empty(a.size)
+    lag = np.empty(a.size, dtype=np.int32)
+    lib.orc_xcor(_ptr(x), K, N * M, M, M, L, _ptr(a), _ptr(b), a.size, _ptr(out), _ptr(lag))
+    return (out, lag) if with_lag else out
 
 
 def as_device_input(x: np.ndarray, cfg: dict) -> np.ndarray:

@@ -25,6 +25,8 @@
  *             DSWPLI = ((Im S)^2 - Q)/(A^2 - Q)   (debiased squared WPLI;
  *                       the printed "WPLI^2" is read as the debiased form)
  *   COR       mean over trials of the Pearson correlation (COR eq.)
+ *   XCOR      mean over trials of the largest cross-correlation over the
+ *             lags -L..L (XCOR eq., both directions; orc_xcor)
  *
  * Readings where the text is silent: sign(0) = 0; a metric whose denominator
  * is exactly zero is 0; the unit phasor of 0 is 0; USPLI and DSWPLI are NaN
@@ -229,6 +231,71 @@ void orc_cor(const double *x, int64_t K, int64_t trial_stride, int64_t node_stri
             acc += d > 0.0 ? sab / d : 0.0;
         }
         cor[p] = K > 0 ? acc / (double)K : 0.0;
+    }
+}
+
+/* Cross-correlation (XCOR) of the time-domain metrics section, maximised
+ * over the lags as the implementation section describes, averaged over the
+ * trials like COR.  For trial k, x = node pi, y = node pj, each centred by
+ * its mean over the M samples (x~, y~):
+ *   XCOR(tau)  = sum_{t<M-tau} x~(t+tau) y~(t)
+ *                / sqrt(sum_{t<M-tau} x~(t+tau)^2 * sum_{t<M} y~(t)^2),  tau = 0..L
+ *   XCOR(-tau) = the same with x and y exchanged                          tau = 1..L
+ * (0 where the denominator is 0).  The trial's value is the largest of the
+ * 2L+1 values; out = its mean over the K trials.  lag_last (optional) gets
+ * the lag of the largest value in the last trial (first such lag from -L). */
+void orc_xcor(const double *x, int64_t K, int64_t trial_stride, int64_t node_stride, int64_t M, int64_t L,
+              const int32_t *pi, const int32_t *pj, int64_t np, double *out, int32_t *lag_last)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t p = 0; p < np; ++p) {
+        double *xa = (double *)malloc((size_t)M * sizeof(double));
+        double *xb = (double *)malloc((size_t)M * sizeof(double));
+        double acc = 0.0;
+        int32_t best_lag = 0;
+        for (int64_t k = 0; k < K; ++k) {
+            const double *a = x + k * trial_stride + (int64_t)pi[p] * node_stride;
+            const double *b = x + k * trial_stride + (int64_t)pj[p] * node_stride;
+            double ma = 0.0, mb = 0.0;
+            for (int64_t n = 0; n < M; ++n) {
+                ma += a[n];
+                mb += b[n];
+            }
+            ma /= (double)M;
+            mb /= (double)M;
+            double ea = 0.0, eb = 0.0;
+            for (int64_t n = 0; n < M; ++n) {
+                xa[n] = a[n] - ma;
+                xb[n] = b[n] - mb;
+                ea += xa[n] * xa[n];
+                eb += xb[n] * xb[n];
+            }
+            double best = -INFINITY;
+            int32_t lag = 0;
+            for (int64_t s = -L; s <= L; ++s) {
+                /* s >= 0: x advanced by s against y; s < 0: y advanced by -s against x */
+                const double *u = s >= 0 ? xa : xb, *v = s >= 0 ? xb : xa;
+                const double ev = s >= 0 ? eb : ea;
+                const int64_t tau = s >= 0 ? s : -s;
+                double num = 0.0, eu = 0.0;
+                for (int64_t t = 0; t < M - tau; ++t) {
+                    num += u[t + tau] * v[t];
+                    eu += u[t + tau] * u[t + tau];
+                }
+                const double d = sqrt(eu * ev);
+                const double r = d > 0.0 ? num / d : 0.0;
+                if (r > best) {
+                    best = r;
+                    lag = (int32_t)s;
+                }
+            }
+            acc += best;
+            best_lag = lag;
+        }
+        out[p] = K > 0 ? acc / (double)K : 0.0;
+        if (lag_last) lag_last[p] = best_lag;
+        free(xa);
+        free(xb);
     }
 }
 

@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 import test_oracle_pins as pins
+import test_oracle_xcor as xpins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -29,6 +30,11 @@ MUTANTS = [
     ("cor_no_centering", "double da = a[n] - ma, db = b[n] - mb;", "double da = a[n], db = b[n];"),
     ("cor_sum_not_mean", "cor[p] = K > 0 ? acc / (double)K : 0.0;", "cor[p] = acc;"),
     ("taper_weight_ignored", "cre += lam[l] * (ar * br + ai * bi);", "cre += (ar * br + ai * bi);"),
+    ("xcor_one_direction", "for (int64_t s = -L; s <= L; ++s) {", "for (int64_t s = 0; s <= L; ++s) {"),
+    ("xcor_full_energy_of_advanced", "const double d = sqrt(eu * ev);", "const double d = sqrt((s >= 0 ? ea : eb) * ev);"),
+    ("xcor_no_centering", "xa[n] = a[n] - ma;", "xa[n] = a[n];"),
+    ("xcor_sum_not_mean", "out[p] = K > 0 ? acc / (double)K : 0.0;", "out[p] = acc;"),
+    ("xcor_min_not_max", "if (r > best) {", "if (-r > -best) {"),
 ]
 
 CHECKS = [
@@ -39,6 +45,9 @@ CHECKS = [
     pins.test_rank1_zero_lag_exact,
     pins.test_cor_matches_corrcoef,
     pins.test_swap_is_hermitian,
+    lambda: xpins.test_literal_formula(10, 9, 0),
+    xpins.test_closed_forms,
+    xpins.test_zero_lag_is_cor_and_invariants,
 ]
 
 
