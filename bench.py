@@ -270,6 +270,41 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
     return out
 
 
+def run_xcor(fcx, torch, cfg, pool_dev, steps):
+    """XCOR-only session on the 5000-node trials (all lags, F = 1024): the
+    node and pair XCOR kernels timed with HIP events per push, after the
+    window is full.  Work is counted as 5 F log2 F / 2 flop per pair for the
+    packed complex inverse FFT (two pairs per transform) plus the product
+    spectrum (6 flop per bin) and the lag scan (2L+1 normalised terms, 3 flop
+    each)."""
+    N, M, W = cfg["n_nodes"], cfg["n_samples"], cfg["window_trials"]
+    c = dict(cfg, metrics=fcx.FCX_XCOR)
+    npool = pool_dev.shape[0]
+    s = fcx.Session(c)
+    for k in range(W + 2):
+        fcx.check(s.push_device(pool_dev[k % npool].data_ptr(), M))
+    fcx.check(s.sync())
+    s.set_timing(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        fcx.check(s.push_device(pool_dev[(W + 2 + k) % npool].data_ptr(), M))
+    fcx.check(s.sync())
+    wall = (time.perf_counter() - t0) / steps
+    n, ms = s.kernel_time(fcx.FCX_K_XCOR)
+    s.close()
+    P = N * (N - 1) // 2
+    L = M - 1
+    F = 256
+    while F < M + L:
+        F *= 2
+    flop = P * (2.5 * F * np.log2(F) + 6 * (F // 2 + 1) + 3 * (2 * L + 1))
+    kms = ms / n if n else None
+    return dict(workload=f"N={N} (P={P}), M={M}, lags -{L}..{L}, F={F}, W={W}, XCOR only, one push per step",
+                ms_per_step=wall * 1e3, xcor_kernels_ms=kms, pairs_per_s=P / wall,
+                gflops=flop / (kms * 1e-3) / 1e9 if kms else None,
+                fp32_vector_frac=flop / (kms * 1e-3) / 157.3e12 if kms else None)
+
+
 def run_netsel(fcx, torch, cfg, pool_dev, reps, fraction=0.05):
     """fcx_network_select on the COH network of a short 5000-node session:
     HIP-event time per call on the calling stream, and its algorithmic HBM
@@ -351,6 +386,8 @@ def main():
                     help="serving-mix arrival window (about 650 arrivals/s), 0 to skip")
     ap.add_argument("--sensor-pushes", type=int, default=300,
                     help="latency pushes of the 306-sensor session (host input), 0 to skip")
+    ap.add_argument("--xcor-steps", type=int, default=5,
+                    help="timed pushes of the 5000-node XCOR-only session, 0 to skip")
     ap.add_argument("--netsel-reps", type=int, default=5,
                     help="timed calls of the network post-processing on a 5000-node network, 0 to skip")
     ap.add_argument("--large-steps", type=int, default=5,
@@ -461,6 +498,11 @@ def main():
                       p99_ms=float(np.percentile(np.array(lat) * 1e3, 99)),
                       pipelined_ms_per_push=ws * 1e3, updates_per_s=Ps * 23 / ws)
 
+    xcor = None
+    if args.xcor_steps > 0:
+        print("[bench] XCOR session", file=sys.stderr, flush=True)
+        xcor = run_xcor(fcx, torch, cfg, pool_dev, args.xcor_steps)
+
     netsel = None
     if args.netsel_reps > 0:
         # display post-processing of a 5000-node network: max-edge normalisation,
@@ -528,6 +570,7 @@ def main():
         "batch": batch,
         "large_multitaper": large,
         "sensor_space": sensor,
+        "xcor": xcor,
         "network_select": netsel,
         "serving": serving,
         "cpu_baseline": base,

@@ -10,8 +10,8 @@
  * the new trial added, the evicted one subtracted — and the band-averaged
  * network of every enabled metric is refreshed.  The metrics are those of the
  * supplementary metric section: COH, IMAGCOHY, PLV, PLI, WPLI, USPLI,
- * debiased squared WPLI and COR.  Only pairs i < j are computed (undirected
- * half, Sec. 2.4).
+ * debiased squared WPLI, COR and XCOR.  Only pairs i < j are computed
+ * (undirected half, Sec. 2.4).
  *
  * Conventions (where the paper is silent):
  *   CSD_ij = X_i conj(X_j); IMCOH_ji = -IMCOH_ij.
@@ -25,6 +25,12 @@
  *   DSWPLI = ((sum Im)^2 - sum Im^2) / ((sum |Im|)^2 - sum Im^2)  (the
  *   debiased estimator the metric is named for).
  *   COR = mean over the window of each trial's Pearson correlation.
+ *   XCOR = mean over the window of each trial's largest cross-correlation
+ *          over the lags -L..L: for lag tau >= 0 the XCOR equation with node
+ *          i advanced by tau against node j (its energy over the overlap,
+ *          node j's over all M samples), for -tau the same with the nodes
+ *          exchanged (so XCOR_ij = XCOR_ji); 0 where a denominator is 0.
+ *          The lag of the maximum is not kept.
  *   Band value = arithmetic mean of the per-bin values.
  *
  * Network layout: packed upper triangle without diagonal, row-major:
@@ -62,7 +68,7 @@ typedef enum {
 /* metric mask bits; fcx_read_network takes exactly one of them */
 enum {
     FCX_COH = 1, FCX_IMCOH = 2, FCX_PLV = 4, FCX_PLI = 8,
-    FCX_WPLI = 16, FCX_USPLI = 32, FCX_DSWPLI = 64, FCX_COR = 128
+    FCX_WPLI = 16, FCX_USPLI = 32, FCX_DSWPLI = 64, FCX_COR = 128, FCX_XCOR = 256
 };
 enum { FCX_TAPER_HANN = 0, FCX_TAPER_DPSS = 1 };
 /* operand precision of the batch Gram sums (fcx_push_batch / fcx_resync) */
@@ -85,6 +91,7 @@ typedef struct {
     uint32_t metrics;       /* OR of metric bits, non-zero                         */
     int32_t gram_precision; /* FCX_GRAM_*                                          */
     int32_t elem;           /* FCX_ELEM_*; input x and outputs use this type       */
+    int32_t xcor_max_lag;   /* XCOR lags -L..L; 0: L = M - 1. Needs M + L <= 2048 */
 } fcx_config;
 
 /* Fill *cfg with defaults (Hann, all 8 metrics, FP32 Gram, F32). */
@@ -143,7 +150,8 @@ fcx_status fcx_push_batch(fcx_session *s, const void *x, int64_t n_trials, int64
 /*
  * Copy the current network of one metric into out (host or device memory).
  * per_bin = 0: band mean, out_len >= P.  per_bin = 1: [B][P], out_len >= B*P
- * (COR is broadband and always [P]).  Element type follows cfg.elem.
+ * (COR and XCOR are broadband and always [P]).  Element type follows
+ * cfg.elem; XCOR is computed in FP32 (an FP32 FFT per pair) for both.
  * *k_trials_out (may be NULL) receives K, the trials in the window.
  * Synchronous.  Returns FCX_E_NOTREADY (and fills NaN) for USPLI/DSWPLI
  * while K < 2 and when no trial was pushed; FCX_E_NONFINITE once after a
@@ -177,7 +185,7 @@ fcx_status fcx_session_counts(fcx_session *s, int64_t *accepted, int64_t *reject
  * (pending events are resolved, which synchronises the stream).
  */
 enum { FCX_K_SPECTRA = 0, FCX_K_PSD = 1, FCX_K_PAIR_UPDATE = 2, FCX_K_COR = 3,
-       FCX_K_PAIR_BATCH = 4, FCX_K_ZNORM = 5, FCX_K_COUNT = 6 };
+       FCX_K_PAIR_BATCH = 4, FCX_K_ZNORM = 5, FCX_K_XCOR = 6, FCX_K_COUNT = 7 };
 fcx_status fcx_set_timing(fcx_session *s, int enable);
 fcx_status fcx_kernel_time(fcx_session *s, int kernel, int64_t *launches, double *total_ms);
 
@@ -239,12 +247,14 @@ fcx_status fcx_network_select(int32_t n_nodes, const float *w, double fraction, 
  * footprint fits what is left (FCX_E_BUSY otherwise; retry after another
  * session closes).  A served session's footprint is fcx_footprint_bytes plus
  * one more N x M float32 input buffer (256-byte aligned): the uploads of one
- * tick run on a copy stream while the previous tick computes.  Submitted trials of all sessions are gathered by a
- * server thread into ticks: one tick runs the spectra, power and pair-update
- * work of every session with pending trials as a few batched launches whose
- * workgroups drain a shared list of (session, tile) items, so sessions of
- * different N and W overlap on the device.  Per session, trials are applied
- * in submission order.  Each result equals the same session run alone.
+ * tick run on a copy stream while the previous tick computes.  Submitted
+ * trials of all sessions are gathered by a server thread into ticks: one
+ * tick runs the spectra, power and pair-update work of every session with
+ * pending trials as a few batched launches whose workgroups drain a shared
+ * list of (session, tile) items, so sessions of different N and W overlap
+ * on the device.  Per session, trials are applied in submission order.  Each
+ * result equals the same session run alone.  Served sessions compute in
+ * float32 and without XCOR (FCX_E_INVAL otherwise).
  * ------------------------------------------------------------------------ */
 fcx_status fcx_server_create(int64_t hbm_budget_bytes, fcx_server **out);
 fcx_status fcx_server_open(fcx_server *srv, const fcx_config *cfg, fcx_session **out);

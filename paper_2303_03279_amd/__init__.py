@@ -31,16 +31,17 @@ lib = ctypes.CDLL(LIB_PATH)
 # ---------------------------------------------------------------- constants
 FCX_OK, FCX_E_INVAL, FCX_E_NOMEM, FCX_E_DEVICE, FCX_E_NOTREADY, FCX_E_BUSY, FCX_E_CLOSED, \
     FCX_E_NONFINITE = range(8)
-FCX_COH, FCX_IMCOH, FCX_PLV, FCX_PLI, FCX_WPLI, FCX_USPLI, FCX_DSWPLI, FCX_COR = (
-    1, 2, 4, 8, 16, 32, 64, 128)
+FCX_COH, FCX_IMCOH, FCX_PLV, FCX_PLI, FCX_WPLI, FCX_USPLI, FCX_DSWPLI, FCX_COR, FCX_XCOR = (
+    1, 2, 4, 8, 16, 32, 64, 128, 256)
 FCX_TAPER_HANN, FCX_TAPER_DPSS = 0, 1
 FCX_GRAM_FP32, FCX_GRAM_BF16, FCX_GRAM_BF16X3 = 0, 1, 2
 FCX_ELEM_F32, FCX_ELEM_F64 = 0, 1
-(FCX_K_SPECTRA, FCX_K_PSD, FCX_K_PAIR_UPDATE, FCX_K_COR, FCX_K_PAIR_BATCH, FCX_K_ZNORM,
- FCX_K_COUNT) = range(7)
+(FCX_K_SPECTRA, FCX_K_PSD, FCX_K_PAIR_UPDATE, FCX_K_COR, FCX_K_PAIR_BATCH, FCX_K_ZNORM, FCX_K_XCOR,
+ FCX_K_COUNT) = range(8)
 
 METRIC_BITS = dict(coh=FCX_COH, imcoh=FCX_IMCOH, plv=FCX_PLV, pli=FCX_PLI, wpli=FCX_WPLI,
-                   uspli=FCX_USPLI, dswpli=FCX_DSWPLI, cor=FCX_COR)
+                   uspli=FCX_USPLI, dswpli=FCX_DSWPLI, cor=FCX_COR, xcor=FCX_XCOR)
+BROADBAND = ("cor", "xcor")
 
 
 class fcx_config(ctypes.Structure):
@@ -59,6 +60,7 @@ class fcx_config(ctypes.Structure):
         ("metrics", ctypes.c_uint32),
         ("gram_precision", ctypes.c_int32),
         ("elem", ctypes.c_int32),
+        ("xcor_max_lag", ctypes.c_int32),
     ]
 
 
@@ -160,6 +162,7 @@ def make_config(cfg: dict) -> fcx_config:
     c.gram_precision = {"fp32": FCX_GRAM_FP32, "bf16": FCX_GRAM_BF16,
                         "bf16x3": FCX_GRAM_BF16X3}[cfg.get("gram", "fp32")]
     c.elem = {"f32": FCX_ELEM_F32, "f64": FCX_ELEM_F64}[cfg.get("elem", "f32")]
+    c.xcor_max_lag = int(cfg.get("xcor_max_lag", 0))
     return c
 
 
@@ -217,11 +220,11 @@ class Session:
     def read(self, metric: str, per_bin: bool = False):
         import numpy as np
         bit = METRIC_BITS[metric]
-        n = self.P * (self.B if (per_bin and metric != "cor") else 1)
+        n = self.P * (self.B if (per_bin and metric not in BROADBAND) else 1)
         out = np.empty(n, dtype=np.float64 if self.f64 else np.float32)
         k = ctypes.c_int32()
         st = lib.fcx_read_network(self.h, bit, out.ctypes.data, n, 0, int(per_bin), ctypes.byref(k))
-        if per_bin and metric != "cor":
+        if per_bin and metric not in BROADBAND:
             out = out.reshape(self.B, self.P)
         return st, out, int(k.value)
 

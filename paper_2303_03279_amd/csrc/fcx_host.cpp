@@ -42,7 +42,8 @@ fcx_status make_geometry(const fcx_config *c, Geometry *g)
     if (!(c->fs_hz > 0.0) || !isfinite(c->fs_hz)) return FCX_E_INVAL;
     if (!isfinite(c->f_lo_hz) || !isfinite(c->f_hi_hz) || c->f_lo_hz < 0.0 || c->f_hi_hz < c->f_lo_hz)
         return FCX_E_INVAL;
-    if (c->metrics == 0 || (c->metrics & ~0xFFu)) return FCX_E_INVAL;
+    if (c->metrics == 0 || (c->metrics & ~0x1FFu)) return FCX_E_INVAL;
+    if (c->xcor_max_lag < 0 || c->xcor_max_lag > c->n_samples - 1) return FCX_E_INVAL;
     if (c->elem != FCX_ELEM_F32 && c->elem != FCX_ELEM_F64) return FCX_E_INVAL;
     if (c->gram_precision < FCX_GRAM_FP32 || c->gram_precision > FCX_GRAM_BF16X3) return FCX_E_INVAL;
     int L = 1;
@@ -70,12 +71,21 @@ fcx_status make_geometry(const fcx_config *c, Geometry *g)
     g->f64 = c->elem == FCX_ELEM_F64;
     g->esz = g->f64 ? 8 : 4;
     g->P = (size_t)g->N * (g->N - 1) / 2;
+    if (c->metrics & M_XCOR) {
+        // linear correlation at lags -L..L from a circular one of length F
+        g->xL = c->xcor_max_lag > 0 ? c->xcor_max_lag : g->M - 1;
+        int F = 256;
+        while (F < g->M + g->xL) F *= 2;
+        if (F > XCOR_MAX_F) return FCX_E_INVAL;
+        g->xF = F;
+    }
     return FCX_OK;
 }
 
 size_t BufferPlan::total() const
 {
     size_t t = ring + psd + gsum + out + ctl + wtw + lamw + tiles + zring + rsum + xbuf;
+    t += xtw + xspec + xsuf + xval + xsum;
     for (int i = 0; i < NPLANES; ++i)
         if (planes_used[i]) t += (i == P_URE || i == P_UIM) ? uplane : plane;
     return t;
@@ -120,12 +130,17 @@ BufferPlan make_plan(const fcx_config &c, const Geometry &g)
         p.wtw = align256((size_t)g.L * g.B * g.M * 2 * g.esz);
         p.lamw = align256((size_t)g.L * 8);
     }
-    p.out = align256(8 * g.P * g.esz);
+    p.out = align256(((m & M_XCOR) ? 9 : 8) * g.P * g.esz);
     p.ctl = align256(2 * sizeof(DevCtl));   // live control + replay control
     p.tiles = align256((size_t)g.ntiles * sizeof(int2));
-    if (m & M_COR) {
-        p.zring = align256(slots * g.N * g.Mz * 4);
-        p.rsum = align256((size_t)g.ntiles * TILE_PAIRS * 8);
+    if (m & (M_COR | M_XCOR)) p.zring = align256(slots * g.N * g.Mz * 4);
+    if (m & M_COR) p.rsum = align256((size_t)g.ntiles * TILE_PAIRS * 8);
+    if (m & M_XCOR) {
+        p.xtw = align256((size_t)g.xF * 8);
+        p.xspec = align256((size_t)g.N * (g.xF / 2 + 1) * 8);
+        p.xsuf = align256((size_t)g.N * (g.xL + 1) * 4);
+        p.xval = align256(slots * g.ntiles * TILE_PAIRS * 4);
+        p.xsum = align256((size_t)g.ntiles * TILE_PAIRS * 8);
     }
     p.xbuf = align256((size_t)g.N * g.M * g.esz);
     return p;
@@ -432,7 +447,23 @@ fcx_status session_alloc(Session *s)
     ALLOC(zring, p.zring);
     ALLOC(rsum, p.rsum);
     ALLOC(xbuf, p.xbuf);
+    ALLOC(xtw, p.xtw);
+    ALLOC(xspec, p.xspec);
+    ALLOC(xsuf, p.xsuf);
+    ALLOC(xval, p.xval);
+    ALLOC(xsum, p.xsum);
 #undef ALLOC
+    if (p.xtw) {
+        std::vector<float2> tw(g.xF);
+        for (int m = 0; m < g.xF; ++m) {
+            double c, sn;
+            unit_root(m, g.xF, &c, &sn);
+            tw[m] = make_float2((float)c, (float)sn);
+        }
+        HIP_OK(hipMemcpyAsync(s->xtw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, s->stream));
+        HIP_OK(hipMemsetAsync(s->xsum, 0, p.xsum, s->stream));
+        HIP_OK(hipStreamSynchronize(s->stream));
+    }
     // tile list: upper-triangle tiles in row-major order
     std::vector<int2> tl;
     tl.reserve(g.ntiles);
@@ -491,6 +522,13 @@ template <typename T> SessDev<T> session_dev(const Session *s, const void *x, lo
     d.zring = s->zring;
     d.rsum = s->rsum;
     d.kbase = -1;
+    d.xL = g.xL;
+    d.xF = g.xF;
+    d.xtw = s->xtw;
+    d.xspec = s->xspec;
+    d.xsuf = s->xsuf;
+    d.xval = s->xval;
+    d.xsum = s->xsum;
     return d;
 }
 template SessDev<float> session_dev<float>(const Session *, const void *, long long);
@@ -558,7 +596,7 @@ template <typename T> static fcx_status enqueue_push_t(Session *s, const void *x
         TimedLaunch t(s, FCX_K_SPECTRA);
         HIP_OK(launch_spectra<T>(d, s->stream));
     }
-    if (s->cfg.metrics & M_COR) {  // also checks finiteness (COR-only sessions)
+    if (s->cfg.metrics & (M_COR | M_XCOR)) {  // also checks finiteness (time-domain-only sessions)
         TimedLaunch t(s, FCX_K_ZNORM);
         HIP_OK(launch_znorm<T>(d, s->stream));
     }
@@ -566,10 +604,14 @@ template <typename T> static fcx_status enqueue_push_t(Session *s, const void *x
         TimedLaunch t(s, FCX_K_PSD);
         HIP_OK(launch_psd<T>(d, s->stream));
     }
-    {
+    if (s->cfg.metrics & (0x7Fu | M_COR)) {
         // spectral running sums and COR Gram blocks of every pair tile
         TimedLaunch t(s, FCX_K_PAIR_UPDATE);
         HIP_OK(launch_pair_update<T>(d, s->stream));
+    }
+    if (s->cfg.metrics & M_XCOR) {
+        TimedLaunch t(s, FCX_K_XCOR);
+        HIP_OK(launch_xcor<T>(d, s->stream));
     }
     HIP_OK(launch_commit(s->ctl, s->stream));
     return FCX_OK;
@@ -622,6 +664,7 @@ template <typename T> static fcx_status replay_window(Session *s, long long push
             HIP_OK(hipMemsetAsync(s->plane[i], 0, (i == P_URE || i == P_UIM) ? p.uplane : p.plane, s->stream));
     if (s->gsum) HIP_OK(hipMemsetAsync(s->gsum, 0, p.gsum, s->stream));
     if (s->rsum) HIP_OK(hipMemsetAsync(s->rsum, 0, p.rsum, s->stream));
+    if (s->xsum) HIP_OK(hipMemsetAsync(s->xsum, 0, p.xsum, s->stream));
     SessDev<T> d = session_dev<T>(s, nullptr, 0);
     d.ctl = s->ctl + 1;
     d.kbase = pushed - K;
@@ -629,7 +672,8 @@ template <typename T> static fcx_status replay_window(Session *s, long long push
     for (long long t = pushed - K; t < pushed; ++t) {
         HIP_OK(launch_set_ctl(d.ctl, t, s->stream));
         if (spectral) HIP_OK(launch_psd<T>(d, s->stream));
-        HIP_OK(launch_pair_update<T>(d, s->stream));
+        if (s->cfg.metrics & (0x7Fu | M_COR)) HIP_OK(launch_pair_update<T>(d, s->stream));
+        if (s->cfg.metrics & M_XCOR) HIP_OK(launch_xcor<T>(d, s->stream));
     }
     HIP_OK(hipStreamSynchronize(s->stream));
     return FCX_OK;
@@ -817,6 +861,7 @@ fcx_status fcx_push_batch(fcx_session *h, const void *x, int64_t n_trials, int64
                 HIP_OK(hipMemsetAsync(s->plane[i], 0, (i == P_URE || i == P_UIM) ? p.uplane : p.plane, s->stream));
         if (s->gsum) HIP_OK(hipMemsetAsync(s->gsum, 0, p.gsum, s->stream));
         if (s->rsum) HIP_OK(hipMemsetAsync(s->rsum, 0, p.rsum, s->stream));
+        if (s->xsum) HIP_OK(hipMemsetAsync(s->xsum, 0, p.xsum, s->stream));
         for (int64_t k = 0; k < n_trials; ++k) {
             const void *xk = (const char *)x + (size_t)k * trial_stride * es;
             long long ldk = ld;
@@ -834,6 +879,7 @@ fcx_status fcx_push_batch(fcx_session *h, const void *x, int64_t n_trials, int64
     // pass with the Gram sums on the matrix cores
     SessDev<float> d = session_dev<float>(s, nullptr, 0);
     const bool spectral = (s->cfg.metrics & 0x7Fu) != 0, cor = (s->cfg.metrics & M_COR) != 0;
+    const bool zneed = (s->cfg.metrics & (M_COR | M_XCOR)) != 0;   // XCOR comes from the replay
     for (int64_t k = 0; k < n_trials; ++k) {
         const void *xk = (const char *)x + (size_t)k * trial_stride * es;
         long long ldk = ld;
@@ -846,7 +892,7 @@ fcx_status fcx_push_batch(fcx_session *h, const void *x, int64_t n_trials, int64
         d.ldx = ldk;
         HIP_OK(launch_set_pushed(s->ctl, k, s->stream));
         if (spectral) HIP_OK(launch_spectra<float>(d, s->stream));
-        if (cor) HIP_OK(launch_znorm<float>(d, s->stream));
+        if (zneed) HIP_OK(launch_znorm<float>(d, s->stream));
     }
     const int prec = s->cfg.gram_precision;
     if (spectral) {
@@ -884,7 +930,7 @@ fcx_status fcx_read_network(fcx_session *h, uint32_t metric, void *out, int64_t 
     if (!out || metric == 0 || (metric & (metric - 1)) || !(metric & s->cfg.metrics)) return FCX_E_INVAL;
     std::lock_guard<std::mutex> lk(s->mu);
     const Geometry &g = s->g;
-    const bool bins = per_bin && metric != M_COR;
+    const bool bins = per_bin && metric != M_COR && metric != M_XCOR;
     const size_t need = bins ? (size_t)g.B * g.P : g.P;
     if (out_len < (int64_t)need) return FCX_E_INVAL;
     DevCtl c;
@@ -897,6 +943,8 @@ fcx_status fcx_read_network(fcx_session *h, uint32_t metric, void *out, int64_t 
     while (!((metric >> mi) & 1u)) ++mi;
     const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (!bins) {
+        // XCOR is not part of the batch pass: its window sum comes from the replay
+        if (metric == M_XCOR && s->stale && (st = rebuild_sums(s)) != FCX_OK) return st;
         const char *src = (const char *)s->out + (size_t)mi * g.P * g.esz;
         HIP_OK(hipMemcpy(out, src, g.P * g.esz, kind));
     } else {

@@ -16,6 +16,7 @@ struct BufferPlan {
     // device byte sizes of every buffer a session allocates
     size_t ring = 0, psd = 0, plane = 0, gsum = 0, out = 0, ctl = 0, wtw = 0, lamw = 0, tiles = 0;
     size_t zring = 0, rsum = 0, xbuf = 0;
+    size_t xtw = 0, xspec = 0, xsuf = 0, xval = 0, xsum = 0;   // XCOR
     int nplanes = 0;
     bool planes_used[NPLANES] = {false, false, false, false, false, false};
     bool g_used = false;
@@ -27,6 +28,7 @@ struct BufferPlan {
 
 struct Geometry {
     int N = 0, M = 0, W = 0, F = 0, B = 0, L = 0, klo = 0, khi = 0, nT = 0, ntiles = 0, Mz = 0;
+    int xL = 0, xF = 0;   // XCOR lag limit and FFT length
     bool f64 = false;
     size_t esz = 4;
     size_t P = 0;
@@ -60,6 +62,10 @@ struct Session {
     double *rsum = nullptr;
     void *xbuf = nullptr;
     void *xbuf2 = nullptr;   // served sessions: input of the other tick buffer
+    float2 *xtw = nullptr;
+    float2 *xspec = nullptr;
+    float *xsuf = nullptr, *xval = nullptr;
+    double *xsum = nullptr;
     std::vector<void *> allocs;
 
     // pinned host staging for host-resident trials (two buffers, each

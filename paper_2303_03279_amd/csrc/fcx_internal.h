@@ -24,7 +24,10 @@ enum { FCX_GRAM_FP32_ID = 0, FCX_GRAM_BF16_ID = 1, FCX_GRAM_BF16X3_ID = 2 };
 
 // metric bits (same values as the public header)
 enum : uint32_t { M_COH = 1, M_IMCOH = 2, M_PLV = 4, M_PLI = 8, M_WPLI = 16, M_USPLI = 32,
-                  M_DSWPLI = 64, M_COR = 128 };
+                  M_DSWPLI = 64, M_COR = 128, M_XCOR = 256 };
+
+// XCOR: largest FFT length (LDS of one wavefront's transform)
+constexpr int XCOR_MAX_F = 2048;
 
 // Device-resident push control.  Every kernel of a push reads it; only the
 // commit kernel advances it, so a rejected (non-finite) trial changes nothing.
@@ -60,6 +63,12 @@ struct SessDev {
     double *rsum;           // [ntiles][TILE_PAIRS] running sum of per-trial r (COR)
     long long kbase;        // -1: sliding push; >= 0: replay of a cached window
                             // (add only, K = pushed - kbase + 1)
+    int xL, xF;             // XCOR: lags -xL..xL, FFT length (power of 2 >= M + xL)
+    const float2 *xtw;      // [xF] exp(-2 pi i m / xF)
+    float2 *xspec;          // [N][xF/2+1] spectrum of the trial's z-scored samples
+    float *xsuf;            // [N][xL+1] energy of the z-scored samples from tau on
+    float *xval;            // [(W+1)][ntiles][TILE_PAIRS] per-trial XCOR maxima
+    double *xsum;           // [ntiles][TILE_PAIRS] their running sum over the window
 };
 
 // Which ring slots a push touches and how many trials the window holds after it.
@@ -104,6 +113,11 @@ hipError_t launch_batch_commit(DevCtl *ctl, long long K, hipStream_t st);
 hipError_t launch_psd_batch(const SessDev<float> &s, int K, hipStream_t st);
 hipError_t launch_pair_batch(const SessDev<float> &s, int K, int prec, hipStream_t st);
 hipError_t launch_cor_batch(const SessDev<float> &s, int K, int prec, hipStream_t st);
+
+// XCOR of the trial at ring slot of the push (fcx_xcor.hip): node spectra and
+// suffix energies, then per pair the FFT correlation, its maximum over the
+// lags and the window sum
+template <typename T> hipError_t launch_xcor(const SessDev<T> &s, hipStream_t st);
 
 // bin-chunk size of the pair kernel for a given (B, L, element size), and the
 // LDS it needs

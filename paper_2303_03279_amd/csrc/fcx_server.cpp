@@ -304,7 +304,7 @@ fcx_status fcx_server_open(fcx_server *h, const fcx_config *cfg, fcx_session **o
     Geometry g;
     fcx_status st = make_geometry(cfg, &g);
     if (st != FCX_OK) return st;
-    if (g.f64) return FCX_E_INVAL;  // served sessions compute in float32
+    if (g.f64 || (cfg->metrics & M_XCOR)) return FCX_E_INVAL;  // served sessions: float32, no XCOR
     const int64_t fp = served_footprint(make_plan(*cfg, g));
     {
         std::lock_guard<std::mutex> lk(sv->mu);

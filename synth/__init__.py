@@ -23,6 +23,7 @@ import numpy as np
 # metric mask bits (same values as the C header)
 COH, IMCOH, PLV, PLI, WPLI, USPLI, DSWPLI, COR = 1, 2, 4, 8, 16, 32, 64, 128
 ALL8 = 255
+XCOR = 256   # cross-correlation (not part of ALL8 nor of the random serving subsets)
 SPECTRAL7 = 127
 METRIC_NAMES = ["coh", "imcoh", "plv", "pli", "wpli", "uspli", "dswpli", "cor"]
 METRIC_BITS = dict(zip(METRIC_NAMES, [COH, IMCOH, PLV, PLI, WPLI, USPLI, DSWPLI, COR]))

@@ -49,7 +49,9 @@ def test_invalid_configs_rejected():
     good = synth.base_config(n_nodes=10, n_samples=100, window_trials=5, n_fft=128, f_lo_hz=8, f_hi_hz=30)
     assert fcx.footprint_bytes(good) > 0
     bad = [dict(n_nodes=1), dict(n_samples=1), dict(window_trials=0), dict(n_fft=50),
-           dict(fs_hz=0.0), dict(f_lo_hz=40, f_hi_hz=30), dict(metrics=0), dict(metrics=256),
+           dict(fs_hz=0.0), dict(f_lo_hz=40, f_hi_hz=30), dict(metrics=0), dict(metrics=512),
+           dict(metrics=synth.XCOR, xcor_max_lag=100), dict(metrics=synth.XCOR, xcor_max_lag=-1),
+           dict(metrics=synth.XCOR, n_samples=1500, n_fft=2048),
            dict(taper="dpss", dpss_k=0, dpss_nw=2.0), dict(taper="dpss", dpss_k=3, dpss_nw=60.0)]
     for b in bad:
         cfg = dict(good)
@@ -114,3 +116,18 @@ def test_network_select_rejects_bad_arguments():
         assert st == fcx.FCX_E_INVAL, f
     st, _ = fcx.network_select(70000, 0x1000, 0.1)
     assert st == fcx.FCX_E_INVAL
+
+
+def test_xcor_config_and_footprint():
+    """XCOR lags -L..L with L <= M - 1 and M + L <= 2048; its buffers: node
+    spectra and energies, the per-trial maxima ring and the window sum."""
+    base = synth.base_config(n_nodes=300, n_samples=500, window_trials=20, n_fft=512, f_lo_hz=8, f_hi_hz=30,
+                             metrics=synth.COH)
+    fp = fcx.footprint_bytes(base)
+    x = fcx.footprint_bytes(dict(base, metrics=synth.COH | synth.XCOR))
+    assert x > fp
+    assert fcx.footprint_bytes(dict(base, metrics=synth.XCOR, xcor_max_lag=499)) > 0
+    assert fcx.footprint_bytes(dict(base, metrics=synth.XCOR, xcor_max_lag=500)) == -1
+    assert fcx.footprint_bytes(dict(base, metrics=synth.XCOR, n_samples=1024, n_fft=1024)) > 0   # 1024+1023 <= 2048
+    assert fcx.footprint_bytes(dict(base, metrics=synth.XCOR, n_samples=1025, n_fft=2048)) == -1
+    assert fcx.footprint_bytes(dict(base, metrics=synth.XCOR, n_samples=1025, n_fft=2048, xcor_max_lag=1023)) > 0
