@@ -66,7 +66,7 @@ struct SessDev {
     int xL, xF;             // XCOR: lags -xL..xL, FFT length (power of 2 >= M + xL)
     const float2 *xtw;      // [xF] exp(-2 pi i m / xF)
     float2 *xspec;          // [N][xF/2+1] spectrum of the trial's z-scored samples
-    float *xsuf;            // [N][xL+1] energy of the z-scored samples from tau on
+    float *xsuf;            // [N][xL+1] 1/sqrt(energy of the z-scored samples from tau on)
     float *xval;            // [(W+1)][ntiles][TILE_PAIRS] per-trial XCOR maxima
     double *xsum;           // [ntiles][TILE_PAIRS] their running sum over the window
 };

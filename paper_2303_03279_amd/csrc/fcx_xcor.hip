@@ -5,9 +5,10 @@
 //
 //   k_xcor_node   per node, from its z-scored samples z (zero mean, unit
 //                 energy, already in the COR sample ring): the energies
-//                 S(tau) = sum_{t >= tau} z(t)^2 for tau = 0..L (FP64 sums,
-//                 stored FP32) and the spectrum Z(f) = sum_t z(t) e^{-2 pi i f t/F},
-//                 f = 0..F/2, F a power of two >= M + L (FP64 sums, FP32 out)
+//                 S(tau) = sum_{t >= tau} z(t)^2 for tau = 0..L (FP64 sums),
+//                 stored as 1/sqrt(S(tau)) in FP32 (0 for S = 0), and the
+//                 spectrum Z(f) = sum_t z(t) e^{-2 pi i f t/F}, f = 0..F/2,
+//                 F a power of two >= M + L (FP64 sums, FP32 out)
 //   k_xcor_pair   per pair tile row: for two columns at a time, the product
 //                 spectra of the pairs are packed as H1 + i H2 (both
 //                 Hermitian), one in-LDS inverse FFT of length F yields both
@@ -21,9 +22,10 @@
 //                 values, so add and remove cancel exactly.
 //
 // The inverse FFT is a radix-4 Stockham (autosorting) transform, with one
-// radix-2 stage when log2 F is odd, done by the whole workgroup in LDS:
-// every stage loads its butterflies' inputs, waits, and stores the outputs
-// in place.
+// radix-2 stage when log2 F is odd, done by one wavefront in its own LDS
+// buffer: every stage loads its butterflies' inputs, then stores the outputs
+// in place; the wavefronts of a workgroup share the row node's data and the
+// twiddles and never wait for each other.
 #include "fcx_device.h"
 
 #include <math.h>
@@ -58,7 +60,7 @@ __global__ __launch_bounds__(XT) void k_xcor_node(SessDev<T> s)
     }
     __syncthreads();
     float *so = s.xsuf + (size_t)node * (L + 1);
-    for (int t = tid; t <= L; t += XT) so[t] = (float)suf[t];
+    for (int t = tid; t <= L; t += XT) so[t] = suf[t] > 0.0 ? (float)(1.0 / sqrt(suf[t])) : 0.f;
     float2 *xo = s.xspec + (size_t)node * (F / 2 + 1);
     const unsigned fm = (unsigned)F - 1u;
     for (int f = tid; f <= F / 2; f += XT) {
@@ -80,86 +82,75 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// in-place inverse DFT (no 1/F) of Z[F] in LDS by the whole workgroup
+// In-place inverse DFT (no 1/F) of Z[F] in LDS by one wavefront.  The LDS
+// operations of a wavefront are performed in order, so a stage's loads (all
+// lanes) precede its stores; the wave barriers keep the compiler from moving
+// LDS accesses across the phase boundaries.
 template <int F>
-__device__ __forceinline__ void ifft_block(float2 *Z, const float2 *__restrict__ tw)
+__device__ __forceinline__ void ifft_wave(float2 *Z, const float2 *tw, int lane)
 {
-    const int tid = threadIdx.x;
     constexpr int NB4 = F / 4;                           // radix-4 butterflies per stage
-    constexpr int PER4 = (NB4 + XT - 1) / XT;
+    constexpr int PER4 = NB4 / 64;
 #pragma unroll
     for (int Ns = 1; Ns * 4 <= F; Ns *= 4) {
         float2 v[PER4][4];
+        const int step = F / (4 * Ns);
 #pragma unroll
         for (int q = 0; q < PER4; ++q) {
-            const int j = tid + q * XT;
-            if (j < NB4) {
-                const int k = j & (Ns - 1);
-                const int step = F / (4 * Ns);
+            const int j = lane + q * 64;
+            const int k = j & (Ns - 1);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float2 a = Z[j + r * NB4];
-                    if (r) {
-                        float2 w = tw[r * k * step];
-                        w.y = -w.y;                      // inverse: exp(+2 pi i m / F)
-                        a = cmul(a, w);
-                    }
-                    v[q][r] = a;
+            for (int r = 0; r < 4; ++r) {
+                float2 a = Z[j + r * NB4];
+                if (r && Ns > 1) {                       // the first stage's twiddles are 1
+                    float2 w = tw[r * k * step];
+                    w.y = -w.y;                          // inverse: exp(+2 pi i m / F)
+                    a = cmul(a, w);
                 }
+                v[q][r] = a;
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int q = 0; q < PER4; ++q) {
-            const int j = tid + q * XT;
-            if (j < NB4) {
-                const int k = j & (Ns - 1);
-                const float2 a0 = v[q][0], a1 = v[q][1], a2 = v[q][2], a3 = v[q][3];
-                const float2 t0 = make_float2(a0.x + a2.x, a0.y + a2.y);
-                const float2 t1 = make_float2(a0.x - a2.x, a0.y - a2.y);
-                const float2 t2 = make_float2(a1.x + a3.x, a1.y + a3.y);
-                const float2 d = make_float2(a1.x - a3.x, a1.y - a3.y);
-                const float2 t3 = make_float2(-d.y, d.x);  // +i (a1 - a3)
-                const int o = (j / Ns) * Ns * 4 + k;
-                Z[o] = make_float2(t0.x + t2.x, t0.y + t2.y);
-                Z[o + Ns] = make_float2(t1.x + t3.x, t1.y + t3.y);
-                Z[o + 2 * Ns] = make_float2(t0.x - t2.x, t0.y - t2.y);
-                Z[o + 3 * Ns] = make_float2(t1.x - t3.x, t1.y - t3.y);
-            }
+            const int j = lane + q * 64;
+            const int k = j & (Ns - 1);
+            const float2 a0 = v[q][0], a1 = v[q][1], a2 = v[q][2], a3 = v[q][3];
+            const float2 t0 = make_float2(a0.x + a2.x, a0.y + a2.y);
+            const float2 t1 = make_float2(a0.x - a2.x, a0.y - a2.y);
+            const float2 t2 = make_float2(a1.x + a3.x, a1.y + a3.y);
+            const float2 d = make_float2(a1.x - a3.x, a1.y - a3.y);
+            const float2 t3 = make_float2(-d.y, d.x);    // +i (a1 - a3)
+            const int o = (j / Ns) * Ns * 4 + k;
+            Z[o] = make_float2(t0.x + t2.x, t0.y + t2.y);
+            Z[o + Ns] = make_float2(t1.x + t3.x, t1.y + t3.y);
+            Z[o + 2 * Ns] = make_float2(t0.x - t2.x, t0.y - t2.y);
+            Z[o + 3 * Ns] = make_float2(t1.x - t3.x, t1.y - t3.y);
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
     constexpr bool odd = (F & 0x55555555) == 0;          // log2 F odd: a last radix-2 stage
     if constexpr (odd) {
         constexpr int NB2 = F / 2;
-        constexpr int PER2 = (NB2 + XT - 1) / XT;
+        constexpr int PER2 = NB2 / 64;
         float2 v0[PER2], v1[PER2];
 #pragma unroll
         for (int q = 0; q < PER2; ++q) {
-            const int j = tid + q * XT;
-            if (j < NB2) {
-                float2 w = tw[j];
-                w.y = -w.y;
-                v0[q] = Z[j];
-                v1[q] = cmul(Z[j + NB2], w);
-            }
+            const int j = lane + q * 64;
+            float2 w = tw[j];
+            w.y = -w.y;
+            v0[q] = Z[j];
+            v1[q] = cmul(Z[j + NB2], w);
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int q = 0; q < PER2; ++q) {
-            const int j = tid + q * XT;
-            if (j < NB2) {
-                Z[j] = make_float2(v0[q].x + v1[q].x, v0[q].y + v1[q].y);
-                Z[j + NB2] = make_float2(v0[q].x - v1[q].x, v0[q].y - v1[q].y);
-            }
+            const int j = lane + q * 64;
+            Z[j] = make_float2(v0[q].x + v1[q].x, v0[q].y + v1[q].y);
+            Z[j + NB2] = make_float2(v0[q].x - v1[q].x, v0[q].y - v1[q].y);
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
-}
-
-__device__ __forceinline__ float xcor_term(float c, float e)
-{
-    return e > 0.f ? c * __builtin_amdgcn_rsqf(e) : 0.f;
 }
 
 __device__ __forceinline__ float wave_max(float v)
@@ -168,38 +159,49 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
+// waves per workgroup of the pair kernel (each has its own transform
+// buffer), and whether the twiddles are staged in LDS (up to F = 1024; the
+// 2048-point kernel reads them from the cache to keep three workgroups per CU)
+template <int F> constexpr int xcor_waves() { return F >= 2048 ? 2 : 4; }
+template <int F> constexpr bool xcor_tw_lds() { return F <= 1024; }
+
 // One workgroup per (tile, row of the tile): row node i against the tile's
-// columns j > i, two columns per transform.
+// columns j > i.  The row's spectrum, energies and the twiddles are shared in
+// LDS; each wavefront takes two columns at a time into its own transform.
 template <typename T, int F>
-__global__ __launch_bounds__(XT) void k_xcor_pair(SessDev<T> s)
+__global__ __launch_bounds__(64 * xcor_waves<F>()) void k_xcor_pair(SessDev<T> s)
 {
-    __shared__ float2 Z[F];
+    constexpr int NW = xcor_waves<F>();
+    __shared__ float2 Zw[NW][F];
     __shared__ float2 Rsp[F / 2 + 1];
     __shared__ float Rsuf[F];
-    __shared__ float red[2][XT / 64];
+    __shared__ float2 tws[xcor_tw_lds<F>() ? F : 1];
     if (s.ctl->bad) return;
     const int item = xcd_item(blockIdx.x, gridDim.x);
     const int tile = item / TILE, r = item % TILE;
     const int2 tt = s.tiles[tile];
-    const int N = s.N, L = s.xL, tid = threadIdx.x;
+    const int N = s.N, L = s.xL, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int i = tt.x * TILE + r, J0 = tt.y * TILE;
     if (i >= N) return;
     const int jlo = max(J0, i + 1), jhi = min(J0 + TILE, N);
     if (jlo >= jhi) return;
     const PushView pv = push_view(s, s.ctl->pushed);
-    for (int f = tid; f <= F / 2; f += XT) Rsp[f] = s.xspec[(size_t)i * (F / 2 + 1) + f];
-    for (int t = tid; t <= L; t += XT) Rsuf[t] = s.xsuf[(size_t)i * (L + 1) + t];
+    for (int f = tid; f <= F / 2; f += 64 * NW) Rsp[f] = s.xspec[(size_t)i * (F / 2 + 1) + f];
+    for (int t = tid; t <= L; t += 64 * NW) Rsuf[t] = s.xsuf[(size_t)i * (L + 1) + t];
+    if constexpr (xcor_tw_lds<F>())
+        for (int m = tid; m < F; m += 64 * NW) tws[m] = s.xtw[m];
     __syncthreads();
-    const float Ei = Rsuf[0];
+    float2 *Z = Zw[wv];
+    const float rEi = Rsuf[0];   // 1/sqrt of node i's energy (0 if none)
     const float invF = 1.0f / (float)F;
     const size_t TP = (size_t)s.ntiles * TILE_PAIRS;
     const size_t P = (size_t)N * (N - 1) / 2;
-    for (int j = jlo; j < jhi; j += 2) {
+    for (int j = jlo + 2 * wv; j < jhi; j += 2 * NW) {
         const int j2 = j + 1 < jhi ? j + 1 : -1;
         const float2 *c1p = s.xspec + (size_t)j * (F / 2 + 1);
         const float2 *c2p = s.xspec + (size_t)(j2 >= 0 ? j2 : j) * (F / 2 + 1);
         // Z = H1 + i H2 over the full circle, H = X_i conj(X_j) (Hermitian)
-        for (int f = tid; f <= F / 2; f += XT) {
+        for (int f = lane; f <= F / 2; f += 64) {
             const float2 a = Rsp[f], b1 = c1p[f];
             float2 b2 = c2p[f];
             if (j2 < 0) b2 = make_float2(0.f, 0.f);
@@ -208,37 +210,31 @@ __global__ __launch_bounds__(XT) void k_xcor_pair(SessDev<T> s)
             Z[f] = make_float2(h1r - h2i, h1i + h2r);
             if (f > 0 && f < F / 2) Z[F - f] = make_float2(h1r + h2i, h2r - h1i);
         }
-        __syncthreads();
-        ifft_block<F>(Z, s.xtw);
+        __builtin_amdgcn_wave_barrier();
+        ifft_wave<F>(Z, xcor_tw_lds<F>() ? tws : s.xtw, lane);
         // largest XCOR over the lags, both pairs
         const float *s1 = s.xsuf + (size_t)j * (L + 1);
         const float *s2 = s.xsuf + (size_t)(j2 >= 0 ? j2 : j) * (L + 1);
-        const float E1 = s1[0], E2 = j2 >= 0 ? s2[0] : 0.f;
+        // XCOR = c / F * (1/sqrt S_advanced(tau)) * (1/sqrt E_other)
+        const float rE1 = s1[0], rE2 = j2 >= 0 ? s2[0] : 0.f;
         float best1 = -INFINITY, best2 = -INFINITY;
-        for (int tau = tid; tau <= L; tau += XT) {
+        for (int tau = lane; tau <= L; tau += 64) {
             const float2 p = Z[tau];
-            const float si = Rsuf[tau];
-            best1 = fmaxf(best1, xcor_term(p.x * invF, si * E1));
-            best2 = fmaxf(best2, xcor_term(p.y * invF, si * E2));
+            const float ri = Rsuf[tau];
+            best1 = fmaxf(best1, p.x * invF * ri * rE1);
+            best2 = fmaxf(best2, p.y * invF * ri * rE2);
             if (tau > 0) {
                 const float2 q = Z[F - tau];
-                best1 = fmaxf(best1, xcor_term(q.x * invF, s1[tau] * Ei));
-                if (j2 >= 0) best2 = fmaxf(best2, xcor_term(q.y * invF, s2[tau] * Ei));
+                best1 = fmaxf(best1, q.x * invF * s1[tau] * rEi);
+                if (j2 >= 0) best2 = fmaxf(best2, q.y * invF * s2[tau] * rEi);
             }
         }
         best1 = wave_max(best1);
         best2 = wave_max(best2);
-        if ((tid & 63) == 0) {
-            red[0][tid >> 6] = best1;
-            red[1][tid >> 6] = best2;
-        }
-        __syncthreads();
-        if (tid < 2) {
-            const int jj = tid == 0 ? j : j2;
+        if (lane < 2) {
+            const int jj = lane == 0 ? j : j2;
             if (jj >= 0) {
-                float v = red[tid][0];
-#pragma unroll
-                for (int w = 1; w < XT / 64; ++w) v = fmaxf(v, red[tid][w]);
+                const float v = lane == 0 ? best1 : best2;
                 const size_t e = (size_t)tile * TILE_PAIRS + (size_t)r * TILE + (jj - J0);
                 double sum = s.xsum[e] + (double)v;
                 if (pv.has_old) sum = sum - (double)s.xval[(size_t)pv.slot_old * TP + e];
@@ -248,19 +244,19 @@ __global__ __launch_bounds__(XT) void k_xcor_pair(SessDev<T> s)
                 s.out[8 * P + idx] = (T)(sum / (double)pv.K);
             }
         }
-        __syncthreads();   // Z and red are reused by the next columns
+        __builtin_amdgcn_wave_barrier();   // Z is rebuilt for the next columns
     }
 }
 
 template <typename T> hipError_t launch_xcor(const SessDev<T> &s, hipStream_t st)
 {
     hipLaunchKernelGGL(k_xcor_node<T>, dim3(s.N), dim3(XT), 0, st, s);
-    const dim3 grid((unsigned)(s.ntiles * TILE)), blk(XT);
+    const dim3 grid((unsigned)(s.ntiles * TILE));
     switch (s.xF) {
-    case 256: hipLaunchKernelGGL((k_xcor_pair<T, 256>), grid, blk, 0, st, s); break;
-    case 512: hipLaunchKernelGGL((k_xcor_pair<T, 512>), grid, blk, 0, st, s); break;
-    case 1024: hipLaunchKernelGGL((k_xcor_pair<T, 1024>), grid, blk, 0, st, s); break;
-    case 2048: hipLaunchKernelGGL((k_xcor_pair<T, 2048>), grid, blk, 0, st, s); break;
+    case 256: hipLaunchKernelGGL((k_xcor_pair<T, 256>), grid, dim3(64 * xcor_waves<256>()), 0, st, s); break;
+    case 512: hipLaunchKernelGGL((k_xcor_pair<T, 512>), grid, dim3(64 * xcor_waves<512>()), 0, st, s); break;
+    case 1024: hipLaunchKernelGGL((k_xcor_pair<T, 1024>), grid, dim3(64 * xcor_waves<1024>()), 0, st, s); break;
+    case 2048: hipLaunchKernelGGL((k_xcor_pair<T, 2048>), grid, dim3(64 * xcor_waves<2048>()), 0, st, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
