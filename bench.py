@@ -479,12 +479,12 @@ def main():
         for k in range(cs["window_trials"]):
             fcx.check(ss.push_host(xs[k % 64]))
         fcx.check(ss.sync())
-        lat = []
+        slat = []
         for k in range(args.sensor_pushes):
             t1 = time.perf_counter()
             fcx.check(ss.push_host(xs[k % 64]))
             fcx.check(ss.sync())
-            lat.append(time.perf_counter() - t1)
+            slat.append(time.perf_counter() - t1)
         t0 = time.perf_counter()
         for k in range(args.sensor_pushes):
             fcx.check(ss.push_host(xs[k % 64]))
@@ -494,9 +494,9 @@ def main():
         Ps = cs["n_nodes"] * (cs["n_nodes"] - 1) // 2
         sensor = dict(workload="N=306 sensors, W=100 x 600 samples, F=1024, 8-30 Hz (23 bins), all 8 metrics, "
                                "host-resident trials (PCIe upload included)",
-                      p50_ms=float(np.percentile(np.array(lat) * 1e3, 50)),
-                      p99_ms=float(np.percentile(np.array(lat) * 1e3, 99)),
-                      pipelined_ms_per_push=ws * 1e3, updates_per_s=Ps * 23 / ws)
+                      p50_ms=float(np.percentile(np.array(slat) * 1e3, 50)),
+                      p99_ms=float(np.percentile(np.array(slat) * 1e3, 99)),
+                      pushes=len(slat), pipelined_ms_per_push=ws * 1e3, updates_per_s=Ps * 23 / ws)
 
     xcor = None
     if args.xcor_steps > 0:
@@ -560,7 +560,7 @@ def main():
                                "fs=1 kHz, F=512, 8-30 Hz (12 bins), Hann, all 8 metrics, one push per step",
                    "n_nodes": N, "pairs": P, "bins": B, "window": cfg["window_trials"]},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
-                       "pushes": len(lat)},
+                       "pushes": int(len(lat))},
         "kernels": kt,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(),
