@@ -305,6 +305,49 @@ def run_xcor(fcx, torch, cfg, pool_dev, steps):
                 fp32_vector_frac=flop / (kms * 1e-3) / 157.3e12 if kms else None)
 
 
+def run_stream(fcx, torch, blocks):
+    """The online pipeline at sensor scale: 306 channels at 1 kHz in blocks of
+    250 samples, band-pass 1-45 Hz (T = 331 taps), a trigger every 0.7 s,
+    trials of 100 + 500 samples pushed into a 306-node session (W = 100,
+    F = 1024, 8-30 Hz, all 8 metrics).  Per block: filter, cut, push and the
+    refreshed networks; host-clock time from block submit to completion."""
+    import synth
+    fs, C, Bl, pre, post = 1000.0, 306, 250, 100, 500
+    n = Bl * (blocks + 8)
+    rng = np.random.default_rng(7)
+    x = np.ascontiguousarray(synth.pink_noise(rng, (C,), n), dtype=np.float32)
+    trig = np.zeros(n, dtype=np.float32)
+    for e in range(200, n, 700):
+        trig[e:e + 10] = 5.0
+    taps = fcx.fir_design(fcx.FCX_FIR_BANDPASS, fs, 1.0, 45.0, n_taps=331)
+    st = fcx.Stream(C, Bl, taps, 1.0, pre, post)
+    cfg = dict(n_nodes=C, n_samples=pre + post, window_trials=100, n_fft=1024, fs_hz=fs, f_lo_hz=8.0,
+               f_hi_hz=30.0, taper="hann", metrics=255)
+    sess = fcx.Session(cfg)
+    xd = torch.from_numpy(x).cuda()
+    td = torch.from_numpy(trig).cuda()
+    tr = torch.empty((4, C, pre + post), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    lat, trials = [], 0
+    for b in range(blocks + 8):
+        t1 = time.perf_counter()
+        status, k, _ = st.push(xd.data_ptr() + 4 * b * Bl, n, td.data_ptr() + 4 * b * Bl, 0, tr.data_ptr(), 4)
+        fcx.check(status)
+        for q in range(k):
+            fcx.check(sess.push_device(tr[q].data_ptr(), pre + post))
+        fcx.check(sess.sync())
+        if b >= 8:
+            lat.append(time.perf_counter() - t1)
+            trials += k
+    sess.close()
+    fcx.check(st.close())
+    lat_ms = np.array(lat) * 1e3
+    return dict(workload=f"{C} channels, {Bl}-sample blocks at 1 kHz, band-pass FIR T=331, trigger every 700 "
+                         f"samples, trials {pre}+{post} pushed into a {C}-node all-8 session (W=100)",
+                blocks=len(lat), trials=trials, block_p50_ms=float(np.percentile(lat_ms, 50)),
+                block_p99_ms=float(np.percentile(lat_ms, 99)), block_budget_ms=Bl / fs * 1e3)
+
+
 def run_netsel(fcx, torch, cfg, pool_dev, reps, fraction=0.05):
     """fcx_network_select on the COH network of a short 5000-node session:
     HIP-event time per call on the calling stream, and its algorithmic HBM
@@ -388,6 +431,8 @@ def main():
                     help="latency pushes of the 306-sensor session (host input), 0 to skip")
     ap.add_argument("--xcor-steps", type=int, default=5,
                     help="timed pushes of the 5000-node XCOR-only session, 0 to skip")
+    ap.add_argument("--stream-blocks", type=int, default=200,
+                    help="timed blocks of the stream -> trials -> session pipeline, 0 to skip")
     ap.add_argument("--netsel-reps", type=int, default=5,
                     help="timed calls of the network post-processing on a 5000-node network, 0 to skip")
     ap.add_argument("--large-steps", type=int, default=5,
@@ -533,6 +578,11 @@ def main():
         del pool_l
         torch.cuda.empty_cache()
 
+    stream_leg = None
+    if args.stream_blocks > 0:
+        print("[bench] stream front end", file=sys.stderr, flush=True)
+        stream_leg = run_stream(fcx, torch, args.stream_blocks)
+
     serving = None
     if args.serving_seconds > 0:
         print("[bench] serving mix", file=sys.stderr, flush=True)
@@ -572,6 +622,7 @@ def main():
         "sensor_space": sensor,
         "xcor": xcor,
         "network_select": netsel,
+        "stream_pipeline": stream_leg,
         "serving": serving,
         "cpu_baseline": base,
     }

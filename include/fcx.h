@@ -241,6 +241,57 @@ fcx_status fcx_network_select(int32_t n_nodes, const float *w, double fraction, 
                               void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Stream front end (the noise-reduction and averaging plug-ins of the online
+ * pipeline, Sec. 2.5): a linear-phase FIR filter applied block by block by
+ * FFT convolution with overlap-add, all channels in parallel, and trials cut
+ * around the rising edges of a trigger channel, ready to push.
+ * ------------------------------------------------------------------------ */
+typedef struct fcx_stream fcx_stream;
+enum { FCX_FIR_LOWPASS = 0, FCX_FIR_HIGHPASS = 1, FCX_FIR_BANDPASS = 2 };
+
+/*
+ * Windowed-sinc FIR design (Hamming window, odd length T, symmetric: linear
+ * phase with group delay (T-1)/2).  Lowpass f1; highpass f1 (spectral
+ * inversion); bandpass f1..f2.  Scaled to gain 1 at DC, at Nyquist, or at
+ * the band centre.  n_taps = 0 takes the odd T >= 3.3 fs / transition_hz.
+ * taps (host, capacity cap) receives the coefficients; taps = NULL only
+ * reports the length in *n_taps_out.  Errors: FCX_E_INVAL (cut-offs outside
+ * (0, fs/2), f2 <= f1 for a bandpass, an even n_taps, cap < T).
+ */
+fcx_status fcx_fir_design(int32_t kind, double fs_hz, double f1_hz, double f2_hz, double transition_hz,
+                          int32_t n_taps, double *taps, int32_t cap, int32_t *n_taps_out);
+
+typedef struct {
+    uint32_t struct_size;      /* sizeof(fcx_stream_config)                          */
+    int32_t n_channels;        /* C data channels (all filtered)                     */
+    int32_t block_len;         /* samples per pushed block                           */
+    int32_t n_taps;            /* T, odd; block_len + T - 1 <= 4096                  */
+    const double *taps;        /* host, T coefficients (copied by fcx_stream_open)   */
+    float trigger_threshold;   /* an event where trig[n-1] < thr <= trig[n]          */
+    int32_t pre_samples;       /* trial = raw times n0 - pre .. n0 + post - 1        */
+    int32_t post_samples;      /* (>= 1)                                             */
+} fcx_stream_config;
+
+/* Open a stream on the current device; work is ordered on hip_stream (NULL:
+ * the default stream).  Errors: FCX_E_INVAL, FCX_E_NOMEM, FCX_E_DEVICE. */
+fcx_status fcx_stream_open(const fcx_stream_config *cfg, void *hip_stream, fcx_stream **out);
+
+/*
+ * Push the next block: x [C][block_len] (device, row stride ld >= block_len)
+ * and the trigger channel trig [block_len] (device).  The data are filtered
+ * (the output lags by D = (T-1)/2 samples; optional y [C][block_len] device
+ * receives the filtered block).  Every trial whose window is complete is
+ * written, filtered and shifted by D (so it covers the raw times around its
+ * event), to trials [k][C][pre + post] (device, up to cap trials), in event
+ * order; *n_trials gets their number.  *n_dropped (may be NULL) counts the
+ * events whose window starts before the stream or that exceeded cap.
+ * Synchronous.  Errors: FCX_E_INVAL, FCX_E_CLOSED, FCX_E_DEVICE.
+ */
+fcx_status fcx_stream_push(fcx_stream *s, const float *x, int64_t ld, const float *trig, float *y,
+                           float *trials, int32_t cap, int32_t *n_trials, int32_t *n_dropped);
+fcx_status fcx_stream_close(fcx_stream *s);
+
+/* ------------------------------------------------------------------------
  * Serving: many concurrent sessions, continuous batching.
  *
  * A server owns an HBM budget.  fcx_server_open admits a session only if its

@@ -74,6 +74,21 @@ class fcx_select_info(ctypes.Structure):
     ]
 
 
+class fcx_stream_config(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("n_channels", ctypes.c_int32),
+        ("block_len", ctypes.c_int32),
+        ("n_taps", ctypes.c_int32),
+        ("taps", ctypes.c_void_p),
+        ("trigger_threshold", ctypes.c_float),
+        ("pre_samples", ctypes.c_int32),
+        ("post_samples", ctypes.c_int32),
+    ]
+
+
+FCX_FIR_LOWPASS, FCX_FIR_HIGHPASS, FCX_FIR_BANDPASS = 0, 1, 2
+
 P = ctypes.c_void_p
 I32, I64, U32, U64, D = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
 PI32, PI64, PD, PU64 = (ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
@@ -101,6 +116,10 @@ _SIGS = {
     "fcx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "fcx_probe_copy": (ctypes.c_int, [P, P, I64, P]),
     "fcx_network_select": (ctypes.c_int, [I32, P, D, P, P, P, P, ctypes.POINTER(fcx_select_info), P]),
+    "fcx_fir_design": (ctypes.c_int, [I32, D, D, D, D, I32, P, I32, PI32]),
+    "fcx_stream_open": (ctypes.c_int, [ctypes.POINTER(fcx_stream_config), P, PP]),
+    "fcx_stream_push": (ctypes.c_int, [P, P, I64, P, P, P, I32, PI32, PI32]),
+    "fcx_stream_close": (ctypes.c_int, [P]),
     "fcx_server_create": (ctypes.c_int, [I64, PP]),
     "fcx_server_open": (ctypes.c_int, [P, PCFG, PP]),
     "fcx_server_submit": (ctypes.c_int, [P, P, P, I64, PU64]),
@@ -141,6 +160,47 @@ def network_select(n_nodes: int, w_ptr: int, fraction: float, w_norm_ptr: int = 
                                 degree_ptr or None, strength_ptr or None, ctypes.byref(info), stream or None)
     return st, dict(max_abs=info.max_abs, threshold=info.threshold, k=info.k, n_finite=info.n_finite,
                     n_selected=info.n_selected)
+
+
+def fir_design(kind: int, fs: float, f1: float, f2: float = 0.0, transition_hz: float = 0.0, n_taps: int = 0):
+    """fcx_fir_design: the taps as a float64 array."""
+    import numpy as np
+    n = ctypes.c_int32()
+    check(lib.fcx_fir_design(kind, fs, f1, f2, transition_hz, n_taps, None, 0, ctypes.byref(n)), "fir_design")
+    taps = np.empty(n.value)
+    check(lib.fcx_fir_design(kind, fs, f1, f2, transition_hz, n_taps, taps.ctypes.data, n.value, ctypes.byref(n)),
+          "fir_design")
+    return taps
+
+
+class Stream:
+    """Stream front end (fcx_stream_*): block filtering and trial cutting on
+    device buffers (pointers as ints)."""
+
+    def __init__(self, n_channels: int, block_len: int, taps, threshold: float, pre: int, post: int,
+                 stream: int = 0):
+        import numpy as np
+        self.taps = np.ascontiguousarray(taps, dtype=np.float64)
+        c = fcx_stream_config()
+        c.struct_size = ctypes.sizeof(fcx_stream_config)
+        c.n_channels, c.block_len, c.n_taps = int(n_channels), int(block_len), int(self.taps.size)
+        c.taps = self.taps.ctypes.data
+        c.trigger_threshold = float(threshold)
+        c.pre_samples, c.post_samples = int(pre), int(post)
+        self.h = ctypes.c_void_p()
+        check(lib.fcx_stream_open(ctypes.byref(c), stream or None, ctypes.byref(self.h)), "stream_open")
+        self.C, self.block_len, self.len = n_channels, block_len, pre + post
+        self.delay = (self.taps.size - 1) // 2
+
+    def push(self, x_ptr: int, ld: int, trig_ptr: int, y_ptr: int = 0, trials_ptr: int = 0, cap: int = 0):
+        """Returns (status, n_trials, n_dropped)."""
+        n, d = ctypes.c_int32(), ctypes.c_int32()
+        st = lib.fcx_stream_push(self.h, x_ptr, ld, trig_ptr, y_ptr or None, trials_ptr or None, cap,
+                                 ctypes.byref(n), ctypes.byref(d))
+        return st, n.value, d.value
+
+    def close(self) -> int:
+        return lib.fcx_stream_close(self.h)
 
 
 def make_config(cfg: dict) -> fcx_config:

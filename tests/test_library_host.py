@@ -131,3 +131,18 @@ def test_xcor_config_and_footprint():
     assert fcx.footprint_bytes(dict(base, metrics=synth.XCOR, n_samples=1024, n_fft=1024)) > 0   # 1024+1023 <= 2048
     assert fcx.footprint_bytes(dict(base, metrics=synth.XCOR, n_samples=1025, n_fft=2048)) == -1
     assert fcx.footprint_bytes(dict(base, metrics=synth.XCOR, n_samples=1025, n_fft=2048, xcor_max_lag=1023)) > 0
+
+
+def test_fir_design_matches_oracle():
+    """The library's FIR design (host code) against the oracle's definition."""
+    from oracle import stream as so
+    for kind, f1, f2, T in [(fcx.FCX_FIR_LOWPASS, 40.0, 0.0, 101), (fcx.FCX_FIR_HIGHPASS, 20.0, 0.0, 401),
+                            (fcx.FCX_FIR_BANDPASS, 8.0, 30.0, 251)]:
+        got = fcx.fir_design(kind, 1000.0, f1, f2, n_taps=T)
+        assert np.allclose(got, so.fir_design(kind, 1000.0, f1, f2, n_taps=T), atol=1e-14, rtol=0)
+    assert fcx.fir_design(fcx.FCX_FIR_LOWPASS, 1000.0, 40.0, transition_hz=10.0).size == so.taps_for(1000.0, 10.0)
+    n = ctypes.c_int32()
+    for args in [(fcx.FCX_FIR_LOWPASS, 1000.0, 600.0, 0.0, 0.0, 101), (fcx.FCX_FIR_BANDPASS, 1000.0, 30.0, 8.0, 0.0, 101),
+                 (fcx.FCX_FIR_LOWPASS, 1000.0, 40.0, 0.0, 0.0, 100), (7, 1000.0, 40.0, 0.0, 0.0, 101),
+                 (fcx.FCX_FIR_LOWPASS, 1000.0, 40.0, 0.0, 0.0, 0)]:
+        assert fcx.lib.fcx_fir_design(*args, None, 0, ctypes.byref(n)) == fcx.FCX_E_INVAL, args
