@@ -9,7 +9,8 @@ Plain FP64 definitions, in this order:
 
   filter    y = h * x, the full causal convolution of the zero-extended
             segment x[0..M-1] with the FIR h[0..T-1] (length M + T - 1)
-  analytic  over F points (a power of two >= M + T - 1, zero padded):
+  analytic  over F points (the smallest power of two >= max(M + T - 1, 256),
+            zero padded):
               Y = DFT_F(y),  Z[k] = m[k] Y[k],
               m[0] = m[F/2] = 1,  m[k] = 2 for 0 < k < F/2,  m[k] = 0 above,
               z[n] = IDFT_F(Z)[n + D],  n = 0..M-1,  D = (T-1)/2
@@ -25,7 +26,10 @@ Plain FP64 definitions, in this order:
 Readings: the paper does not fix the filter, the transform length, the edge
 handling or the averaging axis of this approach; the definitions above are
 the textbook ones (they match scipy.signal.hilbert on the zero-padded full
-convolution, which pins them).
+convolution, which pins them).  The transform is at least 256 points long:
+any length >= M + T - 1 gives the analytic signal of the zero-extended
+filtered segment, a longer one with a finer-sampled spectrum, so the length
+is part of the definition and fixed here.
 """
 from __future__ import annotations
 
@@ -36,7 +40,7 @@ from . import DELTA_F32, METRICS7, _load, _ptr, all_pairs
 
 def fft_len(M: int, T: int) -> int:
     n = M + T - 1
-    F = 1
+    F = 256
     while F < n:
         F *= 2
     return F
