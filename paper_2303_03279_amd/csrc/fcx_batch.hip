@@ -106,20 +106,27 @@ template <> struct Gram<FCX_GRAM_BF16X3_ID> {
 };
 
 // ------------------------------------------------------------- power sums
+// 64 (bin, node) entries per workgroup; its four wavefronts take every fourth
+// trial and their partial sums are added in wavefront order
 __global__ __launch_bounds__(256) void k_psd_batch(SessDev<float> s, int K)
 {
+    __shared__ double part[3][64];
     if (s.ctl->bad) return;
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= s.B * s.N) return;
-    const int b = e / s.N, i = e % s.N;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
+    const bool live = e < s.B * s.N;
+    const int b = live ? e / s.N : 0, i = live ? e % s.N : 0;
     const float2 *ring = (const float2 *)s.ring;
     double p = 0.0;
-    for (int t = 0; t < K; ++t)
-        for (int l = 0; l < s.L; ++l) {
-            const float2 v = ring[(((size_t)t * s.B + b) * s.L + l) * s.N + i];
-            p += s.lamw[l] * ((double)v.x * v.x + (double)v.y * v.y);
-        }
-    s.psd[e] = p;
+    if (live)
+        for (int t = w; t < K; t += 4)
+            for (int l = 0; l < s.L; ++l) {
+                const float2 v = ring[(((size_t)t * s.B + b) * s.L + l) * s.N + i];
+                p += s.lamw[l] * ((double)v.x * v.x + (double)v.y * v.y);
+            }
+    if (w) part[w - 1][lane] = p;
+    __syncthreads();
+    if (w == 0 && live) s.psd[e] = ((p + part[0][lane]) + part[1][lane]) + part[2][lane];
 }
 
 // ---------------------------------------------------------------- pairs
@@ -164,8 +171,10 @@ __global__ __launch_bounds__(BT_THREADS) void k_pair_batch(SessDev<float> s, int
         for (int t0 = 0; t0 < K; t0 += TPC) {
             const int nk = min(TPC, K - t0);
             __syncthreads();
+            // consecutive lanes take consecutive nodes of one column, so a
+            // wavefront reads two contiguous runs of 32 nodes
             for (int e = threadIdx.x; e < 64 * BT_CC; e += BT_THREADS) {
-                const int node = e / BT_CC, col = e % BT_CC;
+                const int node = e & 63, col = e >> 6;
                 const int t = col / L, l = col % L;
                 const int g = node < 32 ? R0 + node : C0 + node - 32;
                 float2 v = make_float2(0.f, 0.f), u = make_float2(0.f, 0.f);
@@ -284,9 +293,9 @@ __device__ __forceinline__ void cor_chunk(const float *Zr, const float *Zc, int 
                 bh[e] = (__bf16)b;
             } else {
                 ah[e] = bf_hi(a);
-            al[e] = bf_lo(a);
+                al[e] = bf_lo(a);
                 bh[e] = bf_hi(b);
-            bl[e] = bf_lo(b);
+                bl[e] = bf_lo(b);
             }
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
@@ -398,7 +407,7 @@ hipError_t launch_batch_commit(DevCtl *ctl, long long K, hipStream_t st)
 
 hipError_t launch_psd_batch(const SessDev<float> &s, int K, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_psd_batch, dim3((s.B * s.N + 255) / 256), dim3(256), 0, st, s, K);
+    hipLaunchKernelGGL(k_psd_batch, dim3((s.B * s.N + 63) / 64), dim3(256), 0, st, s, K);
     return hipGetLastError();
 }
 
