@@ -348,6 +348,43 @@ def run_stream(fcx, torch, blocks):
                 block_p99_ms=float(np.percentile(lat_ms, 99)), block_budget_ms=Bl / fs * 1e3)
 
 
+def run_hilbert(fcx, torch, cfg, pool_dev, reps):
+    """Time-resolved analytic-signal connectivity on one 5000-node trial of
+    the source-space workload: alpha band-pass 8-12 Hz (4 Hz transition,
+    825 taps, F = 2048), all seven phase metrics, (a) windows of 100 samples
+    every 50 (9 networks per segment) and (b) the whole segment as one
+    window.  HIP-event time per segment on the calling stream; the work unit
+    is one pair x sample of a window."""
+    N, M = cfg["n_nodes"], cfg["n_samples"]
+    P = N * (N - 1) // 2
+    fs = cfg["fs_hz"]
+    taps = fcx.fir_design(fcx.FCX_FIR_BANDPASS, fs, 8.0, 12.0, transition_hz=4.0)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, L, H in (("windows_100_hop_50", 100, 50), ("whole_segment", 0, 0)):
+        h = fcx.Hilbert(N, M, taps, L, H, stream=stream.cuda_stream)
+        out = torch.empty((h.n_windows, 7, P), dtype=torch.float32, device="cuda")
+        fcx.check(h.run(pool_dev[0].data_ptr(), M, out.data_ptr()))
+        times = []
+        for r in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fcx.check(h.run(pool_dev[1 + r % (pool_dev.shape[0] - 1)].data_ptr(), M, out.data_ptr()))
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        K = M if L == 0 else L
+        units = P * K * h.n_windows
+        res[name] = dict(windows=h.n_windows, window_len=K, ms_per_segment=ms,
+                         pair_samples_per_s=units / (ms * 1e-3))
+        fcx.check(h.close())
+        del out
+        torch.cuda.empty_cache()
+    return dict(workload=f"N={N} (P={P}), segments of {M} samples at {fs:.0f} Hz, band-pass 8-12 Hz "
+                         f"(T={taps.size}, F=2048), 7 phase metrics", **res)
+
+
 def run_netsel(fcx, torch, cfg, pool_dev, reps, fraction=0.05):
     """fcx_network_select on the COH network of a short 5000-node session:
     HIP-event time per call on the calling stream, and its algorithmic HBM
@@ -435,6 +472,8 @@ def main():
                     help="timed blocks of the stream -> trials -> session pipeline, 0 to skip")
     ap.add_argument("--netsel-reps", type=int, default=5,
                     help="timed calls of the network post-processing on a 5000-node network, 0 to skip")
+    ap.add_argument("--hilbert-reps", type=int, default=5,
+                    help="timed segments of the 5000-node analytic-signal variant, 0 to skip")
     ap.add_argument("--large-steps", type=int, default=5,
                     help="timed pushes of the 10000-node multitaper session, 0 to skip")
     args = ap.parse_args()
@@ -555,6 +594,11 @@ def main():
         print("[bench] network post-processing", file=sys.stderr, flush=True)
         netsel = run_netsel(fcx, torch, cfg, pool_dev, args.netsel_reps)
 
+    hilbert = None
+    if args.hilbert_reps > 0:
+        print("[bench] analytic-signal variant", file=sys.stderr, flush=True)
+        hilbert = run_hilbert(fcx, torch, cfg, pool_dev, args.hilbert_reps)
+
     large = None
     if args.large_steps > 0:
         print("[bench] 10000-node multitaper session", file=sys.stderr, flush=True)
@@ -622,6 +666,7 @@ def main():
         "sensor_space": sensor,
         "xcor": xcor,
         "network_select": netsel,
+        "hilbert": hilbert,
         "stream_pipeline": stream_leg,
         "serving": serving,
         "cpu_baseline": base,

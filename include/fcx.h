@@ -292,6 +292,63 @@ fcx_status fcx_stream_push(fcx_stream *s, const float *x, int64_t ld, const floa
 fcx_status fcx_stream_close(fcx_stream *s);
 
 /* ------------------------------------------------------------------------
+ * Time-resolved phase connectivity from the analytic signal: the approach
+ * the paper sets against its own in Sec. 4 (restrict every node to a narrow
+ * band with a temporal filter, form the analytic signal by the Hilbert
+ * transform, and estimate connectivity from the instantaneous phase and
+ * amplitude), on one segment of N nodes x M samples at a time:
+ *
+ *   y_i   = h * x_i, the full causal convolution of the zero-extended
+ *           segment (length M + T - 1)
+ *   z_i   = analytic signal of y_i over F points (the smallest power of
+ *           two >= max(M + T - 1, 256), zero padded): spectrum x 1 at DC
+ *           and F/2, x 2 at the positive frequencies, 0 at the negative
+ *           ones; samples D .. D + M - 1 with D = (T - 1) / 2 (so Re z_i is
+ *           the delay-compensated filtered segment)
+ *   windows of win_len samples starting at 0, hop, 2 hop, ... (while they
+ *           fit in M): the seven spectral metrics of the session (COH,
+ *           IMCOH, PLV, PLI, WPLI, USPLI, DSWPLI, same conventions) with the
+ *           window's samples in the role of the trials, i.e. from the
+ *           instantaneous cross-spectra z_i(t) conj(z_j(t)) and powers
+ *           |z_i(t)|^2.
+ * ------------------------------------------------------------------------ */
+typedef struct fcx_hilbert fcx_hilbert;
+
+typedef struct {
+    uint32_t struct_size;      /* sizeof(fcx_hilbert_config)                         */
+    int32_t n_nodes;           /* N, 2 <= N <= 65536                                 */
+    int32_t n_samples;         /* M >= 1 samples per segment; M + T - 1 <= 4096      */
+    int32_t n_taps;            /* T, odd (1 with taps {1}: no filter)                */
+    const double *taps;        /* host, T coefficients (copied), e.g. fcx_fir_design */
+    int32_t win_len;           /* samples per window, 1..M; 0: M (one window)        */
+    int32_t win_hop;           /* samples between window starts; 0: win_len          */
+    uint32_t metrics;          /* OR of FCX_COH .. FCX_DSWPLI, non-zero              */
+    int32_t gram_precision;    /* FCX_GRAM_* of the cross-spectrum Gram sums         */
+} fcx_hilbert_config;
+
+/* Open on the current device; work is ordered on hip_stream (NULL: the
+ * default stream).  Errors: FCX_E_INVAL, FCX_E_NOMEM, FCX_E_DEVICE. */
+fcx_status fcx_hilbert_open(const fcx_hilbert_config *cfg, void *hip_stream, fcx_hilbert **out);
+
+/* Number of windows per segment and the transform length F (either pointer
+ * may be NULL). */
+fcx_status fcx_hilbert_info(fcx_hilbert *h, int32_t *n_windows, int32_t *fft_len);
+
+/*
+ * One segment: x [N][M] (device FP32, row stride ld >= M).  out (device
+ * FP32) receives metric m (bit 1 << m) of window w for pair (i, j) at
+ * out[(w * 7 + m) * P + idx(i, j)], P = N (N - 1) / 2, for the requested
+ * metrics (the other rows are not written).  z (device, may be NULL)
+ * receives the analytic signal as [M][N] complex FP32 (re, im).  The call
+ * only enqueues work on the handle's stream.  Nodes 2k and 2k + 1 share one
+ * transform: a non-finite input sample makes the analytic signals of both,
+ * and so the metrics of their pairs, non-finite.  Errors: FCX_E_INVAL (NULL x or
+ * out, ld < M), FCX_E_CLOSED, FCX_E_DEVICE.
+ */
+fcx_status fcx_hilbert_run(fcx_hilbert *h, const float *x, int64_t ld, float *out, float *z);
+fcx_status fcx_hilbert_close(fcx_hilbert *h);
+
+/* ------------------------------------------------------------------------
  * Serving: many concurrent sessions, continuous batching.
  *
  * A server owns an HBM budget.  fcx_server_open admits a session only if its

@@ -89,6 +89,23 @@ class fcx_stream_config(ctypes.Structure):
 
 FCX_FIR_LOWPASS, FCX_FIR_HIGHPASS, FCX_FIR_BANDPASS = 0, 1, 2
 
+
+GRAMS = {"fp32": FCX_GRAM_FP32, "bf16": FCX_GRAM_BF16, "bf16x3": FCX_GRAM_BF16X3}
+
+
+class fcx_hilbert_config(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("n_nodes", ctypes.c_int32),
+        ("n_samples", ctypes.c_int32),
+        ("n_taps", ctypes.c_int32),
+        ("taps", ctypes.c_void_p),
+        ("win_len", ctypes.c_int32),
+        ("win_hop", ctypes.c_int32),
+        ("metrics", ctypes.c_uint32),
+        ("gram_precision", ctypes.c_int32),
+    ]
+
 P = ctypes.c_void_p
 I32, I64, U32, U64, D = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
 PI32, PI64, PD, PU64 = (ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
@@ -120,6 +137,10 @@ _SIGS = {
     "fcx_stream_open": (ctypes.c_int, [ctypes.POINTER(fcx_stream_config), P, PP]),
     "fcx_stream_push": (ctypes.c_int, [P, P, I64, P, P, P, I32, PI32, PI32]),
     "fcx_stream_close": (ctypes.c_int, [P]),
+    "fcx_hilbert_open": (ctypes.c_int, [ctypes.POINTER(fcx_hilbert_config), P, PP]),
+    "fcx_hilbert_info": (ctypes.c_int, [P, PI32, PI32]),
+    "fcx_hilbert_run": (ctypes.c_int, [P, P, I64, P, P]),
+    "fcx_hilbert_close": (ctypes.c_int, [P]),
     "fcx_server_create": (ctypes.c_int, [I64, PP]),
     "fcx_server_open": (ctypes.c_int, [P, PCFG, PP]),
     "fcx_server_submit": (ctypes.c_int, [P, P, P, I64, PU64]),
@@ -203,6 +224,34 @@ class Stream:
         return lib.fcx_stream_close(self.h)
 
 
+class Hilbert:
+    """Time-resolved analytic-signal connectivity (fcx_hilbert_*) on device
+    buffers (pointers as ints)."""
+
+    def __init__(self, n_nodes: int, n_samples: int, taps, win_len: int = 0, win_hop: int = 0,
+                 metrics: int = 0x7F, gram: str = "fp32", stream: int = 0):
+        import numpy as np
+        self.taps = np.ascontiguousarray(taps, dtype=np.float64)
+        c = fcx_hilbert_config()
+        c.struct_size = ctypes.sizeof(fcx_hilbert_config)
+        c.n_nodes, c.n_samples, c.n_taps = int(n_nodes), int(n_samples), int(self.taps.size)
+        c.taps = self.taps.ctypes.data
+        c.win_len, c.win_hop, c.metrics = int(win_len), int(win_hop), int(metrics)
+        c.gram_precision = GRAMS[gram]
+        self.h = ctypes.c_void_p()
+        check(lib.fcx_hilbert_open(ctypes.byref(c), stream or None, ctypes.byref(self.h)), "hilbert_open")
+        nw, F = ctypes.c_int32(), ctypes.c_int32()
+        check(lib.fcx_hilbert_info(self.h, ctypes.byref(nw), ctypes.byref(F)), "hilbert_info")
+        self.N, self.M, self.n_windows, self.fft_len = n_nodes, n_samples, nw.value, F.value
+        self.P = n_nodes * (n_nodes - 1) // 2
+
+    def run(self, x_ptr: int, ld: int, out_ptr: int, z_ptr: int = 0) -> int:
+        return lib.fcx_hilbert_run(self.h, x_ptr, ld, out_ptr, z_ptr or None)
+
+    def close(self) -> int:
+        return lib.fcx_hilbert_close(self.h)
+
+
 def make_config(cfg: dict) -> fcx_config:
     """fcx_config from a plain dict (keys as in the C struct; taper 'hann'/'dpss',
     gram 'fp32'/'bf16'/'bf16x3', elem 'f32'/'f64')."""
@@ -219,8 +268,7 @@ def make_config(cfg: dict) -> fcx_config:
     c.dpss_nw = float(cfg.get("dpss_nw", 0.0))
     c.dpss_k = int(cfg.get("dpss_k", 0))
     c.metrics = int(cfg.get("metrics", 255))
-    c.gram_precision = {"fp32": FCX_GRAM_FP32, "bf16": FCX_GRAM_BF16,
-                        "bf16x3": FCX_GRAM_BF16X3}[cfg.get("gram", "fp32")]
+    c.gram_precision = GRAMS[cfg.get("gram", "fp32")]
     c.elem = {"f32": FCX_ELEM_F32, "f64": FCX_ELEM_F64}[cfg.get("elem", "f32")]
     c.xcor_max_lag = int(cfg.get("xcor_max_lag", 0))
     return c

@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfcx.so")
 
 SOURCES = ["fcx_kernels.hip", "fcx_batch.hip", "fcx_network.hip", "fcx_xcor.hip", "fcx_stream.hip",
-           "fcx_host.cpp", "fcx_server.cpp"]
+           "fcx_hilbert.hip", "fcx_host.cpp", "fcx_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

@@ -1,0 +1,224 @@
+"""Time-resolved analytic-signal connectivity on the device (fcx_hilbert_*)
+against the oracle (oracle/hilbert.py): the analytic signal element by
+element, and every window's seven metrics for every pair (sizes that span
+several tiles with a ragged tail, every transform length, windows of one
+sample, overlapping windows), plus sampled pairs at 5000 nodes.
+
+Tolerances.  The analytic signal: 1e-5 of its largest magnitude.  The
+metrics: 1e-5 absolute, plus for PLI / USPLI the oracle's tie allowances, and
+for WPLI / DSWPLI the first-order effect of the analytic signal's FP32
+deviation: with e the largest deviation of the device's z from the oracle's
+(held to the bar above first; at least one FP32 ulp of max|z|), every
+Im(z_i conj z_j) may move by e (|z_i| + |z_j|).  These two metrics divide by
+sums of |Im| that are small for pairs in near-constant phase, so their
+allowance grows as 1 / sum |Im|; it stays below the base bound for almost all
+pairs (the share is logged)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import TOL, log, tie_bounds
+from oracle import hilbert as oh
+from oracle import stream as so
+
+pytestmark = pytest.mark.gpu
+
+M7 = oracle.METRICS7
+BOUND = {"fp32": dict.fromkeys(M7, TOL),
+         "bf16x3": dict.fromkeys(M7, TOL),
+         "bf16": dict(coh=3e-3, imcoh=3e-3, plv=3e-3, pli=TOL, wpli=5e-3, uspli=TOL, dswpli=5e-3)}
+
+
+@pytest.fixture(scope="module")
+def fcx():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    import paper_2303_03279_amd as m
+    return m
+
+
+def _segment(seed, N, M, fs=1000.0):
+    """Nodes that share three sinusoidal sources at node-specific lags, under
+    independent white noise of about the same in-band power (float32)."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(M + 64) / fs
+    src = 0.2 * np.stack([np.sin(2 * np.pi * f * t + rng.uniform(0, 2 * np.pi)) for f in (10.0, 17.0, 23.0)])
+    x = rng.standard_normal((N, M)).astype(np.float64)
+    for i in range(N):
+        lag = int(rng.integers(0, 64))
+        x[i] += rng.standard_normal(3) @ src[:, lag:lag + M]
+    return x.astype(np.float32)
+
+
+def _taps(T, fs=1000.0, f1=8.0, f2=30.0):
+    return np.ones(1) if T == 1 else so.fir_design(so.BANDPASS, fs, f1, f2, n_taps=T)
+
+
+def _run(fcx, x, taps, L, H, gram="fp32", want_z=True):
+    import torch
+    N, M = x.shape
+    h = fcx.Hilbert(N, M, taps, L, H, gram=gram)
+    xd = torch.from_numpy(x).cuda()
+    out = torch.full((h.n_windows, 7, h.P), float("nan"), dtype=torch.float32, device="cuda")
+    z = torch.empty((M, N, 2), dtype=torch.float32, device="cuda") if want_z else None
+    fcx.check(h.run(xd.data_ptr(), M, out.data_ptr(), z.data_ptr() if want_z else 0), "hilbert_run")
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    zc = None
+    if want_z:
+        zz = z.cpu().numpy()
+        zc = (zz[..., 0] + 1j * zz[..., 1]).T.astype(np.complex128)     # [N][M]
+    nw, F = h.n_windows, h.fft_len
+    fcx.check(h.close())
+    return res, zc, nw, F
+
+
+def _z_deviation(z, zr):
+    return max(float(np.max(np.abs(z - zr))), 2.0 ** -24 * float(np.max(np.abs(zr))))
+
+
+def _rounding_allowance(zr, pi, pj, r, e):
+    """First-order bounds of |d WPLI| and |d DSWPLI| for a perturbation of
+    every z sample by at most e (see the module docstring)."""
+    za, zb = zr[pi, r["start"]:r["start"] + r["K"]], zr[pj, r["start"]:r["start"] + r["K"]]
+    im = (za * np.conj(zb)).imag
+    d = e * (np.abs(za) + np.abs(zb))                 # bound of |d Im| per sample
+    A, Q, Si = np.abs(im).sum(1), (im * im).sum(1), im.sum(1)
+    E1, E2 = d.sum(1), (np.abs(im) * d).sum(1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        wpli = np.where(A > 0, (1.0 + np.abs(Si) / A) * E1 / A, 0.0)
+        den = A * A - Q
+        ds = np.abs((Si * Si - Q) / den)
+        dsw = np.where(den > 0, (2 * np.abs(Si) * E1 + 2 * E2 + ds * (2 * A * E1 + 2 * E2)) / den, 0.0)
+    return {"wpli": wpli, "dswpli": dsw}
+
+
+def _compare(res, ref_windows, bound, label, zr=None, pairs=None, e=0.0):
+    worst, wide = {}, {}
+    for w, r in enumerate(ref_windows):
+        K = r["K"]
+        dpli, dus = tie_bounds(r, K)
+        cond = _rounding_allowance(zr, pairs[0], pairs[1], r, e) if zr is not None else {}
+        for q, m in enumerate(M7):
+            got = res[w, q].astype(np.float64)
+            want = r["band"][m]
+            if m in ("uspli", "dswpli") and K < 2:
+                assert np.all(np.isnan(got)), (label, w, m)
+                continue
+            err = np.abs(got - want)
+            allow = np.full(err.shape, bound[m]) + (dpli if m == "pli" else 0.0) + (dus if m == "uspli" else 0.0)
+            allow = allow + cond.get(m, 0.0)
+            bad = err > allow
+            assert not bad.any(), (f"{label} window {w} {m}: {int(bad.sum())} pairs over, worst {err.max():.3e} "
+                                   f"(gpu {got[np.argmax(err)]:.9f}, oracle {want[np.argmax(err)]:.9f})")
+            worst[m] = max(worst.get(m, 0.0), float(err.max()) if err.size else 0.0)
+            if m in cond and err.size:
+                wide[m] = max(wide.get(m, 0.0), float(np.mean(cond[m] > bound[m])))
+    log(f"{label}: max abs err " + ", ".join(f"{m}={v:.2e}" for m, v in worst.items()) +
+        "; share of pairs whose rounding allowance exceeds the base bound: " +
+        ", ".join(f"{m}={v:.3f}" for m, v in wide.items()))
+
+
+@pytest.mark.parametrize("N,M,T,L,H", [
+    (7, 300, 101, 0, 0),          # F=512, odd N, one window
+    (70, 500, 251, 100, 50),      # F=1024, two tile rows with a ragged tail, overlapping windows
+    (130, 256, 1, 64, 64),        # F=256, no filter, three tile rows
+    (5, 40, 1, 1, 1),             # windows of one sample: USPLI / DSWPLI undefined
+    (33, 1500, 301, 700, 500),    # F=2048, a tail of samples after the last window
+    (9, 1000, 3001, 250, 250),    # F=4096, a long filter
+])
+def test_analytic_and_windows_vs_oracle(fcx, N, M, T, L, H):
+    x = _segment(N * 7 + M, N, M)
+    taps = _taps(T)
+    log(f"hilbert N={N} M={M} T={T} L={L} H={H}")
+    res, z, nw, F = _run(fcx, x, taps, L, H)
+    assert F == oh.fft_len(M, T)
+    zr = oh.analytic(x.astype(np.float64), taps)
+    zerr = np.max(np.abs(z - zr)) / np.max(np.abs(zr))
+    log(f"  F={F} windows={nw}: analytic max rel err {zerr:.2e}")
+    assert zerr <= TOL
+    ref = oh.network(zr, L, H, scale=oh.tie_scale(x, F))
+    assert nw == len(ref)
+    _compare(res, ref, BOUND["fp32"], f"N={N} M={M} T={T}", zr, oracle.all_pairs(N), _z_deviation(z, zr))
+
+
+@pytest.mark.parametrize("gram", ["bf16x3", "bf16"])
+def test_gram_precisions(fcx, gram):
+    N, M, T, L, H = 96, 400, 151, 200, 100
+    x = _segment(5, N, M)
+    taps = _taps(T)
+    res, z, _, F = _run(fcx, x, taps, L, H, gram=gram)
+    zr = oh.analytic(x.astype(np.float64), taps)
+    ref = oh.network(zr, L, H, scale=oh.tie_scale(x, F))
+    _compare(res, ref, BOUND[gram], f"gram {gram}", zr, oracle.all_pairs(N), _z_deviation(z, zr))
+
+
+def test_metric_subset_leaves_other_rows(fcx):
+    import torch
+    N, M = 40, 200
+    x = _segment(9, N, M)
+    taps = _taps(51)
+    h = fcx.Hilbert(N, M, taps, 100, 100, metrics=fcx.FCX_PLV | fcx.FCX_WPLI)
+    xd = torch.from_numpy(x).cuda()
+    out = torch.full((h.n_windows, 7, h.P), 7.0, dtype=torch.float32, device="cuda")
+    fcx.check(h.run(xd.data_ptr(), M, out.data_ptr()))
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    fcx.check(h.close())
+    assert np.all(res[:, [0, 1, 3, 5, 6]] == 7.0)
+    ref = oh.network(oh.analytic(x.astype(np.float64), taps), 100, 100)
+    for w, r in enumerate(ref):
+        assert np.max(np.abs(res[w, 2] - r["band"]["plv"])) <= TOL
+        assert np.max(np.abs(res[w, 4] - r["band"]["wpli"])) <= TOL
+
+
+def test_full_size_sampled_pairs(fcx):
+    """5000 nodes, 500 samples at 1 kHz, an 8-12 Hz band-pass with a 4 Hz
+    transition (825 taps, F=2048), windows of 100 samples every 50: sampled
+    rows x sampled columns against the oracle, and a repeat run bitwise
+    equal."""
+    import torch
+    N, M, fs = 5000, 500, 1000.0
+    rng = np.random.default_rng(77)
+    x = _segment(77, N, M)
+    taps = so.fir_design(so.BANDPASS, fs, 8.0, 12.0, transition_hz=4.0)
+    assert taps.size == 825
+    log(f"hilbert full size N={N} M={M} T={taps.size}")
+    h = fcx.Hilbert(N, M, taps, 100, 50)
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty((h.n_windows, 7, h.P), dtype=torch.float32, device="cuda")
+    zd = torch.empty((M, N, 2), dtype=torch.float32, device="cuda")
+    fcx.check(h.run(xd.data_ptr(), M, out.data_ptr(), zd.data_ptr()))
+    torch.cuda.synchronize()
+    rows = np.sort(rng.choice(N - 1, 24, replace=False))
+    cols = np.sort(rng.choice(N, 160, replace=False))
+    cols = np.unique(np.concatenate([cols, [N - 1, N - 2]]))
+    pi, pj = [], []
+    for r in rows:
+        for c in cols:
+            if c > r:
+                pi.append(r)
+                pj.append(c)
+    pi, pj = np.array(pi), np.array(pj)
+    nodes = np.unique(np.concatenate([pi, pj]))
+    loc = {int(n): k for k, n in enumerate(nodes)}
+    zr = oh.analytic(x[nodes].astype(np.float64), taps)
+    ref = oh.network(zr, 100, 50, pi=[loc[int(a)] for a in pi], pj=[loc[int(b)] for b in pj],
+                     scale=oh.tie_scale(x[nodes], h.fft_len))
+    idx = oracle.packed_index(pi, pj, N)
+    res = out[:, :, torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert h.n_windows == len(ref) == 9
+    la = np.array([loc[int(a)] for a in pi])
+    lb = np.array([loc[int(b)] for b in pj])
+    zs = zd[:, torch.from_numpy(nodes).cuda()].cpu().numpy()
+    zdev = (zs[..., 0] + 1j * zs[..., 1]).T.astype(np.complex128)
+    e = _z_deviation(zdev, zr)
+    log(f"  analytic max rel err {e / np.max(np.abs(zr)):.2e} on the sampled nodes")
+    assert e <= TOL * np.max(np.abs(zr))
+    _compare(res, ref, BOUND["fp32"], f"N={N} sampled {pi.size} pairs", zr, (la, lb), e)
+    out2 = torch.empty_like(out)
+    fcx.check(h.run(xd.data_ptr(), M, out2.data_ptr()))
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+    fcx.check(h.close())

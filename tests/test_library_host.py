@@ -146,3 +146,32 @@ def test_fir_design_matches_oracle():
                  (fcx.FCX_FIR_LOWPASS, 1000.0, 40.0, 0.0, 0.0, 100), (7, 1000.0, 40.0, 0.0, 0.0, 101),
                  (fcx.FCX_FIR_LOWPASS, 1000.0, 40.0, 0.0, 0.0, 0)]:
         assert fcx.lib.fcx_fir_design(*args, None, 0, ctypes.byref(n)) == fcx.FCX_E_INVAL, args
+
+
+def test_hilbert_rejects_bad_configs():
+    """fcx_hilbert_open checks its configuration before any device work; an
+    unknown handle is reported as closed."""
+    taps = np.ones(5) / 5.0
+
+    def cfg(**kw):
+        c = fcx.fcx_hilbert_config()
+        c.struct_size = ctypes.sizeof(fcx.fcx_hilbert_config)
+        c.n_nodes, c.n_samples, c.n_taps, c.taps = 10, 100, taps.size, taps.ctypes.data
+        c.win_len, c.win_hop, c.metrics, c.gram_precision = 0, 0, 0x7F, 0
+        for k, v in kw.items():
+            setattr(c, k, v)
+        return c
+
+    h = ctypes.c_void_p()
+    for bad in [dict(n_nodes=1), dict(n_nodes=70000), dict(n_samples=0), dict(n_taps=4), dict(n_taps=0),
+                dict(metrics=0), dict(metrics=0x80), dict(metrics=0x100), dict(win_len=101), dict(win_len=-1),
+                dict(win_hop=-2), dict(gram_precision=3), dict(n_samples=4000, n_taps=99), dict(taps=None),
+                dict(struct_size=4)]:
+        assert fcx.lib.fcx_hilbert_open(ctypes.byref(cfg(**bad)), None, ctypes.byref(h)) == fcx.FCX_E_INVAL, bad
+    nan_taps = np.array([0.2, np.nan, 0.2])
+    c = cfg(n_taps=3, taps=nan_taps.ctypes.data)
+    assert fcx.lib.fcx_hilbert_open(ctypes.byref(c), None, ctypes.byref(h)) == fcx.FCX_E_INVAL
+    bogus = ctypes.c_void_p(987654321)
+    assert fcx.lib.fcx_hilbert_run(bogus, 1, 100, 1, None) == fcx.FCX_E_CLOSED
+    assert fcx.lib.fcx_hilbert_info(bogus, None, None) == fcx.FCX_E_CLOSED
+    assert fcx.lib.fcx_hilbert_close(bogus) == fcx.FCX_E_CLOSED
