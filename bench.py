@@ -388,10 +388,9 @@ def run_hilbert(fcx, torch, cfg, pool_dev, reps):
 def run_netsel(fcx, torch, cfg, pool_dev, reps, fraction=0.05):
     """fcx_network_select on the COH network of a short 5000-node session:
     HIP-event time per call on the calling stream, and its algorithmic HBM
-    bytes: the network is read once for the maximum, once per radix pass (4),
-    twice by the per-node pass (each edge from both ends) and once by the
-    final pass, which writes the normalised network and the flags:
-    P * (4 * 9 + 4 + 1) bytes."""
+    bytes: the network is read once for the maximum, once per radix pass (3)
+    and once by the row pass, which writes the normalised network and the
+    flags: P * (4 * 5 + 4 + 1) bytes."""
     N, M = cfg["n_nodes"], cfg["n_samples"]
     P = N * (N - 1) // 2
     s = fcx.Session(dict(cfg, metrics=fcx.FCX_COH, window_trials=3))
@@ -418,7 +417,7 @@ def run_netsel(fcx, torch, cfg, pool_dev, reps, fraction=0.05):
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
     ms = float(np.median(times))
-    algo = P * (4 * 9 + 4 + 1)
+    algo = P * (4 * 5 + 4 + 1)
     return dict(workload=f"N={N} COH network (P={P}), strongest {fraction:.0%}", ms=ms,
                 algorithmic_bytes=algo, gbs=algo / (ms * 1e-3) / 1e9,
                 hbm_frac=algo / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), k=info["k"], n_selected=info["n_selected"])

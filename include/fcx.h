@@ -219,12 +219,15 @@ fcx_status fcx_probe_copy(void *dst, const void *src, int64_t n_bytes, void *hip
  *   selected_e  = 1 iff e in E and |w_e| >= threshold (ties are all kept,
  *                 so n_selected >= k; equal when the weights are distinct)
  *   degree_i    = selected edges at node i
- *   strength_i  = sum of |w_norm_e| over them (FP64 sum, stored as FP32)
+ *   strength_i  = sum of |w_norm_e| over them (summed exactly in units of
+ *                 2^-32, stored as FP32)
  * Strength is taken on |w| so that signed ImCoh keeps its strongest negative
  * edges.  w, w_norm [P], selected [P] (bytes), degree and strength [n] are
  * device pointers; any output may be NULL; w_norm may equal w (in place).
  * The call enqueues its kernels on hip_stream (NULL: the default stream),
- * waits for them and fills *info (may be NULL).  Errors: FCX_E_INVAL for
+ * waits for them and fills *info (may be NULL).  The first call on a device
+ * allocates a control block of about 1 MB that is kept until the process
+ * ends; calls on one device are serialised on it.  Errors: FCX_E_INVAL for
  * n_nodes outside [2, 65536], a NULL w or a fraction outside [0, 1];
  * FCX_E_NOMEM / FCX_E_DEVICE from HIP.
  * ------------------------------------------------------------------------ */

@@ -7,17 +7,24 @@
 // On a packed upper-triangle FP32 network w[P]:
 //   k_sel_scan    max |w| over the finite edges and their count
 //   k_sel_init    k = min(ceil(f P), finite edges)
-//   k_sel_hist    \  four passes of an 8-bit radix select on the bits of
-//   k_sel_pick    /  |w| (monotone for non-negative floats): the exact key T
-//                    of the k-th strongest edge
-//   k_sel_nodes   one wavefront per node: degree and strength over its N-1
-//                 edges (ascending partner, FP64 sum)
-//   k_sel_apply   w / max and the selected flags (|w| >= T), counted
+//   k_sel_hist    \  three passes (11, 10, 10 bits) of a radix select on the
+//   k_sel_pick    /  bits of |w| (monotone for non-negative floats): the
+//                    exact key T of the k-th strongest edge
+//   k_sel_rows    one wavefront per row of the triangle: w / max, the
+//                 selected flags (|w| >= T), their count, and the degree and
+//                 strength of both ends of every selected edge
+//   k_sel_node_out  degree and strength out
 // Every edge tied with T is selected, so the selected set is unique.
 #include "fcx_device.h"
 
 #include <math.h>
 #include <string.h>
+
+#include <stddef.h>
+
+#include <mutex>
+#include <new>
+#include <unordered_map>
 
 #include "fcx.h"
 
@@ -25,16 +32,31 @@
 
 namespace fcx {
 
+// Block results are spread over SEL_SLOTS copies of every counter (slot =
+// block index mod SEL_SLOTS) so that no single address takes one atomic per
+// block; the single-block kernels fold the slots.
+constexpr int SEL_SLOTS = 16;
+constexpr int SEL_THREADS = 256;
+constexpr int SEL_BINS = 2048;     // largest digit: 11 bits
+constexpr int SEL_MAX_NODES = 65536;
+constexpr int SEL_MAX_BLOCKS = 2048;          // grid of the streaming passes
+constexpr double SEL_FIX = 4294967296.0;      // 2^32
+constexpr unsigned long long SEL_DEG1 = 1ull << 48;
+
 struct SelCtl {
     unsigned int maxbits;       // max |w| as float bits
     unsigned int prefix, mask;  // radix-select state: key bits found so far
     unsigned int none;          // k == 0: nothing is selected
     long long k, k_left;
     unsigned long long n_finite, n_selected;
-    unsigned int hist[256];
+    unsigned long long slot_ns[SEL_SLOTS];
+    unsigned int blk_max[SEL_MAX_BLOCKS];        // per scan block: max key, finite count
+    unsigned long long blk_nf[SEL_MAX_BLOCKS];
+    unsigned int hist[SEL_SLOTS][SEL_BINS];
+    // per node: selected edges (bits 63..48) and strength in units of 2^-32
+    // (bits 47..0; at most 65535 edges of |w_norm| <= 1 fit without carry)
+    unsigned long long node[SEL_MAX_NODES];
 };
-
-constexpr int SEL_THREADS = 256;
 
 __device__ __forceinline__ bool sel_key(float v, unsigned int &key)
 {
@@ -43,41 +65,113 @@ __device__ __forceinline__ bool sel_key(float v, unsigned int &key)
     return true;
 }
 
-__global__ __launch_bounds__(SEL_THREADS) void k_sel_scan(const float *__restrict__ w, long long P, SelCtl *c)
+// Element e of w, loaded as float4 where the array allows (VEC: w is 16-byte
+// aligned); the loop covers the whole array: P4 = P / 4 vectors, then the
+// P mod 4 tail by the first block.
+template <bool VEC, typename F>
+__device__ __forceinline__ void sel_for_each(const float *__restrict__ w, long long P, F &&f)
 {
-    __shared__ unsigned int smax[SEL_THREADS];
-    __shared__ unsigned long long scnt[SEL_THREADS];
-    unsigned int mx = 0;
-    unsigned long long nf = 0;
-    for (long long e = (long long)blockIdx.x * SEL_THREADS + threadIdx.x; e < P; e += (long long)gridDim.x * SEL_THREADS) {
-        unsigned int key;
-        if (sel_key(w[e], key)) {
-            mx = max(mx, key);
-            ++nf;
+    const long long stride = (long long)gridDim.x * SEL_THREADS;
+    const long long t0 = (long long)blockIdx.x * SEL_THREADS + threadIdx.x;
+    if (VEC) {
+        const long long P4 = P >> 2;
+        const float4 *w4 = (const float4 *)w;
+        // four independent vector loads in flight per thread
+        long long q = t0;
+        for (; q + 3 * stride < P4; q += 4 * stride) {
+            float4 v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = w4[q + r * stride];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long e = 4 * (q + r * stride);
+                f(e, v[r].x);
+                f(e + 1, v[r].y);
+                f(e + 2, v[r].z);
+                f(e + 3, v[r].w);
+            }
         }
-    }
-    smax[threadIdx.x] = mx;
-    scnt[threadIdx.x] = nf;
-    __syncthreads();
-    for (int s = SEL_THREADS / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + s]);
-            scnt[threadIdx.x] += scnt[threadIdx.x + s];
+        for (; q < P4; q += stride) {
+            const float4 v = w4[q];
+            f(4 * q, v.x);
+            f(4 * q + 1, v.y);
+            f(4 * q + 2, v.z);
+            f(4 * q + 3, v.w);
         }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        atomicMax(&c->maxbits, smax[0]);
-        atomicAdd(&c->n_finite, scnt[0]);
+        if (blockIdx.x == 0 && threadIdx.x < (P & 3)) {
+            const long long e = 4 * P4 + threadIdx.x;
+            f(e, w[e]);
+        }
+    } else {
+        for (long long e = t0; e < P; e += stride) f(e, w[e]);
     }
 }
 
-__global__ void k_sel_init(SelCtl *c, double fraction, long long P)
+template <bool VEC>
+__global__ __launch_bounds__(SEL_THREADS) void k_sel_scan(const float *__restrict__ w, long long P, int N, SelCtl *c)
 {
+    for (int i = blockIdx.x * SEL_THREADS + threadIdx.x; i < N; i += gridDim.x * SEL_THREADS) c->node[i] = 0;
+    __shared__ unsigned int smax[SEL_THREADS / 64];
+    __shared__ unsigned long long scnt[SEL_THREADS / 64];
+    unsigned int mx = 0;
+    unsigned long long nf = 0;
+    sel_for_each<VEC>(w, P, [&](long long, float v) {
+        unsigned int key;
+        if (sel_key(v, key)) {
+            mx = max(mx, key);
+            ++nf;
+        }
+    });
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = max(mx, (unsigned int)__shfl_xor((int)mx, o));
+        nf += (unsigned long long)__shfl_xor((long long)nf, o);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        smax[wv] = mx;
+        scnt[wv] = nf;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        for (int q = 1; q < SEL_THREADS / 64; ++q) {
+            mx = max(mx, smax[q]);
+            nf += scnt[q];
+        }
+        c->blk_max[blockIdx.x] = mx;
+        c->blk_nf[blockIdx.x] = nf;
+    }
+}
+
+// folds the scan blocks' partials (nblk of them) and sets up the selection
+__global__ __launch_bounds__(SEL_THREADS) void k_sel_init(SelCtl *c, int nblk, double fraction, long long P)
+{
+    __shared__ unsigned int smax[SEL_THREADS / 64];
+    __shared__ unsigned long long scnt[SEL_THREADS / 64];
+    unsigned int mx = 0;
+    unsigned long long nf = 0;
+    for (int b = threadIdx.x; b < nblk; b += SEL_THREADS) {
+        mx = max(mx, c->blk_max[b]);
+        nf += c->blk_nf[b];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = max(mx, (unsigned int)__shfl_xor((int)mx, o));
+        nf += (unsigned long long)__shfl_xor((long long)nf, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        smax[threadIdx.x >> 6] = mx;
+        scnt[threadIdx.x >> 6] = nf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < SEL_THREADS / 64; ++q) {
+            mx = max(mx, smax[q]);
+            nf += scnt[q];
+        }
+        c->maxbits = mx;
+        c->n_finite = nf;
         const double kk = ceil(fraction * (double)P);
         long long k = (long long)kk;
-        if (k > (long long)c->n_finite) k = (long long)c->n_finite;
+        if (k > (long long)nf) k = (long long)nf;
         c->k = k;
         c->k_left = k;
         c->none = k <= 0;
@@ -86,43 +180,77 @@ __global__ void k_sel_init(SelCtl *c, double fraction, long long P)
     }
 }
 
+// LDS histogram of the digit (key >> shift) & (nb - 1) of the keys that
+// carry the prefix found so far.  The key's sign bit is always 0, so three
+// passes of 11, 10 and 10 bits cover it; the first pass's 2048 bins spread
+// the keys of a [-1, 1] network over many bins (few same-address atomics).
+template <bool VEC>
 __global__ __launch_bounds__(SEL_THREADS) void k_sel_hist(const float *__restrict__ w, long long P, SelCtl *c,
-                                                        int shift)
+                                                        int shift, int nb)
 {
-    __shared__ unsigned int h[256];
-    h[threadIdx.x] = 0;
+    __shared__ unsigned int h[SEL_BINS];
+    for (int d = threadIdx.x; d < nb; d += SEL_THREADS) h[d] = 0;
     __syncthreads();
-    const unsigned int prefix = c->prefix, mask = c->mask;
-    if (!c->none) {
-        for (long long e = (long long)blockIdx.x * SEL_THREADS + threadIdx.x; e < P;
-             e += (long long)gridDim.x * SEL_THREADS) {
+    const unsigned int prefix = c->prefix, mask = c->mask, dm = (unsigned int)nb - 1u;
+    if (!c->none)
+        sel_for_each<VEC>(w, P, [&](long long, float v) {
             unsigned int key;
-            if (sel_key(w[e], key) && (key & mask) == prefix) atomicAdd(&h[(key >> shift) & 255u], 1u);
-        }
-    }
+            if (sel_key(v, key) && (key & mask) == prefix) atomicAdd(&h[(key >> shift) & dm], 1u);
+        });
     __syncthreads();
-    if (h[threadIdx.x]) atomicAdd(&c->hist[threadIdx.x], h[threadIdx.x]);
+    unsigned int *g = c->hist[blockIdx.x % SEL_SLOTS];
+    for (int d = threadIdx.x; d < nb; d += SEL_THREADS)
+        if (h[d]) atomicAdd(&g[d], h[d]);
 }
 
-// picks the digit of the k_left-th largest key among those with the prefix,
-// then clears the histogram for the next pass
-__global__ void k_sel_pick(SelCtl *c, int shift)
+// picks the digit of the k_left-th largest key among those with the prefix
+// (each thread sums a run of nb / 256 bins, then one thread walks the runs
+// from the top), then clears the histograms for the next pass
+__global__ __launch_bounds__(SEL_THREADS) void k_sel_pick(SelCtl *c, int shift, int nb)
 {
-    if (threadIdx.x == 0 && !c->none) {
-        long long cum = 0;
-        for (int d = 255; d >= 0; --d) {
-            const long long h = c->hist[d];
-            if (cum + h >= c->k_left) {
-                c->prefix |= (unsigned int)d << shift;
-                c->mask |= 255u << shift;
-                c->k_left -= cum;
-                break;
-            }
-            cum += h;
-        }
+    __shared__ unsigned int tot[SEL_BINS];
+    __shared__ unsigned long long run[SEL_THREADS];
+    const int per = nb / SEL_THREADS;
+    // read before any barrier: one thread rewrites k_left at the end
+    const bool none = c->none;
+    const long long kl = c->k_left;
+    for (int d = threadIdx.x; d < nb; d += SEL_THREADS) {
+        unsigned int t = 0;
+#pragma unroll
+        for (int sl = 0; sl < SEL_SLOTS; ++sl) t += c->hist[sl][d];
+        tot[d] = t;
     }
     __syncthreads();
-    c->hist[threadIdx.x] = 0;
+    // run q = bins q*per .. q*per + per - 1; above[q] = keys in the runs above q
+    unsigned long long r = 0;
+    for (int q = 0; q < per; ++q) r += tot[threadIdx.x * per + q];
+    run[threadIdx.x] = r;
+    __syncthreads();
+    for (int o = 1; o < SEL_THREADS; o <<= 1) {   // inclusive suffix sums over the runs
+        const unsigned long long add = threadIdx.x + o < SEL_THREADS ? run[threadIdx.x + o] : 0ull;
+        __syncthreads();
+        run[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (!none) {
+        const long long incl = (long long)run[threadIdx.x];
+        const long long above = incl - (long long)r;
+        if (above < kl && incl >= kl) {   // exactly one run holds the k_left-th key
+            long long cum = above;
+            for (int d = threadIdx.x * per + per - 1; d >= threadIdx.x * per; --d) {
+                const long long hd = tot[d];
+                if (cum + hd >= kl) {
+                    c->prefix |= (unsigned int)d << shift;
+                    c->mask |= (unsigned int)(nb - 1) << shift;
+                    c->k_left = kl - cum;
+                    break;
+                }
+                cum += hd;
+            }
+        }
+    }
+    for (int sl = 0; sl < SEL_SLOTS; ++sl)
+        for (int d = threadIdx.x; d < nb; d += SEL_THREADS) c->hist[sl][d] = 0;
 }
 
 __device__ __forceinline__ bool sel_take(float v, const SelCtl &c, unsigned int T)
@@ -137,60 +265,80 @@ __device__ __forceinline__ float sel_norm(float v, float m)
     return isfinite(v) ? 0.f : v;
 }
 
-__global__ __launch_bounds__(SEL_THREADS) void k_sel_nodes(const float *__restrict__ w, int N, const SelCtl *c,
-                                                         int *degree, float *strength)
+// One wavefront per row i of the packed triangle (its edges (i, j), j > i,
+// are contiguous): the normalised network and the flags, the selected count,
+// and the degrees and strengths of both ends.  The row's own share is summed
+// over the wavefront; the partners' shares go straight to their counters.
+// A selected edge adds one edge and its |w_norm| in units of 2^-32 (exact
+// for |w_norm| >= 2^-9) to one 64-bit counter per end, so the sums do not
+// depend on the order of the atomics.
+__global__ __launch_bounds__(SEL_THREADS) void k_sel_rows(const float *w, int N, SelCtl *c, float *w_norm,
+                                                        unsigned char *selected, int nodes)
 {
+    __shared__ unsigned long long scnt[SEL_THREADS / 64];
     const int i = blockIdx.x * (SEL_THREADS / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (i >= N) return;
-    const unsigned int T = c->prefix;
-    const float m = __uint_as_float(c->maxbits);
-    int deg = 0;
-    double str = 0.0;
-    for (int j = lane; j < N; j += 64) {
-        if (j == i) continue;
-        const int a = min(i, j), b = max(i, j);
-        const long long e = (long long)a * (2LL * N - a - 1) / 2 + (b - a - 1);
-        const float v = w[e];
-        if (sel_take(v, *c, T)) {
-            ++deg;
-            str += (double)fabsf(sel_norm(v, m));
-        }
-    }
-    deg = (int)wave_sum((double)deg);
-    str = wave_sum(str);
-    if (lane == 0) {
-        if (degree) degree[i] = deg;
-        if (strength) strength[i] = (float)str;
-    }
-}
-
-__global__ __launch_bounds__(SEL_THREADS) void k_sel_apply(const float *w, long long P, SelCtl *c, float *w_norm,
-                                                         unsigned char *selected)
-{
-    __shared__ unsigned long long scnt[SEL_THREADS];
     const unsigned int T = c->prefix;
     const float m = __uint_as_float(c->maxbits);
     unsigned long long ns = 0;
-    for (long long e = (long long)blockIdx.x * SEL_THREADS + threadIdx.x; e < P; e += (long long)gridDim.x * SEL_THREADS) {
-        const float v = w[e];
-        const bool t = sel_take(v, *c, T);
-        ns += t;
-        if (selected) selected[e] = t;
-        if (w_norm) w_norm[e] = sel_norm(v, m);
+    if (i < N - 1) {
+        const long long r0 = (long long)i * (2LL * N - i - 1) / 2 - (i + 1);   // e = r0 + j
+        int deg = 0;
+        double str = 0.0;
+        for (int j = i + 1 + lane; j < N; j += 64) {
+            const long long e = r0 + j;
+            const float v = w[e];
+            const bool t = sel_take(v, *c, T);
+            const float nv = sel_norm(v, m);
+            if (selected) selected[e] = t;
+            if (w_norm) w_norm[e] = nv;
+            if (t) {
+                ++ns;
+                if (nodes) {
+                    ++deg;
+                    const float a = fabsf(nv);
+                    str += (double)a;
+                    atomicAdd(&c->node[j], SEL_DEG1 + (unsigned long long)rint((double)a * SEL_FIX));
+                }
+            }
+        }
+        if (nodes) {
+            for (int o = 32; o > 0; o >>= 1) {
+                deg += __shfl_xor(deg, o);
+                str += __shfl_xor(str, o);
+            }
+            if (lane == 0 && deg)
+                atomicAdd(&c->node[i], SEL_DEG1 * (unsigned long long)deg + (unsigned long long)rint(str * SEL_FIX));
+        }
     }
-    scnt[threadIdx.x] = ns;
+    for (int o = 32; o > 0; o >>= 1) ns += (unsigned long long)__shfl_xor((long long)ns, o);
+    if (lane == 0) scnt[threadIdx.x >> 6] = ns;
     __syncthreads();
-    for (int s = SEL_THREADS / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) scnt[threadIdx.x] += scnt[threadIdx.x + s];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < SEL_THREADS / 64; ++q) ns += scnt[q];
+        if (ns) atomicAdd(&c->slot_ns[blockIdx.x % SEL_SLOTS], ns);
     }
-    if (threadIdx.x == 0) atomicAdd(&c->n_selected, scnt[0]);
+}
+
+__global__ __launch_bounds__(SEL_THREADS) void k_sel_node_out(const SelCtl *c, int N, int *degree, float *strength)
+{
+    const int i = blockIdx.x * SEL_THREADS + threadIdx.x;
+    if (i >= N) return;
+    const unsigned long long v = c->node[i];
+    if (degree) degree[i] = (int)(v >> 48);
+    if (strength) strength[i] = (float)((double)(v & (SEL_DEG1 - 1)) / SEL_FIX);
 }
 
 }  // namespace fcx
 
 using namespace fcx;
+
+namespace {
+// One control block per device, allocated on first use and kept; calls on a
+// device are serialised on it.
+std::mutex g_sel_mu;
+std::unordered_map<int, SelCtl *> g_sel_ctl;
+}  // namespace
 
 extern "C" fcx_status fcx_network_select(int32_t n_nodes, const float *w, double fraction, float *w_norm,
                                          uint8_t *selected, int32_t *degree, float *strength,
@@ -199,39 +347,58 @@ extern "C" fcx_status fcx_network_select(int32_t n_nodes, const float *w, double
     if (n_nodes < 2 || n_nodes > 65536 || !w || !(fraction >= 0.0 && fraction <= 1.0)) return FCX_E_INVAL;
     const long long P = (long long)n_nodes * (n_nodes - 1) / 2;
     hipStream_t st = (hipStream_t)hip_stream;
-    SelCtl *c = nullptr;
-    if (hipMalloc((void **)&c, sizeof(SelCtl)) != hipSuccess) return FCX_E_NOMEM;
-    fcx_status rs = FCX_OK;
-    long long blocks = (P + SEL_THREADS - 1) / SEL_THREADS;
-    if (blocks > 4096) blocks = 4096;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FCX_E_DEVICE;
+    std::lock_guard<std::mutex> lk(g_sel_mu);
+    SelCtl *&c = g_sel_ctl[dev];
+    if (!c && hipMalloc((void **)&c, sizeof(SelCtl)) != hipSuccess) {
+        c = nullptr;
+        return FCX_E_NOMEM;
+    }
+    const bool vec = ((uintptr_t)w & 15) == 0;   // float4 loads in the scan and histogram passes
+    long long blocks = ((vec ? P / 4 : P) + SEL_THREADS - 1) / SEL_THREADS;
+    if (blocks > SEL_MAX_BLOCKS) blocks = SEL_MAX_BLOCKS;
+    if (blocks < 1) blocks = 1;
     const dim3 grid((unsigned)blocks), blk(SEL_THREADS);
-    SelCtl h;
-    bool ok = hipMemsetAsync(c, 0, sizeof(SelCtl), st) == hipSuccess;
+    SelCtl *h = new (std::nothrow) SelCtl;
+    if (!h) return FCX_E_NOMEM;
+    bool ok = hipMemsetAsync(c, 0, offsetof(SelCtl, node), st) == hipSuccess;
     if (ok) {
-        hipLaunchKernelGGL(k_sel_scan, grid, blk, 0, st, w, P, c);
-        hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(64), 0, st, c, fraction, P);
-        for (int shift = 24; shift >= 0; shift -= 8) {
-            hipLaunchKernelGGL(k_sel_hist, grid, blk, 0, st, w, P, c, shift);
-            hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, st, c, shift);
+        if (vec)
+            hipLaunchKernelGGL(k_sel_scan<true>, grid, blk, 0, st, w, P, (int)n_nodes, c);
+        else
+            hipLaunchKernelGGL(k_sel_scan<false>, grid, blk, 0, st, w, P, (int)n_nodes, c);
+        hipLaunchKernelGGL(k_sel_init, dim3(1), blk, 0, st, c, (int)blocks, fraction, P);
+        // digits of 11, 10 and 10 bits (bits 30..20, 19..10, 9..0)
+        const int shifts[3] = {20, 10, 0}, bins[3] = {2048, 1024, 1024};
+        for (int pass = 0; pass < 3; ++pass) {
+            if (vec)
+                hipLaunchKernelGGL(k_sel_hist<true>, grid, blk, 0, st, w, P, c, shifts[pass], bins[pass]);
+            else
+                hipLaunchKernelGGL(k_sel_hist<false>, grid, blk, 0, st, w, P, c, shifts[pass], bins[pass]);
+            hipLaunchKernelGGL(k_sel_pick, dim3(1), blk, 0, st, c, shifts[pass], bins[pass]);
         }
-        if (degree || strength)
-            hipLaunchKernelGGL(k_sel_nodes, dim3((n_nodes + 3) / 4), blk, 0, st, w, n_nodes, c, degree, strength);
         // last: w_norm may overwrite w
-        hipLaunchKernelGGL(k_sel_apply, grid, blk, 0, st, w, P, c, w_norm, selected);
-        ok = hipGetLastError() == hipSuccess && hipMemcpyAsync(&h, c, sizeof(SelCtl), hipMemcpyDeviceToHost, st) ==
+        const int nodes = degree || strength;
+        hipLaunchKernelGGL(k_sel_rows, dim3((n_nodes + 3) / 4), blk, 0, st, w, n_nodes, c, w_norm, selected, nodes);
+        if (nodes)
+            hipLaunchKernelGGL(k_sel_node_out, dim3((n_nodes + SEL_THREADS - 1) / SEL_THREADS), blk, 0, st, c, n_nodes,
+                               degree, strength);
+        ok = hipGetLastError() == hipSuccess && hipMemcpyAsync(h, c, offsetof(SelCtl, hist), hipMemcpyDeviceToHost, st) ==
                                                      hipSuccess && hipStreamSynchronize(st) == hipSuccess;
     }
-    if (!ok) rs = FCX_E_DEVICE;
-    (void)hipFree(c);
-    if (rs == FCX_OK && info) {
+    if (ok && info) {
         float mx, th;
-        memcpy(&mx, &h.maxbits, sizeof(float));
-        memcpy(&th, &h.prefix, sizeof(float));
+        memcpy(&mx, &h->maxbits, sizeof(float));
+        memcpy(&th, &h->prefix, sizeof(float));
+        unsigned long long ns = 0;
+        for (int q = 0; q < SEL_SLOTS; ++q) ns += h->slot_ns[q];
         info->max_abs = mx;
-        info->threshold = h.none ? INFINITY : th;
-        info->k = h.k;
-        info->n_finite = (int64_t)h.n_finite;
-        info->n_selected = (int64_t)h.n_selected;
+        info->threshold = h->none ? INFINITY : th;
+        info->k = h->k;
+        info->n_finite = (int64_t)h->n_finite;
+        info->n_selected = (int64_t)ns;
     }
-    return rs;
+    delete h;
+    return ok ? FCX_OK : FCX_E_DEVICE;
 }
