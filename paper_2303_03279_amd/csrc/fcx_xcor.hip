@@ -168,10 +168,18 @@ template <int F> constexpr bool xcor_tw_lds() { return F <= 1024; }
 // One workgroup per (tile, row of the tile): row node i against the tile's
 // columns j > i.  The row's spectrum, energies and the twiddles are shared in
 // LDS; each wavefront takes two columns at a time into its own transform.
-template <typename T, int F>
-__global__ __launch_bounds__(64 * xcor_waves<F>()) void k_xcor_pair(SessDev<T> s)
+// Up to F = 1024 the global loads of a job are issued early: this job's
+// column energies and the next job's column spectra go into registers before
+// the transform, so their latency overlaps it.  NL = lag registers per lane:
+// (L + 1) <= 64 NL.
+template <int F> constexpr bool xcor_prefetch() { return F <= 1024; }
+
+template <typename T, int F, int NL>
+__global__ __launch_bounds__(64 * xcor_waves<F>()) __attribute__((amdgpu_waves_per_eu(F == 1024 && NL == 8 ? 3 : 1)))
+void k_xcor_pair(SessDev<T> s)
 {
     constexpr int NW = xcor_waves<F>();
+    constexpr int NF = (F / 2 + 1 + 63) / 64;   // spectrum bins per lane
     __shared__ float2 Zw[NW][F];
     __shared__ float2 Rsp[F / 2 + 1];
     __shared__ float Rsuf[F];
@@ -196,37 +204,88 @@ __global__ __launch_bounds__(64 * xcor_waves<F>()) void k_xcor_pair(SessDev<T> s
     const float invF = 1.0f / (float)F;
     const size_t TP = (size_t)s.ntiles * TILE_PAIRS;
     const size_t P = (size_t)N * (N - 1) / 2;
-    for (int j = jlo + 2 * wv; j < jhi; j += 2 * NW) {
+    // column spectra of a job (j, j + 1 or none) into registers
+    float2 b1[xcor_prefetch<F>() ? NF : 1], b2[xcor_prefetch<F>() ? NF : 1];
+    auto load_spec = [&](int j) {
         const int j2 = j + 1 < jhi ? j + 1 : -1;
         const float2 *c1p = s.xspec + (size_t)j * (F / 2 + 1);
         const float2 *c2p = s.xspec + (size_t)(j2 >= 0 ? j2 : j) * (F / 2 + 1);
-        // Z = H1 + i H2 over the full circle, H = X_i conj(X_j) (Hermitian)
-        for (int f = lane; f <= F / 2; f += 64) {
-            const float2 a = Rsp[f], b1 = c1p[f];
-            float2 b2 = c2p[f];
-            if (j2 < 0) b2 = make_float2(0.f, 0.f);
-            const float h1r = a.x * b1.x + a.y * b1.y, h1i = a.y * b1.x - a.x * b1.y;
-            const float h2r = a.x * b2.x + a.y * b2.y, h2i = a.y * b2.x - a.x * b2.y;
-            Z[f] = make_float2(h1r - h2i, h1i + h2r);
-            if (f > 0 && f < F / 2) Z[F - f] = make_float2(h1r + h2i, h2r - h1i);
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            const int f = lane + 64 * q;
+            b1[q] = make_float2(0.f, 0.f);
+            b2[q] = b1[q];
+            if (f <= F / 2) {
+                b1[q] = c1p[f];
+                if (j2 >= 0) b2[q] = c2p[f];
+            }
         }
+    };
+    // Z = H1 + i H2 over the full circle, H = X_i conj(X_j) (Hermitian)
+    auto put = [&](int f, float2 a, float2 c1, float2 c2) {
+        const float h1r = a.x * c1.x + a.y * c1.y, h1i = a.y * c1.x - a.x * c1.y;
+        const float h2r = a.x * c2.x + a.y * c2.y, h2i = a.y * c2.x - a.x * c2.y;
+        Z[f] = make_float2(h1r - h2i, h1i + h2r);
+        if (f > 0 && f < F / 2) Z[F - f] = make_float2(h1r + h2i, h2r - h1i);
+    };
+    int j = jlo + 2 * wv;
+    if constexpr (xcor_prefetch<F>())
+        if (j < jhi) load_spec(j);
+    for (; j < jhi; j += 2 * NW) {
+        const int j2 = j + 1 < jhi ? j + 1 : -1;
+        if constexpr (xcor_prefetch<F>()) {
+#pragma unroll
+            for (int q = 0; q < NF; ++q) {
+                const int f = lane + 64 * q;
+                if (f <= F / 2) put(f, Rsp[f], b1[q], b2[q]);
+            }
+        } else {
+            const float2 *c1p = s.xspec + (size_t)j * (F / 2 + 1);
+            const float2 *c2p = s.xspec + (size_t)(j2 >= 0 ? j2 : j) * (F / 2 + 1);
+            for (int f = lane; f <= F / 2; f += 64)
+                put(f, Rsp[f], c1p[f], j2 >= 0 ? c2p[f] : make_float2(0.f, 0.f));
+        }
+        // this job's column energies, then the next job's spectra
+        const float *s1 = s.xsuf + (size_t)j * (L + 1);
+        const float *s2 = s.xsuf + (size_t)(j2 >= 0 ? j2 : j) * (L + 1);
+        const float rE1 = s1[0], rE2 = j2 >= 0 ? s2[0] : 0.f;
+        float e1[xcor_prefetch<F>() ? NL : 1], e2[xcor_prefetch<F>() ? NL : 1];
+        if constexpr (xcor_prefetch<F>()) {
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                const int tau = lane + 64 * q;
+                e1[q] = tau <= L ? s1[tau] : 0.f;
+                e2[q] = tau <= L && j2 >= 0 ? s2[tau] : 0.f;
+            }
+        }
+        if constexpr (xcor_prefetch<F>())
+            if (j + 2 * NW < jhi) load_spec(j + 2 * NW);
         __builtin_amdgcn_wave_barrier();
         ifft_wave<F>(Z, xcor_tw_lds<F>() ? tws : s.xtw, lane);
         // largest XCOR over the lags, both pairs
-        const float *s1 = s.xsuf + (size_t)j * (L + 1);
-        const float *s2 = s.xsuf + (size_t)(j2 >= 0 ? j2 : j) * (L + 1);
         // XCOR = c / F * (1/sqrt S_advanced(tau)) * (1/sqrt E_other)
-        const float rE1 = s1[0], rE2 = j2 >= 0 ? s2[0] : 0.f;
         float best1 = -INFINITY, best2 = -INFINITY;
-        for (int tau = lane; tau <= L; tau += 64) {
-            const float2 p = Z[tau];
-            const float ri = Rsuf[tau];
-            best1 = fmaxf(best1, p.x * invF * ri * rE1);
-            best2 = fmaxf(best2, p.y * invF * ri * rE2);
-            if (tau > 0) {
-                const float2 q = Z[F - tau];
-                best1 = fmaxf(best1, q.x * invF * s1[tau] * rEi);
-                if (j2 >= 0) best2 = fmaxf(best2, q.y * invF * s2[tau] * rEi);
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int tau = lane + 64 * q;
+            if (tau <= L) {
+                const float2 p = Z[tau];
+                const float ri = Rsuf[tau];
+                best1 = fmaxf(best1, p.x * invF * ri * rE1);
+                best2 = fmaxf(best2, p.y * invF * ri * rE2);
+                if (tau > 0) {
+                    const float2 qv = Z[F - tau];
+                    float f1, f2;
+                    if constexpr (xcor_prefetch<F>()) {
+                        f1 = e1[q];
+                        f2 = e2[q];
+                    } else {
+                        f1 = s1[tau];
+                        f2 = j2 >= 0 ? s2[tau] : 0.f;
+                    }
+                    best1 = fmaxf(best1, qv.x * invF * f1 * rEi);
+                    if (j2 >= 0) best2 = fmaxf(best2, qv.y * invF * f2 * rEi);
+                }
             }
         }
         best1 = wave_max(best1);
@@ -252,11 +311,27 @@ template <typename T> hipError_t launch_xcor(const SessDev<T> &s, hipStream_t st
 {
     hipLaunchKernelGGL(k_xcor_node<T>, dim3(s.N), dim3(XT), 0, st, s);
     const dim3 grid((unsigned)(s.ntiles * TILE));
+    // lag registers: half the transform when the lags fit, else all of it
+    const bool half = s.xL + 1 <= s.xF / 2;
+    const dim3 b256(64 * xcor_waves<256>()), b512(64 * xcor_waves<512>()), b1k(64 * xcor_waves<1024>()),
+        b2k(64 * xcor_waves<2048>());
     switch (s.xF) {
-    case 256: hipLaunchKernelGGL((k_xcor_pair<T, 256>), grid, dim3(64 * xcor_waves<256>()), 0, st, s); break;
-    case 512: hipLaunchKernelGGL((k_xcor_pair<T, 512>), grid, dim3(64 * xcor_waves<512>()), 0, st, s); break;
-    case 1024: hipLaunchKernelGGL((k_xcor_pair<T, 1024>), grid, dim3(64 * xcor_waves<1024>()), 0, st, s); break;
-    case 2048: hipLaunchKernelGGL((k_xcor_pair<T, 2048>), grid, dim3(64 * xcor_waves<2048>()), 0, st, s); break;
+    case 256:
+        if (half) hipLaunchKernelGGL((k_xcor_pair<T, 256, 2>), grid, b256, 0, st, s);
+        else hipLaunchKernelGGL((k_xcor_pair<T, 256, 4>), grid, b256, 0, st, s);
+        break;
+    case 512:
+        if (half) hipLaunchKernelGGL((k_xcor_pair<T, 512, 4>), grid, b512, 0, st, s);
+        else hipLaunchKernelGGL((k_xcor_pair<T, 512, 8>), grid, b512, 0, st, s);
+        break;
+    case 1024:
+        if (half) hipLaunchKernelGGL((k_xcor_pair<T, 1024, 8>), grid, b1k, 0, st, s);
+        else hipLaunchKernelGGL((k_xcor_pair<T, 1024, 16>), grid, b1k, 0, st, s);
+        break;
+    case 2048:
+        if (half) hipLaunchKernelGGL((k_xcor_pair<T, 2048, 16>), grid, b2k, 0, st, s);
+        else hipLaunchKernelGGL((k_xcor_pair<T, 2048, 32>), grid, b2k, 0, st, s);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
