@@ -21,11 +21,12 @@
 //                 - the evicted trial's maximum kept in a ring of per-trial
 //                 values, so add and remove cancel exactly.
 //
-// The inverse FFT is a radix-4 Stockham (autosorting) transform, with one
-// radix-2 stage when log2 F is odd, done by one wavefront in its own LDS
-// buffer: every stage loads its butterflies' inputs, then stores the outputs
-// in place; the wavefronts of a workgroup share the row node's data and the
-// twiddles and never wait for each other.
+// The inverse FFT is a mixed-radix Stockham (autosorting) transform done by
+// one wavefront in its own LDS buffer: three passes of radix 16, 16 and 4 at
+// F = 1024 (radix-16 butterflies in registers), each loading its
+// butterflies' inputs, then storing the outputs in place; the wavefronts of
+// a workgroup share the row node's data and the twiddles and never wait for
+// each other.
 #include "fcx_device.h"
 
 #include <math.h>
@@ -82,74 +83,123 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-place inverse DFT (no 1/F) of Z[F] in LDS by one wavefront.  The LDS
-// operations of a wavefront are performed in order, so a stage's loads (all
-// lanes) precede its stores; the wave barriers keep the compiler from moving
-// LDS accesses across the phase boundaries.
+// A transform buffer holds element m at m + m / 32: the pad after every 32
+// elements (256 bytes) spreads the strided stores of the early passes over
+// the LDS banks.
+constexpr int XPAD_SHIFT = 5;
+__host__ __device__ constexpr int xpad(int m) { return m + (m >> XPAD_SHIFT); }
+template <int F> constexpr int xbuf_len() { return F + (F >> XPAD_SHIFT); }
+
+// exp(+2 pi i m / 16), m = 0..7
+__constant__ const float W16_RE[8] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+                                      0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f};
+__constant__ const float W16_IM[8] = {0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f,
+                                      1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f};
+
+// In-register inverse DFT of R = 4, 8 or 16 points: y_m = sum_r v_r
+// exp(+2 pi i r m / R), split into even and odd halves down to radix 4.
+template <int R>
+__device__ __forceinline__ void idft_reg(float2 (&v)[R])
+{
+    if constexpr (R == 4) {
+        const float2 t0 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
+        const float2 t1 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
+        const float2 t2 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
+        const float2 d = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
+        const float2 t3 = make_float2(-d.y, d.x);    // +i (v1 - v3)
+        v[0] = make_float2(t0.x + t2.x, t0.y + t2.y);
+        v[1] = make_float2(t1.x + t3.x, t1.y + t3.y);
+        v[2] = make_float2(t0.x - t2.x, t0.y - t2.y);
+        v[3] = make_float2(t1.x - t3.x, t1.y - t3.y);
+    } else {
+        constexpr int H = R / 2;
+        float2 e[H], o[H];
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            e[m] = v[2 * m];
+            o[m] = v[2 * m + 1];
+        }
+        idft_reg<H>(e);
+        idft_reg<H>(o);
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            const int w = m * (16 / R);                  // exp(+2 pi i m / R) = W16^(16 m / R)
+            const float2 t = cmul(o[m], make_float2(W16_RE[w], W16_IM[w]));
+            v[m] = make_float2(e[m].x + t.x, e[m].y + t.y);
+            v[m + H] = make_float2(e[m].x - t.x, e[m].y - t.y);
+        }
+    }
+}
+
+// One pass of radix R of the in-place Stockham (autosorting) inverse FFT by
+// one wavefront; NS = product of the radices before it.  Butterfly j takes
+// Z[j + r F/R] (times exp(+2 pi i r k / (R NS)), k = j mod NS) and writes
+// its R-point DFT to Z[(j / NS) NS R + k + m NS].  A wavefront's LDS
+// operations are performed in order, so all loads of the pass precede its
+// stores; the wave barriers keep the compiler from moving LDS accesses
+// across the phase boundaries.  With the pad every 32 elements both address
+// patterns are one base plus constants (F / R and NS are multiples of 32, or
+// NS < 32 with k + (m NS mod 32) < 32).
+template <int F, int R, int NS>
+__device__ __forceinline__ void xpass(float2 *Z, const float2 *tw, int lane)
+{
+    constexpr int NB = F / R;                   // butterflies
+    constexpr int PER = NB / 64;                // per lane
+    constexpr int STEP = F / (R * NS);          // twiddle stride
+    static_assert(NB % 64 == 0 && NB % 32 == 0, "butterflies per lane");
+    float2 v[PER][R];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = lane + 64 * q;
+        const int k = j & (NS - 1);
+        const float2 *zi = Z + xpad(j);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float2 a = zi[r * NB + ((r * NB) >> XPAD_SHIFT)];
+            if (NS > 1 && r) {
+                float2 w = tw[r * k * STEP];
+                w.y = -w.y;                             // inverse: exp(+2 pi i m / F)
+                a = cmul(a, w);
+            }
+            v[q][r] = a;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = lane + 64 * q;
+        const int k = j & (NS - 1);
+        idft_reg<R>(v[q]);
+        float2 *zo = Z + xpad((j / NS) * NS * R + k);
+#pragma unroll
+        for (int m = 0; m < R; ++m) zo[m * NS + ((m * NS) >> XPAD_SHIFT)] = v[q][m];
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// In-place inverse DFT (no 1/F) of the padded Z[F] in LDS by one wavefront:
+// radices 4-4-4-4 (F = 256), 8-8-8 (512), 16-16-4 (1024), 16-16-8 (2048).
 template <int F>
 __device__ __forceinline__ void ifft_wave(float2 *Z, const float2 *tw, int lane)
 {
-    constexpr int NB4 = F / 4;                           // radix-4 butterflies per stage
-    constexpr int PER4 = NB4 / 64;
-#pragma unroll
-    for (int Ns = 1; Ns * 4 <= F; Ns *= 4) {
-        float2 v[PER4][4];
-        const int step = F / (4 * Ns);
-#pragma unroll
-        for (int q = 0; q < PER4; ++q) {
-            const int j = lane + q * 64;
-            const int k = j & (Ns - 1);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float2 a = Z[j + r * NB4];
-                if (r && Ns > 1) {                       // the first stage's twiddles are 1
-                    float2 w = tw[r * k * step];
-                    w.y = -w.y;                          // inverse: exp(+2 pi i m / F)
-                    a = cmul(a, w);
-                }
-                v[q][r] = a;
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int q = 0; q < PER4; ++q) {
-            const int j = lane + q * 64;
-            const int k = j & (Ns - 1);
-            const float2 a0 = v[q][0], a1 = v[q][1], a2 = v[q][2], a3 = v[q][3];
-            const float2 t0 = make_float2(a0.x + a2.x, a0.y + a2.y);
-            const float2 t1 = make_float2(a0.x - a2.x, a0.y - a2.y);
-            const float2 t2 = make_float2(a1.x + a3.x, a1.y + a3.y);
-            const float2 d = make_float2(a1.x - a3.x, a1.y - a3.y);
-            const float2 t3 = make_float2(-d.y, d.x);    // +i (a1 - a3)
-            const int o = (j / Ns) * Ns * 4 + k;
-            Z[o] = make_float2(t0.x + t2.x, t0.y + t2.y);
-            Z[o + Ns] = make_float2(t1.x + t3.x, t1.y + t3.y);
-            Z[o + 2 * Ns] = make_float2(t0.x - t2.x, t0.y - t2.y);
-            Z[o + 3 * Ns] = make_float2(t1.x - t3.x, t1.y - t3.y);
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-    constexpr bool odd = (F & 0x55555555) == 0;          // log2 F odd: a last radix-2 stage
-    if constexpr (odd) {
-        constexpr int NB2 = F / 2;
-        constexpr int PER2 = NB2 / 64;
-        float2 v0[PER2], v1[PER2];
-#pragma unroll
-        for (int q = 0; q < PER2; ++q) {
-            const int j = lane + q * 64;
-            float2 w = tw[j];
-            w.y = -w.y;
-            v0[q] = Z[j];
-            v1[q] = cmul(Z[j + NB2], w);
-        }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int q = 0; q < PER2; ++q) {
-            const int j = lane + q * 64;
-            Z[j] = make_float2(v0[q].x + v1[q].x, v0[q].y + v1[q].y);
-            Z[j + NB2] = make_float2(v0[q].x - v1[q].x, v0[q].y - v1[q].y);
-        }
-        __builtin_amdgcn_wave_barrier();
+    if constexpr (F == 256) {
+        xpass<F, 4, 1>(Z, tw, lane);
+        xpass<F, 4, 4>(Z, tw, lane);
+        xpass<F, 4, 16>(Z, tw, lane);
+        xpass<F, 4, 64>(Z, tw, lane);
+    } else if constexpr (F == 512) {
+        xpass<F, 8, 1>(Z, tw, lane);
+        xpass<F, 8, 8>(Z, tw, lane);
+        xpass<F, 8, 64>(Z, tw, lane);
+    } else if constexpr (F == 1024) {
+        xpass<F, 16, 1>(Z, tw, lane);
+        xpass<F, 16, 16>(Z, tw, lane);
+        xpass<F, 4, 256>(Z, tw, lane);
+    } else {
+        static_assert(F == 2048, "transform length");
+        xpass<F, 16, 1>(Z, tw, lane);
+        xpass<F, 16, 16>(Z, tw, lane);
+        xpass<F, 8, 256>(Z, tw, lane);
     }
 }
 
@@ -180,7 +230,7 @@ void k_xcor_pair(SessDev<T> s)
 {
     constexpr int NW = xcor_waves<F>();
     constexpr int NF = (F / 2 + 1 + 63) / 64;   // spectrum bins per lane
-    __shared__ float2 Zw[NW][F];
+    __shared__ float2 Zw[NW][xbuf_len<F>()];
     __shared__ float2 Rsp[F / 2 + 1];
     __shared__ float Rsuf[F];
     __shared__ float2 tws[xcor_tw_lds<F>() ? F : 1];
@@ -225,8 +275,8 @@ void k_xcor_pair(SessDev<T> s)
     auto put = [&](int f, float2 a, float2 c1, float2 c2) {
         const float h1r = a.x * c1.x + a.y * c1.y, h1i = a.y * c1.x - a.x * c1.y;
         const float h2r = a.x * c2.x + a.y * c2.y, h2i = a.y * c2.x - a.x * c2.y;
-        Z[f] = make_float2(h1r - h2i, h1i + h2r);
-        if (f > 0 && f < F / 2) Z[F - f] = make_float2(h1r + h2i, h2r - h1i);
+        Z[xpad(f)] = make_float2(h1r - h2i, h1i + h2r);
+        if (f > 0 && f < F / 2) Z[xpad(F - f)] = make_float2(h1r + h2i, h2r - h1i);
     };
     int j = jlo + 2 * wv;
     if constexpr (xcor_prefetch<F>())
@@ -269,12 +319,12 @@ void k_xcor_pair(SessDev<T> s)
         for (int q = 0; q < NL; ++q) {
             const int tau = lane + 64 * q;
             if (tau <= L) {
-                const float2 p = Z[tau];
+                const float2 p = Z[xpad(tau)];
                 const float ri = Rsuf[tau];
                 best1 = fmaxf(best1, p.x * invF * ri * rE1);
                 best2 = fmaxf(best2, p.y * invF * ri * rE2);
                 if (tau > 0) {
-                    const float2 qv = Z[F - tau];
+                    const float2 qv = Z[xpad(F - tau)];
                     float f1, f2;
                     if constexpr (xcor_prefetch<F>()) {
                         f1 = e1[q];
