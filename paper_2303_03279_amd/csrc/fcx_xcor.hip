@@ -8,7 +8,7 @@
 //                 S(tau) = sum_{t >= tau} z(t)^2 for tau = 0..L (FP64 sums),
 //                 stored as 1/sqrt(S(tau)) in FP32 (0 for S = 0), and the
 //                 spectrum Z(f) = sum_t z(t) e^{-2 pi i f t/F}, f = 0..F/2,
-//                 F a power of two >= M + L (FP64 sums, FP32 out)
+//                 F a power of two >= M + L (FP64 sums and phasors, FP32 out)
 //   k_xcor_pair   per pair tile row: for two columns at a time, the product
 //                 spectra of the pairs are packed as H1 + i H2 (both
 //                 Hermitian), one in-LDS inverse FFT of length F yields both
@@ -62,16 +62,45 @@ __global__ __launch_bounds__(XT) void k_xcor_node(SessDev<T> s)
     __syncthreads();
     float *so = s.xsuf + (size_t)node * (L + 1);
     for (int t = tid; t <= L; t += XT) so[t] = suf[t] > 0.0 ? (float)(1.0 / sqrt(suf[t])) : 0.f;
+    // bin f: sum_t z(t) exp(-2 pi i f t / F), the phasor advanced by one
+    // FP64 rotation per sample and restarted from its exact value at the
+    // start of each of XSEG segments (independent chains; the rounding of
+    // the rotation grows by at most a few hundred FP64 ulps)
+    constexpr int XSEG = 4;
     float2 *xo = s.xspec + (size_t)node * (F / 2 + 1);
-    const unsigned fm = (unsigned)F - 1u;
+    const int seg = (M + XSEG - 1) / XSEG;
     for (int f = tid; f <= F / 2; f += XT) {
-        double re = 0.0, im = 0.0;
-        for (int t = 0; t < M; ++t) {
-            const float2 w = s.xtw[((unsigned)f * (unsigned)t) & fm];
-            re += (double)z[t] * (double)w.x;
-            im += (double)z[t] * (double)w.y;
+        double sr, ci0;
+        sincospi(-2.0 * (double)f / (double)F, &sr, &ci0);   // one-sample rotation (cos ci0, sin sr)
+        double re[XSEG], im[XSEG], cr[XSEG], cs[XSEG];
+#pragma unroll
+        for (int g = 0; g < XSEG; ++g) {
+            const int m = (int)(((long long)f * (long long)(g * seg)) % F);
+            sincospi(-2.0 * (double)m / (double)F, &cs[g], &cr[g]);
+            re[g] = 0.0;
+            im[g] = 0.0;
         }
-        xo[f] = make_float2((float)re, (float)im);
+        for (int u = 0; u < seg; ++u) {
+#pragma unroll
+            for (int g = 0; g < XSEG; ++g) {
+                const int t = g * seg + u;
+                if (t < M) {
+                    const double v = (double)z[t];
+                    re[g] += v * cr[g];
+                    im[g] += v * cs[g];
+                    const double nr = cr[g] * ci0 - cs[g] * sr;
+                    cs[g] = cr[g] * sr + cs[g] * ci0;
+                    cr[g] = nr;
+                }
+            }
+        }
+        double tr = 0.0, ti = 0.0;
+#pragma unroll
+        for (int g = 0; g < XSEG; ++g) {
+            tr += re[g];
+            ti += im[g];
+        }
+        xo[f] = make_float2((float)tr, (float)ti);
     }
 }
 
