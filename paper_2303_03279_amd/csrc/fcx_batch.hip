@@ -131,7 +131,9 @@ __global__ __launch_bounds__(256) void k_psd_batch(SessDev<float> s, int K)
 
 // ---------------------------------------------------------------- pairs
 template <int PREC, int LT>
-__global__ __launch_bounds__(BT_THREADS) void k_pair_batch(SessDev<float> s, int K)
+__global__ __launch_bounds__(BT_THREADS)
+__attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))) void k_pair_batch(SessDev<float> s,
+                                                                                                     int K)
 {
     __shared__ float2 Xs[64 * BT_LD];
     __shared__ float2 Us[64 * BT_LD];
@@ -196,10 +198,49 @@ __global__ __launch_bounds__(BT_THREADS) void k_pair_batch(SessDev<float> s, int
                 if (mfmaU) Us[node * BT_LD + col] = u;
             }
             __syncthreads();
-            Gram<PREC>::chunk(Xs, arow, bcol, lg, sre, sim);
-            if (mfmaU) Gram<PREC>::chunk(Us, arow, bcol, lg, ure, uim);
             // per-trial sums of this lane's four pairs (FP32, no contraction)
             float Ap[4] = {0.f, 0.f, 0.f, 0.f}, Qp[4] = {0.f, 0.f, 0.f, 0.f};
+            if constexpr (PREC == FCX_GRAM_FP32_ID && LT == 1) {
+                // FP32 Gram, one taper: each MFMA step (4 trials) is followed by
+                // the vector sums of the same 4 trials, so the matrix-core
+                // latency overlaps vector work (same operations, same order)
+#pragma unroll
+                for (int st = 0; st < BT_CC / 4; ++st) {
+                    {
+                        const float2 a = Xs[arow * BT_LD + 4 * st + lg];
+                        const float2 bb = Xs[bcol * BT_LD + 4 * st + lg];
+                        sre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, sre, 0, 0, 0);
+                        sre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, sre, 0, 0, 0);
+                        sim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, sim, 0, 0, 0);
+                        sim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, bb.y, sim, 0, 0, 0);
+                    }
+                    if (mfmaU) {
+                        const float2 a = Us[arow * BT_LD + 4 * st + lg];
+                        const float2 bb = Us[bcol * BT_LD + 4 * st + lg];
+                        ure = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, ure, 0, 0, 0);
+                        ure = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, ure, 0, 0, 0);
+                        uim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, uim, 0, 0, 0);
+                        uim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, bb.y, uim, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt) {
+                        const int t = 4 * st + tt;
+                        if (t < nk) {
+                            const float2 xj = Xs[bcol * BT_LD + t];
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                const float2 xi = Xs[rows[k] * BT_LD + t];
+                                const float ci = xi.y * xj.x - xi.x * xj.y;
+                                G[k] += (ci > 0.f) - (ci < 0.f);
+                                Ap[k] += fabsf(ci);
+                                Qp[k] += ci * ci;
+                            }
+                        }
+                    }
+                }
+            } else {
+            Gram<PREC>::chunk(Xs, arow, bcol, lg, sre, sim);
+            if (mfmaU) Gram<PREC>::chunk(Us, arow, bcol, lg, ure, uim);
 #pragma unroll 4
             for (int t = 0; t < nk; ++t) {
 #pragma unroll
@@ -223,6 +264,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_pair_batch(SessDev<float> s, int
                         }
                     }
                 }
+            }
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
