@@ -249,12 +249,12 @@ template <int F> constexpr bool xcor_tw_lds() { return F <= 1024; }
 // LDS; each wavefront takes two columns at a time into its own transform.
 // Up to F = 1024 the global loads of a job are issued early: this job's
 // column energies and the next job's column spectra go into registers before
-// the transform, so their latency overlaps it.  NL = lag registers per lane:
-// (L + 1) <= 64 NL.
+// the transform, so their latency overlaps it.  NL = F / 128 lag registers
+// per lane (L + 1 <= F / 2).
 template <int F> constexpr bool xcor_prefetch() { return F <= 1024; }
 
 template <typename T, int F, int NL>
-__global__ __launch_bounds__(64 * xcor_waves<F>()) __attribute__((amdgpu_waves_per_eu(F == 1024 && NL == 8 ? 3 : 1)))
+__global__ __launch_bounds__(64 * xcor_waves<F>()) __attribute__((amdgpu_waves_per_eu(F == 1024 ? 3 : 1)))
 void k_xcor_pair(SessDev<T> s)
 {
     constexpr int NW = xcor_waves<F>();
@@ -390,27 +390,13 @@ template <typename T> hipError_t launch_xcor(const SessDev<T> &s, hipStream_t st
 {
     hipLaunchKernelGGL(k_xcor_node<T>, dim3(s.N), dim3(XT), 0, st, s);
     const dim3 grid((unsigned)(s.ntiles * TILE));
-    // lag registers: half the transform when the lags fit, else all of it
-    const bool half = s.xL + 1 <= s.xF / 2;
-    const dim3 b256(64 * xcor_waves<256>()), b512(64 * xcor_waves<512>()), b1k(64 * xcor_waves<1024>()),
-        b2k(64 * xcor_waves<2048>());
+    // lag registers: L <= M - 1 and M + L <= F give L + 1 <= F / 2
+    if (2 * (s.xL + 1) > s.xF) return hipErrorInvalidValue;
     switch (s.xF) {
-    case 256:
-        if (half) hipLaunchKernelGGL((k_xcor_pair<T, 256, 2>), grid, b256, 0, st, s);
-        else hipLaunchKernelGGL((k_xcor_pair<T, 256, 4>), grid, b256, 0, st, s);
-        break;
-    case 512:
-        if (half) hipLaunchKernelGGL((k_xcor_pair<T, 512, 4>), grid, b512, 0, st, s);
-        else hipLaunchKernelGGL((k_xcor_pair<T, 512, 8>), grid, b512, 0, st, s);
-        break;
-    case 1024:
-        if (half) hipLaunchKernelGGL((k_xcor_pair<T, 1024, 8>), grid, b1k, 0, st, s);
-        else hipLaunchKernelGGL((k_xcor_pair<T, 1024, 16>), grid, b1k, 0, st, s);
-        break;
-    case 2048:
-        if (half) hipLaunchKernelGGL((k_xcor_pair<T, 2048, 16>), grid, b2k, 0, st, s);
-        else hipLaunchKernelGGL((k_xcor_pair<T, 2048, 32>), grid, b2k, 0, st, s);
-        break;
+    case 256: hipLaunchKernelGGL((k_xcor_pair<T, 256, 2>), grid, dim3(64 * xcor_waves<256>()), 0, st, s); break;
+    case 512: hipLaunchKernelGGL((k_xcor_pair<T, 512, 4>), grid, dim3(64 * xcor_waves<512>()), 0, st, s); break;
+    case 1024: hipLaunchKernelGGL((k_xcor_pair<T, 1024, 8>), grid, dim3(64 * xcor_waves<1024>()), 0, st, s); break;
+    case 2048: hipLaunchKernelGGL((k_xcor_pair<T, 2048, 16>), grid, dim3(64 * xcor_waves<2048>()), 0, st, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

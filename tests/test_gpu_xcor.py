@@ -39,8 +39,8 @@ def _check(s, x, cfg, lo, hi, label, pi=None, pj=None, idx=None, tol=TOL):
 @pytest.mark.parametrize("N,M,W,T,L", [(40, 100, 5, 9, 0), (70, 256, 4, 7, 0), (33, 300, 3, 5, 60),
                                        (65, 500, 6, 11, 0), (20, 600, 3, 4, 0), (17, 1000, 2, 3, 1000 - 1)])
 def test_sliding_window_vs_oracle(fcx, N, M, W, T, L):
-    """Windows that fill and evict, FFT lengths 256..2048 (radix-4 only and
-    with the radix-2 stage), full and limited lag ranges, ragged tiles."""
+    """Windows that fill and evict, FFT lengths 256..2048 (every radix set of
+    the transform), full and limited lag ranges, ragged tiles."""
     cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=W, n_fft=max(M, 256), f_lo_hz=8, f_hi_hz=30,
                             metrics=synth.XCOR | synth.COR | synth.COH, xcor_max_lag=L)
     x = synth.source_space(40 + N, N, T, M, 6).astype(np.float32)
