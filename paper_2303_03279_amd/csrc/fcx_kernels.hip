@@ -309,11 +309,18 @@ __device__ __forceinline__ void cor_block(const SessDev<T> &s, const PushView &p
 }
 
 // Bins of a pair whose running-sum loads are issued together (1: the next
-// bin's loads are in flight while the current bin is computed).
-#ifndef FCX_BIN_GROUP
-#define FCX_BIN_GROUP 2
+// bin's loads are in flight while the current bin is computed).  Measured
+// best per variant on the 5000-node and 10000-node pushes: 8 for a single
+// taper without COR, 6 with COR (its operand ring takes registers), 4 for
+// multitaper sums, 2 for FP64 sessions.  FCX_BIN_GROUP overrides all.
+template <typename T, int LT, int COR> constexpr int bin_group()
+{
+#ifdef FCX_BIN_GROUP
+    return FCX_BIN_GROUP;
+#else
+    return sizeof(T) == 8 ? 2 : (LT != 1 ? 4 : (COR ? 6 : 8));
 #endif
-constexpr int BIN_GROUP = FCX_BIN_GROUP;
+}
 
 // running sums of one (pair, bin) as held in the planes
 struct PairState {
@@ -602,6 +609,7 @@ __device__ __forceinline__ void pair_slice_body(const SessDev<T> &s, const PushV
                     acc[6] += K >= 2 ? (dd != 0.0 ? ratio_t<T>(st.sim * st.sim - st.q, dd) : (T)0) : (T)NAN;
                 }
             };
+            constexpr int BIN_GROUP = bin_group<T, LT, COR>();
             if constexpr (BIN_GROUP <= 1) {
                 // software pipelining: the next bin's sums are in flight
                 // while this bin is computed
