@@ -344,9 +344,10 @@ fcx_status fcx_hilbert_info(fcx_hilbert *h, int32_t *n_windows, int32_t *fft_len
  * metrics (the other rows are not written).  z (device, may be NULL)
  * receives the analytic signal as [M][N] complex FP32 (re, im).  The call
  * only enqueues work on the handle's stream.  Nodes 2k and 2k + 1 share one
- * transform: a non-finite input sample makes the analytic signals of both,
- * and so the metrics of their pairs, non-finite.  Errors: FCX_E_INVAL (NULL x or
- * out, ld < M), FCX_E_CLOSED, FCX_E_DEVICE.
+ * transform: a non-finite input sample makes the analytic signals of both
+ * non-finite and the metrics of their pairs meaningless (the zero-denominator
+ * rules may turn them into 0 rather than NaN); other pairs are unaffected.
+ * Errors: FCX_E_INVAL (NULL x or out, ld < M), FCX_E_CLOSED, FCX_E_DEVICE.
  */
 fcx_status fcx_hilbert_run(fcx_hilbert *h, const float *x, int64_t ld, float *out, float *z);
 fcx_status fcx_hilbert_close(fcx_hilbert *h);

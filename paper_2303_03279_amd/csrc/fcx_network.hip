@@ -43,13 +43,18 @@ constexpr int SEL_MAX_BLOCKS = 2048;          // grid of the streaming passes
 constexpr double SEL_FIX = 4294967296.0;      // 2^32
 constexpr unsigned long long SEL_DEG1 = 1ull << 48;
 
-struct SelCtl {
+// the part the host reads back after a call
+struct SelHead {
     unsigned int maxbits;       // max |w| as float bits
     unsigned int prefix, mask;  // radix-select state: key bits found so far
     unsigned int none;          // k == 0: nothing is selected
     long long k, k_left;
     unsigned long long n_finite, n_selected;
     unsigned long long slot_ns[SEL_SLOTS];
+};
+
+struct SelCtl {
+    SelHead h;
     unsigned int blk_max[SEL_MAX_BLOCKS];        // per scan block: max key, finite count
     unsigned long long blk_nf[SEL_MAX_BLOCKS];
     unsigned int hist[SEL_SLOTS][SEL_BINS];
@@ -167,16 +172,16 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_init(SelCtl *c, int nblk, d
             mx = max(mx, smax[q]);
             nf += scnt[q];
         }
-        c->maxbits = mx;
-        c->n_finite = nf;
+        c->h.maxbits = mx;
+        c->h.n_finite = nf;
         const double kk = ceil(fraction * (double)P);
         long long k = (long long)kk;
         if (k > (long long)nf) k = (long long)nf;
-        c->k = k;
-        c->k_left = k;
-        c->none = k <= 0;
-        c->prefix = 0;
-        c->mask = 0;
+        c->h.k = k;
+        c->h.k_left = k;
+        c->h.none = k <= 0;
+        c->h.prefix = 0;
+        c->h.mask = 0;
     }
 }
 
@@ -191,8 +196,8 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_hist(const float *__restric
     __shared__ unsigned int h[SEL_BINS];
     for (int d = threadIdx.x; d < nb; d += SEL_THREADS) h[d] = 0;
     __syncthreads();
-    const unsigned int prefix = c->prefix, mask = c->mask, dm = (unsigned int)nb - 1u;
-    if (!c->none)
+    const unsigned int prefix = c->h.prefix, mask = c->h.mask, dm = (unsigned int)nb - 1u;
+    if (!c->h.none)
         sel_for_each<VEC>(w, P, [&](long long, float v) {
             unsigned int key;
             if (sel_key(v, key) && (key & mask) == prefix) atomicAdd(&h[(key >> shift) & dm], 1u);
@@ -212,8 +217,8 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_pick(SelCtl *c, int shift, 
     __shared__ unsigned long long run[SEL_THREADS];
     const int per = nb / SEL_THREADS;
     // read before any barrier: one thread rewrites k_left at the end
-    const bool none = c->none;
-    const long long kl = c->k_left;
+    const bool none = c->h.none;
+    const long long kl = c->h.k_left;
     for (int d = threadIdx.x; d < nb; d += SEL_THREADS) {
         unsigned int t = 0;
 #pragma unroll
@@ -240,9 +245,9 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_pick(SelCtl *c, int shift, 
             for (int d = threadIdx.x * per + per - 1; d >= threadIdx.x * per; --d) {
                 const long long hd = tot[d];
                 if (cum + hd >= kl) {
-                    c->prefix |= (unsigned int)d << shift;
-                    c->mask |= (unsigned int)(nb - 1) << shift;
-                    c->k_left = kl - cum;
+                    c->h.prefix |= (unsigned int)d << shift;
+                    c->h.mask |= (unsigned int)(nb - 1) << shift;
+                    c->h.k_left = kl - cum;
                     break;
                 }
                 cum += hd;
@@ -256,7 +261,7 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_pick(SelCtl *c, int shift, 
 __device__ __forceinline__ bool sel_take(float v, const SelCtl &c, unsigned int T)
 {
     unsigned int key;
-    return sel_key(v, key) && !c.none && key >= T;
+    return sel_key(v, key) && !c.h.none && key >= T;
 }
 
 __device__ __forceinline__ float sel_norm(float v, float m)
@@ -278,8 +283,8 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_rows(const float *w, int N,
     __shared__ unsigned long long scnt[SEL_THREADS / 64];
     const int i = blockIdx.x * (SEL_THREADS / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const unsigned int T = c->prefix;
-    const float m = __uint_as_float(c->maxbits);
+    const unsigned int T = c->h.prefix;
+    const float m = __uint_as_float(c->h.maxbits);
     unsigned long long ns = 0;
     if (i < N - 1) {
         const long long r0 = (long long)i * (2LL * N - i - 1) / 2 - (i + 1);   // e = r0 + j
@@ -316,7 +321,7 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_rows(const float *w, int N,
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int q = 1; q < SEL_THREADS / 64; ++q) ns += scnt[q];
-        if (ns) atomicAdd(&c->slot_ns[blockIdx.x % SEL_SLOTS], ns);
+        if (ns) atomicAdd(&c->h.slot_ns[blockIdx.x % SEL_SLOTS], ns);
     }
 }
 
@@ -360,8 +365,8 @@ extern "C" fcx_status fcx_network_select(int32_t n_nodes, const float *w, double
     if (blocks > SEL_MAX_BLOCKS) blocks = SEL_MAX_BLOCKS;
     if (blocks < 1) blocks = 1;
     const dim3 grid((unsigned)blocks), blk(SEL_THREADS);
-    SelCtl *h = new (std::nothrow) SelCtl;
-    if (!h) return FCX_E_NOMEM;
+    SelHead hh{};
+    SelHead *h = &hh;
     bool ok = hipMemsetAsync(c, 0, offsetof(SelCtl, node), st) == hipSuccess;
     if (ok) {
         if (vec)
@@ -384,7 +389,7 @@ extern "C" fcx_status fcx_network_select(int32_t n_nodes, const float *w, double
         if (nodes)
             hipLaunchKernelGGL(k_sel_node_out, dim3((n_nodes + SEL_THREADS - 1) / SEL_THREADS), blk, 0, st, c, n_nodes,
                                degree, strength);
-        ok = hipGetLastError() == hipSuccess && hipMemcpyAsync(h, c, offsetof(SelCtl, hist), hipMemcpyDeviceToHost, st) ==
+        ok = hipGetLastError() == hipSuccess && hipMemcpyAsync(h, &c->h, sizeof(SelHead), hipMemcpyDeviceToHost, st) ==
                                                      hipSuccess && hipStreamSynchronize(st) == hipSuccess;
     }
     if (ok && info) {
@@ -399,6 +404,5 @@ extern "C" fcx_status fcx_network_select(int32_t n_nodes, const float *w, double
         info->n_finite = (int64_t)h->n_finite;
         info->n_selected = (int64_t)ns;
     }
-    delete h;
     return ok ? FCX_OK : FCX_E_DEVICE;
 }

@@ -222,3 +222,33 @@ def test_full_size_sampled_pairs(fcx):
     torch.cuda.synchronize()
     assert torch.equal(out, out2)
     fcx.check(h.close())
+
+
+def test_smallest_segment(fcx):
+    """Two nodes and one sample: one window of one sample (PLV = PLI = WPLI =
+    COH = 1 for non-zero samples, USPLI / DSWPLI undefined)."""
+    x = np.array([[0.7], [-1.3]], dtype=np.float32)
+    taps = np.ones(1)
+    res, z, nw, F = _run(fcx, x, taps, 0, 0)
+    assert nw == 1 and F == 256 and res.shape == (1, 7, 1)
+    zr = oh.analytic(x.astype(np.float64), taps)
+    assert np.max(np.abs(z - zr)) <= TOL * np.max(np.abs(zr))
+    ref = oh.network(zr)
+    _compare(res, ref, BOUND["fp32"], "N=2 M=1", zr, oracle.all_pairs(2), _z_deviation(z, zr))
+
+
+def test_nonfinite_sample_poisons_its_transform_pair_only(fcx):
+    """A NaN in node 5 makes the analytic signals of nodes 4 and 5 (one
+    transform) non-finite, so the metrics of the pairs touching them are
+    meaningless; every other pair equals the run on clean data bit for bit."""
+    N, M = 12, 300
+    x = _segment(21, N, M)
+    taps = _taps(101)
+    clean, _, _, _ = _run(fcx, x, taps, 100, 100, want_z=False)
+    x2 = x.copy()
+    x2[5, 17] = np.nan
+    dirty, _, _, _ = _run(fcx, x2, taps, 100, 100, want_z=False)
+    pi, pj = oracle.all_pairs(N)
+    hit = np.isin(pi, [4, 5]) | np.isin(pj, [4, 5])
+    assert np.array_equal(dirty[:, :, ~hit], clean[:, :, ~hit])
+    assert not np.array_equal(dirty[:, :, hit], clean[:, :, hit], equal_nan=True)
