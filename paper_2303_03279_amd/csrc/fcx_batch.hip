@@ -203,7 +203,9 @@ __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))
             if constexpr (PREC == FCX_GRAM_FP32_ID && LT == 1) {
                 // FP32 Gram, one taper: each MFMA step (4 trials) is followed by
                 // the vector sums of the same 4 trials, so the matrix-core
-                // latency overlaps vector work (same operations, same order)
+                // latency overlaps vector work.  Im(x_i conj x_j) and the Im^2
+                // sum use fused multiply-adds (the kernel is bound by these
+                // vector sums)
 #pragma unroll
                 for (int st = 0; st < BT_CC / 4; ++st) {
                     {
@@ -230,10 +232,10 @@ __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))
 #pragma unroll
                             for (int k = 0; k < 4; ++k) {
                                 const float2 xi = Xs[rows[k] * BT_LD + t];
-                                const float ci = xi.y * xj.x - xi.x * xj.y;
+                                const float ci = __builtin_fmaf(xi.y, xj.x, -(xi.x * xj.y));
                                 G[k] += (ci > 0.f) - (ci < 0.f);
                                 Ap[k] += fabsf(ci);
-                                Qp[k] += ci * ci;
+                                Qp[k] = __builtin_fmaf(ci, ci, Qp[k]);
                             }
                         }
                     }
