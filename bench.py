@@ -477,8 +477,8 @@ def main():
                     help="timed pushes of the 10000-node multitaper session, 0 to skip")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path (the update shards by pair "
-              "tiles, see the design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the update would shard by "
+              "pair tiles over GPUs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
