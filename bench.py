@@ -29,6 +29,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# vector-unit lane operations per second: 256 CUs x 4 SIMD16 x 2.4 GHz
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+# least vector work per pair x trial (or sample) of the sign / |Im| / Im^2
+# sums: Im(x_i conj x_j) 2, sign count 2, |Im| 1, Im^2 1, ... rounded to 8
+VALU_OPS_PER_PAIR_TRIAL = 8
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "pair_update_n5000_all8_traffic.json")
 
 
@@ -377,7 +382,8 @@ def run_hilbert(fcx, torch, cfg, pool_dev, reps):
         K = M if L == 0 else L
         units = P * K * h.n_windows
         res[name] = dict(windows=h.n_windows, window_len=K, ms_per_segment=ms,
-                         pair_samples_per_s=units / (ms * 1e-3))
+                         pair_samples_per_s=units / (ms * 1e-3),
+                         valu_frac=units * VALU_OPS_PER_PAIR_TRIAL / (ms * 1e-3) / VALU_LANE_OPS)
         fcx.check(h.close())
         del out
         torch.cuda.empty_cache()
@@ -549,7 +555,9 @@ def main():
             batch[prec] = dict(ms_per_batch=w * 1e3, updates_per_s=P * B * K / w,
                                pair_batch_ms=pms, cor_batch_ms=cms,
                                gram_tflops=gram_flops / (pms * 1e-3) / 1e12 if pms else None,
-                               cor_tflops=cor_flops / (cms * 1e-3) / 1e12 if cms else None)
+                               cor_tflops=cor_flops / (cms * 1e-3) / 1e12 if cms else None,
+                               pair_valu_frac=(P * B * K * VALU_OPS_PER_PAIR_TRIAL / (pms * 1e-3) / VALU_LANE_OPS
+                                               if pms else None))
 
     sensor = None
     if args.sensor_pushes > 0:
