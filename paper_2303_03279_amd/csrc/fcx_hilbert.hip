@@ -8,11 +8,15 @@
 //                  DFT, m = 1 at DC and F/2, 2 at the positive frequencies,
 //                  0 above), two inverse transforms; samples D .. D + M - 1
 //                  of the result go to z [M][N] (sample-major, complex)
-//   per window     the window sum of |z_i|^2 (k_psd_batch) and the pair pass
-//                  of the batch path (k_pair_batch): the cross-spectrum Gram
-//                  on the matrix cores and the sign / |Im| / Im^2 sums on the
-//                  vector units, with the window's samples in the role of the
-//                  trials (one bin, one taper)
+//   windows        FP32 Gram with overlapping windows (blocks of at least 8
+//                  samples, at most 3 windows open): k_window_psd and one pass of
+//                  k_hilbert_windows over blocks of gcd(L, H) samples, each
+//                  block's sums added to the windows holding it; otherwise per
+//                  window the window sum of |z_i|^2 (k_psd_batch) and the pair
+//                  pass of the batch path (k_pair_batch).  Both take the
+//                  cross-spectrum Gram on the matrix cores and the sign / |Im|
+//                  / Im^2 sums on the vector units, with the window's samples
+//                  in the role of the trials (one bin, one taper)
 #include "fcx_device.h"
 #include "fcx_fft.h"
 
@@ -84,6 +88,199 @@ __global__ __launch_bounds__(HT) void k_analytic(int N, int M, int D, const floa
     }
 }
 
+// ---------------------------------------------------------------------------
+// Overlapping windows in one pass (FP32 Gram).  The sample axis is cut into
+// blocks of Bk = gcd(L, H) samples; a window is bl = L / Bk consecutive blocks
+// and windows start every bh = H / Bk blocks.  Every block's sums are
+// computed once, in 32-sample chunks staged through LDS (complex Gram on the
+// matrix cores, sign / |Im| / Im^2 sums on the vector units), and added to
+// each of the NWO = ceil(bl / bh) (2 or 3) windows that hold it; a window's
+// metrics are written when its last block is done.
+// ---------------------------------------------------------------------------
+constexpr int HW_CC = 32;            // samples per staged chunk
+constexpr int HW_LD = HW_CC + 1;     // LDS row stride in float2
+
+struct HWin {
+    int Bk, bl, bh, nwin, nblk;
+    const double *psd;   // [nwin][N] window power sums
+    float *out;          // [nwin][7][P]
+};
+
+// window power sums: psd[w][i] = sum over the window's samples of |z_i|^2
+__global__ __launch_bounds__(256) void k_window_psd(const float2 *__restrict__ z, int N, int L, int H, double *psd)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x, w = blockIdx.y;
+    if (i >= N) return;
+    double p = 0.0;
+    for (int t = w * H; t < w * H + L; ++t) {
+        const float2 v = z[(size_t)t * N + i];
+        p += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    psd[(size_t)w * N + i] = p;
+}
+
+template <int NWO>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NWO == 2 ? 3 : 1))) void k_hilbert_windows(
+    SessDev<float> s, HWin hw)
+{
+    __shared__ float2 Xs[64 * HW_LD];
+    __shared__ float2 Us[64 * HW_LD];
+    const int tile = blockIdx.x >> 2, qd = blockIdx.x & 3;
+    const int2 tt = s.tiles[tile];
+    const int R0 = tt.x * TILE + 32 * (qd >> 1), C0 = tt.y * TILE + 32 * (qd & 1);
+    const int N = s.N;
+    if (R0 >= N || R0 >= min(C0 + 31, N - 1)) return;   // no pair i < j < N here
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int wr = w >> 1, wc = w & 1;
+    const int arow = 16 * wr + lr;           // LDS node of this lane's A fragment
+    const int bcol = 32 + 16 * wc + lr;      // LDS node of this lane's B fragment = its pairs' column
+    const int j = C0 + 16 * wc + lr;
+    int rows[4];                             // accumulator element k: row 4 lg + k of the wave's block
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rows[k] = 16 * wr + 4 * lg + k;
+    const uint32_t mm = s.metrics;
+    const bool needU = mm & M_PLV;
+    const float2 *z = (const float2 *)s.ring;   // [M][N]
+    const size_t P = (size_t)N * (N - 1) / 2;
+    const int K = hw.bl * hw.Bk;
+    const double Kd = (double)K;
+
+    // open windows: slot q holds window wid[q] (-1: none)
+    int wid[NWO];
+    float wsr[NWO][4], wsi[NWO][4], wur[NWO][4], wui[NWO][4];
+    int wg[NWO][4];
+    double wa[NWO][4], wq[NWO][4];
+#pragma unroll
+    for (int q = 0; q < NWO; ++q) wid[q] = -1;
+
+    for (int blk = 0; blk < hw.nblk; ++blk) {
+        if (blk % hw.bh == 0 && blk / hw.bh < hw.nwin) {   // a window starts here
+            const int wn = blk / hw.bh;
+#pragma unroll
+            for (int q = 0; q < NWO; ++q)
+                if (q == wn % NWO) {
+                    wid[q] = wn;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        wsr[q][k] = wsi[q][k] = wur[q][k] = wui[q][k] = 0.f;
+                        wg[q][k] = 0;
+                        wa[q][k] = wq[q][k] = 0.0;
+                    }
+                }
+        }
+        floatx4 sre = {0.f, 0.f, 0.f, 0.f}, sim = sre, ure = sre, uim = sre;
+        int G[4] = {0, 0, 0, 0};
+        double Ab[4] = {0.0, 0.0, 0.0, 0.0}, Qb[4] = {0.0, 0.0, 0.0, 0.0};
+        const int tb = blk * hw.Bk;
+        for (int t0 = tb; t0 < tb + hw.Bk; t0 += HW_CC) {
+            const int nk = min(HW_CC, tb + hw.Bk - t0);
+            float Ap[4] = {0.f, 0.f, 0.f, 0.f}, Qp[4] = {0.f, 0.f, 0.f, 0.f};   // FP32 within a chunk
+            __syncthreads();
+            // consecutive lanes take consecutive nodes of one sample
+            for (int e = threadIdx.x; e < 64 * HW_CC; e += 256) {
+                const int node = e & 63, col = e >> 6;
+                const int g = node < 32 ? R0 + node : C0 + node - 32;
+                float2 v = make_float2(0.f, 0.f), u = v;
+                if (col < nk && g < N) {
+                    v = z[(size_t)(t0 + col) * N + g];
+                    if (needU) {
+                        const double m2 = (double)v.x * v.x + (double)v.y * v.y;
+                        const double r = m2 > 0.0 ? rsqrt(m2) : 0.0;
+                        u.x = (float)(v.x * r);
+                        u.y = (float)(v.y * r);
+                    }
+                }
+                Xs[node * HW_LD + col] = v;
+                if (needU) Us[node * HW_LD + col] = u;
+            }
+            __syncthreads();
+            // each MFMA step (4 samples) is followed by the vector sums of
+            // the same samples
+#pragma unroll
+            for (int st = 0; st < HW_CC / 4; ++st) {
+                {
+                    const float2 a = Xs[arow * HW_LD + 4 * st + lg];
+                    const float2 bb = Xs[bcol * HW_LD + 4 * st + lg];
+                    sre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, sre, 0, 0, 0);
+                    sre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, sre, 0, 0, 0);
+                    sim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, sim, 0, 0, 0);
+                    sim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, bb.y, sim, 0, 0, 0);
+                }
+                if (needU) {
+                    const float2 a = Us[arow * HW_LD + 4 * st + lg];
+                    const float2 bb = Us[bcol * HW_LD + 4 * st + lg];
+                    ure = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, ure, 0, 0, 0);
+                    ure = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, ure, 0, 0, 0);
+                    uim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, uim, 0, 0, 0);
+                    uim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, bb.y, uim, 0, 0, 0);
+                }
+#pragma unroll
+                for (int t4 = 0; t4 < 4; ++t4) {
+                    const int t = 4 * st + t4;
+                    if (t < nk) {
+                        const float2 xj = Xs[bcol * HW_LD + t];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const float2 xi = Xs[rows[k] * HW_LD + t];
+                            const float ci = __builtin_fmaf(xi.y, xj.x, -(xi.x * xj.y));
+                            G[k] += (ci > 0.f) - (ci < 0.f);
+                            Ap[k] += fabsf(ci);
+                            Qp[k] = __builtin_fmaf(ci, ci, Qp[k]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                Ab[k] += (double)Ap[k];
+                Qb[k] += (double)Qp[k];
+            }
+        }
+        // the block into every open window, then the windows that end here
+#pragma unroll
+        for (int q = 0; q < NWO; ++q) {
+            if (wid[q] < 0) continue;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                wsr[q][k] += sre[k];
+                wsi[q][k] += sim[k];
+                wur[q][k] += ure[k];
+                wui[q][k] += uim[k];
+                wg[q][k] += G[k];
+                wa[q][k] += Ab[k];
+                wq[q][k] += Qb[k];
+            }
+            if (blk != wid[q] * hw.bh + hw.bl - 1) continue;
+            const int wn = wid[q];
+            wid[q] = -1;
+            const double *ps = hw.psd + (size_t)wn * N;
+            float *out = hw.out + (size_t)wn * 7 * P;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int i = R0 + rows[k];
+                if (!(i < j && j < N)) continue;
+                const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+                const double Sr = wsr[q][k], Si = wsi[q][k], A = wa[q][k], Q = wq[q][k];
+                const double pp = ps[i] * ps[j];
+                if (mm & M_COH) out[idx] = pp > 0.0 ? (float)sqrt((Sr * Sr + Si * Si) / pp) : 0.f;
+                if (mm & M_IMCOH) out[P + idx] = pp > 0.0 ? (float)(Si / sqrt(pp)) : 0.f;
+                if (mm & M_PLV) {
+                    const double ur = wur[q][k], ui = wui[q][k];
+                    out[2 * P + idx] = (float)(sqrt(ur * ur + ui * ui) / Kd);
+                }
+                const double pli = fabs((double)wg[q][k]) / Kd;
+                if (mm & M_PLI) out[3 * P + idx] = (float)pli;
+                if (mm & M_WPLI) out[4 * P + idx] = A > 0.0 ? ratio_t<float>(fabs(Si), A) : 0.f;
+                if (mm & M_USPLI) out[5 * P + idx] = K >= 2 ? (float)((Kd * pli * pli - 1.0) / (Kd - 1.0)) : NAN;
+                if (mm & M_DSWPLI) {
+                    const double dd = A * A - Q;
+                    out[6 * P + idx] = K >= 2 ? (dd != 0.0 ? ratio_t<float>(Si * Si - Q, dd) : 0.f) : NAN;
+                }
+            }
+        }
+    }
+}
+
 }  // namespace fcx
 
 using namespace fcx;
@@ -96,8 +293,11 @@ struct fcx_hilbert {
     std::vector<double> taps;
     hipStream_t st = nullptr;
     int F = 0, D = 0, K = 0, hop = 0, n_win = 0;
+    // one pass over overlapping windows (FP32 Gram): blocks of Bk samples,
+    // windows of bl blocks every bh blocks, nwo windows open at a time
+    int Bk = 0, bl = 0, bh = 0, nblk = 0, nwo = 0;
     float2 *tw = nullptr, *g = nullptr, *z = nullptr;
-    double *psd = nullptr, *lamw = nullptr;
+    double *psd = nullptr, *lamw = nullptr, *wpsd = nullptr;
     int2 *tiles = nullptr;
     DevCtl *ctl = nullptr;
     SessDev<float> dev{};
@@ -118,7 +318,7 @@ fcx_hilbert *lookup_hilbert(fcx_hilbert *h)
 
 void hilbert_free(fcx_hilbert *s)
 {
-    void *bufs[] = {s->tw, s->g, s->z, s->psd, s->lamw, s->tiles, s->ctl};
+    void *bufs[] = {s->tw, s->g, s->z, s->psd, s->lamw, s->tiles, s->ctl, s->wpsd};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
 }
@@ -153,6 +353,22 @@ fcx_status fcx_hilbert_open(const fcx_hilbert_config *cfg, void *hip_stream, fcx
     s->K = K;
     s->hop = hop;
     s->n_win = 1 + (M - K) / hop;
+    {
+        int a = K, b = hop;
+        while (b) {
+            const int t = a % b;
+            a = b;
+            b = t;
+        }
+        const int Bk = a, bl = K / Bk, bh = hop / Bk, nwo = (bl + bh - 1) / bh;
+        if (cfg->gram_precision == FCX_GRAM_FP32 && hop < K && Bk >= 8 && nwo <= 3) {
+            s->Bk = Bk;
+            s->bl = bl;
+            s->bh = bh;
+            s->nwo = nwo;
+            s->nblk = (s->n_win - 1) * bh + bl;
+        }
+    }
     const int nT = (N + TILE - 1) / TILE;
     const int ntiles = nT * (nT + 1) / 2;
     bool ok = hipMalloc((void **)&s->tw, F * sizeof(float2)) == hipSuccess;
@@ -162,6 +378,7 @@ fcx_status fcx_hilbert_open(const fcx_hilbert_config *cfg, void *hip_stream, fcx
     ok = ok && hipMalloc((void **)&s->lamw, sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc((void **)&s->tiles, (size_t)ntiles * sizeof(int2)) == hipSuccess;
     ok = ok && hipMalloc((void **)&s->ctl, sizeof(DevCtl)) == hipSuccess;
+    if (s->nwo) ok = ok && hipMalloc((void **)&s->wpsd, (size_t)s->n_win * N * sizeof(double)) == hipSuccess;
     if (!ok) {
         hilbert_free(s);
         delete s;
@@ -253,7 +470,19 @@ fcx_status fcx_hilbert_run(fcx_hilbert *h, const float *x, int64_t ld, float *ou
     if (hipGetLastError() != hipSuccess) return FCX_E_DEVICE;
     const size_t P = (size_t)N * (N - 1) / 2;
     SessDev<float> d = s->dev;
-    for (int w = 0; w < s->n_win; ++w) {
+    if (s->nwo) {
+        d.ring = (float *)s->z;
+        HWin hw{s->Bk, s->bl, s->bh, s->n_win, s->nblk, s->wpsd, out};
+        hipLaunchKernelGGL(k_window_psd, dim3((unsigned)((N + 255) / 256), (unsigned)s->n_win), dim3(256), 0, s->st,
+                           (const float2 *)s->z, N, s->K, s->hop, s->wpsd);
+        const dim3 pg((unsigned)(d.ntiles * 4)), pb(256);
+        if (s->nwo == 2)
+            hipLaunchKernelGGL(k_hilbert_windows<2>, pg, pb, 0, s->st, d, hw);
+        else
+            hipLaunchKernelGGL(k_hilbert_windows<3>, pg, pb, 0, s->st, d, hw);
+        if (hipGetLastError() != hipSuccess) return FCX_E_DEVICE;
+    }
+    for (int w = 0; w < (s->nwo ? 0 : s->n_win); ++w) {
         d.ring = (float *)(s->z + (size_t)w * s->hop * N);
         d.out = out + (size_t)w * 7 * P;
         if (launch_psd_batch(d, s->K, s->st) != hipSuccess ||

@@ -2,7 +2,8 @@
 against the oracle (oracle/hilbert.py): the analytic signal element by
 element, and every window's seven metrics for every pair (sizes that span
 several tiles with a ragged tail, every transform length, windows of one
-sample, overlapping windows), plus sampled pairs at 5000 nodes.
+sample, overlapping windows on both the one-pass block path and the
+window-by-window path), plus sampled pairs at 5000 nodes.
 
 Tolerances.  The analytic signal: 1e-5 of its largest magnitude.  The
 metrics: 1e-5 absolute, plus for PLI / USPLI the oracle's tie allowances, and
@@ -127,6 +128,9 @@ def _compare(res, ref_windows, bound, label, zr=None, pairs=None, e=0.0):
     (5, 40, 1, 1, 1),             # windows of one sample: USPLI / DSWPLI undefined
     (33, 1500, 301, 700, 500),    # F=2048, a tail of samples after the last window
     (9, 1000, 3001, 250, 250),    # F=4096, a long filter
+    (40, 600, 101, 150, 50),      # one pass over blocks of 50 samples, three windows open at a time
+    (20, 300, 51, 30, 20),        # blocks of 10 samples (gcd of 30 and 20), windows of 3 blocks every 2
+    (20, 200, 51, 10, 4),         # blocks of 2 samples: window by window
 ])
 def test_analytic_and_windows_vs_oracle(fcx, N, M, T, L, H):
     x = _segment(N * 7 + M, N, M)
