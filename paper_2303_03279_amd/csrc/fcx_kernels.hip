@@ -239,7 +239,7 @@ __host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes, uint32_
 // The new and the evicted trial are contracted separately so the evicted r is
 // bit-identical to the r added.
 #ifndef FCX_COR_DEPTH
-#define FCX_COR_DEPTH 4
+#define FCX_COR_DEPTH 2
 #endif
 constexpr int COR_DEPTH = FCX_COR_DEPTH;
 
