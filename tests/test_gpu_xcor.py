@@ -122,3 +122,19 @@ def test_served_xcor_rejected(fcx):
     st, h = srv.open(cfg)
     assert st == fcx.FCX_E_INVAL and h is None
     fcx.check(srv.destroy())
+
+
+def test_f64_session(fcx):
+    """An FP64 session with XCOR and COH: XCOR runs its FP32 transform (FP32
+    tolerance), COH stays at the FP64 bound, after the window slides."""
+    from gpu_helpers import TOL_F64, compare_network
+    N, M, W, T = 40, 200, 3, 5
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=W, n_fft=256, f_lo_hz=8, f_hi_hz=30,
+                            metrics=synth.XCOR | synth.COH)
+    cfg["elem"] = "f64"
+    x = synth.source_space(17, N, T, M, 5)
+    s = run_pushes(fcx, cfg, x)
+    _check(s, x, cfg, T - W, T, "f64 session")
+    ref = oracle.network(oracle.as_device_input(x[T - W:], cfg), cfg)
+    compare_network(s, ref, cfg, ["coh"], tol=TOL_F64, label="f64 session coh")
+    s.close()
