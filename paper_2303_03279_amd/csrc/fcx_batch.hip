@@ -8,7 +8,7 @@
 //                   and per pair on the vector units, over the trials:
 //                     G = sum sign(Im), A = sum |Im|, Q = sum Im^2
 //                   then the seven metrics and their band mean
-//   k_cor_batch     per 64x64 tile: sum over trials of the per-trial Pearson r
+//   k_cor_batch     per 128x128 tile: sum over trials of the per-trial Pearson r
 //                   as an LDS-staged MFMA GEMM over the z-scored samples
 //
 // The Gram operands run in the session's precision: FP32
@@ -311,110 +311,228 @@ __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))
 }
 
 // ------------------------------------------------------------------ COR
-// One 64x64 tile per workgroup, 4 wavefronts each with a 32x32 quadrant
-// (2x2 blocks of 16x16).  For every trial the z-scored samples of the tile's
-// 64 row and 64 column nodes are staged through LDS 32 samples at a time;
-// each trial's r is accumulated in FP32 by the MFMAs and added to an FP64
-// sum, so the window sum carries no FP32 growth across trials.
-constexpr int CR_CH = 32;
-constexpr int CR_LD = CR_CH + 1;
+// One 128x128 tile of pairs per workgroup; each wavefront owns a block of
+// CR_WR x CR_WC MFMA blocks of 16x16.  For every trial the z-scored samples
+// of the tile's 128 row and 128 column nodes stream through LDS CR_CH samples
+// at a time, in two buffers, while the next chunks are already on their way
+// into registers.  The BF16 forms round the samples (and, for BF16x3, their
+// remainders) once, as they are written to LDS.  Inside 32 samples lane group
+// lg supplies samples 8lg..8lg+7 (the contraction order is free), so an
+// operand fragment is one or two 16-byte LDS reads.  Each trial's r is
+// accumulated in FP32 by the MFMAs and added to an FP64 sum at the trial's
+// end, so the window sum carries no FP32 growth across trials.  Tiles are
+// numbered in bands of CR_BAND tile rows (column by column inside a band) and
+// each XCD takes a contiguous run of those numbers, so the workgroups resident
+// on one XCD share a few row and column strips in its L2.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+constexpr int CR_T = 128;     // tile edge in nodes
+#ifndef FCX_COR_CH
+#define FCX_COR_CH 32
+#endif
+constexpr int CR_CH = FCX_COR_CH;  // samples per staged chunk (divides the padded trial length)
+constexpr int CR_LD = CR_CH + 4;   // LDS row stride in floats: 16-byte lane reads hit distinct banks
+constexpr int CR_LDH = CR_CH + 8;  // the same for rows of BF16
+constexpr int CR_BAND = 4;
+#ifndef FCX_COR_WR
+#define FCX_COR_WR 2
+#endif
+#ifndef FCX_COR_WC
+#define FCX_COR_WC 4
+#endif
+#ifndef FCX_COR_PF32
+#define FCX_COR_PF32 1      // chunks in flight ahead of the FP32 MFMAs
+#endif
+#ifndef FCX_COR_PF16
+#define FCX_COR_PF16 3      // and ahead of the (shorter) BF16 ones
+#endif
 
-template <int PREC>
-__device__ __forceinline__ void cor_chunk(const float *Zr, const float *Zc, int ra, int cb, int lg, floatx4 &acc)
+// Tile (row, column), row <= column, of number lin in the band order.
+__device__ __forceinline__ int2 cor_tile(int lin, int T)
 {
-    if (PREC == FCX_GRAM_FP32_ID) {
-#pragma unroll
-        for (int st = 0; st < CR_CH / 4; ++st)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Zr[ra * CR_LD + 4 * st + lg], Zc[cb * CR_LD + 4 * st + lg], acc,
-                                                       0, 0, 0);
-    } else {
-        bf16x8 ah, al, bh, bl;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float a = Zr[ra * CR_LD + 8 * lg + e], b = Zc[cb * CR_LD + 8 * lg + e];
-            if (PREC == FCX_GRAM_BF16_ID) {
-                ah[e] = (__bf16)a;
-                bh[e] = (__bf16)b;
-            } else {
-                ah[e] = bf_hi(a);
-                al[e] = bf_lo(a);
-                bh[e] = bf_hi(b);
-                bl[e] = bf_lo(b);
+    for (int r0 = 0; r0 < T; r0 += CR_BAND) {
+        const int h = min(CR_BAND, T - r0);
+        const int tri = h * (h + 1) / 2;
+        const int cnt = tri + (T - r0 - h) * h;
+        if (lin < cnt) {
+            if (lin < tri) {  // the band's diagonal block: column r0 + q holds rows r0 .. r0 + q
+                int q = 0;
+                while ((q + 1) * (q + 2) / 2 <= lin) ++q;
+                return make_int2(r0 + lin - q * (q + 1) / 2, r0 + q);
             }
+            lin -= tri;
+            return make_int2(r0 + lin % h, r0 + h + lin / h);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-        if (PREC == FCX_GRAM_BF16X3_ID) {
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-        }
+        lin -= cnt;
     }
+    return make_int2(0, 0);
 }
 
-template <int PREC>
-__global__ __launch_bounds__(256) void k_cor_batch(SessDev<float> s, int K)
+__device__ __forceinline__ float cor_pick(float4 v, int e)
 {
-    __shared__ float Zr[64 * CR_LD];
-    __shared__ float Zc[64 * CR_LD];
+    return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+}
+
+template <int PREC, int WR, int WC, int PF>
+__global__ __launch_bounds__(64 * (CR_T / (16 * WR)) * (CR_T / (16 * WC))) void k_cor_batch(SessDev<float> s, int K)
+{
+    constexpr int WAVES_C = CR_T / (16 * WC);
+    constexpr int NT = 64 * (CR_T / (16 * WR)) * WAVES_C;
+    constexpr int V4 = 2 * CR_T * (CR_CH / 4) / NT;  // float4 staged per thread and chunk
+    static_assert(V4 * NT == 2 * CR_T * (CR_CH / 4), "staging must cover the chunk");
+    // one buffer: FP32 rows of CR_LD floats, or BF16 rows of CR_LDH (hi, then for
+    // BF16x3 a plane of lo parts)
+    constexpr int ZBUF = PREC == FCX_GRAM_FP32_ID ? 2 * CR_T * CR_LD
+                         : (PREC == FCX_GRAM_BF16_ID ? 1 : 2) * 2 * CR_T * CR_LDH / 2;
+    __shared__ __attribute__((aligned(16))) float Z[2][ZBUF];
     if (s.ctl->bad) return;
-    const int tile = blockIdx.x;
-    const int2 tt = s.tiles[tile];
-    const int I0 = tt.x * TILE, J0 = tt.y * TILE;
     const int N = s.N, Mz = s.Mz;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-    const int qi = w >> 1, qj = w & 1;
-    double R[2][2][4];
+    const int T = (N + CR_T - 1) / CR_T;
+    const int n = T * (T + 1) / 2;
+    const int xcd = blockIdx.x & 7, q = n >> 3, rem = n & 7;
+    const int2 tt = cor_tile(xcd * q + min(xcd, rem) + (int)(blockIdx.x >> 3), T);
+    const int I0 = tt.x * CR_T, J0 = tt.y * CR_T;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+    const int wr = w / WAVES_C, wc = w % WAVES_C;
+
+    // staging: float4 number e = tid + NT v of a chunk is node e / (CR_CH / 4)
+    // (the 128 row nodes, then the 128 column nodes), samples 4 (e % (CR_CH / 4))
+    // .. + 3; rows past N read node N - 1 and only feed outputs never written
+    unsigned off[V4];
+    int lds[V4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int v = 0; v < V4; ++v) {
+        const int e = tid + NT * v, node = e / (CR_CH / 4), q4 = e % (CR_CH / 4);
+        const int g = min(node < CR_T ? I0 + node : J0 + node - CR_T, N - 1);
+        off[v] = (unsigned)g * (unsigned)Mz + 4u * (unsigned)q4;
+        lds[v] = node * (PREC == FCX_GRAM_FP32_ID ? CR_LD : CR_LDH) + 4 * q4;
+    }
+    const int nch = Mz / CR_CH, total = K * nch;
+    const size_t trial = (size_t)N * Mz;
+    // chunk cc = trial * nch + chunk within the trial; chunks past the last
+    // load the last one again (never used)
+    auto chunk_base = [&](int cc) {
+        cc = min(cc, total - 1);
+        const int tq = cc / nch;
+        return s.zring + (size_t)tq * trial + (cc - tq * nch) * CR_CH;
+    };
+    floatx4 pre[PF][V4];
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+    for (int p = 0; p < PF; ++p) {
+        const float *base = chunk_base(p);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) R[a][b][k] = 0.0;
-    for (int t = 0; t < K; ++t) {
-        const float *z = s.zring + (size_t)t * N * Mz;
-        floatx4 r[2][2];
+        for (int v = 0; v < V4; ++v) pre[p][v] = *(const floatx4 *)(base + off[v]);
+    }
+    floatx4 acc[WR][WC];
+    double R[WR][WC][4];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < WR; ++i)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) r[a][b] = (floatx4){0.f, 0.f, 0.f, 0.f};
-        for (int n0 = 0; n0 < Mz; n0 += CR_CH) {
-            __syncthreads();
-            // 128 nodes x 32 samples: 8 float4 per node row chunk
-            for (int e = threadIdx.x; e < 128 * (CR_CH / 4); e += 256) {
-                const int node = e / (CR_CH / 4), q4 = e % (CR_CH / 4);
-                const int g = node < 64 ? I0 + node : J0 + node - 64;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (g < N) v = *(const float4 *)(z + (size_t)g * Mz + n0 + 4 * q4);
-                float *dst = node < 64 ? Zr + node * CR_LD : Zc + (node - 64) * CR_LD;
-                dst[4 * q4 + 0] = v.x;
-                dst[4 * q4 + 1] = v.y;
-                dst[4 * q4 + 2] = v.z;
-                dst[4 * q4 + 3] = v.w;
+        for (int j = 0; j < WC; ++j) {
+            acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) R[i][j][k] = 0.0;
+        }
+    for (int c0 = 0; c0 < total; c0 += PF) {
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int c = c0 + p;
+            if (c >= total) break;
+            float *Zb = Z[c & 1];
+#pragma unroll
+            for (int v = 0; v < V4; ++v) {
+                const floatx4 x = pre[p][v];
+                if (PREC == FCX_GRAM_FP32_ID) {
+                    *(floatx4 *)(Zb + lds[v]) = x;
+                } else {  // rounded once here, for every wavefront that reads it
+                    __bf16 *Zh = (__bf16 *)Zb;
+                    const bf16x4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
+                    *(bf16x4 *)(Zh + lds[v]) = h;
+                    if (PREC == FCX_GRAM_BF16X3_ID)
+                        *(bf16x4 *)(Zh + 2 * CR_T * CR_LDH + lds[v]) =
+                            (bf16x4){(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
+                                     (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
+                }
             }
             __syncthreads();
+            {   // chunk c + PF into the registers just emptied
+                const float *base = chunk_base(c + PF);
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+                for (int v = 0; v < V4; ++v) pre[p][v] = *(const floatx4 *)(base + off[v]);
+            }
+            __builtin_amdgcn_sched_barrier(0);  // the loads go out before the chunk's LDS reads and MFMAs
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    cor_chunk<PREC>(Zr, Zc, 32 * qi + 16 * a + lr, 32 * qj + 16 * b + lr, lg, r[a][b]);
+            for (int sub = 0; sub < CR_CH / 32; ++sub) {
+                const float *Ap = Zb + (16 * WR * wr + lr) * CR_LD + 32 * sub + 8 * lg;
+                const float *Bp = Zb + (CR_T + 16 * WC * wc + lr) * CR_LD + 32 * sub + 8 * lg;
+                if (PREC == FCX_GRAM_FP32_ID) {
+#pragma unroll
+                    for (int half = 0; half < 2; ++half) {
+                        float4 a[WR], b[WC];
+#pragma unroll
+                        for (int i = 0; i < WR; ++i) a[i] = *(const float4 *)(Ap + 16 * i * CR_LD + 4 * half);
+#pragma unroll
+                        for (int j = 0; j < WC; ++j) b[j] = *(const float4 *)(Bp + 16 * j * CR_LD + 4 * half);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+#pragma unroll
+                            for (int i = 0; i < WR; ++i)
+#pragma unroll
+                                for (int j = 0; j < WC; ++j)
+                                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                        cor_pick(a[i], e), cor_pick(b[j], e), acc[i][j], 0, 0, 0);
+                    }
+                } else {
+                    const __bf16 *Zh = (const __bf16 *)Zb, *Zl = Zh + 2 * CR_T * CR_LDH;
+                    const int ra = (16 * WR * wr + lr) * CR_LDH + 32 * sub + 8 * lg;
+                    const int rb = (CR_T + 16 * WC * wc + lr) * CR_LDH + 32 * sub + 8 * lg;
+                    bf16x8 ah[WR], bh[WC], al[WR], bl[WC];
+#pragma unroll
+                    for (int i = 0; i < WR; ++i) {
+                        ah[i] = *(const bf16x8 *)(Zh + ra + 16 * i * CR_LDH);
+                        if (PREC == FCX_GRAM_BF16X3_ID) al[i] = *(const bf16x8 *)(Zl + ra + 16 * i * CR_LDH);
+                    }
+#pragma unroll
+                    for (int j = 0; j < WC; ++j) {
+                        bh[j] = *(const bf16x8 *)(Zh + rb + 16 * j * CR_LDH);
+                        if (PREC == FCX_GRAM_BF16X3_ID) bl[j] = *(const bf16x8 *)(Zl + rb + 16 * j * CR_LDH);
+                    }
+#pragma unroll
+                    for (int i = 0; i < WR; ++i)
+#pragma unroll
+                        for (int j = 0; j < WC; ++j) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                            if (PREC == FCX_GRAM_BF16X3_ID) {
+                                acc[i][j] =
+                                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                                acc[i][j] =
+                                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                            }
+                        }
+                }
+            }
+            if ((c + 1) % nch == 0) {  // end of a trial: its r joins the FP64 window sum
+#pragma unroll
+                for (int i = 0; i < WR; ++i)
+#pragma unroll
+                    for (int j = 0; j < WC; ++j) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) R[i][j][k] += (double)acc[i][j][k];
+                        acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+                    }
+            }
         }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) R[a][b][k] += (double)r[a][b][k];
     }
     const size_t P = (size_t)N * (N - 1) / 2;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < WR; ++i)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int j = 0; j < WC; ++j)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int i = I0 + 32 * qi + 16 * a + 4 * lg + k, j = J0 + 32 * qj + 16 * b + lr;
-                if (!(i < j && j < N)) continue;
-                const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
-                s.out[7 * P + idx] = (float)(R[a][b][k] / (double)K);
+                const int r = I0 + 16 * WR * wr + 16 * i + 4 * lg + k, col = J0 + 16 * WC * wc + 16 * j + lr;
+                if (!(r < col && col < N)) continue;
+                const size_t idx = (size_t)r * (2 * (size_t)N - r - 1) / 2 + (size_t)(col - r - 1);
+                s.out[7 * P + idx] = (float)(R[i][j][k] / (double)K);
             }
 }
 
@@ -476,11 +594,18 @@ hipError_t launch_pair_batch(const SessDev<float> &s, int K, int prec, hipStream
 
 hipError_t launch_cor_batch(const SessDev<float> &s, int K, int prec, hipStream_t st)
 {
-    const dim3 grid(s.ntiles);
+    constexpr int WR = FCX_COR_WR, WC = FCX_COR_WC;
+    constexpr int NT = 64 * (CR_T / (16 * WR)) * (CR_T / (16 * WC));
+    const int T = (s.N + CR_T - 1) / CR_T;
+    const dim3 grid(T * (T + 1) / 2), blk(NT);
     switch (prec) {
-    case FCX_GRAM_BF16_ID: hipLaunchKernelGGL(k_cor_batch<FCX_GRAM_BF16_ID>, grid, dim3(256), 0, st, s, K); break;
-    case FCX_GRAM_BF16X3_ID: hipLaunchKernelGGL(k_cor_batch<FCX_GRAM_BF16X3_ID>, grid, dim3(256), 0, st, s, K); break;
-    default: hipLaunchKernelGGL(k_cor_batch<FCX_GRAM_FP32_ID>, grid, dim3(256), 0, st, s, K); break;
+    case FCX_GRAM_BF16_ID:
+        hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16_ID, WR, WC, FCX_COR_PF16>), grid, blk, 0, st, s, K);
+        break;
+    case FCX_GRAM_BF16X3_ID:
+        hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16X3_ID, WR, WC, FCX_COR_PF16>), grid, blk, 0, st, s, K);
+        break;
+    default: hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_FP32_ID, WR, WC, FCX_COR_PF32>), grid, blk, 0, st, s, K); break;
     }
     return hipGetLastError();
 }

@@ -143,3 +143,25 @@ def test_batch_full_source_size_sampled(fcx):
     log("batch c3 fp32: " + json.dumps({k: f"{v:.2e}" for k, v in err.items()}))
     assert max(err.values()) <= TOL
     s.close()
+
+
+@pytest.mark.parametrize("N,prec", [(1100, "bf16x3"), (2000, "fp32"), (1100, "bf16"), (129, "fp32")])
+def test_batch_cor_every_pair(fcx, N, prec):
+    """COR alone, every pair: many 128-node tiles in several bands (a band of
+    one tile row at N=1100), a ragged last tile, trials of 160 samples (five
+    staged chunks each), against the oracle's per-trial Pearson r."""
+    M, K = 160, 6
+    rng = np.random.default_rng(N)
+    x = rng.standard_normal((K, N, M))
+    x[:, 1::7, 5:] += 0.8 * x[:, 0:N - 1:7, :-5]     # correlated pairs (lag 5)
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=K, n_fft=256, f_lo_hz=8, f_hi_hz=30,
+                            metrics=synth.COR, gram=prec)
+    s, _ = _batch(fcx, cfg, x)
+    pi, pj = oracle.all_pairs(N)
+    ref = oracle.cor(oracle.as_device_input(x, cfg), pi, pj)
+    st, got, k = s.read("cor")
+    assert st == 0 and k == K
+    err = float(np.max(np.abs(got.astype(np.float64) - ref)))
+    log(f"batch cor N={N} {prec}: max abs error {err:.2e} (|r| up to {np.max(np.abs(ref)):.2f})")
+    assert err <= BOUND[prec]["cor"], (N, prec, err)
+    s.close()
