@@ -373,7 +373,8 @@ __device__ __forceinline__ float cor_pick(float4 v, int e)
 }
 
 template <int PREC, int WR, int WC, int PF>
-__global__ __launch_bounds__(64 * (CR_T / (16 * WR)) * (CR_T / (16 * WC))) void k_cor_batch(SessDev<float> s, int K)
+__global__ __launch_bounds__(64 * (CR_T / (16 * WR)) * (CR_T / (16 * WC))) void k_cor_batch(SessDev<float> s, int K,
+                                                                                  int G, double *scratch, int *count)
 {
     constexpr int WAVES_C = CR_T / (16 * WC);
     constexpr int NT = 64 * (CR_T / (16 * WR)) * WAVES_C;
@@ -384,156 +385,209 @@ __global__ __launch_bounds__(64 * (CR_T / (16 * WR)) * (CR_T / (16 * WC))) void 
     constexpr int ZBUF = PREC == FCX_GRAM_FP32_ID ? 2 * CR_T * CR_LD
                          : (PREC == FCX_GRAM_BF16_ID ? 1 : 2) * 2 * CR_T * CR_LDH / 2;
     __shared__ __attribute__((aligned(16))) float Z[2][ZBUF];
+    __shared__ int last;
     if (s.ctl->bad) return;
     const int N = s.N, Mz = s.Mz;
     const int T = (N + CR_T - 1) / CR_T;
     const int n = T * (T + 1) / 2;
-    const int xcd = blockIdx.x & 7, q = n >> 3, rem = n & 7;
-    const int2 tt = cor_tile(xcd * q + min(xcd, rem) + (int)(blockIdx.x >> 3), T);
-    const int I0 = tt.x * CR_T, J0 = tt.y * CR_T;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
     const int wr = w / WAVES_C, wc = w % WAVES_C;
-
-    // staging: float4 number e = tid + NT v of a chunk is node e / (CR_CH / 4)
-    // (the 128 row nodes, then the 128 column nodes), samples 4 (e % (CR_CH / 4))
-    // .. + 3; rows past N read node N - 1 and only feed outputs never written
-    unsigned off[V4];
-    int lds[V4];
-#pragma unroll
-    for (int v = 0; v < V4; ++v) {
-        const int e = tid + NT * v, node = e / (CR_CH / 4), q4 = e % (CR_CH / 4);
-        const int g = min(node < CR_T ? I0 + node : J0 + node - CR_T, N - 1);
-        off[v] = (unsigned)g * (unsigned)Mz + 4u * (unsigned)q4;
-        lds[v] = node * (PREC == FCX_GRAM_FP32_ID ? CR_LD : CR_LDH) + 4 * q4;
-    }
-    const int nch = Mz / CR_CH, total = K * nch;
-    const size_t trial = (size_t)N * Mz;
-    // chunk cc = trial * nch + chunk within the trial; chunks past the last
-    // load the last one again (never used)
-    auto chunk_base = [&](int cc) {
-        cc = min(cc, total - 1);
-        const int tq = cc / nch;
-        return s.zring + (size_t)tq * trial + (cc - tq * nch) * CR_CH;
-    };
-    floatx4 pre[PF][V4];
-#pragma unroll
-    for (int p = 0; p < PF; ++p) {
-        const float *base = chunk_base(p);
-#pragma unroll
-        for (int v = 0; v < V4; ++v) pre[p][v] = *(const floatx4 *)(base + off[v]);
-    }
-    floatx4 acc[WR][WC];
-    double R[WR][WC][4];
-#pragma unroll
-    for (int i = 0; i < WR; ++i)
-#pragma unroll
-        for (int j = 0; j < WC; ++j) {
-            acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) R[i][j][k] = 0.0;
+    const size_t P = (size_t)N * (N - 1) / 2;
+    // G resident workgroups; workgroups on one XCD hold neighbouring places.
+    // Whole tiles go out round by round while at least two rounds remain; the
+    // last ns tiles (G <= ns < 2G) are cut as ns x K units (tile, trial) into
+    // G equal runs, each of at least K units, so such a tile is shared by at
+    // most two workgroups.  With n <= G every workgroup takes one whole tile.
+    const int xcd = blockIdx.x & 7, gq = G >> 3, grem = G & 7;
+    const int pos = xcd * gq + min(xcd, grem) + (int)(blockIdx.x >> 3);
+    const int rounds = n > G ? n / G - 1 : 0, nd = rounds * G;
+    const long long U = (long long)(n - nd) * K, us1 = U * (pos + 1) / G;
+    long long u = U * pos / G;
+    for (int seg = 0;; ++seg) {
+        int lin, t0, t1;
+        if (seg < rounds) {
+            lin = seg * G + pos;
+            t0 = 0;
+            t1 = K;
+        } else {
+            if (u >= us1) break;
+            const int l = (int)(u / K);
+            t0 = (int)(u - (long long)l * K);
+            t1 = (int)min((long long)K, t0 + (us1 - u));
+            u += t1 - t0;
+            lin = nd + l;
         }
-    for (int c0 = 0; c0 < total; c0 += PF) {
+        const int2 tt = cor_tile(lin, T);
+        const int I0 = tt.x * CR_T, J0 = tt.y * CR_T;
+
+        // staging: float4 number e = tid + NT v of a chunk is node e / (CR_CH / 4)
+        // (the 128 row nodes, then the 128 column nodes), samples 4 (e % (CR_CH / 4))
+        // .. + 3; rows past N read node N - 1 and only feed outputs never written
+        unsigned off[V4];
+        int lds[V4];
+#pragma unroll
+        for (int v = 0; v < V4; ++v) {
+            const int e = tid + NT * v, node = e / (CR_CH / 4), q4 = e % (CR_CH / 4);
+            const int g = min(node < CR_T ? I0 + node : J0 + node - CR_T, N - 1);
+            off[v] = (unsigned)g * (unsigned)Mz + 4u * (unsigned)q4;
+            lds[v] = node * (PREC == FCX_GRAM_FP32_ID ? CR_LD : CR_LDH) + 4 * q4;
+        }
+        const int nch = Mz / CR_CH, cbeg = t0 * nch, total = t1 * nch;
+        const size_t trial = (size_t)N * Mz;
+        // chunk cc = trial * nch + chunk within the trial; chunks past the
+        // segment's last load that one again (never used)
+        auto chunk_base = [&](int cc) {
+            cc = min(cc, total - 1);
+            const int tq = cc / nch;
+            return s.zring + (size_t)tq * trial + (cc - tq * nch) * CR_CH;
+        };
+        floatx4 pre[PF][V4];
 #pragma unroll
         for (int p = 0; p < PF; ++p) {
-            const int c = c0 + p;
-            if (c >= total) break;
-            float *Zb = Z[c & 1];
+            const float *base = chunk_base(cbeg + p);
 #pragma unroll
-            for (int v = 0; v < V4; ++v) {
-                const floatx4 x = pre[p][v];
-                if (PREC == FCX_GRAM_FP32_ID) {
-                    *(floatx4 *)(Zb + lds[v]) = x;
-                } else {  // rounded once here, for every wavefront that reads it
-                    __bf16 *Zh = (__bf16 *)Zb;
-                    const bf16x4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
-                    *(bf16x4 *)(Zh + lds[v]) = h;
-                    if (PREC == FCX_GRAM_BF16X3_ID)
-                        *(bf16x4 *)(Zh + 2 * CR_T * CR_LDH + lds[v]) =
-                            (bf16x4){(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
-                                     (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
+            for (int v = 0; v < V4; ++v) pre[p][v] = *(const floatx4 *)(base + off[v]);
+        }
+        floatx4 acc[WR][WC];
+        double R[WR][WC][4];
+#pragma unroll
+        for (int i = 0; i < WR; ++i)
+#pragma unroll
+            for (int j = 0; j < WC; ++j) {
+                acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) R[i][j][k] = 0.0;
+            }
+        for (int c0 = cbeg; c0 < total; c0 += PF) {
+#pragma unroll
+            for (int p = 0; p < PF; ++p) {
+                const int c = c0 + p;
+                if (c >= total) break;
+                float *Zb = Z[c & 1];
+#pragma unroll
+                for (int v = 0; v < V4; ++v) {
+                    const floatx4 x = pre[p][v];
+                    if (PREC == FCX_GRAM_FP32_ID) {
+                        *(floatx4 *)(Zb + lds[v]) = x;
+                    } else {  // rounded once here, for every wavefront that reads it
+                        __bf16 *Zh = (__bf16 *)Zb;
+                        const bf16x4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
+                        *(bf16x4 *)(Zh + lds[v]) = h;
+                        if (PREC == FCX_GRAM_BF16X3_ID)
+                            *(bf16x4 *)(Zh + 2 * CR_T * CR_LDH + lds[v]) =
+                                (bf16x4){(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
+                                         (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
+                    }
                 }
-            }
-            __syncthreads();
-            {   // chunk c + PF into the registers just emptied
-                const float *base = chunk_base(c + PF);
+                __syncthreads();
+                {   // chunk c + PF into the registers just emptied
+                    const float *base = chunk_base(c + PF);
 #pragma unroll
-                for (int v = 0; v < V4; ++v) pre[p][v] = *(const floatx4 *)(base + off[v]);
-            }
-            __builtin_amdgcn_sched_barrier(0);  // the loads go out before the chunk's LDS reads and MFMAs
+                    for (int v = 0; v < V4; ++v) pre[p][v] = *(const floatx4 *)(base + off[v]);
+                }
+                __builtin_amdgcn_sched_barrier(0);  // the loads go out before the chunk's LDS reads and MFMAs
 #pragma unroll
-            for (int sub = 0; sub < CR_CH / 32; ++sub) {
-                const float *Ap = Zb + (16 * WR * wr + lr) * CR_LD + 32 * sub + 8 * lg;
-                const float *Bp = Zb + (CR_T + 16 * WC * wc + lr) * CR_LD + 32 * sub + 8 * lg;
-                if (PREC == FCX_GRAM_FP32_ID) {
+                for (int sub = 0; sub < CR_CH / 32; ++sub) {
+                    const float *Ap = Zb + (16 * WR * wr + lr) * CR_LD + 32 * sub + 8 * lg;
+                    const float *Bp = Zb + (CR_T + 16 * WC * wc + lr) * CR_LD + 32 * sub + 8 * lg;
+                    if (PREC == FCX_GRAM_FP32_ID) {
 #pragma unroll
-                    for (int half = 0; half < 2; ++half) {
-                        float4 a[WR], b[WC];
+                        for (int half = 0; half < 2; ++half) {
+                            float4 a[WR], b[WC];
 #pragma unroll
-                        for (int i = 0; i < WR; ++i) a[i] = *(const float4 *)(Ap + 16 * i * CR_LD + 4 * half);
+                            for (int i = 0; i < WR; ++i) a[i] = *(const float4 *)(Ap + 16 * i * CR_LD + 4 * half);
 #pragma unroll
-                        for (int j = 0; j < WC; ++j) b[j] = *(const float4 *)(Bp + 16 * j * CR_LD + 4 * half);
+                            for (int j = 0; j < WC; ++j) b[j] = *(const float4 *)(Bp + 16 * j * CR_LD + 4 * half);
 #pragma unroll
-                        for (int e = 0; e < 4; ++e)
+                            for (int e = 0; e < 4; ++e)
 #pragma unroll
-                            for (int i = 0; i < WR; ++i)
+                                for (int i = 0; i < WR; ++i)
 #pragma unroll
-                                for (int j = 0; j < WC; ++j)
-                                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                        cor_pick(a[i], e), cor_pick(b[j], e), acc[i][j], 0, 0, 0);
+                                    for (int j = 0; j < WC; ++j)
+                                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                            cor_pick(a[i], e), cor_pick(b[j], e), acc[i][j], 0, 0, 0);
+                        }
+                    } else {
+                        const __bf16 *Zh = (const __bf16 *)Zb, *Zl = Zh + 2 * CR_T * CR_LDH;
+                        const int ra = (16 * WR * wr + lr) * CR_LDH + 32 * sub + 8 * lg;
+                        const int rb = (CR_T + 16 * WC * wc + lr) * CR_LDH + 32 * sub + 8 * lg;
+                        bf16x8 ah[WR], bh[WC], al[WR], bl[WC];
+#pragma unroll
+                        for (int i = 0; i < WR; ++i) {
+                            ah[i] = *(const bf16x8 *)(Zh + ra + 16 * i * CR_LDH);
+                            if (PREC == FCX_GRAM_BF16X3_ID) al[i] = *(const bf16x8 *)(Zl + ra + 16 * i * CR_LDH);
+                        }
+#pragma unroll
+                        for (int j = 0; j < WC; ++j) {
+                            bh[j] = *(const bf16x8 *)(Zh + rb + 16 * j * CR_LDH);
+                            if (PREC == FCX_GRAM_BF16X3_ID) bl[j] = *(const bf16x8 *)(Zl + rb + 16 * j * CR_LDH);
+                        }
+#pragma unroll
+                        for (int i = 0; i < WR; ++i)
+#pragma unroll
+                            for (int j = 0; j < WC; ++j) {
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                                if (PREC == FCX_GRAM_BF16X3_ID) {
+                                    acc[i][j] =
+                                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                                    acc[i][j] =
+                                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                                }
+                            }
                     }
-                } else {
-                    const __bf16 *Zh = (const __bf16 *)Zb, *Zl = Zh + 2 * CR_T * CR_LDH;
-                    const int ra = (16 * WR * wr + lr) * CR_LDH + 32 * sub + 8 * lg;
-                    const int rb = (CR_T + 16 * WC * wc + lr) * CR_LDH + 32 * sub + 8 * lg;
-                    bf16x8 ah[WR], bh[WC], al[WR], bl[WC];
-#pragma unroll
-                    for (int i = 0; i < WR; ++i) {
-                        ah[i] = *(const bf16x8 *)(Zh + ra + 16 * i * CR_LDH);
-                        if (PREC == FCX_GRAM_BF16X3_ID) al[i] = *(const bf16x8 *)(Zl + ra + 16 * i * CR_LDH);
-                    }
-#pragma unroll
-                    for (int j = 0; j < WC; ++j) {
-                        bh[j] = *(const bf16x8 *)(Zh + rb + 16 * j * CR_LDH);
-                        if (PREC == FCX_GRAM_BF16X3_ID) bl[j] = *(const bf16x8 *)(Zl + rb + 16 * j * CR_LDH);
-                    }
+                }
+                if ((c + 1) % nch == 0) {  // end of a trial: its r joins the FP64 window sum
 #pragma unroll
                     for (int i = 0; i < WR; ++i)
 #pragma unroll
                         for (int j = 0; j < WC; ++j) {
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                            if (PREC == FCX_GRAM_BF16X3_ID) {
-                                acc[i][j] =
-                                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                                acc[i][j] =
-                                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                            }
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) R[i][j][k] += (double)acc[i][j][k];
+                            acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
                         }
                 }
             }
-            if ((c + 1) % nch == 0) {  // end of a trial: its r joins the FP64 window sum
-#pragma unroll
-                for (int i = 0; i < WR; ++i)
-#pragma unroll
-                    for (int j = 0; j < WC; ++j) {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) R[i][j][k] += (double)acc[i][j][k];
-                        acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
-                    }
-            }
         }
+        const bool whole = t0 == 0 && t1 == K;
+        if (!whole) {
+            // a shared tile: both partial sums are added to the zeroed FP64
+            // scratch (two addends, so the sum is the same in either order); the
+            // workgroup that finishes second writes the tile
+#pragma unroll
+            for (int i = 0; i < WR; ++i)
+#pragma unroll
+                for (int j = 0; j < WC; ++j)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int r = I0 + 16 * WR * wr + 16 * i + 4 * lg + k, col = J0 + 16 * WC * wc + 16 * j + lr;
+                        if (!(r < col && col < N)) continue;
+                        const size_t idx = (size_t)r * (2 * (size_t)N - r - 1) / 2 + (size_t)(col - r - 1);
+                        unsafeAtomicAdd(scratch + idx, R[i][j][k]);
+                    }
+            __threadfence();
+            __syncthreads();
+            if (tid == 0)
+                last = __hip_atomic_fetch_add(count + lin, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1;
+            __syncthreads();
+        }
+        if (whole || last) {
+#pragma unroll
+            for (int i = 0; i < WR; ++i)
+#pragma unroll
+                for (int j = 0; j < WC; ++j)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int r = I0 + 16 * WR * wr + 16 * i + 4 * lg + k, col = J0 + 16 * WC * wc + 16 * j + lr;
+                        if (!(r < col && col < N)) continue;
+                        const size_t idx = (size_t)r * (2 * (size_t)N - r - 1) / 2 + (size_t)(col - r - 1);
+                        const double sum = whole ? R[i][j][k]
+                                                 : __hip_atomic_load(scratch + idx, __ATOMIC_RELAXED,
+                                                                     __HIP_MEMORY_SCOPE_AGENT);
+                        s.out[7 * P + idx] = (float)(sum / (double)K);
+                    }
+        }
+        __syncthreads();  // LDS buffers and `last` are reused by the next segment
     }
-    const size_t P = (size_t)N * (N - 1) / 2;
-#pragma unroll
-    for (int i = 0; i < WR; ++i)
-#pragma unroll
-        for (int j = 0; j < WC; ++j)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int r = I0 + 16 * WR * wr + 16 * i + 4 * lg + k, col = J0 + 16 * WC * wc + 16 * j + lr;
-                if (!(r < col && col < N)) continue;
-                const size_t idx = (size_t)r * (2 * (size_t)N - r - 1) / 2 + (size_t)(col - r - 1);
-                s.out[7 * P + idx] = (float)(R[i][j][k] / (double)K);
-            }
 }
 
 // ------------------------------------------------------------------ launch
@@ -592,20 +646,51 @@ hipError_t launch_pair_batch(const SessDev<float> &s, int K, int prec, hipStream
     return hipGetLastError();
 }
 
+__global__ void k_zero_u64(unsigned long long *p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
 hipError_t launch_cor_batch(const SessDev<float> &s, int K, int prec, hipStream_t st)
 {
     constexpr int WR = FCX_COR_WR, WC = FCX_COR_WC;
     constexpr int NT = 64 * (CR_T / (16 * WR)) * (CR_T / (16 * WC));
     const int T = (s.N + CR_T - 1) / CR_T;
-    const dim3 grid(T * (T + 1) / 2), blk(NT);
+    const int n = T * (T + 1) / 2;
+    // one resident workgroup per compute unit; with more tiles than that the
+    // (tile, trial) units are shared out evenly and a tile cut between two
+    // workgroups meets in the COR running-sum buffer, which a batch leaves
+    // stale (the replay of the window clears and rebuilds it): its first P
+    // doubles take the pair sums, the words after them one counter per tile
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const size_t P = (size_t)s.N * (s.N - 1) / 2;
+    const size_t words = P + ((size_t)n + 1) / 2;
+    int G = n;
+    double *scratch = nullptr;
+    int *count = nullptr;
+    if (ncu > 0 && n > ncu && s.rsum && (size_t)s.ntiles * TILE_PAIRS >= words) {
+        G = ncu;
+        scratch = s.rsum;
+        count = (int *)(s.rsum + P);
+        hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, st, (unsigned long long *)s.rsum, words);
+    }
+    const dim3 grid(G), blk(NT);
     switch (prec) {
     case FCX_GRAM_BF16_ID:
-        hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16_ID, WR, WC, FCX_COR_PF16>), grid, blk, 0, st, s, K);
+        hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16_ID, WR, WC, FCX_COR_PF16>), grid, blk, 0, st, s, K, G, scratch,
+                           count);
         break;
     case FCX_GRAM_BF16X3_ID:
-        hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16X3_ID, WR, WC, FCX_COR_PF16>), grid, blk, 0, st, s, K);
+        hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16X3_ID, WR, WC, FCX_COR_PF16>), grid, blk, 0, st, s, K, G,
+                           scratch, count);
         break;
-    default: hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_FP32_ID, WR, WC, FCX_COR_PF32>), grid, blk, 0, st, s, K); break;
+    default:
+        hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_FP32_ID, WR, WC, FCX_COR_PF32>), grid, blk, 0, st, s, K, G, scratch,
+                           count);
+        break;
     }
     return hipGetLastError();
 }

@@ -165,3 +165,40 @@ def test_batch_cor_every_pair(fcx, N, prec):
     log(f"batch cor N={N} {prec}: max abs error {err:.2e} (|r| up to {np.max(np.abs(ref)):.2f})")
     assert err <= BOUND[prec]["cor"], (N, prec, err)
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_batch_cor_shared_tiles(fcx, prec):
+    """3000 nodes: more 128-node tiles (300) than compute units, so tiles are
+    cut between two workgroups that meet in the COR running-sum buffer.
+    Every pair against the oracle; a second batch gives the same bits (the
+    two partial sums may land in either order); then the window slides and
+    the rebuilt running sums are checked on sampled rows."""
+    N, M, W = 3000, 96, 5
+    rng = np.random.default_rng(77)
+    x = rng.standard_normal((W + 2, N, M))
+    x[:, 1::5, 2:] += 0.7 * x[:, 0:N - 1:5, :-2]
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=W, n_fft=128, f_lo_hz=8, f_hi_hz=30,
+                            metrics=synth.COR, gram=prec)
+    s, xd = _batch(fcx, cfg, x[:W])
+    st, a, k = s.read("cor")
+    assert st == 0 and k == W
+    a = a.copy()
+    pi, pj = oracle.all_pairs(N)
+    ref = oracle.cor(oracle.as_device_input(x[:W], cfg), pi, pj)
+    err = float(np.max(np.abs(a.astype(np.float64) - ref)))
+    log(f"batch cor N={N} {prec} shared tiles: max abs error {err:.2e}")
+    assert err <= BOUND[prec]["cor"], err
+    fcx.check(s.push_batch_device(xd.data_ptr(), W, N * M, M))
+    fcx.check(s.sync())
+    assert np.array_equal(a, s.read("cor")[1])
+    for t in range(W, W + 2):
+        fcx.check(s.push_host(np.ascontiguousarray(x[t], dtype=np.float32)))
+    rows = [0, 1, 1499, 2998]
+    qi, qj = oracle.row_pairs(rows, N)
+    ref2 = oracle.cor(oracle.as_device_input(x[2:W + 2], cfg), qi, qj)
+    got2 = s.read("cor")[1][oracle.packed_index(qi, qj, N)].astype(np.float64)
+    err2 = float(np.max(np.abs(got2 - ref2)))
+    log(f"batch cor N={N} {prec} then two sliding pushes: max abs error {err2:.2e}")
+    assert err2 <= TOL, err2
+    s.close()
