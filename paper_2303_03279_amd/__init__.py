@@ -324,6 +324,14 @@ class Session:
     def push_batch_device(self, ptr: int, n_trials: int, trial_stride: int, ld: int) -> int:
         return lib.fcx_push_batch(self.h, ptr, n_trials, trial_stride, ld, 1)
 
+    def push_batch_host(self, x) -> int:
+        """x: numpy array [K][N][M] of the session's element type (rows and
+        trials may be strided, samples contiguous)."""
+        if x.ndim != 3 or x.strides[2] != x.itemsize:
+            raise ValueError("push_batch_host takes a [K][N][M] array with contiguous samples")
+        return lib.fcx_push_batch(self.h, x.ctypes.data, x.shape[0], x.strides[0] // x.itemsize,
+                                  x.strides[1] // x.itemsize, 0)
+
     # -- reads ---------------------------------------------------------------
     def read(self, metric: str, per_bin: bool = False):
         import numpy as np

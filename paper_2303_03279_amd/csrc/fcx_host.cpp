@@ -880,19 +880,28 @@ fcx_status fcx_push_batch(fcx_session *h, const void *x, int64_t n_trials, int64
     SessDev<float> d = session_dev<float>(s, nullptr, 0);
     const bool spectral = (s->cfg.metrics & 0x7Fu) != 0, cor = (s->cfg.metrics & M_COR) != 0;
     const bool zneed = (s->cfg.metrics & (M_COR | M_XCOR)) != 0;   // XCOR comes from the replay
-    for (int64_t k = 0; k < n_trials; ++k) {
-        const void *xk = (const char *)x + (size_t)k * trial_stride * es;
-        long long ldk = ld;
-        if (!x_on_device) {
-            if ((st = upload_host_trial(s, xk, ld)) != FCX_OK) return st;
-            xk = s->xbuf;
-            ldk = g.M;
+    if (x_on_device && n_trials <= 65535) {
+        // every trial is already in device memory: one launch each for the
+        // spectra and the z-scored samples of all of them (trial k -> slot k)
+        d.x = x;
+        d.ldx = ld;
+        if (spectral) HIP_OK(launch_spectra_batch<float>(d, (int)n_trials, trial_stride, s->stream));
+        if (zneed) HIP_OK(launch_znorm_batch<float>(d, (int)n_trials, trial_stride, s->stream));
+    } else {
+        for (int64_t k = 0; k < n_trials; ++k) {
+            const void *xk = (const char *)x + (size_t)k * trial_stride * es;
+            long long ldk = ld;
+            if (!x_on_device) {
+                if ((st = upload_host_trial(s, xk, ld)) != FCX_OK) return st;
+                xk = s->xbuf;
+                ldk = g.M;
+            }
+            d.x = xk;
+            d.ldx = ldk;
+            HIP_OK(launch_set_pushed(s->ctl, k, s->stream));
+            if (spectral) HIP_OK(launch_spectra<float>(d, s->stream));
+            if (zneed) HIP_OK(launch_znorm<float>(d, s->stream));
         }
-        d.x = xk;
-        d.ldx = ldk;
-        HIP_OK(launch_set_pushed(s->ctl, k, s->stream));
-        if (spectral) HIP_OK(launch_spectra<float>(d, s->stream));
-        if (zneed) HIP_OK(launch_znorm<float>(d, s->stream));
     }
     const int prec = s->cfg.gram_precision;
     if (spectral) {

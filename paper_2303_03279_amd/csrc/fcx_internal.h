@@ -101,6 +101,10 @@ template <typename T> hipError_t launch_spectra(const SessDev<T> &s, hipStream_t
 template <typename T> hipError_t launch_psd(const SessDev<T> &s, hipStream_t st);
 template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStream_t st);
 template <typename T> hipError_t launch_znorm(const SessDev<T> &s, hipStream_t st);
+// trials k = 0..K-1 of a device-resident batch (at x + k * stride elements)
+// into ring slot k
+template <typename T> hipError_t launch_spectra_batch(const SessDev<T> &s, int K, long long stride, hipStream_t st);
+template <typename T> hipError_t launch_znorm_batch(const SessDev<T> &s, int K, long long stride, hipStream_t st);
 hipError_t launch_commit(DevCtl *ctl, hipStream_t st);
 hipError_t launch_set_ctl(DevCtl *ctl, long long pushed, hipStream_t st);
 template <typename T>

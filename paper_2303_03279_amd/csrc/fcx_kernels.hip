@@ -35,7 +35,7 @@ constexpr int SP_NODES = 16;
 constexpr int SP_CH = 256;
 
 template <typename T>
-__device__ __forceinline__ void spectra_body(const SessDev<T> &s, int bx, int by, T (*xs)[SP_CH + 1])
+__device__ __forceinline__ void spectra_body(const SessDev<T> &s, int bx, int by, T (*xs)[SP_CH + 1], int slot)
 {
     const int t = threadIdx.x;
     const int node0 = bx * SP_NODES;
@@ -43,8 +43,6 @@ __device__ __forceinline__ void spectra_body(const SessDev<T> &s, int bx, int by
     const int bl = by * (256 / SP_NODES) + (t / SP_NODES);   // l * B + b
     const int BL = s.B * s.L;
     const bool active = bl < BL && node0 + nl < s.N;
-    const long long tp = s.ctl->pushed;
-    const int slot = (int)(tp % (long long)(s.W + 1));
     const T *x = (const T *)s.x;
     const T *tw = s.wtw + (size_t)(active ? bl : 0) * s.M * 2;
     T acc_re = 0, acc_im = 0;
@@ -90,7 +88,18 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_spectra(SessDev<T> s)
 {
     __shared__ T xs[SP_NODES][SP_CH + 1];
-    spectra_body(s, blockIdx.x, blockIdx.y, xs);
+    spectra_body(s, blockIdx.x, blockIdx.y, xs, (int)(s.ctl->pushed % (long long)(s.W + 1)));
+}
+
+// a batch of trials resident on the device: trial blockIdx.z (at x + z * stride
+// elements) into ring slot z
+template <typename T>
+__global__ __launch_bounds__(256) void k_spectra_batch(SessDev<T> s, long long stride)
+{
+    __shared__ T xs[SP_NODES][SP_CH + 1];
+    SessDev<T> d = s;
+    d.x = (const T *)s.x + (size_t)blockIdx.z * stride;
+    spectra_body(d, blockIdx.x, blockIdx.y, xs, (int)blockIdx.z);
 }
 
 template <typename T> hipError_t launch_spectra(const SessDev<T> &s, hipStream_t st)
@@ -100,19 +109,24 @@ template <typename T> hipError_t launch_spectra(const SessDev<T> &s, hipStream_t
     return hipGetLastError();
 }
 
+template <typename T> hipError_t launch_spectra_batch(const SessDev<T> &s, int K, long long stride, hipStream_t st)
+{
+    dim3 grid((s.N + SP_NODES - 1) / SP_NODES, (s.B * s.L + 15) / 16, K);
+    hipLaunchKernelGGL(k_spectra_batch<T>, grid, dim3(256), 0, st, s, stride);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // z-scored samples for COR: z = (x - mean) / ||x - mean|| (0 for a constant
 // row), so that the Pearson r of a trial is the plain dot product z_i . z_j.
 // One wavefront per node; rows padded with zeros to Mz.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void znorm_body(const SessDev<T> &s, int bx)
+__device__ __forceinline__ void znorm_body(const SessDev<T> &s, int bx, int slot)
 {
     const int lane = threadIdx.x & 63;
     const int node = bx * 4 + (threadIdx.x >> 6);
     if (node >= s.N) return;
-    const long long tp = s.ctl->pushed;
-    const int slot = (int)(tp % (long long)(s.W + 1));
     const T *xr = (const T *)s.x + (size_t)node * s.ldx;
     double sum = 0.0;
     int bad = 0;
@@ -137,12 +151,26 @@ __device__ __forceinline__ void znorm_body(const SessDev<T> &s, int bx)
 template <typename T>
 __global__ __launch_bounds__(256) void k_znorm(SessDev<T> s)
 {
-    znorm_body(s, blockIdx.x);
+    znorm_body(s, blockIdx.x, (int)(s.ctl->pushed % (long long)(s.W + 1)));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_znorm_batch(SessDev<T> s, long long stride)
+{
+    SessDev<T> d = s;
+    d.x = (const T *)s.x + (size_t)blockIdx.y * stride;
+    znorm_body(d, blockIdx.x, (int)blockIdx.y);
 }
 
 template <typename T> hipError_t launch_znorm(const SessDev<T> &s, hipStream_t st)
 {
     hipLaunchKernelGGL(k_znorm<T>, dim3((s.N + 3) / 4), dim3(256), 0, st, s);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t launch_znorm_batch(const SessDev<T> &s, int K, long long stride, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_znorm_batch<T>, dim3((s.N + 3) / 4, K), dim3(256), 0, st, s, stride);
     return hipGetLastError();
 }
 
@@ -875,7 +903,8 @@ __global__ __launch_bounds__(256) void kb_spectra(const SessDev<float> *S, const
     __shared__ float xs[SP_NODES][SP_CH + 1];
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
-        spectra_body(S[w.x], w.y, w.z, xs);
+        const SessDev<float> &d = S[w.x];
+        spectra_body(d, w.y, w.z, xs, (int)(d.ctl->pushed % (long long)(d.W + 1)));
         __syncthreads();
     }
 }
@@ -884,7 +913,8 @@ __global__ __launch_bounds__(256) void kb_znorm(const SessDev<float> *S, const i
 {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
-        znorm_body(S[w.x], w.y);
+        const SessDev<float> &d = S[w.x];
+        znorm_body(d, w.y, (int)(d.ctl->pushed % (long long)(d.W + 1)));
     }
 }
 
@@ -988,6 +1018,8 @@ hipError_t launch_copy_probe(void *dst, const void *src, int64_t n_bytes, hipStr
     template hipError_t launch_psd<T>(const SessDev<T> &, hipStream_t);                       \
     template hipError_t launch_pair_update<T>(const SessDev<T> &, hipStream_t);               \
     template hipError_t launch_znorm<T>(const SessDev<T> &, hipStream_t);                     \
+    template hipError_t launch_spectra_batch<T>(const SessDev<T> &, int, long long, hipStream_t); \
+    template hipError_t launch_znorm_batch<T>(const SessDev<T> &, int, long long, hipStream_t);   \
     template hipError_t launch_finalize_bins<T>(const SessDev<T> &, uint32_t, T *, hipStream_t);
 FCX_INST(float)
 FCX_INST(double)

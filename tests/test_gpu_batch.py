@@ -202,3 +202,26 @@ def test_batch_cor_shared_tiles(fcx, prec):
     log(f"batch cor N={N} {prec} then two sliding pushes: max abs error {err2:.2e}")
     assert err2 <= TOL, err2
     s.close()
+
+
+def test_batch_host_equals_device(fcx, mid):
+    """The same window from host memory (trials uploaded and transformed one
+    by one) and from device memory (every trial's spectra and z-scored
+    samples in one launch each) gives the same networks bit for bit; the
+    host array has strided rows."""
+    x, cfg = mid
+    K = 9
+    cfg = dict(cfg, window_trials=K)
+    xs = np.ascontiguousarray(x[:K], dtype=np.float32)
+    wide = np.zeros((K, xs.shape[1], xs.shape[2] + 7), dtype=np.float32)
+    wide[:, :, :xs.shape[2]] = xs
+    s1, _ = _batch(fcx, cfg, xs)
+    s2 = fcx.Session(cfg)
+    fcx.check(s2.push_batch_host(wide[:, :, :xs.shape[2]]))
+    fcx.check(s2.sync())
+    for m in ALL:
+        a = s1.read(m)[1]
+        b = s2.read(m)[1]
+        assert np.array_equal(a, b), m
+    s1.close()
+    s2.close()
