@@ -28,8 +28,9 @@ namespace fcx {
 // ---------------------------------------------------------------------------
 // spectra: X[b][l][i] = sum_n (w_l[n] e^{-2 pi i k_b n / F}) x_i[n]
 // A workgroup owns 16 nodes and 16 (taper, bin) outputs per node; samples are
-// staged through LDS 256 at a time and summed in blocks of 256 (block sums
-// added to the total) to keep the FP32 rounding growth small.
+// staged through LDS 256 at a time and summed in blocks of 256 (four
+// interleaved chains per block, block sums added to the total) to keep the
+// FP32 rounding growth small.
 // ---------------------------------------------------------------------------
 constexpr int SP_NODES = 16;
 constexpr int SP_CH = 256;
@@ -60,15 +61,27 @@ __device__ __forceinline__ void spectra_body(const SessDev<T> &s, int bx, int by
         }
         __syncthreads();
         if (active) {
+            // four independent chains over samples c = 4q + r, joined at the
+            // end of the block
             const int nmax = min(SP_CH, s.M - n0);
-            T pr = 0, pi = 0;
-            for (int c = 0; c < nmax; ++c) {
-                const T xv = xs[nl][c];
-                pr = fma(xv, tw[2 * (n0 + c)], pr);
-                pi = fma(xv, tw[2 * (n0 + c) + 1], pi);
+            T pr[4] = {0, 0, 0, 0}, pi[4] = {0, 0, 0, 0};
+            int c = 0;
+#pragma unroll 4
+            for (; c + 4 <= nmax; c += 4) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const T xv = xs[nl][c + r];
+                    pr[r] = fma(xv, tw[2 * (n0 + c + r)], pr[r]);
+                    pi[r] = fma(xv, tw[2 * (n0 + c + r) + 1], pi[r]);
+                }
             }
-            acc_re += pr;
-            acc_im += pi;
+            for (int r = 0; c < nmax; ++c, ++r) {
+                const T xv = xs[nl][c];
+                pr[r] = fma(xv, tw[2 * (n0 + c)], pr[r]);
+                pi[r] = fma(xv, tw[2 * (n0 + c) + 1], pi[r]);
+            }
+            acc_re += (pr[0] + pr[1]) + (pr[2] + pr[3]);
+            acc_im += (pi[0] + pi[1]) + (pi[2] + pi[3]);
         }
         __syncthreads();
     }
@@ -121,6 +134,8 @@ template <typename T> hipError_t launch_spectra_batch(const SessDev<T> &s, int K
 // row), so that the Pearson r of a trial is the plain dot product z_i . z_j.
 // One wavefront per node; rows padded with zeros to Mz.
 // ---------------------------------------------------------------------------
+constexpr int ZN_REG = 16;   // rows of up to 64 * ZN_REG samples are held in registers
+
 template <typename T>
 __device__ __forceinline__ void znorm_body(const SessDev<T> &s, int bx, int slot)
 {
@@ -128,8 +143,43 @@ __device__ __forceinline__ void znorm_body(const SessDev<T> &s, int bx, int slot
     const int node = bx * 4 + (threadIdx.x >> 6);
     if (node >= s.N) return;
     const T *xr = (const T *)s.x + (size_t)node * s.ldx;
+    float *z = s.zring + ((size_t)slot * s.N + node) * s.Mz;
     double sum = 0.0;
     int bad = 0;
+    if (s.M <= 64 * ZN_REG) {
+        // the row is read once into registers; the sums run in the same order
+        // as the three passes below, so the results are the same
+        T v[ZN_REG];
+#pragma unroll
+        for (int r = 0; r < ZN_REG; ++r) {
+            const int n = lane + 64 * r;
+            v[r] = n < s.M ? xr[n] : (T)0;
+        }
+#pragma unroll
+        for (int r = 0; r < ZN_REG; ++r)
+            if (lane + 64 * r < s.M) {
+                if (!finite_v(v[r])) bad = 1;
+                sum += (double)v[r];
+            }
+        if (bad) s.ctl->bad = 1;
+        const double mean = wave_sum(sum) / (double)s.M;
+        double ss = 0.0;
+#pragma unroll
+        for (int r = 0; r < ZN_REG; ++r)
+            if (lane + 64 * r < s.M) {
+                const double d = (double)v[r] - mean;
+                ss += d * d;
+            }
+        ss = wave_sum(ss);
+        const double inv = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+#pragma unroll
+        for (int r = 0; r < ZN_REG; ++r) {
+            const int n = lane + 64 * r;
+            if (n < s.Mz) z[n] = n < s.M ? (float)(((double)v[r] - mean) * inv) : 0.0f;
+        }
+        for (int n = lane + 64 * ZN_REG; n < s.Mz; n += 64) z[n] = 0.0f;
+        return;
+    }
     for (int n = lane; n < s.M; n += 64) {
         const T v = xr[n];
         if (!finite_v(v)) bad = 1;
@@ -144,7 +194,6 @@ __device__ __forceinline__ void znorm_body(const SessDev<T> &s, int bx, int slot
     }
     ss = wave_sum(ss);
     const double inv = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
-    float *z = s.zring + ((size_t)slot * s.N + node) * s.Mz;
     for (int n = lane; n < s.Mz; n += 64) z[n] = n < s.M ? (float)(((double)xr[n] - mean) * inv) : 0.0f;
 }
 
