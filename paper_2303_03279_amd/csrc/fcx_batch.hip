@@ -50,46 +50,45 @@ template <> struct Gram<FCX_GRAM_FP32_ID> {
     }
 };
 
+// BF16 forms: the operands were rounded once, as they entered LDS, into
+// planes of rows of BT_LDH values: plane 0 Re hi, 1 Im hi, 2 Re lo, 3 Im lo
+// (lo = bf16(x - hi), BF16x3 only).  Lane group lg reads the 8 columns
+// 8lg..8lg+7 of its row as one 16-byte load; -Re is Re with the sign bits
+// flipped (rounding to nearest commutes with negation).
+constexpr int BT_LDH = BT_CC + 8;   // 80-byte rows: the 16-byte lane reads hit distinct banks
+constexpr int BT_PLANE = 64 * BT_LDH;
+
+__device__ __forceinline__ bf16x8 bf_row(const __bf16 *P, int plane, int node, int lg)
+{
+    return *(const bf16x8 *)(P + plane * BT_PLANE + node * BT_LDH + 8 * lg);
+}
+
+__device__ __forceinline__ bf16x8 bf_neg(bf16x8 v)
+{
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    return __builtin_bit_cast(bf16x8, __builtin_bit_cast(u32x4, v) ^ 0x80008000u);
+}
+
 template <> struct Gram<FCX_GRAM_BF16_ID> {
-    __device__ static void chunk(const float2 *X, int arow, int bcol, int lg, floatx4 &re, floatx4 &im)
+    __device__ static void chunk(const __bf16 *P, int arow, int bcol, int lg, floatx4 &re, floatx4 &im)
     {
-        bf16x8 ar, ai, an, br, bi;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float2 a = X[arow * BT_LD + 8 * lg + e];
-            const float2 b = X[bcol * BT_LD + 8 * lg + e];
-            ar[e] = (__bf16)a.x;
-            ai[e] = (__bf16)a.y;
-            an[e] = (__bf16)(-a.x);
-            br[e] = (__bf16)b.x;
-            bi[e] = (__bf16)b.y;
-        }
+        const bf16x8 ar = bf_row(P, 0, arow, lg), ai = bf_row(P, 1, arow, lg);
+        const bf16x8 br = bf_row(P, 0, bcol, lg), bi = bf_row(P, 1, bcol, lg);
         re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, re, 0, 0, 0);
         re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, bi, re, 0, 0, 0);
         im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(an, bi, im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf_neg(ar), bi, im, 0, 0, 0);
     }
 };
 
 template <> struct Gram<FCX_GRAM_BF16X3_ID> {
-    __device__ static void chunk(const float2 *X, int arow, int bcol, int lg, floatx4 &re, floatx4 &im)
+    __device__ static void chunk(const __bf16 *P, int arow, int bcol, int lg, floatx4 &re, floatx4 &im)
     {
-        bf16x8 arh, arl, aih, ail, anh, anl, brh, brl, bih, bil;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float2 a = X[arow * BT_LD + 8 * lg + e];
-            const float2 b = X[bcol * BT_LD + 8 * lg + e];
-            arh[e] = bf_hi(a.x);
-            arl[e] = bf_lo(a.x);
-            aih[e] = bf_hi(a.y);
-            ail[e] = bf_lo(a.y);
-            anh[e] = bf_hi(-a.x);
-            anl[e] = bf_lo(-a.x);
-            brh[e] = bf_hi(b.x);
-            brl[e] = bf_lo(b.x);
-            bih[e] = bf_hi(b.y);
-            bil[e] = bf_lo(b.y);
-        }
+        const bf16x8 arh = bf_row(P, 0, arow, lg), aih = bf_row(P, 1, arow, lg);
+        const bf16x8 arl = bf_row(P, 2, arow, lg), ail = bf_row(P, 3, arow, lg);
+        const bf16x8 brh = bf_row(P, 0, bcol, lg), bih = bf_row(P, 1, bcol, lg);
+        const bf16x8 brl = bf_row(P, 2, bcol, lg), bil = bf_row(P, 3, bcol, lg);
+        const bf16x8 anh = bf_neg(arh), anl = bf_neg(arl);
         re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, re, 0, 0, 0);
         re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, re, 0, 0, 0);
         re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, re, 0, 0, 0);
@@ -104,6 +103,18 @@ template <> struct Gram<FCX_GRAM_BF16X3_ID> {
         im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anl, bih, im, 0, 0, 0);
     }
 };
+
+// the planes of one staged value
+template <int PREC> __device__ __forceinline__ void bf_stage(__bf16 *P, int node, int col, float2 v)
+{
+    const __bf16 hr = (__bf16)v.x, hi = (__bf16)v.y;
+    P[0 * BT_PLANE + node * BT_LDH + col] = hr;
+    P[1 * BT_PLANE + node * BT_LDH + col] = hi;
+    if (PREC == FCX_GRAM_BF16X3_ID) {
+        P[2 * BT_PLANE + node * BT_LDH + col] = (__bf16)(v.x - (float)hr);
+        P[3 * BT_PLANE + node * BT_LDH + col] = (__bf16)(v.y - (float)hi);
+    }
+}
 
 // ------------------------------------------------------------- power sums
 // 64 (bin, node) entries per workgroup; its four wavefronts take every fourth
@@ -145,8 +156,12 @@ __global__ __launch_bounds__(BT_THREADS)
 __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))) void k_pair_batch(SessDev<float> s,
                                                                                                      int K)
 {
-    __shared__ float2 Xs[64 * BT_LD];
-    __shared__ float2 Us[64 * BT_LD];
+    constexpr bool BFP = PREC != FCX_GRAM_FP32_ID;
+    constexpr int NPL = PREC == FCX_GRAM_BF16X3_ID ? 4 : 2;   // BF16 planes per operand
+    __shared__ float2 Xs[64 * BT_LD];                         // FP32 values (the vector sums read them)
+    __shared__ float2 Us[BFP ? 1 : 64 * BT_LD];               // FP32 unit phasors
+    __shared__ __attribute__((aligned(16))) __bf16 Xh[BFP ? NPL * BT_PLANE : 8];
+    __shared__ __attribute__((aligned(16))) __bf16 Uh[BFP ? NPL * BT_PLANE : 8];
     if (s.ctl->bad) return;
     const int tile = blockIdx.x >> 2, qd = blockIdx.x & 3;
     const int2 tt = s.tiles[tile];
@@ -205,7 +220,12 @@ __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))
                     }
                 }
                 Xs[node * BT_LD + col] = v;
-                if (mfmaU) Us[node * BT_LD + col] = u;
+                if constexpr (BFP) {
+                    bf_stage<PREC>(Xh, node, col, v);
+                    if (mfmaU) bf_stage<PREC>(Uh, node, col, u);
+                } else {
+                    if (mfmaU) Us[node * BT_LD + col] = u;
+                }
             }
             __syncthreads();
             // per-trial sums of this lane's four pairs (FP32, no contraction)
@@ -250,9 +270,114 @@ __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))
                         }
                     }
                 }
+            } else if constexpr (PREC == FCX_GRAM_BF16X3_ID && LT == 1) {
+                // BF16x3, one taper: one 16x16x32 step covers the chunk; its
+                // 12 MFMAs per Gram are spread over the eight groups of four
+                // trials of the vector sums, so that the matrix cores and the
+                // vector units work side by side (plain BF16, with 4 MFMAs,
+                // runs faster as below: it keeps a fourth wavefront per SIMD)
+                const bf16x8 arh = bf_row(Xh, 0, arow, lg), aih = bf_row(Xh, 1, arow, lg);
+                const bf16x8 brh = bf_row(Xh, 0, bcol, lg), bih = bf_row(Xh, 1, bcol, lg);
+                bf16x8 arl = arh, ail = aih, brl = brh, bil = bih;
+                if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
+                    arl = bf_row(Xh, 2, arow, lg);
+                    ail = bf_row(Xh, 3, arow, lg);
+                    brl = bf_row(Xh, 2, bcol, lg);
+                    bil = bf_row(Xh, 3, bcol, lg);
+                }
+                bf16x8 urh = arh, uih = aih, vrh = brh, vih = bih, url = arh, uil = aih, vrl = brh, vil = bih;
+                if (mfmaU) {
+                    urh = bf_row(Uh, 0, arow, lg);
+                    uih = bf_row(Uh, 1, arow, lg);
+                    vrh = bf_row(Uh, 0, bcol, lg);
+                    vih = bf_row(Uh, 1, bcol, lg);
+                    if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
+                        url = bf_row(Uh, 2, arow, lg);
+                        uil = bf_row(Uh, 3, arow, lg);
+                        vrl = bf_row(Uh, 2, bcol, lg);
+                        vil = bf_row(Uh, 3, bcol, lg);
+                    }
+                }
+#define FCX_MF(acc, a, b) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0)
+#pragma unroll
+                for (int g = 0; g < 8; ++g) {
+                    // group g: X's Gram in groups 0-3, U's in groups 4-7
+                    if (g == 0) {
+                        FCX_MF(sre, arh, brh);
+                        if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
+                            FCX_MF(sre, arh, brl);
+                            FCX_MF(sre, arl, brh);
+                        }
+                    } else if (g == 1) {
+                        FCX_MF(sre, aih, bih);
+                        if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
+                            FCX_MF(sre, aih, bil);
+                            FCX_MF(sre, ail, bih);
+                        }
+                    } else if (g == 2) {
+                        FCX_MF(sim, aih, brh);
+                        if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
+                            FCX_MF(sim, aih, brl);
+                            FCX_MF(sim, ail, brh);
+                        }
+                    } else if (g == 3) {
+                        FCX_MF(sim, bf_neg(arh), bih);
+                        if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
+                            FCX_MF(sim, bf_neg(arh), bil);
+                            FCX_MF(sim, bf_neg(arl), bih);
+                        }
+                    } else if (mfmaU) {
+                        if (g == 4) {
+                            FCX_MF(ure, urh, vrh);
+                            if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
+                                FCX_MF(ure, urh, vrl);
+                                FCX_MF(ure, url, vrh);
+                            }
+                        } else if (g == 5) {
+                            FCX_MF(ure, uih, vih);
+                            if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
+                                FCX_MF(ure, uih, vil);
+                                FCX_MF(ure, uil, vih);
+                            }
+                        } else if (g == 6) {
+                            FCX_MF(uim, uih, vrh);
+                            if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
+                                FCX_MF(uim, uih, vrl);
+                                FCX_MF(uim, uil, vrh);
+                            }
+                        } else {
+                            FCX_MF(uim, bf_neg(urh), vih);
+                            if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
+                                FCX_MF(uim, bf_neg(urh), vil);
+                                FCX_MF(uim, bf_neg(url), vih);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt) {
+                        const int t = 4 * g + tt;
+                        if (t < nk) {
+                            const float2 xj = Xs[bcol * BT_LD + t];
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                const float2 xi = Xs[rows[k] * BT_LD + t];
+                                const float ci = __builtin_fmaf(xi.y, xj.x, -(xi.x * xj.y));
+                                G[k] += sign_of(ci);
+                                Ap[k] += fabsf(ci);
+                                Qp[k] = __builtin_fmaf(ci, ci, Qp[k]);
+                            }
+                        }
+                    }
+                }
+#undef FCX_MF
             } else {
-            Gram<PREC>::chunk(Xs, arow, bcol, lg, sre, sim);
-            if (mfmaU) Gram<PREC>::chunk(Us, arow, bcol, lg, ure, uim);
+            if constexpr (BFP) {
+                Gram<PREC>::chunk(Xh, arow, bcol, lg, sre, sim);
+                if (mfmaU) Gram<PREC>::chunk(Uh, arow, bcol, lg, ure, uim);
+            } else {
+                Gram<PREC>::chunk(Xs, arow, bcol, lg, sre, sim);
+                if (mfmaU) Gram<PREC>::chunk(Us, arow, bcol, lg, ure, uim);
+            }
 #pragma unroll 4
             for (int t = 0; t < nk; ++t) {
 #pragma unroll
