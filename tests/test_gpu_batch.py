@@ -225,3 +225,35 @@ def test_batch_host_equals_device(fcx, mid):
         assert np.array_equal(a, b), m
     s1.close()
     s2.close()
+
+
+@pytest.mark.parametrize("N,K,M,prec", [(2, 1, 33, "fp32"), (3, 2, 33, "fp32"), (2, 3, 7, "fp32"), (5, 4, 70, "bf16x3"), (5, 6, 70, "bf16")])
+def test_batch_smallest(fcx, N, K, M, prec):
+    """The smallest batches: one pair, one trial (the debiased forms need two
+    and are NaN), seven-sample trials, trial lengths that end inside a staged
+    chunk of samples.  (Two-sample trials are left out: the periodic Hann
+    taper keeps one sample, every cross-spectrum is then real, and WPLI
+    becomes a ratio of rounding noise on either side.)"""
+    rng = np.random.default_rng(N * 100 + K)
+    x = rng.standard_normal((K, N, M))
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=K, n_fft=max(64, M), fs_hz=1000.0,
+                            f_lo_hz=8.0, f_hi_hz=120.0, metrics=synth.ALL8, gram=prec)
+    s, _ = _batch(fcx, cfg, x)
+    ref = oracle.network(oracle.as_device_input(x, cfg), cfg)
+    dpli, dus = tie_bounds(ref, K)
+    for m in ALL:
+        st, got, k = s.read(m)
+        if K < 2 and m in ("uspli", "dswpli"):   # not ready below two trials, filled with NaN
+            assert st == fcx.FCX_E_NOTREADY and np.all(np.isnan(got)), (m, st)
+            continue
+        assert st == 0 and k == K, (m, st, k)
+        got = got.astype(np.float64)
+        want = ref["band"][m]
+        err = np.abs(got - want)
+        if m == "pli":
+            err = np.maximum(err - dpli, 0.0)
+        if m == "uspli":
+            err = np.maximum(err - dus, 0.0)
+        log(f"batch N={N} K={K} M={M} {prec} {m}: max abs error {float(err.max()):.2e}")
+        assert float(err.max()) <= BOUND[prec][m], (m, float(err.max()))
+    s.close()
