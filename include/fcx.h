@@ -142,7 +142,12 @@ fcx_status fcx_push_trial(fcx_session *s, const void *x, int64_t ld, int x_on_de
  * batch pass: dense Gram sums on the matrix cores in the session's
  * gram_precision, sign/|Im| sums on the vector units.  Inputs must be finite
  * (checked on the device; a non-finite batch leaves the session empty and
- * reports FCX_E_NONFINITE at the next sync).
+ * reports FCX_E_NONFINITE at the next sync).  Strides are in elements of
+ * cfg.elem.  A device-resident batch (x_on_device = 1) is transformed in one
+ * launch per kernel; host trials are uploaded one at a time.  The batch
+ * writes the band-mean networks directly; the running sums (which the batch
+ * pass uses as scratch) are rebuilt from the cached window by the next
+ * sliding push, per-bin read or fcx_resync.
  */
 fcx_status fcx_push_batch(fcx_session *s, const void *x, int64_t n_trials, int64_t trial_stride,
                           int64_t ld, int x_on_device);

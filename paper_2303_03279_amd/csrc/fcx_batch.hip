@@ -26,13 +26,10 @@ constexpr int BT_CC = 32;           // contraction columns (trial x taper) stage
 constexpr int BT_LD = BT_CC + 1;    // LDS row stride in float2 (spreads banks)
 
 // ---------------------------------------------------------------- operands
-__device__ __forceinline__ __bf16 bf_hi(float x) { return (__bf16)x; }
-__device__ __forceinline__ __bf16 bf_lo(float x) { return (__bf16)(x - (float)(__bf16)x); }
-
 // One chunk of BT_CC columns of the complex Gram for a 16x16 block:
 // re += Re_a Re_b + Im_a Im_b, im += Im_a Re_b - Re_a Im_b.
-// X: LDS [64 nodes][BT_LD] float2; arow / bcol: this lane's A row node and
-// B column node; lg = lane >> 4.
+// FP32: X is LDS [64 nodes][BT_LD] float2; the BF16 forms read planes (below).
+// arow / bcol: this lane's A row node and B column node; lg = lane >> 4.
 template <int PREC> struct Gram;
 
 template <> struct Gram<FCX_GRAM_FP32_ID> {
