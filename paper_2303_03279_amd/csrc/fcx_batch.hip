@@ -138,16 +138,6 @@ __global__ __launch_bounds__(256) void k_psd_batch(SessDev<float> s, int K)
 }
 
 // ---------------------------------------------------------------- pairs
-// sign(c) as -1, 0 or 1 in two vector operations: c + 0 turns -0 into +0, and
-// the bits of a float read as a signed integer are positive, zero or negative
-// with it, so clamping them to [-1, 1] gives the sign (an integer median)
-__device__ __forceinline__ int sign_of(float c)
-{
-    int r;
-    asm("v_med3_i32 %0, %1, -1, 1" : "=v"(r) : "v"(__float_as_int(c + 0.0f)));
-    return r;
-}
-
 template <int PREC, int LT>
 __global__ __launch_bounds__(BT_THREADS)
 __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))) void k_pair_batch(SessDev<float> s,

@@ -115,6 +115,16 @@ template <> __device__ __forceinline__ double ratio_t<double>(double num, double
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+// sign(c) as -1, 0 or 1 in two vector operations: c + 0 turns -0 into +0, and
+// the bits of a float read as a signed integer are positive, zero or negative
+// with it, so clamping them to [-1, 1] gives the sign (an integer median)
+__device__ __forceinline__ int sign_of(float c)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, -1, 1" : "=v"(r) : "v"(__float_as_int(c + 0.0f)));
+    return r;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  This bijection on [0, n) gives the workgroups of one XCD a contiguous
 // run of work items, so neighbouring items (slices of one tile, tiles of one

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NWO == 2 ? 
                         for (int k = 0; k < 4; ++k) {
                             const float2 xi = Xs[rows[k] * HW_LD + t];
                             const float ci = __builtin_fmaf(xi.y, xj.x, -(xi.x * xj.y));
-                            G[k] += (ci > 0.f) - (ci < 0.f);
+                            G[k] += sign_of(ci);
                             Ap[k] += fabsf(ci);
                             Qp[k] = __builtin_fmaf(ci, ci, Qp[k]);
                         }
