@@ -52,24 +52,17 @@ __global__ __launch_bounds__(XT) void k_xcor_node(SessDev<T> s)
     const float *zr = s.zring + ((size_t)pv.slot_new * s.N + node) * s.Mz;
     for (int t = tid; t < M; t += XT) z[t] = zr[t];
     __syncthreads();
-    if (tid == 0) {
-        double acc = 0.0;
-        for (int t = M - 1; t >= 0; --t) {
-            acc += (double)z[t] * (double)z[t];
-            suf[t] = acc;
-        }
-    }
-    __syncthreads();
-    float *so = s.xsuf + (size_t)node * (L + 1);
-    for (int t = tid; t <= L; t += XT) so[t] = suf[t] > 0.0 ? (float)(1.0 / sqrt(suf[t])) : 0.f;
     // bin f: sum_t z(t) exp(-2 pi i f t / F), the phasor advanced by one
     // FP64 rotation per sample and restarted from its exact value at the
     // start of each of XSEG segments (independent chains; the rounding of
-    // the rotation grows by at most a few hundred FP64 ulps)
+    // the rotation grows by at most a few hundred FP64 ulps).  The bins
+    // 1..F/2-1 go round the threads; f = 0 and f = F/2, whose phasors are
+    // exactly +-1, are plain sums over the same segments, taken by the last
+    // thread, which has the fewest rotating bins
     constexpr int XSEG = 4;
     float2 *xo = s.xspec + (size_t)node * (F / 2 + 1);
     const int seg = (M + XSEG - 1) / XSEG;
-    for (int f = tid; f <= F / 2; f += XT) {
+    for (int f = 1 + tid; f < F / 2; f += XT) {
         double sr, ci0;
         sincospi(-2.0 * (double)f / (double)F, &sr, &ci0);   // one-sample rotation (cos ci0, sin sr)
         double re[XSEG], im[XSEG], cr[XSEG], cs[XSEG];
@@ -102,6 +95,36 @@ __global__ __launch_bounds__(XT) void k_xcor_node(SessDev<T> s)
         }
         xo[f] = make_float2((float)tr, (float)ti);
     }
+    if (tid == XT - 1) {
+        double d[XSEG], q[XSEG];   // f = 0: sum z(t); f = F/2: sum (-1)^t z(t)
+#pragma unroll
+        for (int g = 0; g < XSEG; ++g) {
+            d[g] = 0.0;
+            q[g] = 0.0;
+            for (int t = g * seg; t < min(M, (g + 1) * seg); ++t) {
+                const double v = (double)z[t];
+                d[g] += v;
+                q[g] += (t & 1) ? -v : v;
+            }
+        }
+        double td = 0.0, tq = 0.0;
+#pragma unroll
+        for (int g = 0; g < XSEG; ++g) {
+            td += d[g];
+            tq += q[g];
+        }
+        xo[0] = make_float2((float)td, 0.f);
+        xo[F / 2] = make_float2((float)tq, 0.f);
+        // suffix energies, FP64, one thread (deterministic order)
+        double acc = 0.0;
+        for (int t = M - 1; t >= 0; --t) {
+            acc += (double)z[t] * (double)z[t];
+            suf[t] = acc;
+        }
+    }
+    __syncthreads();
+    float *so = s.xsuf + (size_t)node * (L + 1);
+    for (int t = tid; t <= L; t += XT) so[t] = suf[t] > 0.0 ? (float)(1.0 / sqrt(suf[t])) : 0.f;
 }
 
 // ---------------------------------------------------------------------------
