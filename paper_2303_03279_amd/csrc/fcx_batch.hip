@@ -223,36 +223,38 @@ __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))
                 // latency overlaps vector work.  Im(x_i conj x_j) and the Im^2
                 // sum use fused multiply-adds (the kernel is bound by these
                 // vector sums)
+                {
 #pragma unroll
-                for (int st = 0; st < BT_CC / 4; ++st) {
-                    {
-                        const float2 a = Xs[arow * BT_LD + 4 * st + lg];
-                        const float2 bb = Xs[bcol * BT_LD + 4 * st + lg];
-                        sre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, sre, 0, 0, 0);
-                        sre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, sre, 0, 0, 0);
-                        sim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, sim, 0, 0, 0);
-                        sim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, bb.y, sim, 0, 0, 0);
-                    }
-                    if (mfmaU) {
-                        const float2 a = Us[arow * BT_LD + 4 * st + lg];
-                        const float2 bb = Us[bcol * BT_LD + 4 * st + lg];
-                        ure = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, ure, 0, 0, 0);
-                        ure = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, ure, 0, 0, 0);
-                        uim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, uim, 0, 0, 0);
-                        uim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, bb.y, uim, 0, 0, 0);
-                    }
+                    for (int st = 0; st < BT_CC / 4; ++st) {
+                        {
+                            const float2 a = Xs[arow * BT_LD + 4 * st + lg];
+                            const float2 bb = Xs[bcol * BT_LD + 4 * st + lg];
+                            sre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, sre, 0, 0, 0);
+                            sre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, sre, 0, 0, 0);
+                            sim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, sim, 0, 0, 0);
+                            sim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, bb.y, sim, 0, 0, 0);
+                        }
+                        if (mfmaU) {
+                            const float2 a = Us[arow * BT_LD + 4 * st + lg];
+                            const float2 bb = Us[bcol * BT_LD + 4 * st + lg];
+                            ure = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, ure, 0, 0, 0);
+                            ure = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, ure, 0, 0, 0);
+                            uim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, uim, 0, 0, 0);
+                            uim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, bb.y, uim, 0, 0, 0);
+                        }
 #pragma unroll
-                    for (int tt = 0; tt < 4; ++tt) {
-                        const int t = 4 * st + tt;
-                        if (t < nk) {
-                            const float2 xj = Xs[bcol * BT_LD + t];
+                        for (int tt = 0; tt < 4; ++tt) {
+                            const int t = 4 * st + tt;
+                            if (t < nk) {
+                                const float2 xj = Xs[bcol * BT_LD + t];
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                const float2 xi = Xs[rows[k] * BT_LD + t];
-                                const float ci = __builtin_fmaf(xi.y, xj.x, -(xi.x * xj.y));
-                                G[k] += sign_of(ci);
-                                Ap[k] += fabsf(ci);
-                                Qp[k] = __builtin_fmaf(ci, ci, Qp[k]);
+                                for (int k = 0; k < 4; ++k) {
+                                    const float2 xi = Xs[rows[k] * BT_LD + t];
+                                    const float ci = __builtin_fmaf(xi.y, xj.x, -(xi.x * xj.y));
+                                    G[k] += sign_of(ci);
+                                    Ap[k] += fabsf(ci);
+                                    Qp[k] = __builtin_fmaf(ci, ci, Qp[k]);
+                                }
                             }
                         }
                     }
@@ -340,10 +342,10 @@ __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))
                             }
                         }
                     }
+                    if (4 * g < nk) {   // zero columns past the trials add nothing
 #pragma unroll
-                    for (int tt = 0; tt < 4; ++tt) {
-                        const int t = 4 * g + tt;
-                        if (t < nk) {
+                        for (int tt = 0; tt < 4; ++tt) {
+                            const int t = 4 * g + tt;
                             const float2 xj = Xs[bcol * BT_LD + t];
 #pragma unroll
                             for (int k = 0; k < 4; ++k) {
