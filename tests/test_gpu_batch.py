@@ -170,7 +170,8 @@ def test_batch_cor_every_pair(fcx, N, prec):
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_batch_cor_shared_tiles(fcx, prec):
     """3000 nodes: more 128-node tiles (300) than compute units, so tiles are
-    cut between two workgroups that meet in the COR running-sum buffer.
+    cut between two workgroups that meet in the COR running-sum buffer (which
+    holds a sliding history when the batch starts).
     Every pair against the oracle; a second batch gives the same bits (the
     two partial sums may land in either order); then the window slides and
     the rebuilt running sums are checked on sampled rows."""
@@ -180,7 +181,14 @@ def test_batch_cor_shared_tiles(fcx, prec):
     x[:, 1::5, 2:] += 0.7 * x[:, 0:N - 1:5, :-2]
     cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=W, n_fft=128, f_lo_hz=8, f_hi_hz=30,
                             metrics=synth.COR, gram=prec)
-    s, xd = _batch(fcx, cfg, x[:W])
+    import torch
+    s = fcx.Session(cfg)
+    for t in range(2):   # a sliding history first: the COR sums the batch borrows are not zero
+        fcx.check(s.push_host(np.ascontiguousarray(x[W + t], dtype=np.float32)))
+    xd = torch.from_numpy(np.ascontiguousarray(x[:W], dtype=np.float32)).cuda()
+    torch.cuda.synchronize()
+    fcx.check(s.push_batch_device(xd.data_ptr(), W, N * M, M))
+    fcx.check(s.sync())
     st, a, k = s.read("cor")
     assert st == 0 and k == W
     a = a.copy()
