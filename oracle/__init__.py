@@ -59,7 +59,7 @@ def _load():
         I64, I32, D = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         lib.orc_spectra.argtypes = [P, I64, I64, I64, I64, P, I32, I64, P, I32, P, I64, P, P, P]
         lib.orc_spectra.restype = None
-        lib.orc_pairs.argtypes = [P, P, P, I64, I64, I32, I32, P, P, P, I64, D, P, P, P, P, P]
+        lib.orc_pairs.argtypes = [P, P, P, I64, I64, I32, I32, P, P, P, I64, D, P, P, P, P, P, P]
         lib.orc_pairs.restype = None
         lib.orc_cor.argtypes = [P, I64, I64, I64, I64, P, P, I64, P]
         lib.orc_cor.restype = None
@@ -193,7 +193,8 @@ def network(x: np.ndarray, cfg: dict, pi=None, pj=None, delta=None, with_sums=Fa
 
     Returns a dict with band means `band[m]` ([np]), per-bin values
     `per_bin[m]` ([np][B]), sign sums `G` and tie counts `ties` ([np][B]),
-    `cor` ([np]) and `K`.
+    the |Im| and Im^2 sums `A`, `Q` and the sum of the trials' tie thresholds
+    `tsum` ([np][B]), `cor` ([np]) and `K`.
     """
     lib = _load()
     x = np.ascontiguousarray(x, dtype=np.float64)
@@ -217,11 +218,13 @@ def network(x: np.ndarray, cfg: dict, pi=None, pj=None, delta=None, with_sums=Fa
     G = np.empty((npairs, B), dtype=np.int32)
     ties = np.empty((npairs, B), dtype=np.int32)
     sums = np.empty((npairs, B, 8)) if with_sums else None
+    aqt = np.empty((npairs, B, 3))
     lam = np.ascontiguousarray(lam, dtype=np.float64)
     lib.orc_pairs(_ptr(Xre), _ptr(Xim), _ptr(l1), K, nodes.size, L, B, _ptr(lam), _ptr(pa),
                   _ptr(pb), npairs, float(delta), _ptr(per_bin), _ptr(band), _ptr(G), _ptr(ties),
-                  _ptr(sums) if with_sums else None)
-    out = dict(K=K, bins=bins, pi=pi, pj=pj, G=G, ties=ties,
+                  _ptr(sums) if with_sums else None, _ptr(aqt))
+    out = dict(K=K, bins=bins, pi=pi, pj=pj, G=G, ties=ties, A=aqt[:, :, 0], Q=aqt[:, :, 1],
+               tsum=aqt[:, :, 2],
                band={m: band[:, q] for q, m in enumerate(METRICS7)},
                per_bin={m: per_bin[:, :, q] for q, m in enumerate(METRICS7)})
     if with_sums:

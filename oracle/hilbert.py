@@ -82,8 +82,8 @@ def tie_scale(x: np.ndarray, F: int) -> np.ndarray:
 
 def network(z: np.ndarray, win_len: int = 0, hop: int = 0, pi=None, pj=None, scale=None,
             delta: float = DELTA_F32) -> list[dict]:
-    """Per window: dict(K, start, band={metric: [np]}, G, ties) for pairs
-    (pi, pj) (default every pair i < j in packed order)."""
+    """Per window: dict(K, start, band={metric: [np]}, G, ties, A, Q, tsum)
+    for pairs (pi, pj) (default every pair i < j in packed order)."""
     lib = _load()
     z = np.atleast_2d(np.asarray(z, dtype=np.complex128))
     N, M = z.shape
@@ -105,7 +105,9 @@ def network(z: np.ndarray, win_len: int = 0, hop: int = 0, pi=None, pj=None, sca
         band = np.empty((npairs, 7))
         G = np.empty((npairs, 1), dtype=np.int32)
         ties = np.empty((npairs, 1), dtype=np.int32)
+        aqt = np.empty((npairs, 1, 3))
         lib.orc_pairs(_ptr(Xre), _ptr(Xim), _ptr(l1), K, N, 1, 1, _ptr(lam), _ptr(pa), _ptr(pb), npairs,
-                      float(delta), _ptr(per_bin), _ptr(band), _ptr(G), _ptr(ties), None)
-        res.append(dict(K=K, start=a, G=G, ties=ties, band={m: band[:, q] for q, m in enumerate(METRICS7)}))
+                      float(delta), _ptr(per_bin), _ptr(band), _ptr(G), _ptr(ties), None, _ptr(aqt))
+        res.append(dict(K=K, start=a, G=G, ties=ties, A=aqt[:, :, 0], Q=aqt[:, :, 1], tsum=aqt[:, :, 2],
+                        band={m: band[:, q] for q, m in enumerate(METRICS7)}))
     return res

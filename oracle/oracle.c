@@ -117,11 +117,14 @@ void orc_spectra(const double *x, int64_t K, int64_t trial_stride, int64_t node_
  *   per_bin [np][B][7], band [np][7]  (metric order COH IMCOH PLV PLI WPLI USPLI DSWPLI)
  *   gsum [np][B] (sign sums G), ties [np][B]
  *   sums [np][B][8] (S_re, S_im, P_a, P_b, U_re, U_im, A, Q) if non-NULL
+ *   aqt  [np][B][3] (A, Q, and the sum over the trials of the tie thresholds)
+ *        if non-NULL: the scale on which WPLI and DSWPLI are decided by
+ *        rounding alone (SI-1 WPLI and DSWPLI equations)
  */
 void orc_pairs(const double *Xre, const double *Xim, const double *l1, int64_t K, int64_t nn,
                int32_t L, int32_t B, const double *lam, const int32_t *pa, const int32_t *pb,
                int64_t np, double delta, double *per_bin, double *band, int32_t *gsum,
-               int32_t *ties, double *sums)
+               int32_t *ties, double *sums, double *aqt)
 {
     double lsum = 0.0;
     for (int32_t l = 0; l < L; ++l) lsum += lam[l];
@@ -134,6 +137,7 @@ void orc_pairs(const double *Xre, const double *Xim, const double *l1, int64_t K
         for (int32_t b = 0; b < B; ++b) {
             double Sre = 0, Sim = 0, Pa = 0, Pb = 0, Ure = 0, Uim = 0, A = 0, Q = 0;
             int32_t G = 0, T = 0;
+            double Tsum = 0.0;
             for (int64_t k = 0; k < K; ++k) {
                 double cre = 0, cim = 0, pwa = 0, pwb = 0, tau = 0;
                 for (int32_t l = 0; l < L; ++l) {
@@ -164,6 +168,7 @@ void orc_pairs(const double *Xre, const double *Xim, const double *l1, int64_t K
                 }
                 G += (int32_t)sgn(cim);
                 if (fabs(cim) <= tau) T += 1;
+                Tsum += tau;
                 A += fabs(cim);
                 Q += cim * cim;
             }
@@ -190,6 +195,10 @@ void orc_pairs(const double *Xre, const double *Xim, const double *l1, int64_t K
             }
             gsum[p * B + b] = G;
             ties[p * B + b] = T;
+            if (aqt) {
+                double *t = aqt + (p * B + b) * 3;
+                t[0] = A; t[1] = Q; t[2] = Tsum;
+            }
             if (sums) {
                 double *s = sums + (p * B + b) * 8;
                 s[0] = Sre; s[1] = Sim; s[2] = Pa; s[3] = Pb;

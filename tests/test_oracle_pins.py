@@ -176,6 +176,43 @@ def test_dc_and_nyquist_are_real():
         assert np.all(r["ties"][:, b] == K)
 
 
+def test_tie_count_interior_bin():
+    """Tie counts at an interior bin: trials in which node 1 is node 0 at
+    zero lag (twice the amplitude, so Im CSD is an exact 0), plus a lagged
+    component of relative size eps.  With the FP32 threshold eps = 0 and 1e-9
+    give |Im| far below it (ties) and eps = 1e-3 far above it; with the FP64
+    threshold only eps = 0 is a tie.  The count must be exactly the number of
+    tie trials, every nonzero eps must count in G, and a bin of only zero-lag
+    trials has its |Im| sum within the tie-threshold sum (the degenerate-bin
+    rule)."""
+    M = F = 256
+    k0 = 20
+    f0 = 1000.0 * k0 / F
+    t = np.arange(M) / 1000.0
+    eps = [0.0, 1e-9, 1e-3, 0.0, 1e-3, 1e-9, 1e-3]
+    rng = np.random.default_rng(5)
+    x = np.empty((len(eps), 3, M))
+    for k, e in enumerate(eps):
+        th = rng.uniform(0, 2 * np.pi)
+        s = np.cos(2 * np.pi * f0 * t + th)
+        lagged = np.cos(2 * np.pi * f0 * t + th - np.pi / 2)
+        x[k, 0] = s
+        x[k, 1] = 2.0 * s + e * lagged
+        x[k, 2] = -4.0 * s
+    for elem, n_tie in (("f32", 4), ("f64", 2)):
+        # FP32 spectra: threshold 2^-18 of the scale, so eps = 1e-9 is a tie;
+        # FP64: 2^-44, so only the exact zeros are
+        cfg = _cfg(M, F, f_lo=f0, f_hi=f0, elem=elem)
+        r = oracle.network(x, cfg, pi=[0, 0], pj=[1, 2])
+        assert list(r["bins"]) == [k0]
+        assert r["ties"][0, 0] == n_tie, elem
+        assert r["ties"][1, 0] == len(eps)          # exact multiples: every trial a tie
+        assert r["G"][1, 0] == 0 and r["A"][1, 0] == 0.0
+        assert r["A"][1, 0] <= r["tsum"][1, 0]      # a degenerate bin
+        assert r["A"][0, 0] > r["tsum"][0, 0]       # the lagged trials carry real |Im|
+        assert abs(r["G"][0, 0]) == sum(1 for e in eps if e > 0.0)
+
+
 # ------------------------------------------------------------------ statistics
 
 def test_null_statistics_zero_lag_mixture():
