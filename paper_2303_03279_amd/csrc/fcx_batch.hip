@@ -137,23 +137,305 @@ __global__ __launch_bounds__(256) void k_psd_batch(SessDev<float> s, int K)
     if (w == 0 && live) s.psd[e] = ((p + part[0][lane]) + part[1][lane]) + part[2][lane];
 }
 
-// ---------------------------------------------------------------- pairs
-template <int PREC, int LT>
-__global__ __launch_bounds__(BT_THREADS)
-__attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))) void k_pair_batch(SessDev<float> s,
-                                                                                                     int K)
+// --------------------------------------------------------- pairs, one taper
+// One 64x64 pair tile per workgroup of 8 wavefronts.  Wavefront w owns the
+// tile rows 16(w >> 1) .. +15 and columns 32(w & 1) .. +31 as two 16x16 MFMA
+// blocks; lane (lr = lane & 15, lg = lane >> 4) holds the accumulator rows
+// 4lg .. 4lg+3 of column lr of both blocks, i.e. 4 x 2 = 8 pairs, and the
+// vector-unit sums of the same 8 pairs, so the epilogue of a bin finds every
+// sum of a pair in one lane.
+//
+// Per trial the vector units form v = Im(X_i conj X_j) in FP64 from the FP32
+// spectra: both products are exact in FP64, so v is the correctly rounded
+// value of the exact difference.  Its sign is therefore exact (an exact zero
+// gives +0: the first product enters as fma(-a, b, +0), which is never -0),
+// and v, |v| and v^2 are summed in FP64, so Im S, A and Q carry no FP32
+// growth and no Gram rounding.  The matrix cores compute Re S and the unit
+// phasor Gram (and Im S too when no vector sums are asked for).
+//
+// A chunk of PB_CC trials of the 64 row and 64 column nodes is staged in LDS
+// (row values FP32; column values FP32 for the Gram and FP64 for the vector
+// sums; unit phasors; BF16 planes for the BF16 Grams), while the next chunk
+// is already loaded into registers.
+constexpr int PB_THREADS = 512;
+constexpr int PB_CC = 32;             // trials per staged chunk (one 16x16x32 BF16 step)
+constexpr int PB_LD = PB_CC + 1;      // LDS row stride of float2 / double2 rows
+constexpr int PB_PER = 128 * PB_CC / PB_THREADS;   // staged values per thread and chunk
+constexpr int PB_LDH = PB_CC + 8;     // BF16 plane rows (80 bytes)
+constexpr int PB_PLANE = 128 * PB_LDH;
+
+template <int PREC> __device__ __forceinline__ void pb_stage(__bf16 *P, int node, int col, float2 v)
+{
+    const __bf16 hr = (__bf16)v.x, hi = (__bf16)v.y;
+    P[0 * PB_PLANE + node * PB_LDH + col] = hr;
+    P[1 * PB_PLANE + node * PB_LDH + col] = hi;
+    if (PREC == FCX_GRAM_BF16X3_ID) {
+        P[2 * PB_PLANE + node * PB_LDH + col] = (__bf16)(v.x - (float)hr);
+        P[3 * PB_PLANE + node * PB_LDH + col] = (__bf16)(v.y - (float)hi);
+    }
+}
+
+__device__ __forceinline__ bf16x8 pb_row(const __bf16 *P, int plane, int node, int lg)
+{
+    return *(const bf16x8 *)(P + plane * PB_PLANE + node * PB_LDH + 8 * lg);
+}
+
+// Complex Gram of one 32-trial chunk for the lane's two 16x16 blocks: Re S
+// always; Im S when IM; in the BF16 forms, from the rounded planes
+template <int PREC, bool IM>
+__device__ __forceinline__ void pb_gram(const float2 *Xs, const __bf16 *Xh, int arow, int bcol0, int lg,
+                                        floatx4 (&re)[2], floatx4 (&im)[2])
+{
+    if constexpr (PREC == FCX_GRAM_FP32_ID) {
+#pragma unroll
+        for (int st = 0; st < PB_CC / 4; ++st) {
+            const float2 a = Xs[arow * PB_LD + 4 * st + lg];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float2 b = Xs[(bcol0 + 16 * c) * PB_LD + 4 * st + lg];
+                re[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, re[c], 0, 0, 0);
+                re[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, re[c], 0, 0, 0);
+                if constexpr (IM) {
+                    im[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, im[c], 0, 0, 0);
+                    im[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, b.y, im[c], 0, 0, 0);
+                }
+            }
+        }
+    } else {
+        constexpr bool X3 = PREC == FCX_GRAM_BF16X3_ID;
+        const bf16x8 arh = pb_row(Xh, 0, arow, lg), aih = pb_row(Xh, 1, arow, lg);
+        bf16x8 arl = arh, ail = aih;
+        if constexpr (X3) {
+            arl = pb_row(Xh, 2, arow, lg);
+            ail = pb_row(Xh, 3, arow, lg);
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int bn = bcol0 + 16 * c;
+            const bf16x8 brh = pb_row(Xh, 0, bn, lg), bih = pb_row(Xh, 1, bn, lg);
+#define FCX_MF(acc, a, b) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0)
+            FCX_MF(re[c], arh, brh);
+            FCX_MF(re[c], aih, bih);
+            if constexpr (IM) {
+                FCX_MF(im[c], aih, brh);
+                FCX_MF(im[c], bf_neg(arh), bih);
+            }
+            if constexpr (X3) {
+                const bf16x8 brl = pb_row(Xh, 2, bn, lg), bil = pb_row(Xh, 3, bn, lg);
+                FCX_MF(re[c], arh, brl);
+                FCX_MF(re[c], arl, brh);
+                FCX_MF(re[c], aih, bil);
+                FCX_MF(re[c], ail, bih);
+                if constexpr (IM) {
+                    FCX_MF(im[c], aih, brl);
+                    FCX_MF(im[c], ail, brh);
+                    FCX_MF(im[c], bf_neg(arh), bil);
+                    FCX_MF(im[c], bf_neg(arl), bih);
+                }
+            }
+#undef FCX_MF
+        }
+    }
+}
+
+template <int PREC, bool VS>
+__global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, int K)
+{
+    constexpr bool BFP = PREC != FCX_GRAM_FP32_ID;
+    constexpr int NPL = PREC == FCX_GRAM_BF16X3_ID ? 4 : 2;
+    // Xs: FP32 values, rows 0..63 then (FP32 Gram only) columns 64..127
+    __shared__ float2 Xs[(BFP ? 64 : 128) * PB_LD];
+    __shared__ double2 Xd[VS ? 64 * PB_LD : 1];        // columns in FP64 (vector sums)
+    __shared__ float2 Us[BFP ? 1 : 128 * PB_LD];       // FP32 unit phasors
+    __shared__ __attribute__((aligned(16))) __bf16 Xh[BFP ? NPL * PB_PLANE : 8];
+    __shared__ __attribute__((aligned(16))) __bf16 Uh[BFP ? NPL * PB_PLANE : 8];
+    __shared__ double SR[128];                          // 1/sqrt(P) of the staged nodes
+    if (s.ctl->bad) return;
+    const int tile = xcd_item(blockIdx.x, gridDim.x);
+    const int2 tt = s.tiles[tile];
+    const int R0 = tt.x * TILE, C0 = tt.y * TILE;
+    const int N = s.N, B = s.B;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+    const int wr = w >> 1, wc = w & 1;
+    const int arow = 16 * wr + lr;            // Gram A operand: a row node
+    const int bcol0 = 64 + 32 * wc + lr;      // Gram B operand of block 0: a column node
+    const int rbase = 16 * wr + 4 * lg;       // the lane's pair rows rbase + k (tile rows)
+    const int cbase = 32 * wc + lr;           // the lane's pair columns cbase + 16c (tile columns)
+    const uint32_t mm = s.metrics;
+    const bool needU = mm & M_PLV;
+    const float2 *ring = (const float2 *)s.ring;
+    const int nch = (K + PB_CC - 1) / PB_CC, total = B * nch;
+    const float invK = 1.0f / (float)K;
+    const float invKm1 = K >= 2 ? 1.0f / (float)(K - 1) : 0.f;
+
+    // staged value v of this thread: node e & 127 (64 rows, then 64 columns),
+    // trial column e >> 7 of the chunk
+    int gnode[PB_PER];
+#pragma unroll
+    for (int v = 0; v < PB_PER; ++v) {
+        const int node = (tid + PB_THREADS * v) & 127;
+        gnode[v] = node < 64 ? R0 + node : C0 + node - 64;
+    }
+    auto fetch = [&](int cc, float2 (&dst)[PB_PER]) {
+        const int b = cc / nch, t0 = (cc - b * nch) * PB_CC;
+#pragma unroll
+        for (int v = 0; v < PB_PER; ++v) {
+            const int t = t0 + ((tid + PB_THREADS * v) >> 7);
+            dst[v] = (cc < total && t < K && gnode[v] < N) ? ring[((size_t)t * B + b) * N + gnode[v]]
+                                                          : make_float2(0.f, 0.f);
+        }
+    };
+    float2 pre[PB_PER];
+    fetch(0, pre);
+
+    float acc[8][7];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int m = 0; m < 7; ++m) acc[p][m] = 0.f;
+
+    for (int b = 0; b < B; ++b) {
+        floatx4 sre[2], sim[2], ure[2], uim[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) sre[c] = sim[c] = ure[c] = uim[c] = (floatx4){0.f, 0.f, 0.f, 0.f};
+        int G[8];
+        double Sv[8], Av[8], Qv[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            G[p] = 0;
+            Sv[p] = Av[p] = Qv[p] = 0.0;
+        }
+        for (int ch = 0; ch < nch; ++ch) {
+            const int cc = b * nch + ch;
+            const int nk = min(PB_CC, K - ch * PB_CC);
+            __syncthreads();   // the previous chunk's readers are done
+#pragma unroll
+            for (int v = 0; v < PB_PER; ++v) {
+                const int e = tid + PB_THREADS * v, node = e & 127, col = e >> 7;
+                const float2 x = pre[v];
+                float2 u = make_float2(0.f, 0.f);
+                if (needU) {
+                    // unit phasor X / |X| (0 for X = 0), magnitude formed in FP64
+                    const double m2 = (double)x.x * x.x + (double)x.y * x.y;
+                    const double r = m2 > 0.0 ? __builtin_amdgcn_rsq(m2) : 0.0;
+                    u.x = (float)(x.x * r);
+                    u.y = (float)(x.y * r);
+                }
+                if (!BFP || node < 64) Xs[node * PB_LD + col] = x;
+                if constexpr (VS) {
+                    if (node >= 64) Xd[(node - 64) * PB_LD + col] = make_double2(x.x, x.y);
+                }
+                if constexpr (BFP) {
+                    pb_stage<PREC>(Xh, node, col, x);
+                    if (needU) pb_stage<PREC>(Uh, node, col, u);
+                } else {
+                    if (needU) Us[node * PB_LD + col] = u;
+                }
+            }
+            if (ch == 0 && tid < 128) {
+                const int g = tid < 64 ? R0 + tid : C0 + tid - 64;
+                double r = 0.0;
+                if (g < N) {
+                    const double p = s.psd[(size_t)b * N + g];
+                    r = p > 0.0 ? rsqrt(p) : 0.0;
+                }
+                SR[tid] = r;
+            }
+            __syncthreads();
+            fetch(cc + 1, pre);   // the next chunk is on its way while this one is computed
+
+            pb_gram<PREC, !VS>(Xs, Xh, arow, bcol0, lg, sre, sim);
+            if (needU) pb_gram<PREC, true>(Us, Uh, arow, bcol0, lg, ure, uim);
+            if constexpr (VS) {
+                for (int t4 = 0; t4 < nk; t4 += 4) {   // columns past the trials are 0 and add nothing
+#pragma unroll
+                    for (int tq = 0; tq < 4; ++tq) {
+                        const int t = t4 + tq;
+                        const double2 xj0 = Xd[cbase * PB_LD + t];
+                        const double2 xj1 = Xd[(cbase + 16) * PB_LD + t];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const float2 xf = Xs[(rbase + k) * PB_LD + t];
+                            const double xr = xf.x, xi = xf.y;
+#pragma unroll
+                            for (int c = 0; c < 2; ++c) {
+                                const double2 xj = c ? xj1 : xj0;
+                                const double v = __builtin_fma(xi, xj.x, __builtin_fma(-xr, xj.y, 0.0));
+                                const int p = 2 * k + c;
+                                G[p] += sign_of_f64(v);
+                                Av[p] = Av[p] + fabs(v);
+                                Qv[p] = __builtin_fma(v, v, Qv[p]);
+                                Sv[p] = Sv[p] + v;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        // metrics of this bin for the lane's pairs, into the band means
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int p = 2 * k + c;
+                const int ri = rbase + k, cj = cbase + 16 * c;
+                const int i = R0 + ri, j = C0 + cj;
+                if (!(i < j && j < N)) continue;
+                const double Sr = sre[c][k];
+                const double Si = VS ? Sv[p] : (double)sim[c][k];
+                const double srij = SR[ri] * SR[64 + cj];
+                if (mm & M_COH) acc[p][0] += sqrt_ratio<float>((Sr * Sr + Si * Si) * srij * srij);
+                if (mm & M_IMCOH) acc[p][1] += (float)(Si * srij);
+                if (mm & M_PLV) {
+                    const float ur = ure[c][k], ui = uim[c][k];
+                    acc[p][2] += __builtin_amdgcn_sqrtf(ur * ur + ui * ui) * invK;
+                }
+                if constexpr (VS) {
+                    const float pli = (float)abs(G[p]) * invK;
+                    if (mm & M_PLI) acc[p][3] += pli;
+                    if (mm & M_USPLI) acc[p][5] += K >= 2 ? ((float)K * pli * pli - 1.0f) * invKm1 : NAN;
+                    if (mm & M_WPLI) acc[p][4] += Av[p] > 0.0 ? ratio_t<float>(fabs(Si), Av[p]) : 0.f;
+                    if (mm & M_DSWPLI) {
+                        const double dd = Av[p] * Av[p] - Qv[p];
+                        acc[p][6] += K >= 2 ? (dd != 0.0 ? ratio_t<float>(Si * Si - Qv[p], dd) : 0.f) : NAN;
+                    }
+                }
+            }
+    }
+    const size_t P = (size_t)N * (N - 1) / 2;
+    const float invB = 1.0f / (float)B;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int i = R0 + rbase + k, j = C0 + cbase + 16 * c;
+            if (!(i < j && j < N)) continue;
+            const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+#pragma unroll
+            for (int m = 0; m < 7; ++m)
+                if (mm & (1u << m)) s.out[(size_t)m * P + idx] = acc[2 * k + c][m] * invB;
+        }
+}
+
+// ------------------------------------------------------ pairs, several tapers
+// Per 32x32 quarter tile and bin (4 wavefronts of one 16x16 block each): the
+// Gram of Re S over (trial, taper) columns weighted by sqrt(lambda_l / sum
+// lambda) on the matrix cores; per pair and trial on the vector units the
+// taper-combined CSD c = sum_l w_l X_il conj(X_jl) with each taper's products
+// exact in FP64 (so Im c of a zero-lag pair is an exact 0), its sign, |Im c|,
+// (Im c)^2 and Im c summed in FP64, and the unit phasor of c for PLV.
+template <int PREC>
+__global__ __launch_bounds__(BT_THREADS) void k_pair_batchL(SessDev<float> s, int K)
 {
     constexpr bool BFP = PREC != FCX_GRAM_FP32_ID;
     constexpr int NPL = PREC == FCX_GRAM_BF16X3_ID ? 4 : 2;   // BF16 planes per operand
     __shared__ float2 Xs[64 * BT_LD];                         // FP32 values (the vector sums read them)
-    __shared__ float2 Us[BFP ? 1 : 64 * BT_LD];               // FP32 unit phasors
     __shared__ __attribute__((aligned(16))) __bf16 Xh[BFP ? NPL * BT_PLANE : 8];
-    __shared__ __attribute__((aligned(16))) __bf16 Uh[BFP ? NPL * BT_PLANE : 8];
     if (s.ctl->bad) return;
     const int tile = blockIdx.x >> 2, qd = blockIdx.x & 3;
     const int2 tt = s.tiles[tile];
     const int R0 = tt.x * TILE + 32 * (qd >> 1), C0 = tt.y * TILE + 32 * (qd & 1);
-    const int N = s.N, B = s.B, L = LT ? LT : s.L;
+    const int N = s.N, B = s.B, L = s.L;
     if (R0 >= N || R0 >= min(C0 + 31, N - 1)) return;   // no pair i < j < N here
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
     const int wr = w >> 1, wc = w & 1;
@@ -166,7 +448,6 @@ __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))
     for (int k = 0; k < 4; ++k) rows[k] = 16 * wr + 4 * lg + k;
     const uint32_t mm = s.metrics;
     const bool needU = mm & M_PLV;
-    const bool mfmaU = needU && L == 1;
     const int TPC = BT_CC / L;   // whole trials per chunk
     const int CC = TPC * L;
     const float2 *ring = (const float2 *)s.ring;
@@ -179,9 +460,10 @@ __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))
         for (int m = 0; m < 7; ++m) acc[k][m] = 0.f;
 
     for (int b = 0; b < B; ++b) {
-        floatx4 sre = {0.f, 0.f, 0.f, 0.f}, sim = sre, ure = sre, uim = sre;
+        floatx4 sre = {0.f, 0.f, 0.f, 0.f}, sdum = sre;
         int G[4] = {0, 0, 0, 0};
-        double A[4] = {0, 0, 0, 0}, Q[4] = {0, 0, 0, 0}, VUr[4] = {0, 0, 0, 0}, VUi[4] = {0, 0, 0, 0};
+        double A[4] = {0, 0, 0, 0}, Q[4] = {0, 0, 0, 0}, S[4] = {0, 0, 0, 0};
+        double VUr[4] = {0, 0, 0, 0}, VUi[4] = {0, 0, 0, 0};
         for (int t0 = 0; t0 < K; t0 += TPC) {
             const int nk = min(TPC, K - t0);
             __syncthreads();
@@ -191,198 +473,39 @@ __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))
                 const int node = e & 63, col = e >> 6;
                 const int t = col / L, l = col % L;
                 const int g = node < 32 ? R0 + node : C0 + node - 32;
-                float2 v = make_float2(0.f, 0.f), u = make_float2(0.f, 0.f);
+                float2 v = make_float2(0.f, 0.f);
                 if (col < CC && t < nk && g < N) {
                     v = ring[(((size_t)(t0 + t) * B + b) * L + l) * N + g];
-                    if (L > 1) {
-                        const float wl = (float)sqrt(s.lamw[l]);
-                        v.x *= wl;
-                        v.y *= wl;
-                    }
-                    if (mfmaU) {
-                        const double m2 = (double)v.x * v.x + (double)v.y * v.y;
-                        const double r = m2 > 0.0 ? rsqrt(m2) : 0.0;
-                        u.x = (float)(v.x * r);
-                        u.y = (float)(v.y * r);
-                    }
+                    const float wl = (float)sqrt(s.lamw[l]);
+                    v.x *= wl;
+                    v.y *= wl;
                 }
                 Xs[node * BT_LD + col] = v;
-                if constexpr (BFP) {
-                    bf_stage<PREC>(Xh, node, col, v);
-                    if (mfmaU) bf_stage<PREC>(Uh, node, col, u);
-                } else {
-                    if (mfmaU) Us[node * BT_LD + col] = u;
-                }
+                if constexpr (BFP) bf_stage<PREC>(Xh, node, col, v);
             }
             __syncthreads();
-            // per-trial sums of this lane's four pairs (FP32, no contraction)
-            float Ap[4] = {0.f, 0.f, 0.f, 0.f}, Qp[4] = {0.f, 0.f, 0.f, 0.f};
-            if constexpr (PREC == FCX_GRAM_FP32_ID && LT == 1) {
-                // FP32 Gram, one taper: each MFMA step (4 trials) is followed by
-                // the vector sums of the same 4 trials, so the matrix-core
-                // latency overlaps vector work.  Im(x_i conj x_j) and the Im^2
-                // sum use fused multiply-adds (the kernel is bound by these
-                // vector sums)
-                {
-#pragma unroll
-                    for (int st = 0; st < BT_CC / 4; ++st) {
-                        {
-                            const float2 a = Xs[arow * BT_LD + 4 * st + lg];
-                            const float2 bb = Xs[bcol * BT_LD + 4 * st + lg];
-                            sre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, sre, 0, 0, 0);
-                            sre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, sre, 0, 0, 0);
-                            sim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, sim, 0, 0, 0);
-                            sim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, bb.y, sim, 0, 0, 0);
-                        }
-                        if (mfmaU) {
-                            const float2 a = Us[arow * BT_LD + 4 * st + lg];
-                            const float2 bb = Us[bcol * BT_LD + 4 * st + lg];
-                            ure = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, ure, 0, 0, 0);
-                            ure = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, ure, 0, 0, 0);
-                            uim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, uim, 0, 0, 0);
-                            uim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, bb.y, uim, 0, 0, 0);
-                        }
-#pragma unroll
-                        for (int tt = 0; tt < 4; ++tt) {
-                            const int t = 4 * st + tt;
-                            if (t < nk) {
-                                const float2 xj = Xs[bcol * BT_LD + t];
-#pragma unroll
-                                for (int k = 0; k < 4; ++k) {
-                                    const float2 xi = Xs[rows[k] * BT_LD + t];
-                                    const float ci = __builtin_fmaf(xi.y, xj.x, -(xi.x * xj.y));
-                                    G[k] += sign_of(ci);
-                                    Ap[k] += fabsf(ci);
-                                    Qp[k] = __builtin_fmaf(ci, ci, Qp[k]);
-                                }
-                            }
-                        }
-                    }
-                }
-            } else if constexpr (PREC == FCX_GRAM_BF16X3_ID && LT == 1) {
-                // BF16x3, one taper: one 16x16x32 step covers the chunk; its
-                // 12 MFMAs per Gram are spread over the eight groups of four
-                // trials of the vector sums, so that the matrix cores and the
-                // vector units work side by side (plain BF16, with 4 MFMAs,
-                // runs faster as below: it keeps a fourth wavefront per SIMD)
-                const bf16x8 arh = bf_row(Xh, 0, arow, lg), aih = bf_row(Xh, 1, arow, lg);
-                const bf16x8 brh = bf_row(Xh, 0, bcol, lg), bih = bf_row(Xh, 1, bcol, lg);
-                bf16x8 arl = arh, ail = aih, brl = brh, bil = bih;
-                if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
-                    arl = bf_row(Xh, 2, arow, lg);
-                    ail = bf_row(Xh, 3, arow, lg);
-                    brl = bf_row(Xh, 2, bcol, lg);
-                    bil = bf_row(Xh, 3, bcol, lg);
-                }
-                bf16x8 urh = arh, uih = aih, vrh = brh, vih = bih, url = arh, uil = aih, vrl = brh, vil = bih;
-                if (mfmaU) {
-                    urh = bf_row(Uh, 0, arow, lg);
-                    uih = bf_row(Uh, 1, arow, lg);
-                    vrh = bf_row(Uh, 0, bcol, lg);
-                    vih = bf_row(Uh, 1, bcol, lg);
-                    if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
-                        url = bf_row(Uh, 2, arow, lg);
-                        uil = bf_row(Uh, 3, arow, lg);
-                        vrl = bf_row(Uh, 2, bcol, lg);
-                        vil = bf_row(Uh, 3, bcol, lg);
-                    }
-                }
-#define FCX_MF(acc, a, b) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0)
-#pragma unroll
-                for (int g = 0; g < 8; ++g) {
-                    // group g: X's Gram in groups 0-3, U's in groups 4-7
-                    if (g == 0) {
-                        FCX_MF(sre, arh, brh);
-                        if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
-                            FCX_MF(sre, arh, brl);
-                            FCX_MF(sre, arl, brh);
-                        }
-                    } else if (g == 1) {
-                        FCX_MF(sre, aih, bih);
-                        if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
-                            FCX_MF(sre, aih, bil);
-                            FCX_MF(sre, ail, bih);
-                        }
-                    } else if (g == 2) {
-                        FCX_MF(sim, aih, brh);
-                        if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
-                            FCX_MF(sim, aih, brl);
-                            FCX_MF(sim, ail, brh);
-                        }
-                    } else if (g == 3) {
-                        FCX_MF(sim, bf_neg(arh), bih);
-                        if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
-                            FCX_MF(sim, bf_neg(arh), bil);
-                            FCX_MF(sim, bf_neg(arl), bih);
-                        }
-                    } else if (mfmaU) {
-                        if (g == 4) {
-                            FCX_MF(ure, urh, vrh);
-                            if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
-                                FCX_MF(ure, urh, vrl);
-                                FCX_MF(ure, url, vrh);
-                            }
-                        } else if (g == 5) {
-                            FCX_MF(ure, uih, vih);
-                            if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
-                                FCX_MF(ure, uih, vil);
-                                FCX_MF(ure, uil, vih);
-                            }
-                        } else if (g == 6) {
-                            FCX_MF(uim, uih, vrh);
-                            if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
-                                FCX_MF(uim, uih, vrl);
-                                FCX_MF(uim, uil, vrh);
-                            }
-                        } else {
-                            FCX_MF(uim, bf_neg(urh), vih);
-                            if constexpr (PREC == FCX_GRAM_BF16X3_ID) {
-                                FCX_MF(uim, bf_neg(urh), vil);
-                                FCX_MF(uim, bf_neg(url), vih);
-                            }
-                        }
-                    }
-                    if (4 * g < nk) {   // zero columns past the trials add nothing
-#pragma unroll
-                        for (int tt = 0; tt < 4; ++tt) {
-                            const int t = 4 * g + tt;
-                            const float2 xj = Xs[bcol * BT_LD + t];
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                const float2 xi = Xs[rows[k] * BT_LD + t];
-                                const float ci = __builtin_fmaf(xi.y, xj.x, -(xi.x * xj.y));
-                                G[k] += sign_of(ci);
-                                Ap[k] += fabsf(ci);
-                                Qp[k] = __builtin_fmaf(ci, ci, Qp[k]);
-                            }
-                        }
-                    }
-                }
-#undef FCX_MF
-            } else {
             if constexpr (BFP) {
-                Gram<PREC>::chunk(Xh, arow, bcol, lg, sre, sim);
-                if (mfmaU) Gram<PREC>::chunk(Uh, arow, bcol, lg, ure, uim);
+                Gram<PREC>::chunk(Xh, arow, bcol, lg, sre, sdum);
             } else {
-                Gram<PREC>::chunk(Xs, arow, bcol, lg, sre, sim);
-                if (mfmaU) Gram<PREC>::chunk(Us, arow, bcol, lg, ure, uim);
+                Gram<PREC>::chunk(Xs, arow, bcol, lg, sre, sdum);
             }
-#pragma unroll 4
             for (int t = 0; t < nk; ++t) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    float cr = 0.f, ci = 0.f;
+                    double cr = 0.0, ci = 0.0;
                     for (int l = 0; l < L; ++l) {
                         const float2 xi = Xs[rows[k] * BT_LD + t * L + l];
                         const float2 xj = Xs[bcol * BT_LD + t * L + l];
-                        cr = cr + (xi.x * xj.x + xi.y * xj.y);
-                        ci = ci + (xi.y * xj.x - xi.x * xj.y);
+                        // exact FP64 products; the +0 keeps an exact zero positive
+                        ci = ci + im_cross(xi, xj.x, xj.y);
+                        if (needU) cr = cr + ((double)xi.x * xj.x + (double)xi.y * xj.y);
                     }
-                    G[k] += sign_of(ci);
-                    Ap[k] += fabsf(ci);
-                    Qp[k] += ci * ci;
-                    if (needU && L > 1) {
-                        const double m2 = (double)cr * cr + (double)ci * ci;
+                    G[k] += sign_of_f64(ci);
+                    A[k] = A[k] + fabs(ci);
+                    Q[k] = __builtin_fma(ci, ci, Q[k]);
+                    S[k] = S[k] + ci;
+                    if (needU) {
+                        const double m2 = cr * cr + ci * ci;
                         if (m2 > 0.0) {
                             const double rm = rsqrt(m2);
                             VUr[k] += cr * rm;
@@ -391,27 +514,17 @@ __attribute__((amdgpu_waves_per_eu(PREC == FCX_GRAM_FP32_ID && LT == 1 ? 4 : 1))
                     }
                 }
             }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                A[k] += Ap[k];
-                Q[k] += Qp[k];
-            }
         }
         // metrics of this bin for the lane's pairs, into the band means
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int i = R0 + rows[k];
             if (!(i < j && j < N)) continue;
-            const double Sr = sre[k], Si = sim[k];
+            const double Sr = sre[k], Si = S[k];
             const double pp = s.psd[(size_t)b * N + i] * s.psd[(size_t)b * N + j];
             if (mm & M_COH) acc[k][0] += pp > 0.0 ? (float)sqrt((Sr * Sr + Si * Si) / pp) : 0.f;
             if (mm & M_IMCOH) acc[k][1] += pp > 0.0 ? (float)(Si / sqrt(pp)) : 0.f;
-            if (mm & M_PLV) {
-                const double ur = mfmaU ? (double)ure[k] : VUr[k];
-                const double ui = mfmaU ? (double)uim[k] : VUi[k];
-                acc[k][2] += (float)(sqrt(ur * ur + ui * ui) / Kd);
-            }
+            if (mm & M_PLV) acc[k][2] += (float)(sqrt(VUr[k] * VUr[k] + VUi[k] * VUi[k]) / Kd);
             const double pli = fabs((double)G[k]) / Kd;
             if (mm & M_PLI) acc[k][3] += (float)pli;
             if (mm & M_USPLI) acc[k][5] += K >= 2 ? (float)((Kd * pli * pli - 1.0) / (Kd - 1.0)) : NAN;
@@ -751,22 +864,35 @@ hipError_t launch_psd_batch(const SessDev<float> &s, int K, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int LT> static void launch_pair_batch_l(const SessDev<float> &s, int K, int prec, hipStream_t st)
+template <bool VS> static void launch_pair_batch1(const SessDev<float> &s, int K, int prec, hipStream_t st)
 {
-    const dim3 grid(s.ntiles * 4), blk(BT_THREADS);
+    const dim3 grid(s.ntiles), blk(PB_THREADS);
     switch (prec) {
-    case FCX_GRAM_BF16_ID: hipLaunchKernelGGL((k_pair_batch<FCX_GRAM_BF16_ID, LT>), grid, blk, 0, st, s, K); break;
-    case FCX_GRAM_BF16X3_ID: hipLaunchKernelGGL((k_pair_batch<FCX_GRAM_BF16X3_ID, LT>), grid, blk, 0, st, s, K); break;
-    default: hipLaunchKernelGGL((k_pair_batch<FCX_GRAM_FP32_ID, LT>), grid, blk, 0, st, s, K); break;
+    case FCX_GRAM_BF16_ID: hipLaunchKernelGGL((k_pair_batch1<FCX_GRAM_BF16_ID, VS>), grid, blk, 0, st, s, K); break;
+    case FCX_GRAM_BF16X3_ID: hipLaunchKernelGGL((k_pair_batch1<FCX_GRAM_BF16X3_ID, VS>), grid, blk, 0, st, s, K); break;
+    default: hipLaunchKernelGGL((k_pair_batch1<FCX_GRAM_FP32_ID, VS>), grid, blk, 0, st, s, K); break;
     }
 }
 
 hipError_t launch_pair_batch(const SessDev<float> &s, int K, int prec, hipStream_t st)
 {
-    if (s.L == 1)
-        launch_pair_batch_l<1>(s, K, prec, st);
-    else
-        launch_pair_batch_l<0>(s, K, prec, st);
+    if (s.L == 1) {
+        // the sign, |Im|, Im^2 and Im sums run on the vector units only when a
+        // metric needs them
+        if (s.metrics & (M_PLI | M_WPLI | M_USPLI | M_DSWPLI))
+            launch_pair_batch1<true>(s, K, prec, st);
+        else
+            launch_pair_batch1<false>(s, K, prec, st);
+    } else {
+        const dim3 grid(s.ntiles * 4), blk(BT_THREADS);
+        switch (prec) {
+        case FCX_GRAM_BF16_ID: hipLaunchKernelGGL((k_pair_batchL<FCX_GRAM_BF16_ID>), grid, blk, 0, st, s, K); break;
+        case FCX_GRAM_BF16X3_ID:
+            hipLaunchKernelGGL((k_pair_batchL<FCX_GRAM_BF16X3_ID>), grid, blk, 0, st, s, K);
+            break;
+        default: hipLaunchKernelGGL((k_pair_batchL<FCX_GRAM_FP32_ID>), grid, blk, 0, st, s, K); break;
+        }
+    }
     return hipGetLastError();
 }
 

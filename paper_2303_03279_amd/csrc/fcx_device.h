@@ -115,13 +115,23 @@ template <> __device__ __forceinline__ double ratio_t<double>(double num, double
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// sign(c) as -1, 0 or 1 in two vector operations: c + 0 turns -0 into +0, and
-// the bits of a float read as a signed integer are positive, zero or negative
-// with it, so clamping them to [-1, 1] gives the sign (an integer median)
-__device__ __forceinline__ int sign_of(float c)
+// Im(a conj b) of two FP32 values in FP64: both products are exact in FP64,
+// so the result is the correctly rounded value of the exact difference, an
+// exact zero included.  The first product enters as fma(-a.x, b.y, +0), which
+// is never -0, so the result is never -0 either.
+__device__ __forceinline__ double im_cross(float2 a, double bx, double by)
+{
+    return __builtin_fma((double)a.y, bx, __builtin_fma(-(double)a.x, by, 0.0));
+}
+
+// sign of an FP64 value that is not -0, as -1, 0 or 1 in one vector
+// operation: its high word read as a signed integer is positive, zero or
+// negative with it (a nonzero product difference of FP32 values is at least
+// 2^-298, so its high word is never 0), clamped to [-1, 1] (an integer median)
+__device__ __forceinline__ int sign_of_f64(double v)
 {
     int r;
-    asm("v_med3_i32 %0, %1, -1, 1" : "=v"(r) : "v"(__float_as_int(c + 0.0f)));
+    asm("v_med3_i32 %0, %1, -1, 1" : "=v"(r) : "v"(__double2hiint(v)));
     return r;
 }
 

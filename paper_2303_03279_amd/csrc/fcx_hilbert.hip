@@ -13,10 +13,12 @@
 //                  k_hilbert_windows over blocks of gcd(L, H) samples, each
 //                  block's sums added to the windows holding it; otherwise per
 //                  window the window sum of |z_i|^2 (k_psd_batch) and the pair
-//                  pass of the batch path (k_pair_batch).  Both take the
-//                  cross-spectrum Gram on the matrix cores and the sign / |Im|
-//                  / Im^2 sums on the vector units, with the window's samples
-//                  in the role of the trials (one bin, one taper)
+//                  pass of the batch path (k_pair_batch1).  Both take Re of
+//                  the cross-spectrum Gram (and the unit-phasor Gram) on the
+//                  matrix cores, and Im(z_i conj z_j) exact-rounded in FP64
+//                  with its sign, |Im|, Im^2 and Im sums on the vector units,
+//                  with the window's samples in the role of the trials (one
+//                  bin, one taper)
 #include "fcx_device.h"
 #include "fcx_fft.h"
 
@@ -92,8 +94,9 @@ __global__ __launch_bounds__(HT) void k_analytic(int N, int M, int D, const floa
 // Overlapping windows in one pass (FP32 Gram).  The sample axis is cut into
 // blocks of Bk = gcd(L, H) samples; a window is bl = L / Bk consecutive blocks
 // and windows start every bh = H / Bk blocks.  Every block's sums are
-// computed once, in 32-sample chunks staged through LDS (complex Gram on the
-// matrix cores, sign / |Im| / Im^2 sums on the vector units), and added to
+// computed once, in 32-sample chunks staged through LDS (Re S and the phasor
+// Gram on the matrix cores; Im, its sign, |Im| and Im^2 sums in FP64 on the
+// vector units), and added to
 // each of the NWO = ceil(bl / bh) (2 or 3) windows that hold it; a window's
 // metrics are written when its last block is done.
 // ---------------------------------------------------------------------------
@@ -147,9 +150,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NWO == 2 ? 
 
     // open windows: slot q holds window wid[q] (-1: none)
     int wid[NWO];
-    float wsr[NWO][4], wsi[NWO][4], wur[NWO][4], wui[NWO][4];
+    float wsr[NWO][4], wur[NWO][4], wui[NWO][4];
     int wg[NWO][4];
-    double wa[NWO][4], wq[NWO][4];
+    double wsi[NWO][4], wa[NWO][4], wq[NWO][4];
 #pragma unroll
     for (int q = 0; q < NWO; ++q) wid[q] = -1;
 
@@ -162,19 +165,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NWO == 2 ? 
                     wid[q] = wn;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        wsr[q][k] = wsi[q][k] = wur[q][k] = wui[q][k] = 0.f;
+                        wsr[q][k] = wur[q][k] = wui[q][k] = 0.f;
                         wg[q][k] = 0;
-                        wa[q][k] = wq[q][k] = 0.0;
+                        wsi[q][k] = wa[q][k] = wq[q][k] = 0.0;
                     }
                 }
         }
-        floatx4 sre = {0.f, 0.f, 0.f, 0.f}, sim = sre, ure = sre, uim = sre;
+        floatx4 sre = {0.f, 0.f, 0.f, 0.f}, ure = sre, uim = sre;
         int G[4] = {0, 0, 0, 0};
-        double Ab[4] = {0.0, 0.0, 0.0, 0.0}, Qb[4] = {0.0, 0.0, 0.0, 0.0};
+        double Sb[4] = {0.0, 0.0, 0.0, 0.0}, Ab[4] = {0.0, 0.0, 0.0, 0.0}, Qb[4] = {0.0, 0.0, 0.0, 0.0};
         const int tb = blk * hw.Bk;
         for (int t0 = tb; t0 < tb + hw.Bk; t0 += HW_CC) {
             const int nk = min(HW_CC, tb + hw.Bk - t0);
-            float Ap[4] = {0.f, 0.f, 0.f, 0.f}, Qp[4] = {0.f, 0.f, 0.f, 0.f};   // FP32 within a chunk
             __syncthreads();
             // consecutive lanes take consecutive nodes of one sample
             for (int e = threadIdx.x; e < 64 * HW_CC; e += 256) {
@@ -203,8 +205,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NWO == 2 ? 
                     const float2 bb = Xs[bcol * HW_LD + 4 * st + lg];
                     sre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, sre, 0, 0, 0);
                     sre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, sre, 0, 0, 0);
-                    sim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, sim, 0, 0, 0);
-                    sim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, bb.y, sim, 0, 0, 0);
                 }
                 if (needU) {
                     const float2 a = Us[arow * HW_LD + 4 * st + lg];
@@ -219,21 +219,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NWO == 2 ? 
                     const int t = 4 * st + t4;
                     if (t < nk) {
                         const float2 xj = Xs[bcol * HW_LD + t];
+                        const double jx = xj.x, jy = xj.y;
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            const float2 xi = Xs[rows[k] * HW_LD + t];
-                            const float ci = __builtin_fmaf(xi.y, xj.x, -(xi.x * xj.y));
-                            G[k] += sign_of(ci);
-                            Ap[k] += fabsf(ci);
-                            Qp[k] = __builtin_fmaf(ci, ci, Qp[k]);
+                            // Im(z_i conj z_j) exact-rounded in FP64; sums in FP64
+                            const double ci = im_cross(Xs[rows[k] * HW_LD + t], jx, jy);
+                            G[k] += sign_of_f64(ci);
+                            Ab[k] = Ab[k] + fabs(ci);
+                            Qb[k] = __builtin_fma(ci, ci, Qb[k]);
+                            Sb[k] = Sb[k] + ci;
                         }
                     }
                 }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                Ab[k] += (double)Ap[k];
-                Qb[k] += (double)Qp[k];
             }
         }
         // the block into every open window, then the windows that end here
@@ -243,7 +240,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NWO == 2 ? 
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 wsr[q][k] += sre[k];
-                wsi[q][k] += sim[k];
+                wsi[q][k] += Sb[k];
                 wur[q][k] += ure[k];
                 wui[q][k] += uim[k];
                 wg[q][k] += G[k];

@@ -41,11 +41,29 @@ def tie_bounds(ref, K):
     return dpli, dus
 
 
+def degenerate_bounds(ref):
+    """Per-pair band-mean allowances for WPLI and DSWPLI from the oracle's
+    sums: in a bin whose |Im| sum A is within the sum of the trials' tie
+    thresholds, every cross-spectrum's imaginary part may be rounding alone,
+    so WPLI = |sum Im| / A and DSWPLI are ratios of rounding and any value in
+    their ranges ([0, 1] and [-1, 1]) is correct there."""
+    deg = (ref["A"] <= ref["tsum"]).astype(np.float64)
+    B = deg.shape[1]
+    return deg.sum(axis=1) / B, 2.0 * deg.sum(axis=1) / B
+
+
+def allowances(ref, K):
+    """Extra allowance per metric and pair on top of the base tolerance."""
+    dpli, dus = tie_bounds(ref, K)
+    dw, dds = degenerate_bounds(ref)
+    return {"pli": dpli, "uspli": dus, "wpli": dw, "dswpli": dds}
+
+
 def compare_network(s, ref, cfg, metrics, idx=None, tol=TOL, label=""):
     """Compare band-mean networks of session s with oracle result ref.
     idx: packed indices of the oracle's pairs (default: all pairs in order)."""
     K = ref["K"]
-    dpli, dus = tie_bounds(ref, K)
+    extra = allowances(ref, K)
     worst = {}
     for m in metrics:
         st, out, k = s.read(m)
@@ -58,11 +76,7 @@ def compare_network(s, ref, cfg, metrics, idx=None, tol=TOL, label=""):
             assert np.all(np.isnan(got)), m
             continue
         err = np.abs(got - want)
-        allow = np.full(err.shape, tol)
-        if m == "pli":
-            allow = allow + dpli
-        if m == "uspli":
-            allow = allow + dus
+        allow = np.full(err.shape, tol) + extra.get(m, 0.0)
         bad = err > allow
         worst[m] = float(err.max()) if err.size else 0.0
         assert not bad.any(), (
