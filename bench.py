@@ -37,6 +37,22 @@ VALU_OPS_PER_PAIR_TRIAL = 8
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "pair_update_n5000_all8_traffic.json")
 
 
+def algorithmic_bytes(fcx, cfg):
+    """Algorithmic HBM bytes of one sliding push's pair update: every running
+    sum the enabled metrics need, as FP64 values (int16 sign counts), read and
+    written once per pair and bin, plus the FP64 COR sum once per pair.  All 8
+    metrics: 100 B per pair.bin + 16 B per pair; COH or WPLI alone: 32 B per
+    pair.bin.  (The library stores the phasor and sign sums narrower; its own
+    byte count is fcx_pair_update_bytes, reported beside this one.)"""
+    m = cfg.get("metrics", 0xFF)
+    N = cfg["n_nodes"]
+    P = N * (N - 1) // 2
+    B = fcx.band_bins(cfg)[0]
+    per = (8 * bool(m & 1) + 8 * bool(m & (1 | 2 | 16 | 64)) + 16 * bool(m & 4) + 8 * bool(m & (16 | 64))
+           + 8 * bool(m & 64) + 2 * bool(m & (8 | 32)))
+    return 2 * per * P * B + (16 * P if m & 128 else 0)
+
+
 def measured_traffic():
     """HBM bytes per pair-update launch from the committed rocprofv3 counter
     record (FETCH_SIZE + WRITE_SIZE scaled by the copy-probe calibration),
@@ -54,13 +70,53 @@ def measured_traffic():
         return None
 
 
+def _time_launches(torch, fn, reps):
+    stream = torch.cuda.current_stream()
+    fn(stream.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn(stream.cuda_stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_rmw_probe(fcx, torch, n_elems, reps=5):
+    """Streaming read-modify-write of the all-8 state layout (41 bytes per
+    pair.bin, read and written): what state streaming alone reaches."""
+    buf = torch.zeros(41 * n_elems, dtype=torch.uint8, device="cuda")
+    ms = _time_launches(torch, lambda st: fcx.check(fcx.lib.fcx_probe_rmw(buf.data_ptr(), n_elems, st),
+                                                    "probe_rmw"), reps)
+    del buf
+    torch.cuda.empty_cache()
+    return dict(elements=n_elems, bytes_per_launch=82 * n_elems, avg_ms=ms,
+                gbs=82 * n_elems / (ms * 1e-3) / 1e9)
+
+
+def run_mfma_probes(fcx, torch, iters=4000, reps=3):
+    """Register-only MFMA chains per instruction form: the matrix-core rate
+    this device reaches, next to the published peaks."""
+    import ctypes
+    out = torch.empty(524288, dtype=torch.float32, device="cuda")
+    res = {}
+    for kind, name, peak in [(0, "fp32_16x16x4", 157.3), (1, "fp32_32x32x2", 157.3), (2, "bf16_16x16x32", 2500.0)]:
+        fl = ctypes.c_double()
+        ms = _time_launches(torch, lambda st: fcx.check(
+            fcx.lib.fcx_probe_mfma(kind, iters, out.data_ptr(), ctypes.byref(fl), st), "probe_mfma"), reps)
+        tf = fl.value / (ms * 1e-3) / 1e12
+        res[name] = dict(avg_ms=ms, tflops=tf, peak_tflops=peak, frac=tf / peak)
+    del out
+    return res
+
+
 def make_pool(n_trials: int, seed: int = 3):
     import synth
     x, cfg = synth.c3_source(seed=seed, n_trials=n_trials)
     return x.astype(np.float32), cfg
 
 
-def run_session(fcx, torch, cfg, pool_dev, steps, warmup, timing=True, lat_pushes=0):
+def run_session(fcx, torch, cfg, pool_dev, steps, warmup, timing=True, lat_pushes=0, resync_reps=0):
     W = cfg["window_trials"]
     M = cfg["n_samples"]
     npool = pool_dev.shape[0]
@@ -94,6 +150,14 @@ def run_session(fcx, torch, cfg, pool_dev, steps, warmup, timing=True, lat_pushe
         fcx.check(s.push_device(pool_dev[k % npool].data_ptr(), M), "push")
         fcx.check(s.sync(), "sync")
         lat.append(time.perf_counter() - t1)
+    if resync_reps > 0:
+        # one-pass rebuild of every running sum of the full window (synchronous)
+        rs = []
+        for _ in range(resync_reps):
+            t1 = time.perf_counter()
+            fcx.check(s.resync(), "resync")
+            rs.append(time.perf_counter() - t1)
+        kt["resync_ms"] = 1e3 * min(rs)
     s.close()
     return wall, kt, lat
 
@@ -180,7 +244,7 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
     ts, ss = synth.c4_arrivals(np.random.default_rng(seed + 1), len(sess), duration_s)
     upd = [fcx.band_bins(c)[0] * c["n_nodes"] * (c["n_nodes"] - 1) // 2 for c, _ in sess]
     # algorithmic HBM bytes of one push of each session (its pair update)
-    pbytes = [fcx.pair_update_bytes(c) for c, _ in sess]
+    pbytes = [algorithmic_bytes(fcx, c) for c, _ in sess]
     offered = float(sum(pbytes[k] for k in ss))
     fp = sum(fcx.footprint_bytes(c) for c, _ in sess)
     out = {"sessions": len(sess), "arrivals": int(ts.size), "duration_s": duration_s, "footprint_gb": fp / 1e9}
@@ -467,6 +531,9 @@ def main():
     ap.add_argument("--copy-probe-mb", type=int, default=1024,
                     help="size of the HBM copy probe (read + write), 0 to skip")
     ap.add_argument("--batch-reps", type=int, default=2, help="batch passes per Gram precision, 0 to skip")
+    ap.add_argument("--resync-reps", type=int, default=2,
+                    help="timed one-pass rebuilds of the running sums (fcx_resync) of the 5000-node and "
+                         "10000-node windows, 0 to skip")
     ap.add_argument("--serving-seconds", type=float, default=16.0,
                     help="serving-mix arrival window (about 650 arrivals/s), 0 to skip")
     ap.add_argument("--sensor-pushes", type=int, default=300,
@@ -519,13 +586,16 @@ def main():
         probe = dict(bytes_per_launch=2 * nbytes, avg_ms=ms, gbs=2 * nbytes / (ms * 1e-3) / 1e9)
         del src, dst
         torch.cuda.empty_cache()
+        probe["rmw_state"] = run_rmw_probe(fcx, torch, P * B)
+        probe["mfma"] = run_mfma_probes(fcx, torch)
 
     print("[bench] all-8 session", file=sys.stderr, flush=True)
     wall, kt, lat = run_session(fcx, torch, cfg, pool_dev, args.steps, args.warmup,
-                                lat_pushes=args.latency_pushes)
+                                lat_pushes=args.latency_pushes, resync_reps=args.resync_reps)
     ups = P * B * args.steps / wall
     pu = kt.get("pair_update", {})
-    algo = fcx.pair_update_bytes(cfg)
+    algo = algorithmic_bytes(fcx, cfg)
+    impl = fcx.pair_update_bytes(cfg)
     achieved = algo / (pu["avg_ms"] * 1e-3) / 1e9 if pu else None
     lat_ms = np.array(lat) * 1e3 if lat else np.array([np.nan])
 
@@ -536,7 +606,7 @@ def main():
             c2 = dict(cfg, metrics=mask)
             w2, k2, l2 = run_session(fcx, torch, c2, pool_dev, args.steps, args.warmup, lat_pushes=100)
             p2 = k2.get("pair_update", {})
-            a2 = fcx.pair_update_bytes(c2) / (p2["avg_ms"] * 1e-3) / 1e9 if p2 else None
+            a2 = algorithmic_bytes(fcx, c2) / (p2["avg_ms"] * 1e-3) / 1e9 if p2 else None
             sessions[name] = dict(value=P * B * args.steps / w2, ms_per_step=w2 * 1e3 / args.steps,
                                   p50_ms=float(np.percentile(np.array(l2) * 1e3, 50)),
                                   p99_ms=float(np.percentile(np.array(l2) * 1e3, 99)),
@@ -632,16 +702,16 @@ def main():
         xl, cl = synth.c5_multitaper(n_trials=16)
         pool_l = torch.from_numpy(xl).cuda()
         del xl
-        wl, kl, _ = run_session(fcx, torch, cl, pool_l, args.large_steps, 1)
+        wl, kl, _ = run_session(fcx, torch, cl, pool_l, args.large_steps, 1, resync_reps=args.resync_reps)
         Nl = cl["n_nodes"]
         Pl = Nl * (Nl - 1) // 2
         Bl = fcx.band_bins(cl)[0]
         pl = kl.get("pair_update", {})
-        gl = fcx.pair_update_bytes(cl) / (pl["avg_ms"] * 1e-3) / 1e9 if pl else None
+        gl = algorithmic_bytes(fcx, cl) / (pl["avg_ms"] * 1e-3) / 1e9 if pl else None
         large = dict(workload="N=10000 (50M pairs), DPSS NW=2 x 3 tapers, 4-40 Hz (37 bins), W=200 x 1000 "
                               "samples, all 8 metrics, one push per step",
                      value=Pl * Bl * args.large_steps / wl, ms_per_step=wl * 1e3 / args.large_steps,
-                     pair_update_avg_ms=pl.get("avg_ms"), pair_update_gbs=gl,
+                     pair_update_avg_ms=pl.get("avg_ms"), pair_update_gbs=gl, resync_ms=kl.get("resync_ms"),
                      hbm_frac=(gl / HBM_PEAK_GBS) if gl else None,
                      footprint_gb=fcx.footprint_bytes(cl) / 1e9)
         del pool_l
@@ -680,10 +750,13 @@ def main():
                    "n_nodes": N, "pairs": P, "bins": B, "window": cfg["window_trials"]},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "pushes": int(len(lat))},
-        "kernels": kt,
+        "kernels": {k: v for k, v in kt.items() if k != "resync_ms"},
+        "resync_ms": kt.get("resync_ms"),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(),
-                     "kernel": "pair_update", "algorithmic_bytes_per_launch": algo},
+                     "kernel": "pair_update", "algorithmic_bytes_per_launch": algo,
+                     "library_state_bytes_per_launch": impl,
+                     "library_state_gbs": (impl / (pu["avg_ms"] * 1e-3) / 1e9) if pu else None},
         "hbm_copy_probe": probe,
         "sessions": sessions,
         "batch": batch,

@@ -115,7 +115,10 @@ int64_t fcx_pair_update_bytes(const fcx_config *cfg);
 int32_t fcx_band_bins(const fcx_config *cfg, int32_t *k_lo, int32_t *k_hi);
 
 /*
- * Open a session on the current HIP device.  hip_stream is a hipStream_t to
+ * Open a session on the current HIP device (Sec. 2.4: the connectivity
+ * library's metric routines and the container of the resulting networks
+ * behind an API; Sec. 2.5: the connectivity plug-in's settings, the number of
+ * averaged trials W and the frequency band).  hip_stream is a hipStream_t to
  * order all the session's work on (NULL: the session creates its own).  The
  * library owns every device buffer it allocates here and frees them in
  * fcx_close.
@@ -124,8 +127,10 @@ int32_t fcx_band_bins(const fcx_config *cfg, int32_t *k_lo, int32_t *k_hi);
 fcx_status fcx_open(const fcx_config *cfg, void *hip_stream, fcx_session **out);
 
 /*
- * Push one trial x[N][M] (row stride ld >= M elements; float for ELEM_F32,
- * double for ELEM_F64).  x_on_device = 0: x is host memory, copied before
+ * Push one trial x[N][M] (Sec. 2.5: each trial the averaging plug-in cuts
+ * goes to the connectivity plug-in; SI-1 PSD/CSD: its spectra; Sec. 2.4: the
+ * sums over trials kept up to date, stored per-trial values reused) (row
+ * stride ld >= M elements; float for ELEM_F32, double for ELEM_F64).  x_on_device = 0: x is host memory, copied before
  * the call returns, so the caller may reuse it at once.  x_on_device = 1:
  * x is device memory that must stay valid until fcx_sync returns.
  * The push is stream-ordered and returns before the GPU work finishes.  It
@@ -138,22 +143,26 @@ fcx_status fcx_push_trial(fcx_session *s, const void *x, int64_t ld, int x_on_de
 
 /*
  * Replace the window with n_trials trials (trial k at x + k*trial_stride,
- * node rows ld apart), n_trials <= W, and compute the running sums in one
- * batch pass: dense Gram sums on the matrix cores in the session's
- * gram_precision, sign/|Im| sums on the vector units.  Inputs must be finite
+ * node rows ld apart), n_trials <= W, and compute its networks in one batch
+ * pass (SI-1 metric equations over a set of trials; Sec. 2.4: the metrics of
+ * all trials at once): Re of the cross-spectral Gram and the unit-phasor Gram
+ * on the matrix cores in the session's gram_precision, Im(X_i conj X_j) in
+ * FP64 with its sign, |Im|, Im^2 and Im sums on the vector units.  Inputs must be finite
  * (checked on the device; a non-finite batch leaves the session empty and
  * reports FCX_E_NONFINITE at the next sync).  Strides are in elements of
  * cfg.elem.  A device-resident batch (x_on_device = 1) is transformed in one
  * launch per kernel; host trials are uploaded one at a time.  The batch
  * writes the band-mean networks directly; the running sums (which the batch
- * pass uses as scratch) are rebuilt from the cached window by the next
- * sliding push, per-bin read or fcx_resync.
+ * pass uses as scratch) are rebuilt from the cached window, in one pass, by
+ * the next sliding push, per-bin read or fcx_resync.
  */
 fcx_status fcx_push_batch(fcx_session *s, const void *x, int64_t n_trials, int64_t trial_stride,
                           int64_t ld, int x_on_device);
 
 /*
- * Copy the current network of one metric into out (host or device memory).
+ * Copy the current network of one metric into out (host or device memory)
+ * (Sec. 2.4: the network container; Sec. 3.2: the frequency bins of an edge
+ * averaged).
  * per_bin = 0: band mean, out_len >= P.  per_bin = 1: [B][P], out_len >= B*P
  * (COR and XCOR are broadband and always [P]).  Element type follows
  * cfg.elem; XCOR is computed in FP32 (an FP32 FFT per pair) for both.
@@ -165,16 +174,22 @@ fcx_status fcx_push_batch(fcx_session *s, const void *x, int64_t n_trials, int64
 fcx_status fcx_read_network(fcx_session *s, uint32_t metric, void *out, int64_t out_len,
                             int out_on_device, int per_bin, int32_t *k_trials_out);
 
-/* Wait for the session's queued work. Returns FCX_E_NONFINITE once after a
- * rejected push. */
+/* Wait for the session's queued work (stream ordering; not a step of the
+ * paper's method).  Returns FCX_E_NONFINITE once after a rejected push. */
 fcx_status fcx_sync(fcx_session *s);
 
-/* Rebuild every running sum from the cached spectra of the window (batch
- * recompute); used after a precision change or to discard accumulated
- * rounding of a very long run. */
+/* Rebuild every running sum from the cached trials of the window in one
+ * pass (Sec. 2.4: the sums over the stored per-trial values): per pair and
+ * bin the K cached trials are added oldest first with the sliding update's
+ * own per-trial arithmetic, so the sums equal, bit for bit, those of pushing
+ * the window's trials into an empty session, and each state element is
+ * written once (XCOR's window sum is recomputed trial by trial).  Used after
+ * a batch pass and to discard the rounding a very long run accumulates.
+ * Synchronous.  Errors: FCX_E_CLOSED, FCX_E_DEVICE. */
 fcx_status fcx_resync(fcx_session *s);
 
-/* Release the session; the handle becomes invalid (FCX_E_CLOSED). */
+/* Release the session and every device buffer it owns; the handle becomes
+ * invalid (FCX_E_CLOSED afterwards).  Not a step of the paper's method. */
 fcx_status fcx_close(fcx_session *s);
 
 /* The hipStream_t the session orders its work on. */
@@ -205,6 +220,26 @@ const char *fcx_status_str(fcx_status st);
  * bandwidth.  Device pointers.
  */
 fcx_status fcx_probe_copy(void *dst, const void *src, int64_t n_bytes, void *hip_stream);
+
+/*
+ * Read-modify-write probe of the pair state layout of an FP32 all-8 session:
+ * buf (device, 41 * n_elems bytes) holds four FP64 planes, two int32 planes
+ * and one int8 plane of n_elems elements, in that order; every element of
+ * every plane is read, incremented and written once per call (non-temporal
+ * hint, as the pair update uses).  Enqueued on hip_stream; the caller times
+ * it.  Errors: FCX_E_INVAL, FCX_E_DEVICE.
+ */
+fcx_status fcx_probe_rmw(void *buf, int64_t n_elems, void *hip_stream);
+
+/*
+ * Matrix-core probe: 8192 wavefronts each run `iters` rounds of independent
+ * MFMA chains on register operands (kind 0: v_mfma_f32_16x16x4_f32, 8
+ * chains; 1: v_mfma_f32_32x32x2_f32, 4 chains; 2: v_mfma_f32_16x16x32_bf16,
+ * 8 chains) and write one float per lane to out (device, >= 524288 floats).
+ * *flops receives the floating-point operations of the call.  Enqueued on
+ * hip_stream; the caller times it.  Errors: FCX_E_INVAL, FCX_E_DEVICE.
+ */
+fcx_status fcx_probe_mfma(int32_t kind, int32_t iters, float *out, double *flops, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Network post-processing for display (results sections and the online

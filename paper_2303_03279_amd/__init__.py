@@ -132,6 +132,8 @@ _SIGS = {
     "fcx_dpss": (ctypes.c_int, [I32, D, I32, P, P]),
     "fcx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "fcx_probe_copy": (ctypes.c_int, [P, P, I64, P]),
+    "fcx_probe_rmw": (ctypes.c_int, [P, I64, P]),
+    "fcx_probe_mfma": (ctypes.c_int, [I32, I32, P, ctypes.POINTER(ctypes.c_double), P]),
     "fcx_network_select": (ctypes.c_int, [I32, P, D, P, P, P, P, ctypes.POINTER(fcx_select_info), P]),
     "fcx_fir_design": (ctypes.c_int, [I32, D, D, D, D, I32, P, I32, PI32]),
     "fcx_stream_open": (ctypes.c_int, [ctypes.POINTER(fcx_stream_config), P, PP]),

@@ -910,7 +910,7 @@ hipError_t launch_cor_batch(const SessDev<float> &s, int K, int prec, hipStream_
     // one resident workgroup per compute unit; with more tiles than that the
     // (tile, trial) units are shared out evenly and a tile cut between two
     // workgroups meets in the COR running-sum buffer, which a batch leaves
-    // stale (the replay of the window clears and rebuilds it): its first P
+    // stale (the rebuild of the window's sums rewrites it): its first P
     // doubles take the pair sums, the words after them one counter per tile
     int dev = 0, ncu = 0;
     hipError_t e = hipGetDevice(&dev);

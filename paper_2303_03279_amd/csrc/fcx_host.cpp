@@ -650,30 +650,38 @@ static fcx_status upload_host_trial(Session *s, const void *x, int64_t ld)
     return FCX_OK;
 }
 
-// Rebuild every running sum from the cached window: zero them, then add the
-// K cached trials oldest first through the same kernels, driven by a private
-// control block (no eviction, no new spectra).
-template <typename T> static fcx_status replay_window(Session *s, long long pushed)
+// Rebuild every running sum from the cached window in one pass per kernel
+// (power sums; pair planes, COR sums and networks), the trials added oldest
+// first with the sliding update's own per-trial terms.  XCOR keeps its
+// per-trial path: its window sum is zeroed and each cached trial's maxima are
+// recomputed and added, driven by a private control block.
+template <typename T> static fcx_status rebuild_window(Session *s, long long pushed)
 {
     const Geometry &g = s->g;
     const BufferPlan &p = s->plan;
     const long long K = pushed < g.W ? pushed : g.W;
-    if (p.psd) HIP_OK(hipMemsetAsync(s->psd, 0, p.psd, s->stream));
-    for (int i = 0; i < NPLANES; ++i)
-        if (s->plane[i])
-            HIP_OK(hipMemsetAsync(s->plane[i], 0, (i == P_URE || i == P_UIM) ? p.uplane : p.plane, s->stream));
-    if (s->gsum) HIP_OK(hipMemsetAsync(s->gsum, 0, p.gsum, s->stream));
-    if (s->rsum) HIP_OK(hipMemsetAsync(s->rsum, 0, p.rsum, s->stream));
-    if (s->xsum) HIP_OK(hipMemsetAsync(s->xsum, 0, p.xsum, s->stream));
+    const long long first = pushed - K;
     SessDev<T> d = session_dev<T>(s, nullptr, 0);
-    d.ctl = s->ctl + 1;
-    d.kbase = pushed - K;
     const bool spectral = (s->cfg.metrics & 0x7Fu) != 0;
-    for (long long t = pushed - K; t < pushed; ++t) {
-        HIP_OK(launch_set_ctl(d.ctl, t, s->stream));
-        if (spectral) HIP_OK(launch_psd<T>(d, s->stream));
-        if (s->cfg.metrics & (0x7Fu | M_COR)) HIP_OK(launch_pair_update<T>(d, s->stream));
-        if (s->cfg.metrics & M_XCOR) HIP_OK(launch_xcor<T>(d, s->stream));
+    if (K == 0) {   // an empty window: every sum is zero
+        if (p.psd) HIP_OK(hipMemsetAsync(s->psd, 0, p.psd, s->stream));
+        for (int i = 0; i < NPLANES; ++i)
+            if (s->plane[i])
+                HIP_OK(hipMemsetAsync(s->plane[i], 0, (i == P_URE || i == P_UIM) ? p.uplane : p.plane, s->stream));
+        if (s->gsum) HIP_OK(hipMemsetAsync(s->gsum, 0, p.gsum, s->stream));
+        if (s->rsum) HIP_OK(hipMemsetAsync(s->rsum, 0, p.rsum, s->stream));
+    } else {
+        if (spectral) HIP_OK(launch_psd_rebuild<T>(d, first, (int)K, s->stream));
+        if (s->cfg.metrics & (0x7Fu | M_COR)) HIP_OK(launch_pair_rebuild<T>(d, first, (int)K, s->stream));
+    }
+    if (s->xsum) {
+        HIP_OK(hipMemsetAsync(s->xsum, 0, p.xsum, s->stream));
+        d.ctl = s->ctl + 1;
+        d.kbase = first;
+        for (long long t = first; t < pushed; ++t) {
+            HIP_OK(launch_set_ctl(d.ctl, t, s->stream));
+            HIP_OK(launch_xcor<T>(d, s->stream));
+        }
     }
     HIP_OK(hipStreamSynchronize(s->stream));
     return FCX_OK;
@@ -693,7 +701,7 @@ static fcx_status rebuild_sums(Session *s)
     DevCtl c;
     fcx_status st = read_ctl(s, &c);
     if (st != FCX_OK) return st;
-    st = s->g.f64 ? replay_window<double>(s, c.pushed) : replay_window<float>(s, c.pushed);
+    st = s->g.f64 ? rebuild_window<double>(s, c.pushed) : rebuild_window<float>(s, c.pushed);
     if (st == FCX_OK) s->stale = false;
     return st;
 }
@@ -879,7 +887,7 @@ fcx_status fcx_push_batch(fcx_session *h, const void *x, int64_t n_trials, int64
     // pass with the Gram sums on the matrix cores
     SessDev<float> d = session_dev<float>(s, nullptr, 0);
     const bool spectral = (s->cfg.metrics & 0x7Fu) != 0, cor = (s->cfg.metrics & M_COR) != 0;
-    const bool zneed = (s->cfg.metrics & (M_COR | M_XCOR)) != 0;   // XCOR comes from the replay
+    const bool zneed = (s->cfg.metrics & (M_COR | M_XCOR)) != 0;   // XCOR comes from the rebuild
     if (x_on_device && n_trials <= 65535) {
         // every trial is already in device memory: one launch each for the
         // spectra and the z-scored samples of all of them (trial k -> slot k)
@@ -952,7 +960,7 @@ fcx_status fcx_read_network(fcx_session *h, uint32_t metric, void *out, int64_t 
     while (!((metric >> mi) & 1u)) ++mi;
     const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (!bins) {
-        // XCOR is not part of the batch pass: its window sum comes from the replay
+        // XCOR is not part of the batch pass: its window sum comes from the rebuild
         if (metric == M_XCOR && s->stale && (st = rebuild_sums(s)) != FCX_OK) return st;
         const char *src = (const char *)s->out + (size_t)mi * g.P * g.esz;
         HIP_OK(hipMemcpy(out, src, g.P * g.esz, kind));
@@ -1062,6 +1070,19 @@ fcx_status fcx_probe_copy(void *dst, const void *src, int64_t n_bytes, void *hip
 {
     if (!dst || !src || n_bytes <= 0 || (n_bytes % 16)) return FCX_E_INVAL;
     return launch_copy_probe(dst, src, n_bytes, (hipStream_t)hip_stream) == hipSuccess ? FCX_OK : FCX_E_DEVICE;
+}
+
+fcx_status fcx_probe_rmw(void *buf, int64_t n_elems, void *hip_stream)
+{
+    if (!buf || n_elems <= 0) return FCX_E_INVAL;
+    return launch_rmw_probe(buf, n_elems, (hipStream_t)hip_stream) == hipSuccess ? FCX_OK : FCX_E_DEVICE;
+}
+
+fcx_status fcx_probe_mfma(int32_t kind, int32_t iters, float *out, double *flops, void *hip_stream)
+{
+    if (kind < 0 || kind > 2 || iters <= 0 || !out || !flops) return FCX_E_INVAL;
+    return launch_mfma_probe(kind, iters, out, flops, (hipStream_t)hip_stream) == hipSuccess ? FCX_OK
+                                                                                            : FCX_E_DEVICE;
 }
 
 }  // extern "C"

@@ -101,6 +101,11 @@ template <typename T> hipError_t launch_spectra(const SessDev<T> &s, hipStream_t
 template <typename T> hipError_t launch_psd(const SessDev<T> &s, hipStream_t st);
 template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStream_t st);
 template <typename T> hipError_t launch_znorm(const SessDev<T> &s, hipStream_t st);
+// the running sums (pair planes, COR sums, networks; power sums) of the K
+// cached trials first .. first + K - 1 rebuilt in one pass, bit for bit the
+// sums a replay of those pushes from zero gives
+template <typename T> hipError_t launch_pair_rebuild(const SessDev<T> &s, long long first, int K, hipStream_t st);
+template <typename T> hipError_t launch_psd_rebuild(const SessDev<T> &s, long long first, int K, hipStream_t st);
 // trials k = 0..K-1 of a device-resident batch (at x + k * stride elements)
 // into ring slot k
 template <typename T> hipError_t launch_spectra_batch(const SessDev<T> &s, int K, long long stride, hipStream_t st);
@@ -110,6 +115,8 @@ hipError_t launch_set_ctl(DevCtl *ctl, long long pushed, hipStream_t st);
 template <typename T>
 hipError_t launch_finalize_bins(const SessDev<T> &s, uint32_t metric, T *out, hipStream_t st);
 hipError_t launch_copy_probe(void *dst, const void *src, int64_t n_bytes, hipStream_t st);
+hipError_t launch_rmw_probe(void *buf, int64_t n_elems, hipStream_t st);
+hipError_t launch_mfma_probe(int kind, int iters, float *out, double *flops, hipStream_t st);
 
 // batch (window recompute) path, float sessions (fcx_batch.hip)
 hipError_t launch_set_pushed(DevCtl *ctl, long long pushed, hipStream_t st);

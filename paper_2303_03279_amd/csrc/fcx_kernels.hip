@@ -405,6 +405,95 @@ struct PairState {
     int uqr, uqi, g;
 };
 
+// ---- one trial's terms: shared by the sliding update and the rebuild, so
+// ---- that a trial removed later cancels the bits it added
+//
+// Unit phasor X / |X| (0 for X = 0) of a staged spectrum value; the
+// magnitude is formed in FP64 so that tiny amplitudes cannot underflow.
+template <typename T> __device__ __forceinline__ typename V2<T>::t unit_phasor(typename V2<T>::t x)
+{
+    typename V2<T>::t u;
+    const double m2 = (double)x.x * x.x + (double)x.y * x.y;
+    const double r = m2 > 0.0 ? rsqrt(m2) : 0.0;
+    u.x = (T)(x.x * r);
+    u.y = (T)(x.y * r);
+    return u;
+}
+
+// The trial's CSD X_i conj(X_j) (taper-combined) of row node r and column
+// node c from staged values: taper l of node n at X[l * PAIR_NODES + n] (the
+// columns after the SLICE_ROWS rows).  FP32 operands give exact FP64 products.
+template <typename T>
+__device__ __forceinline__ void trial_csd(const typename V2<T>::t *X, int r, int c, int L, const double *lamw,
+                                          double &cr, double &ci)
+{
+    cr = 0.0;
+    ci = 0.0;
+    for (int l = 0; l < L; ++l) {
+        const typename V2<T>::t a = X[(size_t)l * PAIR_NODES + r], b = X[(size_t)l * PAIR_NODES + SLICE_ROWS + c];
+        const double re = (double)a.x * b.x + (double)a.y * b.y;
+        const double im = (double)a.y * b.x - (double)a.x * b.y;
+        if (L == 1) {
+            cr = re;
+            ci = im;
+        } else {
+            cr += lamw[l] * re;
+            ci += lamw[l] * im;
+        }
+    }
+}
+
+// The trial's unit-phasor product: single taper from the staged phasors
+// U[n] (in the session's precision), several tapers the unit phasor of the
+// taper-combined CSD
+template <typename T>
+__device__ __forceinline__ void trial_uprod(const typename V2<T>::t *U, int r, int c, int L, double cr, double ci,
+                                            double &ur, double &ui)
+{
+    if (L == 1) {
+        const typename V2<T>::t a = U[r], b = U[SLICE_ROWS + c];
+        const T nr = a.x * b.x + a.y * b.y, ni = a.y * b.x - a.x * b.y;
+        ur = nr;
+        ui = ni;
+    } else {
+        const double m2 = cr * cr + ci * ci;
+        const double rm = m2 > 0.0 ? rsqrt_t<T>(m2) : 0.0;
+        ur = cr * rm;
+        ui = ci * rm;
+    }
+}
+
+// a phasor component as the fixed-point integer of the sums: u * 2^k is exact
+// in FP32, so the integer of an evicted trial equals the one it added
+__device__ __forceinline__ int ufix_of(double u, float uscale) { return (int)rintf((float)u * uscale); }
+
+// The seven spectral metrics of one (pair, bin) from its sums, added to the
+// band sums acc[7] (metric order COH IMCOH PLV PLI WPLI USPLI DSWPLI).
+// srij = 1/sqrt(P_i P_j); ur, ui the phasor sums as values.
+template <typename T>
+__device__ __forceinline__ void bin_metrics(uint32_t mm, const PairState &st, double srij, T ur, T ui, int K,
+                                            T (&acc)[7])
+{
+    const T Kt = (T)K;
+    const T invK = (T)(1.0 / (double)K);
+    const T invKm1 = K >= 2 ? (T)(1.0 / (double)(K - 1)) : (T)0;
+    if (mm & (M_COH | M_IMCOH)) {
+        if (mm & M_COH) acc[0] += sqrt_ratio<T>((st.sre * st.sre + st.sim * st.sim) * srij * srij);
+        if (mm & M_IMCOH) acc[1] += (T)(st.sim * srij);
+    }
+    if (mm & M_PLV) acc[2] += sqrt_t<T>(ur * ur + ui * ui) * invK;   // |U| <= K: safe in the session's precision
+    if (mm & (M_PLI | M_USPLI)) {
+        const T pli = (T)abs(st.g) * invK;
+        if (mm & M_PLI) acc[3] += pli;
+        if (mm & M_USPLI) acc[5] += K >= 2 ? (Kt * pli * pli - (T)1) * invKm1 : (T)NAN;
+    }
+    if (mm & M_WPLI) acc[4] += st.a > 0.0 ? ratio_t<T>(fabs(st.sim), st.a) : (T)0;
+    if (mm & M_DSWPLI) {
+        const double dd = st.a * st.a - st.q;
+        acc[6] += K >= 2 ? (dd != 0.0 ? ratio_t<T>(st.sim * st.sim - st.q, dd) : (T)0) : (T)NAN;
+    }
+}
+
 // SPEC != 0 fixes the spectral metric set at compile time (the branches on
 // it fold away); LT != 0 fixes the taper count; COR = 1 / 0 compiles the COR
 // part in / out (-1: decided by the session's metric bits).  SPEC = 0, LT = 0,
@@ -454,9 +543,6 @@ __device__ __forceinline__ void pair_slice_body(const SessDev<T> &s, const PushV
     const Rsrc rQ = plane_rsrc(needQ, s.plane[P_Q], 8);
     const Rsrc rG = plane_rsrc(needG, s.gsum, gsz);
 
-    const T Kt = (T)K;
-    const T invK = (T)(1.0 / (double)K);
-    const T invKm1 = K >= 2 ? (T)(1.0 / (double)(K - 1)) : (T)0;
     const T uinvT = (T)uinv;
     const size_t P = (size_t)N * (N - 1) / 2;
 
@@ -506,19 +592,8 @@ __device__ __forceinline__ void pair_slice_body(const SessDev<T> &s, const PushV
             Xn[(size_t)bl * PAIR_NODES + nl] = xn;
             Xo[(size_t)bl * PAIR_NODES + nl] = xo;
             if (stageU) {
-                // unit phasor X / |X| (0 for X = 0); the magnitude is formed
-                // in FP64 so that tiny amplitudes cannot underflow
-                T2 un, uo;
-                const double m2n = (double)xn.x * xn.x + (double)xn.y * xn.y;
-                const double m2o = (double)xo.x * xo.x + (double)xo.y * xo.y;
-                const double rn = m2n > 0.0 ? rsqrt(m2n) : 0.0;
-                const double ro = m2o > 0.0 ? rsqrt(m2o) : 0.0;
-                un.x = (T)(xn.x * rn);
-                un.y = (T)(xn.y * rn);
-                uo.x = (T)(xo.x * ro);
-                uo.y = (T)(xo.y * ro);
-                Un[(size_t)bb * PAIR_NODES + nl] = un;
-                Uo[(size_t)bb * PAIR_NODES + nl] = uo;
+                Un[(size_t)bb * PAIR_NODES + nl] = unit_phasor<T>(xn);
+                Uo[(size_t)bb * PAIR_NODES + nl] = unit_phasor<T>(xo);
             }
         }
         if (mm & (M_COH | M_IMCOH)) {
@@ -553,33 +628,9 @@ __device__ __forceinline__ void pair_slice_body(const SessDev<T> &s, const PushV
             // state, store them, add the bin's metrics to the band sums
             auto bin_step = [&](int bb, PairState st) {
                 const uint32_t e = e0 + (uint32_t)bb * TILE_PAIRS;
-                double cnr = 0.0, cni = 0.0, cor_ = 0.0, coi = 0.0;
-                for (int l = 0; l < L; ++l) {
-                    const size_t ob = (size_t)(bb * L + l) * PAIR_NODES;
-                    const T2 a = Xn[ob + r], bx = Xn[ob + SLICE_ROWS + c];
-                    // X_i conj(X_j): FP32 operands give exact FP64 products
-                    double re = (double)a.x * bx.x + (double)a.y * bx.y;
-                    double im = (double)a.y * bx.x - (double)a.x * bx.y;
-                    if (L == 1) {
-                        cnr = re;
-                        cni = im;
-                    } else {
-                        cnr += s.lamw[l] * re;
-                        cni += s.lamw[l] * im;
-                    }
-                    if (has_old) {
-                        const T2 ao = Xo[ob + r], bo = Xo[ob + SLICE_ROWS + c];
-                        re = (double)ao.x * bo.x + (double)ao.y * bo.y;
-                        im = (double)ao.y * bo.x - (double)ao.x * bo.y;
-                        if (L == 1) {
-                            cor_ = re;
-                            coi = im;
-                        } else {
-                            cor_ += s.lamw[l] * re;
-                            coi += s.lamw[l] * im;
-                        }
-                    }
-                }
+                double cnr, cni, cor_ = 0.0, coi = 0.0;
+                trial_csd<T>(Xn + (size_t)bb * L * PAIR_NODES, r, c, L, s.lamw, cnr, cni);
+                if (has_old) trial_csd<T>(Xo + (size_t)bb * L * PAIR_NODES, r, c, L, s.lamw, cor_, coi);
                 if (needSre) {
                     st.sre = st.sre + cnr;
                     if (has_old) st.sre = st.sre - cor_;
@@ -590,45 +641,16 @@ __device__ __forceinline__ void pair_slice_body(const SessDev<T> &s, const PushV
                     if (has_old) st.sim = st.sim - coi;
                     buf_st_f64(rSim, e * 8u, st.sim);
                 }
-                double ure = 0.0, uim = 0.0;
                 if (needU) {
                     double unr, uni, uor = 0.0, uoi = 0.0;
-                    if (L == 1) {
-                        const T2 ui = Un[(size_t)bb * PAIR_NODES + r];
-                        const T2 uj = Un[(size_t)bb * PAIR_NODES + SLICE_ROWS + c];
-                        const T nr = ui.x * uj.x + ui.y * uj.y, ni = ui.y * uj.x - ui.x * uj.y;
-                        T orr = 0, oi = 0;
-                        if (has_old) {
-                            const T2 vi = Uo[(size_t)bb * PAIR_NODES + r];
-                            const T2 vj = Uo[(size_t)bb * PAIR_NODES + SLICE_ROWS + c];
-                            orr = vi.x * vj.x + vi.y * vj.y;
-                            oi = vi.y * vj.x - vi.x * vj.y;
-                        }
-                        unr = nr;
-                        uni = ni;
-                        uor = orr;
-                        uoi = oi;
-                    } else {
-                        // unit phasor of the taper-combined CSD (0 for 0)
-                        const double m2n = cnr * cnr + cni * cni;
-                        const double rn = m2n > 0.0 ? rsqrt_t<T>(m2n) : 0.0;
-                        unr = cnr * rn;
-                        uni = cni * rn;
-                        if (has_old) {
-                            const double m2o = cor_ * cor_ + coi * coi;
-                            const double ro = m2o > 0.0 ? rsqrt_t<T>(m2o) : 0.0;
-                            uor = cor_ * ro;
-                            uoi = coi * ro;
-                        }
-                    }
+                    trial_uprod<T>(Un + (size_t)bb * PAIR_NODES, r, c, L, cnr, cni, unr, uni);
+                    if (has_old) trial_uprod<T>(Uo + (size_t)bb * PAIR_NODES, r, c, L, cor_, coi, uor, uoi);
                     if (ufix) {
-                        // u * 2^k is exact in FP32; the rounded integer of
-                        // the evicted trial equals the one it added
-                        st.uqr += (int)rintf((float)unr * uscale);
-                        st.uqi += (int)rintf((float)uni * uscale);
+                        st.uqr += ufix_of(unr, uscale);
+                        st.uqi += ufix_of(uni, uscale);
                         if (has_old) {
-                            st.uqr -= (int)rintf((float)uor * uscale);
-                            st.uqi -= (int)rintf((float)uoi * uscale);
+                            st.uqr -= ufix_of(uor, uscale);
+                            st.uqi -= ufix_of(uoi, uscale);
                         }
                         buf_st_i32(rUre, e * 4u, st.uqr);
                         buf_st_i32(rUim, e * 4u, st.uqi);
@@ -641,8 +663,6 @@ __device__ __forceinline__ void pair_slice_body(const SessDev<T> &s, const PushV
                         }
                         buf_st_f64(rUre, e * 8u, st.ure);
                         buf_st_f64(rUim, e * 8u, st.uim);
-                        ure = st.ure;
-                        uim = st.uim;
                     }
                 }
                 if (needG) {
@@ -664,27 +684,11 @@ __device__ __forceinline__ void pair_slice_body(const SessDev<T> &s, const PushV
                     buf_st_f64(rQ, e * 8u, st.q);
                 }
                 // metrics of this bin, into the band mean
-                if (mm & (M_COH | M_IMCOH)) {
-                    const double srij = SR[bb * PAIR_NODES + r] * SR[bb * PAIR_NODES + SLICE_ROWS + c];
-                    if (mm & M_COH) acc[0] += sqrt_ratio<T>((st.sre * st.sre + st.sim * st.sim) * srij * srij);
-                    if (mm & M_IMCOH) acc[1] += (T)(st.sim * srij);
-                }
-                if (mm & M_PLV) {
-                    // |U| <= K: safe in the session's precision
-                    const T ur = ufix ? (T)st.uqr * uinvT : (T)ure;
-                    const T ui = ufix ? (T)st.uqi * uinvT : (T)uim;
-                    acc[2] += sqrt_t<T>(ur * ur + ui * ui) * invK;
-                }
-                if (mm & (M_PLI | M_USPLI)) {
-                    const T pli = (T)abs(st.g) * invK;
-                    if (mm & M_PLI) acc[3] += pli;
-                    if (mm & M_USPLI) acc[5] += K >= 2 ? (Kt * pli * pli - (T)1) * invKm1 : (T)NAN;
-                }
-                if (mm & M_WPLI) acc[4] += st.a > 0.0 ? ratio_t<T>(fabs(st.sim), st.a) : (T)0;
-                if (mm & M_DSWPLI) {
-                    const double dd = st.a * st.a - st.q;
-                    acc[6] += K >= 2 ? (dd != 0.0 ? ratio_t<T>(st.sim * st.sim - st.q, dd) : (T)0) : (T)NAN;
-                }
+                const double srij = (mm & (M_COH | M_IMCOH))
+                                        ? SR[bb * PAIR_NODES + r] * SR[bb * PAIR_NODES + SLICE_ROWS + c] : 0.0;
+                const T ur = ufix ? (T)st.uqr * uinvT : (T)st.ure;
+                const T ui = ufix ? (T)st.uqi * uinvT : (T)st.uim;
+                bin_metrics<T>(mm, st, srij, ur, ui, K, acc);
             };
             constexpr int BIN_GROUP = bin_group<T, LT, COR>();
             if constexpr (BIN_GROUP <= 1) {
@@ -824,6 +828,262 @@ template <typename T> hipError_t launch_pair_update(const SessDev<T> &s, hipStre
             hipLaunchKernelGGL((k_pair_update<T, 0u, 0, 1, -1>), grid, blk, lds, st, s, CB);
         else
             hipLaunchKernelGGL((k_pair_update<T, 0u, 0, 0, -1>), grid, blk, lds, st, s, CB);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// rebuild: every running sum of the window recomputed from the cached trials
+// in one pass (after a batch pass, or on request), instead of replaying the
+// window push by push.  Per (pair, bin) the K cached trials are added oldest
+// first with the same per-trial terms as the sliding update (trial_csd,
+// trial_uprod, ufix_of, the same FP64 additions), so the sums are bit for bit
+// those a replay from zero gives, and a trial evicted later cancels exactly
+// what it added.  Each state element is written once; the trials' spectra
+// stream through LDS TT at a time, one bin after the other.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_psd_rebuild(SessDev<T> s, long long first, int K)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= s.B * s.N) return;
+    const int b = e / s.N, i = e % s.N;
+    double v = 0.0;
+    for (int t = 0; t < K; ++t) v = v + trial_psd(s, (int)((first + t) % (long long)(s.W + 1)), b, i);
+    s.psd[e] = v;
+}
+
+template <typename T> hipError_t launch_psd_rebuild(const SessDev<T> &s, long long first, int K, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_psd_rebuild<T>, dim3((s.B * s.N + 255) / 256), dim3(256), 0, st, s, first, K);
+    return hipGetLastError();
+}
+
+// the COR sums of a slice: per trial the same 16x16 MFMA chain over the
+// z-scored samples as cor_block (steps in order, components x, y, z, w),
+// each trial's block added to the FP64 sums in trial order
+template <typename T>
+__device__ __forceinline__ void cor_rebuild(const SessDev<T> &s, long long first, int K, int tile, int sub, int J0,
+                                            int R0, int w)
+{
+    const int N = s.N, Mz = s.Mz;
+    const int C0 = J0 + 16 * w;
+    if (R0 >= N || C0 >= N || R0 >= C0 + 15) return;
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int row = R0 + lr, col = C0 + lr;
+    const bool rv = row < N, cv = col < N;
+    const int steps = Mz / 16;
+    double R[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < K; ++t) {
+        const int slot = (int)((first + t) % (long long)(s.W + 1));
+        const float4 *rn = (const float4 *)(s.zring + ((size_t)slot * N + (rv ? row : 0)) * Mz) + lg;
+        const float4 *cn = (const float4 *)(s.zring + ((size_t)slot * N + (cv ? col : 0)) * Mz) + lg;
+        floatx4 an = {0.f, 0.f, 0.f, 0.f};
+        float4 a[COR_DEPTH], b[COR_DEPTH];
+#pragma unroll
+        for (int d = 0; d < COR_DEPTH; ++d) {
+            const int o = 4 * min(d, steps - 1);
+            a[d] = rn[o];
+            b[d] = cn[o];
+        }
+        for (int st = 0; st < steps; st += COR_DEPTH) {
+#pragma unroll
+            for (int d = 0; d < COR_DEPTH; ++d) {
+                if (st + d >= steps) break;
+                const float4 x = a[d], y = b[d];
+                const int o = 4 * min(st + d + COR_DEPTH, steps - 1);
+                a[d] = rn[o];
+                b[d] = cn[o];
+                an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, y.x, an, 0, 0, 0);
+                an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, y.y, an, 0, 0, 0);
+                an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, y.z, an, 0, 0, 0);
+                an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, y.w, an, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) R[k] = R[k] + (double)an[k];
+    }
+    const size_t P = (size_t)N * (N - 1) / 2;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int ri = 16 * sub + 4 * lg + k, cj = 16 * w + lr;
+        const int i = R0 + 4 * lg + k, j = C0 + lr;
+        if (!(i < j && j < N)) continue;
+        s.rsum[(size_t)tile * TILE_PAIRS + (size_t)ri * TILE + cj] = R[k];
+        const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+        s.out[7 * P + idx] = (T)(R[k] / (double)K);
+    }
+}
+
+// LDS of the rebuild: TT trials x L tapers of the 80 staged nodes, their
+// unit phasors (single taper with PLV), 1/sqrt(P) of the nodes
+__host__ __device__ static int rebuild_trial_bytes(int L, int elem_bytes, uint32_t metrics)
+{
+    return PAIR_NODES * 2 * elem_bytes * (L + ((L == 1 && (metrics & M_PLV)) ? 1 : 0));
+}
+
+template <typename T, uint32_t SPEC, int LT, int COR, int UG>
+__global__ __launch_bounds__(PAIR_THREADS) void k_pair_rebuild(SessDev<T> s, long long first, int K, int TT)
+{
+    extern __shared__ __align__(16) char lds[];
+    typedef typename V2<T>::t T2;
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    const int tile = item / SLICES, sub = item % SLICES;
+    const int2 tt2 = s.tiles[tile];
+    const int N = s.N, B = s.B, L = LT ? LT : s.L;
+    const int J0 = tt2.y * TILE, R0 = tt2.x * TILE + SLICE_ROWS * sub;
+    if (R0 >= N || R0 >= min(J0 + TILE - 1, N - 1)) return;   // no pair i < j < N in this slice
+    const int tid = threadIdx.x, c = tid & (TILE - 1), w = tid >> 6;
+    const uint32_t mm = SPEC ? SPEC : (s.metrics & 0x7Fu);
+    const bool needSre = mm & M_COH;
+    const bool needSim = mm & (M_COH | M_IMCOH | M_WPLI | M_DSWPLI);
+    const bool needU = mm & M_PLV;
+    const bool needG = mm & (M_PLI | M_USPLI);
+    const bool needA = mm & (M_WPLI | M_DSWPLI);
+    const bool needQ = mm & M_DSWPLI;
+    const bool ufix = UG >= 0 ? (UG & 1) != 0 : s.u_fixed != 0;
+    const bool g8 = UG >= 0 ? (UG & 2) != 0 : s.g_narrow != 0;
+    const float uscale = ldexpf(1.0f, s.ufix_bits);
+    const T uinvT = (T)ldexp(1.0, -s.ufix_bits);
+    const bool with_cor = COR > 0 || (COR < 0 && (s.metrics & M_COR));
+    const bool stageU = L == 1 && needU;
+    const T2 *ring = (const T2 *)s.ring;
+    const size_t P = (size_t)N * (N - 1) / 2;
+    if (mm) {
+        T2 *X = (T2 *)lds;                                  // [TT][L][PAIR_NODES]
+        T2 *U = X + (size_t)TT * L * PAIR_NODES;            // [TT][PAIR_NODES]
+        double *SR = (double *)(U + (stageU ? (size_t)TT * PAIR_NODES : 0));
+        T acc[4][7];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < 7; ++m) acc[q][m] = (T)0;
+        for (int b = 0; b < B; ++b) {
+            PairState st[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                st[q].sre = st[q].sim = st[q].ure = st[q].uim = st[q].a = st[q].q = 0.0;
+                st[q].uqr = st[q].uqi = st[q].g = 0;
+            }
+            for (int t0 = 0; t0 < K; t0 += TT) {
+                const int nt = min(TT, K - t0);
+                __syncthreads();
+                for (int e = tid; e < nt * L * PAIR_NODES; e += PAIR_THREADS) {
+                    const int nl = e % PAIR_NODES, tl = e / PAIR_NODES;
+                    const int l = tl % L, t = tl / L;
+                    const int node = nl < SLICE_ROWS ? R0 + nl : J0 + nl - SLICE_ROWS;
+                    const long long slot = (first + t0 + t) % (long long)(s.W + 1);
+                    T2 x;
+                    x.x = x.y = 0;
+                    if (node < N) x = ring[(((size_t)slot * B + b) * L + l) * N + node];
+                    X[(size_t)tl * PAIR_NODES + nl] = x;
+                    if (stageU) U[(size_t)t * PAIR_NODES + nl] = unit_phasor<T>(x);
+                }
+                if (t0 == 0 && (mm & (M_COH | M_IMCOH))) {
+                    for (int nl = tid; nl < PAIR_NODES; nl += PAIR_THREADS) {
+                        const int node = nl < SLICE_ROWS ? R0 + nl : J0 + nl - SLICE_ROWS;
+                        double sr = 0.0;
+                        if (node < N) {
+                            const double p = s.psd[(size_t)b * N + node];
+                            sr = p > 0.0 ? rsqrt(p) : 0.0;
+                        }
+                        SR[nl] = sr;
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = 4 * q + w, i = R0 + r, j = J0 + c;
+                    if (!(i < j && j < N)) continue;
+                    PairState &z = st[q];
+                    for (int t = 0; t < nt; ++t) {
+                        double cnr, cni;
+                        trial_csd<T>(X + (size_t)t * L * PAIR_NODES, r, c, L, s.lamw, cnr, cni);
+                        if (needSre) z.sre = z.sre + cnr;
+                        if (needSim) z.sim = z.sim + cni;
+                        if (needU) {
+                            double unr, uni;
+                            trial_uprod<T>(U + (size_t)t * PAIR_NODES, r, c, L, cnr, cni, unr, uni);
+                            if (ufix) {
+                                z.uqr += ufix_of(unr, uscale);
+                                z.uqi += ufix_of(uni, uscale);
+                            } else {
+                                z.ure = z.ure + unr;
+                                z.uim = z.uim + uni;
+                            }
+                        }
+                        if (needG) z.g = z.g + sgn_of(cni);
+                        if (needA) z.a = z.a + fabs(cni);
+                        if (needQ) z.q = z.q + cni * cni;
+                    }
+                }
+            }
+            // the bin's sums, written once, and its metrics into the band means
+            const size_t tb = ((size_t)tile * B + b) * TILE_PAIRS;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = 4 * q + w, i = R0 + r, j = J0 + c;
+                if (!(i < j && j < N)) continue;
+                const size_t e = tb + (size_t)(SLICE_ROWS * sub + r) * TILE + c;
+                const PairState &z = st[q];
+                if (needSre) ((double *)s.plane[P_SRE])[e] = z.sre;
+                if (needSim) ((double *)s.plane[P_SIM])[e] = z.sim;
+                if (needU) {
+                    if (ufix) {
+                        ((int *)s.plane[P_URE])[e] = z.uqr;
+                        ((int *)s.plane[P_UIM])[e] = z.uqi;
+                    } else {
+                        ((double *)s.plane[P_URE])[e] = z.ure;
+                        ((double *)s.plane[P_UIM])[e] = z.uim;
+                    }
+                }
+                if (needG) {
+                    if (g8)
+                        ((signed char *)s.gsum)[e] = (signed char)z.g;
+                    else
+                        ((short *)s.gsum)[e] = (short)z.g;
+                }
+                if (needA) ((double *)s.plane[P_A])[e] = z.a;
+                if (needQ) ((double *)s.plane[P_Q])[e] = z.q;
+                const double srij = (mm & (M_COH | M_IMCOH)) ? SR[r] * SR[SLICE_ROWS + c] : 0.0;
+                const T ur = ufix ? (T)z.uqr * uinvT : (T)z.ure;
+                const T ui = ufix ? (T)z.uqi * uinvT : (T)z.uim;
+                bin_metrics<T>(mm, z, srij, ur, ui, K, acc[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 4 * q + w, i = R0 + r, j = J0 + c;
+            if (!(i < j && j < N)) continue;
+            const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+#pragma unroll
+            for (int m = 0; m < 7; ++m)
+                if (mm & (1u << m)) s.out[(size_t)m * P + idx] = acc[q][m] / (T)B;
+        }
+    }
+    if (with_cor) cor_rebuild(s, first, K, tile, sub, J0, R0, w);
+}
+
+template <typename T> hipError_t launch_pair_rebuild(const SessDev<T> &s, long long first, int K, hipStream_t st)
+{
+    if (K <= 0) return hipSuccess;
+    const uint32_t spec = s.metrics & 0x7Fu;
+    const int per = rebuild_trial_bytes(s.L, (int)sizeof(T), spec);
+    int TT = (PAIR_LDS_BYTES - PAIR_NODES * 8) / per;
+    TT = TT < 1 ? 1 : (TT > K ? K : TT);
+    const size_t lds = spec ? (size_t)TT * per + PAIR_NODES * 8 : 0;
+    const dim3 grid(s.ntiles * SLICES), blk(PAIR_THREADS);
+    if constexpr (sizeof(T) == 4) {
+        dispatch_pair_class(pair_kernel_class(s), [&](auto v) {
+            using V = decltype(v);
+            hipLaunchKernelGGL((k_pair_rebuild<float, V::spec, V::lt, V::cor, V::ug>), grid, blk, lds, st, s,
+                               first, K, TT);
+        });
+    } else {
+        if (s.metrics & M_COR)
+            hipLaunchKernelGGL((k_pair_rebuild<T, 0u, 0, 1, -1>), grid, blk, lds, st, s, first, K, TT);
+        else
+            hipLaunchKernelGGL((k_pair_rebuild<T, 0u, 0, 0, -1>), grid, blk, lds, st, s, first, K, TT);
     }
     return hipGetLastError();
 }
@@ -1061,11 +1321,122 @@ hipError_t launch_copy_probe(void *dst, const void *src, int64_t n_bytes, hipStr
     return hipGetLastError();
 }
 
+// Read-modify-write probe of the pair state layout of an FP32 all-8 session:
+// per element four FP64 planes, two int32 planes and one int8 plane (41
+// bytes), each element of each plane read and written once per launch, with
+// the non-temporal hint the pair update uses on its planes.  It bounds what
+// streaming the state alone can reach on this device.
+__global__ __launch_bounds__(256) void k_rmw_probe(char *base, size_t n)
+{
+    double *d = (double *)base;
+    int *q = (int *)(d + 4 * n);
+    signed char *g = (signed char *)(q + 2 * n);
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        double v[4];
+        int w[2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = __builtin_nontemporal_load(d + k * n + i);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) w[k] = __builtin_nontemporal_load(q + k * n + i);
+        const signed char c = __builtin_nontemporal_load(g + i);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(v[k] + 1.0, d + k * n + i);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) __builtin_nontemporal_store(w[k] + 1, q + k * n + i);
+        __builtin_nontemporal_store((signed char)(c + 1), g + i);
+    }
+}
+
+hipError_t launch_rmw_probe(void *buf, int64_t n_elems, hipStream_t st)
+{
+    size_t blocks = ((size_t)n_elems + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_rmw_probe, dim3((unsigned)blocks), dim3(256), 0, st, (char *)buf, (size_t)n_elems);
+    return hipGetLastError();
+}
+
+// Matrix-core probe: every wavefront runs `iters` rounds of independent
+// MFMA chains on register operands (no memory traffic inside the loop) and
+// writes one value per lane at the end so the work stays live.
+//   kind 0: v_mfma_f32_16x16x4_f32, 8 chains (2048 flop each)
+//   kind 1: v_mfma_f32_32x32x2_f32, 4 chains (4096 flop each)
+//   kind 2: v_mfma_f32_16x16x32_bf16, 8 chains (16384 flop each)
+constexpr int MFMA_PROBE_BLOCKS = 2048;
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <int KIND> __global__ __launch_bounds__(256) void k_mfma_probe(float *out, int iters)
+{
+    const int lane = threadIdx.x & 63;
+    const float a = 1.0f + lane * 1e-3f, b = 1.0f - lane * 1e-3f;
+    float r = 0.f;
+    if constexpr (KIND == 0) {
+        floatx4 acc[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = (floatx4){0.f, 0.f, 0.f, (float)j};
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r += acc[j][0] + acc[j][3];
+    } else if constexpr (KIND == 1) {
+        floatx16 acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[j][e] = (float)(j + e);
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r += acc[j][0] + acc[j][15];
+    } else {
+        bf16x8 va, vb;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            va[e] = (__bf16)(a + e * 1e-2f);
+            vb[e] = (__bf16)(b - e * 1e-2f);
+        }
+        floatx4 acc[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = (floatx4){0.f, 0.f, 0.f, (float)j};
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, acc[j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r += acc[j][0] + acc[j][3];
+    }
+    out[(size_t)blockIdx.x * 256 + threadIdx.x] = r;
+}
+
+hipError_t launch_mfma_probe(int kind, int iters, float *out, double *flops, hipStream_t st)
+{
+    const dim3 grid(MFMA_PROBE_BLOCKS), blk(256);
+    const double waves = (double)MFMA_PROBE_BLOCKS * 4;
+    switch (kind) {
+    case 0:
+        hipLaunchKernelGGL(k_mfma_probe<0>, grid, blk, 0, st, out, iters);
+        *flops = waves * iters * 8 * 2048.0;
+        break;
+    case 1:
+        hipLaunchKernelGGL(k_mfma_probe<1>, grid, blk, 0, st, out, iters);
+        *flops = waves * iters * 4 * 4096.0;
+        break;
+    default:
+        hipLaunchKernelGGL(k_mfma_probe<2>, grid, blk, 0, st, out, iters);
+        *flops = waves * iters * 8 * 16384.0;
+        break;
+    }
+    return hipGetLastError();
+}
+
 // explicit instantiations
 #define FCX_INST(T)                                                                          \
     template hipError_t launch_spectra<T>(const SessDev<T> &, hipStream_t);                   \
     template hipError_t launch_psd<T>(const SessDev<T> &, hipStream_t);                       \
     template hipError_t launch_pair_update<T>(const SessDev<T> &, hipStream_t);               \
+    template hipError_t launch_pair_rebuild<T>(const SessDev<T> &, long long, int, hipStream_t); \
+    template hipError_t launch_psd_rebuild<T>(const SessDev<T> &, long long, int, hipStream_t); \
     template hipError_t launch_znorm<T>(const SessDev<T> &, hipStream_t);                     \
     template hipError_t launch_spectra_batch<T>(const SessDev<T> &, int, long long, hipStream_t); \
     template hipError_t launch_znorm_batch<T>(const SessDev<T> &, int, long long, hipStream_t);   \
