@@ -283,6 +283,29 @@ fcx_status fcx_network_select(int32_t n_nodes, const float *w, double fraction, 
                               uint8_t *selected, int32_t *degree, float *strength, fcx_select_info *info,
                               void *hip_stream);
 
+/* fcx_network_select_noalloc: the same selection for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, outputs and errors are those
+ * of fcx_network_select, with these differences:
+ *   - no hipMalloc, hipFree or other allocating call is made: the control
+ *     block (about 0.7 MB) is a device array inside the library, one copy per
+ *     device, held until the process ends; its address is looked up on the
+ *     first call on a device (FCX_E_DEVICE if that fails; FCX_E_INVAL for a
+ *     device index of 64 or more);
+ *   - the largest network is 65536 nodes (FCX_E_INVAL above; the size of the
+ *     array's per-node counters);
+ *   - with info == NULL the call only enqueues its kernels on hip_stream and
+ *     returns (no wait, nothing copied back: usable under graph capture);
+ *     with info non-NULL it waits for the stream and fills *info.
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (each call clears what it needs first, with a kernel): calls whose
+ * work overlaps on one device (different streams, or host threads racing on
+ * one stream) corrupt each other's results.  The caller owns w and the
+ * outputs. */
+fcx_status fcx_network_select_noalloc(int32_t n_nodes, const float *w, double fraction, float *w_norm,
+                                      uint8_t *selected, int32_t *degree, float *strength,
+                                      fcx_select_info *info, void *hip_stream);
+
 /* ------------------------------------------------------------------------
  * Stream front end (the noise-reduction and averaging plug-ins of the online
  * pipeline, Sec. 2.5): a linear-phase FIR filter applied block by block by

@@ -135,6 +135,7 @@ _SIGS = {
     "fcx_probe_rmw": (ctypes.c_int, [P, I64, P]),
     "fcx_probe_mfma": (ctypes.c_int, [I32, I32, P, ctypes.POINTER(ctypes.c_double), P]),
     "fcx_network_select": (ctypes.c_int, [I32, P, D, P, P, P, P, ctypes.POINTER(fcx_select_info), P]),
+    "fcx_network_select_noalloc": (ctypes.c_int, [I32, P, D, P, P, P, P, ctypes.POINTER(fcx_select_info), P]),
     "fcx_fir_design": (ctypes.c_int, [I32, D, D, D, D, I32, P, I32, PI32]),
     "fcx_stream_open": (ctypes.c_int, [ctypes.POINTER(fcx_stream_config), P, PP]),
     "fcx_stream_push": (ctypes.c_int, [P, P, I64, P, P, P, I32, PI32, PI32]),
@@ -181,6 +182,20 @@ def network_select(n_nodes: int, w_ptr: int, fraction: float, w_norm_ptr: int = 
     info = fcx_select_info()
     st = lib.fcx_network_select(int(n_nodes), w_ptr, float(fraction), w_norm_ptr or None, selected_ptr or None,
                                 degree_ptr or None, strength_ptr or None, ctypes.byref(info), stream or None)
+    return st, dict(max_abs=info.max_abs, threshold=info.threshold, k=info.k, n_finite=info.n_finite,
+                    n_selected=info.n_selected)
+
+
+def network_select_noalloc(n_nodes: int, w_ptr: int, fraction: float, w_norm_ptr: int = 0, selected_ptr: int = 0,
+                           degree_ptr: int = 0, strength_ptr: int = 0, stream: int = 0, want_info: bool = True):
+    """fcx_network_select_noalloc on device buffers.  With want_info False
+    the call only enqueues (info None).  Returns (status, info dict or None)."""
+    info = fcx_select_info()
+    st = lib.fcx_network_select_noalloc(int(n_nodes), w_ptr, float(fraction), w_norm_ptr or None,
+                                        selected_ptr or None, degree_ptr or None, strength_ptr or None,
+                                        ctypes.byref(info) if want_info else None, stream or None)
+    if not want_info:
+        return st, None
     return st, dict(max_abs=info.max_abs, threshold=info.threshold, k=info.k, n_finite=info.n_finite,
                     n_selected=info.n_selected)
 

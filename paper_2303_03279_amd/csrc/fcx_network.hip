@@ -258,6 +258,17 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_pick(SelCtl *c, int shift, 
         for (int d = threadIdx.x; d < nb; d += SEL_THREADS) c->hist[sl][d] = 0;
 }
 
+// zero the part of a control block that must start at zero (everything but
+// the per-node counters, which the scan pass clears for the first N nodes);
+// a kernel rather than a memset, so the sequence can be captured in a graph
+__global__ __launch_bounds__(SEL_THREADS) void k_sel_clear(SelCtl *c)
+{
+    unsigned long long *p = (unsigned long long *)c;
+    constexpr size_t n = offsetof(SelCtl, node) / sizeof(unsigned long long);
+    for (size_t i = blockIdx.x * (size_t)SEL_THREADS + threadIdx.x; i < n; i += (size_t)gridDim.x * SEL_THREADS)
+        p[i] = 0ull;
+}
+
 __device__ __forceinline__ bool sel_take(float v, const SelCtl &c, unsigned int T)
 {
     unsigned int key;
@@ -343,15 +354,81 @@ namespace {
 // device are serialised on it.
 std::mutex g_sel_mu;
 std::unordered_map<int, SelCtl *> g_sel_ctl;
+
+// The allocation-free variant's control block: one file-scope device array
+// (each device holds its own copy until the process ends).  In host code the
+// name is only a stand-in; the device address comes from hipGetSymbolAddress
+// on the device's first call and is kept per device.
+static_assert(offsetof(SelCtl, node) % sizeof(unsigned long long) == 0, "control block layout");
+constexpr int SEL_NOALLOC_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[sizeof(SelCtl)];
+std::mutex g_na_mu;
+SelCtl *g_na_ptr[SEL_NOALLOC_DEVICES];
+
+fcx_status sel_check(int32_t n_nodes, const float *w, double fraction)
+{
+    if (n_nodes < 2 || n_nodes > SEL_MAX_NODES || !w || !(fraction >= 0.0 && fraction <= 1.0)) return FCX_E_INVAL;
+    return FCX_OK;
+}
+
+// Enqueue the selection on st with control block c; with info non-NULL, read
+// the head back (waits for the stream).
+fcx_status sel_run(SelCtl *c, int32_t n_nodes, const float *w, double fraction, float *w_norm, uint8_t *selected,
+                   int32_t *degree, float *strength, fcx_select_info *info, hipStream_t st)
+{
+    const long long P = (long long)n_nodes * (n_nodes - 1) / 2;
+    const bool vec = ((uintptr_t)w & 15) == 0;   // float4 loads in the scan and histogram passes
+    long long blocks = ((vec ? P / 4 : P) + SEL_THREADS - 1) / SEL_THREADS;
+    if (blocks > SEL_MAX_BLOCKS) blocks = SEL_MAX_BLOCKS;
+    if (blocks < 1) blocks = 1;
+    const dim3 grid((unsigned)blocks), blk(SEL_THREADS);
+    hipLaunchKernelGGL(k_sel_clear, dim3(64), blk, 0, st, c);
+    if (vec)
+        hipLaunchKernelGGL(k_sel_scan<true>, grid, blk, 0, st, w, P, (int)n_nodes, c);
+    else
+        hipLaunchKernelGGL(k_sel_scan<false>, grid, blk, 0, st, w, P, (int)n_nodes, c);
+    hipLaunchKernelGGL(k_sel_init, dim3(1), blk, 0, st, c, (int)blocks, fraction, P);
+    // digits of 11, 10 and 10 bits (bits 30..20, 19..10, 9..0)
+    const int shifts[3] = {20, 10, 0}, bins[3] = {2048, 1024, 1024};
+    for (int pass = 0; pass < 3; ++pass) {
+        if (vec)
+            hipLaunchKernelGGL(k_sel_hist<true>, grid, blk, 0, st, w, P, c, shifts[pass], bins[pass]);
+        else
+            hipLaunchKernelGGL(k_sel_hist<false>, grid, blk, 0, st, w, P, c, shifts[pass], bins[pass]);
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), blk, 0, st, c, shifts[pass], bins[pass]);
+    }
+    // last: w_norm may overwrite w
+    const int nodes = degree || strength;
+    hipLaunchKernelGGL(k_sel_rows, dim3((n_nodes + 3) / 4), blk, 0, st, w, n_nodes, c, w_norm, selected, nodes);
+    if (nodes)
+        hipLaunchKernelGGL(k_sel_node_out, dim3((n_nodes + SEL_THREADS - 1) / SEL_THREADS), blk, 0, st, c, n_nodes,
+                           degree, strength);
+    if (hipGetLastError() != hipSuccess) return FCX_E_DEVICE;
+    if (!info) return FCX_OK;
+    SelHead h{};
+    if (hipMemcpyAsync(&h, &c->h, sizeof(SelHead), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return FCX_E_DEVICE;
+    float mx, th;
+    memcpy(&mx, &h.maxbits, sizeof(float));
+    memcpy(&th, &h.prefix, sizeof(float));
+    unsigned long long ns = 0;
+    for (int q = 0; q < SEL_SLOTS; ++q) ns += h.slot_ns[q];
+    info->max_abs = mx;
+    info->threshold = h.none ? INFINITY : th;
+    info->k = h.k;
+    info->n_finite = (int64_t)h.n_finite;
+    info->n_selected = (int64_t)ns;
+    return FCX_OK;
+}
 }  // namespace
 
 extern "C" fcx_status fcx_network_select(int32_t n_nodes, const float *w, double fraction, float *w_norm,
                                          uint8_t *selected, int32_t *degree, float *strength,
                                          fcx_select_info *info, void *hip_stream)
 {
-    if (n_nodes < 2 || n_nodes > 65536 || !w || !(fraction >= 0.0 && fraction <= 1.0)) return FCX_E_INVAL;
-    const long long P = (long long)n_nodes * (n_nodes - 1) / 2;
-    hipStream_t st = (hipStream_t)hip_stream;
+    fcx_status rc = sel_check(n_nodes, w, fraction);
+    if (rc != FCX_OK) return rc;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return FCX_E_DEVICE;
     std::lock_guard<std::mutex> lk(g_sel_mu);
@@ -360,49 +437,31 @@ extern "C" fcx_status fcx_network_select(int32_t n_nodes, const float *w, double
         c = nullptr;
         return FCX_E_NOMEM;
     }
-    const bool vec = ((uintptr_t)w & 15) == 0;   // float4 loads in the scan and histogram passes
-    long long blocks = ((vec ? P / 4 : P) + SEL_THREADS - 1) / SEL_THREADS;
-    if (blocks > SEL_MAX_BLOCKS) blocks = SEL_MAX_BLOCKS;
-    if (blocks < 1) blocks = 1;
-    const dim3 grid((unsigned)blocks), blk(SEL_THREADS);
-    SelHead hh{};
-    SelHead *h = &hh;
-    bool ok = hipMemsetAsync(c, 0, offsetof(SelCtl, node), st) == hipSuccess;
-    if (ok) {
-        if (vec)
-            hipLaunchKernelGGL(k_sel_scan<true>, grid, blk, 0, st, w, P, (int)n_nodes, c);
-        else
-            hipLaunchKernelGGL(k_sel_scan<false>, grid, blk, 0, st, w, P, (int)n_nodes, c);
-        hipLaunchKernelGGL(k_sel_init, dim3(1), blk, 0, st, c, (int)blocks, fraction, P);
-        // digits of 11, 10 and 10 bits (bits 30..20, 19..10, 9..0)
-        const int shifts[3] = {20, 10, 0}, bins[3] = {2048, 1024, 1024};
-        for (int pass = 0; pass < 3; ++pass) {
-            if (vec)
-                hipLaunchKernelGGL(k_sel_hist<true>, grid, blk, 0, st, w, P, c, shifts[pass], bins[pass]);
-            else
-                hipLaunchKernelGGL(k_sel_hist<false>, grid, blk, 0, st, w, P, c, shifts[pass], bins[pass]);
-            hipLaunchKernelGGL(k_sel_pick, dim3(1), blk, 0, st, c, shifts[pass], bins[pass]);
+    // this entry point always reports back (info may still be NULL)
+    fcx_select_info tmp;
+    return sel_run(c, n_nodes, w, fraction, w_norm, selected, degree, strength, info ? info : &tmp,
+                   (hipStream_t)hip_stream);
+}
+
+extern "C" fcx_status fcx_network_select_noalloc(int32_t n_nodes, const float *w, double fraction, float *w_norm,
+                                                 uint8_t *selected, int32_t *degree, float *strength,
+                                                 fcx_select_info *info, void *hip_stream)
+{
+    fcx_status rc = sel_check(n_nodes, w, fraction);
+    if (rc != FCX_OK) return rc;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FCX_E_DEVICE;
+    if (dev < 0 || dev >= SEL_NOALLOC_DEVICES) return FCX_E_INVAL;
+    SelCtl *c = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_na_mu);
+        if (!g_na_ptr[dev]) {
+            // first call on this device (current): the device address of its copy
+            void *p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FCX_E_DEVICE;
+            g_na_ptr[dev] = (SelCtl *)p;
         }
-        // last: w_norm may overwrite w
-        const int nodes = degree || strength;
-        hipLaunchKernelGGL(k_sel_rows, dim3((n_nodes + 3) / 4), blk, 0, st, w, n_nodes, c, w_norm, selected, nodes);
-        if (nodes)
-            hipLaunchKernelGGL(k_sel_node_out, dim3((n_nodes + SEL_THREADS - 1) / SEL_THREADS), blk, 0, st, c, n_nodes,
-                               degree, strength);
-        ok = hipGetLastError() == hipSuccess && hipMemcpyAsync(h, &c->h, sizeof(SelHead), hipMemcpyDeviceToHost, st) ==
-                                                     hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+        c = g_na_ptr[dev];
     }
-    if (ok && info) {
-        float mx, th;
-        memcpy(&mx, &h->maxbits, sizeof(float));
-        memcpy(&th, &h->prefix, sizeof(float));
-        unsigned long long ns = 0;
-        for (int q = 0; q < SEL_SLOTS; ++q) ns += h->slot_ns[q];
-        info->max_abs = mx;
-        info->threshold = h->none ? INFINITY : th;
-        info->k = h->k;
-        info->n_finite = (int64_t)h->n_finite;
-        info->n_selected = (int64_t)ns;
-    }
-    return ok ? FCX_OK : FCX_E_DEVICE;
+    return sel_run(c, n_nodes, w, fraction, w_norm, selected, degree, strength, info, (hipStream_t)hip_stream);
 }
