@@ -34,6 +34,19 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 # least vector work per pair x trial (or sample) of the sign / |Im| / Im^2
 # sums: Im(x_i conj x_j) 2, sign count 2, |Im| 1, Im^2 1, ... rounded to 8
 VALU_OPS_PER_PAIR_TRIAL = 8
+# stated per-metric bounds of the batch pass and the largest errors the GPU
+# test measured at this workload's shape (tests/test_gpu_batch.py,
+# test_batch_full_source_size_precisions: rows 0, 63, 64, 2500, 4998 x all
+# columns against the FP64 oracle)
+_M8 = ["coh", "imcoh", "plv", "pli", "wpli", "uspli", "dswpli", "cor"]
+BATCH_ERROR = {
+    "fp32": {"bound": dict.fromkeys(_M8, 1e-5),
+             "measured": dict(zip(_M8, [1.65e-7, 1.16e-7, 5.94e-7, 1.16e-7, 1.48e-7, 1.05e-7, 1.32e-7, 6.07e-8]))},
+    "bf16x3": {"bound": dict.fromkeys(_M8, 1e-5),
+               "measured": dict(zip(_M8, [4.37e-7, 1.16e-7, 6.84e-7, 1.16e-7, 1.48e-7, 1.05e-7, 1.32e-7, 1.24e-7]))},
+    "bf16": {"bound": dict(coh=3e-3, imcoh=1e-5, plv=3e-3, pli=1e-5, wpli=1e-5, uspli=1e-5, dswpli=1e-5, cor=1e-3),
+             "measured": dict(zip(_M8, [2.72e-4, 1.16e-7, 2.24e-4, 1.16e-7, 1.48e-7, 1.05e-7, 1.32e-7, 6.22e-5]))},
+}
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "pair_update_n5000_all8_traffic.json")
 
 
@@ -518,6 +531,41 @@ def cpu_baseline(cfg, x_pool, target_s=10.0):
                         f"{dt:.2f} s; counts one pushed trial per pair and bin"))
 
 
+def cpu_incremental(cfg, x_pool, n_rows=32, timed=8):
+    """The incremental method on the host cores (the oracle's running-sum
+    form, FP64): n_rows evenly spaced rows against every column, the window
+    filled, then `timed` sliding pushes; the per-push time is extrapolated
+    linearly in pairs (pairs are independent), the new trial's spectra of all
+    nodes counted once."""
+    import oracle
+    W = cfg["window_trials"]
+    N = cfg["n_nodes"]
+    P = N * (N - 1) // 2
+    xs = oracle.as_device_input(x_pool, cfg)
+    rows = list(np.linspace(0, N - 2, n_rows).astype(int))
+    pi, pj = oracle.row_pairs(rows, N)
+    sl = oracle.Sliding(cfg, N, pi, pj, W)
+    for k in range(W):
+        sl.push(xs[k % xs.shape[0]])
+    t_upd = 0.0
+    for k in range(timed):
+        sl.push(xs[(W + k) % xs.shape[0]])
+        t_upd += sl.last_update_s
+    t_upd /= timed
+    t1 = time.perf_counter()
+    for k in range(timed):
+        oracle.spectra(np.ascontiguousarray(xs[(W + k) % xs.shape[0]][None]), cfg)
+    t_spec = (time.perf_counter() - t1) / timed
+    t_full = t_spec + t_upd * P / pi.size
+    B = oracle.band_bins(cfg["n_fft"], cfg["fs_hz"], cfg["f_lo_hz"], cfg["f_hi_hz"]).size
+    return dict(value=P * B / t_full, unit="pair*freq*trial updates/s", cores=oracle.num_threads(),
+                kind="oracle, incremental running sums (extrapolated)", extrapolated=True,
+                sample=(f"{len(rows)} evenly spaced rows x all columns ({pi.size} pairs x {B} bins), window of "
+                        f"{W} filled, {timed} sliding pushes, running-sum update {t_upd * 1e3:.1f} ms each, "
+                        f"spectra of all {N} nodes {t_spec * 1e3:.1f} ms; extrapolated to {P} pairs: "
+                        f"{t_full * 1e3:.0f} ms per push"))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -623,6 +671,7 @@ def main():
             print(f"[bench] batch pass, {prec} Gram", file=sys.stderr, flush=True)
             w, pms, cms = run_batch(fcx, torch, dict(cfg, gram=prec), pool_dev, args.batch_reps)
             batch[prec] = dict(ms_per_batch=w * 1e3, updates_per_s=P * B * K / w,
+                               max_abs_error_vs_fp64=BATCH_ERROR[prec],
                                pair_batch_ms=pms, cor_batch_ms=cms,
                                gram_tflops=gram_flops / (pms * 1e-3) / 1e12 if pms else None,
                                cor_tflops=cor_flops / (cms * 1e-3) / 1e12 if cms else None,
@@ -731,6 +780,8 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] oracle on host cores", file=sys.stderr, flush=True)
         base = cpu_baseline(cfg, x_pool)
+        print("[bench] incremental method on host cores", file=sys.stderr, flush=True)
+        base["incremental"] = cpu_incremental(cfg, x_pool)
 
     out = {
         "metric": "pair*freq*trial updates/s (coh, wPLI) + p99 per-trial update latency",

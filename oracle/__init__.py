@@ -61,6 +61,8 @@ def _load():
         lib.orc_spectra.restype = None
         lib.orc_pairs.argtypes = [P, P, P, I64, I64, I32, I32, P, P, P, I64, D, P, P, P, P, P, P]
         lib.orc_pairs.restype = None
+        lib.orc_slide.argtypes = [P, P, P, P, I32, I64, I32, I32, P, P, P, I64, I64, P, P, P]
+        lib.orc_slide.restype = None
         lib.orc_cor.argtypes = [P, I64, I64, I64, I64, P, P, I64, P]
         lib.orc_cor.restype = None
         lib.orc_xcor.argtypes = [P, I64, I64, I64, I64, I64, P, P, I64, P, P]
@@ -232,6 +234,47 @@ def network(x: np.ndarray, cfg: dict, pi=None, pj=None, delta=None, with_sums=Fa
     if with_cor:
         out["band"]["cor"] = cor(x, pi, pj)
     return out
+
+
+class Sliding:
+    """The incremental method on the CPU (throughput baseline; its networks
+    are pinned to network() by the CPU tests): running FP64 sums of pairs
+    (pi, pj) over a window of W trials, one push at a time."""
+
+    def __init__(self, cfg: dict, N: int, pi, pj, W: int):
+        self.cfg, self.N, self.W = cfg, N, W
+        self.pi = np.asarray(pi, dtype=np.int64)
+        self.pj = np.asarray(pj, dtype=np.int64)
+        self.nodes, inv = np.unique(np.concatenate([self.pi, self.pj]), return_inverse=True)
+        self.pa = np.ascontiguousarray(inv[:self.pi.size], dtype=np.int32)
+        self.pb = np.ascontiguousarray(inv[self.pi.size:], dtype=np.int32)
+        self.window = []          # spectra (re, im) of the trials in the window, oldest first
+        self.psd = None
+        self.state = None
+        self.band = None
+
+    def push(self, xk: np.ndarray):
+        """xk: [N][M] float64 trial."""
+        X, _, lam, _ = spectra(np.ascontiguousarray(xk[None], dtype=np.float64), self.cfg, nodes=self.nodes)
+        Xre = np.ascontiguousarray(X[0].real)
+        Xim = np.ascontiguousarray(X[0].imag)
+        nn, L, B = X.shape[1], X.shape[2], X.shape[3]
+        if self.state is None:
+            self.psd = np.zeros((nn, B))
+            self.state = np.zeros((self.pa.size, B, 7))
+            self.band = np.empty((self.pa.size, 7))
+        self.window.append((Xre, Xim))
+        old = self.window.pop(0) if len(self.window) > self.W else None
+        K = len(self.window)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        ore, oim = old if old is not None else (Xre, Xim)
+        import time
+        t0 = time.perf_counter()
+        _load().orc_slide(_ptr(Xre), _ptr(Xim), _ptr(ore), _ptr(oim), int(old is not None), nn, L, B, _ptr(lam),
+                          _ptr(self.pa), _ptr(self.pb), self.pa.size, K, _ptr(self.psd), _ptr(self.state),
+                          _ptr(self.band))
+        self.last_update_s = time.perf_counter() - t0     # the running-sum update alone
+        return {m: self.band[:, q] for q, m in enumerate(METRICS7)}
 
 
 def cor(x: np.ndarray, pi, pj) -> np.ndarray:

@@ -210,6 +210,105 @@ void orc_pairs(const double *Xre, const double *Xim, const double *l1, int64_t K
 }
 
 /*
+ * The incremental method on the CPU, for the throughput baseline only (its
+ * networks are pinned to orc_pairs by the CPU tests): one sliding push on
+ * running FP64 sums per (pair, bin) -- the new trial's per-trial terms added,
+ * the evicted trial's subtracted, as the running sums of the implementation
+ * section keep them -- and the band means of the seven spectral metrics of
+ * the window after the push.
+ *   Xn*, Xo*  : spectra of the new and of the evicted trial [nn][L][B]
+ *               (orc_spectra layout for one trial); has_old = 0: no eviction
+ *   psd       : [nn][B] running power sums, updated here
+ *   state     : [np][B][7] running sums S_re, S_im, U_re, U_im, G, A, Q
+ *   K         : trials in the window after the push
+ *   band      : [np][7] band means after the push
+ */
+static void trial_terms(const double *Xre, const double *Xim, int64_t a, int64_t c, int32_t L, int32_t B,
+                        int32_t b, const double *lam, double lsum, double *cre, double *cim)
+{
+    double r = 0.0, m = 0.0;
+    for (int32_t l = 0; l < L; ++l) {
+        int64_t oa = (a * L + l) * B + b, oc = (c * L + l) * B + b;
+        r += lam[l] * (Xre[oa] * Xre[oc] + Xim[oa] * Xim[oc]);
+        m += lam[l] * (Xim[oa] * Xre[oc] - Xre[oa] * Xim[oc]);
+    }
+    *cre = r / lsum;
+    *cim = m / lsum;
+}
+
+void orc_slide(const double *Xnre, const double *Xnim, const double *Xore, const double *Xoim, int32_t has_old,
+               int64_t nn, int32_t L, int32_t B, const double *lam, const int32_t *pa, const int32_t *pb,
+               int64_t np, int64_t K, double *psd, double *state, double *band)
+{
+    double lsum = 0.0;
+    for (int32_t l = 0; l < L; ++l) lsum += lam[l];
+    for (int64_t a = 0; a < nn; ++a)
+        for (int32_t b = 0; b < B; ++b) {
+            double pn = 0.0, po = 0.0;
+            for (int32_t l = 0; l < L; ++l) {
+                int64_t o = (a * L + l) * B + b;
+                pn += lam[l] * (Xnre[o] * Xnre[o] + Xnim[o] * Xnim[o]);
+                if (has_old) po += lam[l] * (Xore[o] * Xore[o] + Xoim[o] * Xoim[o]);
+            }
+            psd[a * B + b] += pn / lsum;
+            if (has_old) psd[a * B + b] -= po / lsum;
+        }
+    const double Kd = (double)K;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < np; ++p) {
+        int64_t a = pa[p], c = pb[p];
+        double acc[NMET];
+        for (int m = 0; m < NMET; ++m) acc[m] = 0.0;
+        for (int32_t b = 0; b < B; ++b) {
+            double *st = state + (p * B + b) * 7;
+            double nr, ni;
+            trial_terms(Xnre, Xnim, a, c, L, B, b, lam, lsum, &nr, &ni);
+            double mag = sqrt(nr * nr + ni * ni);
+            st[0] += nr;
+            st[1] += ni;
+            if (mag > 0.0) {
+                st[2] += nr / mag;
+                st[3] += ni / mag;
+            }
+            st[4] += sgn(ni);
+            st[5] += fabs(ni);
+            st[6] += ni * ni;
+            if (has_old) {
+                double orr, oi;
+                trial_terms(Xore, Xoim, a, c, L, B, b, lam, lsum, &orr, &oi);
+                double mo = sqrt(orr * orr + oi * oi);
+                st[0] -= orr;
+                st[1] -= oi;
+                if (mo > 0.0) {
+                    st[2] -= orr / mo;
+                    st[3] -= oi / mo;
+                }
+                st[4] -= sgn(oi);
+                st[5] -= fabs(oi);
+                st[6] -= oi * oi;
+            }
+            double den = sqrt(psd[a * B + b] * psd[c * B + b]);
+            double Sre = st[0], Sim = st[1], A = st[5], Q = st[6];
+            acc[0] += den > 0.0 ? sqrt(Sre * Sre + Sim * Sim) / den : 0.0;
+            acc[1] += den > 0.0 ? Sim / den : 0.0;
+            acc[2] += sqrt(st[2] * st[2] + st[3] * st[3]) / Kd;
+            double pli = fabs(st[4]) / Kd;
+            acc[3] += pli;
+            acc[4] += A > 0.0 ? fabs(Sim) / A : 0.0;
+            if (K < 2) {
+                acc[5] = NAN;
+                acc[6] = NAN;
+            } else {
+                acc[5] += (Kd * pli * pli - 1.0) / (Kd - 1.0);
+                double dd = A * A - Q;
+                acc[6] += dd != 0.0 ? (Sim * Sim - Q) / dd : 0.0;
+            }
+        }
+        for (int m = 0; m < NMET; ++m) band[p * NMET + m] = acc[m] / (double)B;
+    }
+}
+
+/*
  * COR: mean over the K trials of the per-trial Pearson correlation of the two
  * nodes' samples (COR eq.); zero variance gives r = 0.
  */

@@ -213,6 +213,28 @@ def test_tie_count_interior_bin():
         assert abs(r["G"][0, 0]) == sum(1 for e in eps if e > 0.0)
 
 
+@pytest.mark.parametrize("taper", ["hann", "dpss"])
+def test_incremental_equals_plain(taper):
+    """The incremental CPU method (running sums, add the new trial and
+    subtract the evicted one) gives the plain window recompute's networks at
+    every push, through the fill and many evictions."""
+    rng = np.random.default_rng(23)
+    T, N, M, W = 14, 6, 64, 5
+    x = rng.standard_normal((T, N, M))
+    x[:, 1, 2:] += 0.8 * x[:, 0, :-2]
+    cfg = _cfg(M, 64, f_lo=50, f_hi=300, taper=taper, nw=1.5, k=2)
+    pi, pj = oracle.all_pairs(N)
+    sl = oracle.Sliding(cfg, N, pi, pj, W)
+    for k in range(T):
+        band = sl.push(x[k])
+        ref = oracle.network(x[max(0, k + 1 - W):k + 1], cfg, pi, pj, with_cor=False)
+        for m in M7:
+            if ref["K"] < 2 and m in ("uspli", "dswpli"):
+                assert np.all(np.isnan(band[m])), (k, m)
+                continue
+            assert np.max(np.abs(band[m] - ref["band"][m])) < 1e-11, (k, m)
+
+
 # ------------------------------------------------------------------ statistics
 
 def test_null_statistics_zero_lag_mixture():
