@@ -138,12 +138,15 @@ __global__ __launch_bounds__(256) void k_psd_batch(SessDev<float> s, int K)
 }
 
 // --------------------------------------------------------- pairs, one taper
-// One 64x64 pair tile per workgroup of 8 wavefronts.  Wavefront w owns the
-// tile rows 16(w >> 1) .. +15 and columns 32(w & 1) .. +31 as two 16x16 MFMA
-// blocks; lane (lr = lane & 15, lg = lane >> 4) holds the accumulator rows
-// 4lg .. 4lg+3 of column lr of both blocks, i.e. 4 x 2 = 8 pairs, and the
-// vector-unit sums of the same 8 pairs, so the epilogue of a bin finds every
-// sum of a pair in one lane.
+// One 64x64 pair tile per workgroup of 8 wavefronts.  Wavefront w owns 16
+// tile rows (block 16(w >> 1)) and the columns 32(w & 1) .. +31 as two 16x16
+// MFMA blocks.  The MFMA's row r feeds from tile row pi(r) = (r >> 2) +
+// 4 (r & 3) of the block, so lane (lr = lane & 15, lg = lane >> 4), which
+// holds the accumulator rows 4lg + k of column lr, holds the pairs of tile
+// rows lg + 4k (k < 4) and columns 16c + lr (c < 2): 8 pairs, whose vector
+// sums it also keeps, so the epilogue of a bin finds every sum of a pair in
+// one lane.  (The permutation makes the four lane groups read four
+// consecutive rows: their 16-byte LDS reads fall in distinct banks.)
 //
 // Per trial the vector units form v = Im(X_i conj X_j) in FP64 from the FP32
 // spectra: both products are exact in FP64, so v is the correctly rounded
@@ -154,15 +157,16 @@ __global__ __launch_bounds__(256) void k_psd_batch(SessDev<float> s, int K)
 // phasor Gram (and Im S too when no vector sums are asked for).
 //
 // A chunk of PB_CC trials of the 64 row and 64 column nodes is staged in LDS
-// (row values FP32; column values FP32 for the Gram and FP64 for the vector
-// sums; unit phasors; BF16 planes for the BF16 Grams), while the next chunk
-// is already loaded into registers.
+// (rows in FP64, columns in FP32, unit phasors, BF16 planes for the BF16
+// Grams) while the next chunk is already loaded into registers.
 constexpr int PB_THREADS = 512;
 constexpr int PB_CC = 32;             // trials per staged chunk (one 16x16x32 BF16 step)
 constexpr int PB_LD = PB_CC + 1;      // LDS row stride of float2 / double2 rows
 constexpr int PB_PER = 128 * PB_CC / PB_THREADS;   // staged values per thread and chunk
 constexpr int PB_LDH = PB_CC + 8;     // BF16 plane rows (80 bytes)
 constexpr int PB_PLANE = 128 * PB_LDH;
+
+__device__ __forceinline__ int pb_perm(int r) { return (r >> 2) + 4 * (r & 3); }
 
 template <int PREC> __device__ __forceinline__ void pb_stage(__bf16 *P, int node, int col, float2 v)
 {
@@ -180,19 +184,41 @@ __device__ __forceinline__ bf16x8 pb_row(const __bf16 *P, int plane, int node, i
     return *(const bf16x8 *)(P + plane * PB_PLANE + node * PB_LDH + 8 * lg);
 }
 
+// unit phasor X / |X| (0 for X = 0): FP32 where |X|^2 is safely inside the
+// normal range, otherwise with the magnitude formed in FP64
+__device__ __forceinline__ float2 pb_phasor(float2 x)
+{
+    const float m2 = __builtin_fmaf(x.x, x.x, x.y * x.y);
+    if (m2 >= 0x1p-100f && m2 <= 0x1p100f) {
+        const float r = __builtin_amdgcn_rsqf(m2);
+        return make_float2(x.x * r, x.y * r);
+    }
+    const double d2 = (double)x.x * x.x + (double)x.y * x.y;
+    const double r = d2 > 0.0 ? __builtin_amdgcn_rsq(d2) : 0.0;
+    return make_float2((float)(x.x * r), (float)(x.y * r));
+}
+
 // Complex Gram of one 32-trial chunk for the lane's two 16x16 blocks: Re S
-// always; Im S when IM; in the BF16 forms, from the rounded planes
+// always; Im S when IM.  FP32: A operand from the FP64 rows Ar (or FP32 rows
+// when Ar is null), B operand from the FP32 columns; BF16: the planes.
 template <int PREC, bool IM>
-__device__ __forceinline__ void pb_gram(const float2 *Xs, const __bf16 *Xh, int arow, int bcol0, int lg,
-                                        floatx4 (&re)[2], floatx4 (&im)[2])
+__device__ __forceinline__ void pb_gram(const double2 *Ar, const float2 *Af, const float2 *Bc, const __bf16 *Ph,
+                                        int arow, int bcol0, int hrow, int hcol0, int lg, floatx4 (&re)[2],
+                                        floatx4 (&im)[2])
 {
     if constexpr (PREC == FCX_GRAM_FP32_ID) {
 #pragma unroll
         for (int st = 0; st < PB_CC / 4; ++st) {
-            const float2 a = Xs[arow * PB_LD + 4 * st + lg];
+            float2 a;
+            if (Ar) {
+                const double2 ad = Ar[arow * PB_LD + 4 * st + lg];
+                a = make_float2((float)ad.x, (float)ad.y);
+            } else {
+                a = Af[arow * PB_LD + 4 * st + lg];
+            }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const float2 b = Xs[(bcol0 + 16 * c) * PB_LD + 4 * st + lg];
+                const float2 b = Bc[(bcol0 + 16 * c) * PB_LD + 4 * st + lg];
                 re[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, re[c], 0, 0, 0);
                 re[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, re[c], 0, 0, 0);
                 if constexpr (IM) {
@@ -203,16 +229,16 @@ __device__ __forceinline__ void pb_gram(const float2 *Xs, const __bf16 *Xh, int 
         }
     } else {
         constexpr bool X3 = PREC == FCX_GRAM_BF16X3_ID;
-        const bf16x8 arh = pb_row(Xh, 0, arow, lg), aih = pb_row(Xh, 1, arow, lg);
+        const bf16x8 arh = pb_row(Ph, 0, hrow, lg), aih = pb_row(Ph, 1, hrow, lg);
         bf16x8 arl = arh, ail = aih;
         if constexpr (X3) {
-            arl = pb_row(Xh, 2, arow, lg);
-            ail = pb_row(Xh, 3, arow, lg);
+            arl = pb_row(Ph, 2, hrow, lg);
+            ail = pb_row(Ph, 3, hrow, lg);
         }
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const int bn = bcol0 + 16 * c;
-            const bf16x8 brh = pb_row(Xh, 0, bn, lg), bih = pb_row(Xh, 1, bn, lg);
+            const int bn = hcol0 + 16 * c;
+            const bf16x8 brh = pb_row(Ph, 0, bn, lg), bih = pb_row(Ph, 1, bn, lg);
 #define FCX_MF(acc, a, b) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0)
             FCX_MF(re[c], arh, brh);
             FCX_MF(re[c], aih, bih);
@@ -221,7 +247,7 @@ __device__ __forceinline__ void pb_gram(const float2 *Xs, const __bf16 *Xh, int 
                 FCX_MF(im[c], bf_neg(arh), bih);
             }
             if constexpr (X3) {
-                const bf16x8 brl = pb_row(Xh, 2, bn, lg), bil = pb_row(Xh, 3, bn, lg);
+                const bf16x8 brl = pb_row(Ph, 2, bn, lg), bil = pb_row(Ph, 3, bn, lg);
                 FCX_MF(re[c], arh, brl);
                 FCX_MF(re[c], arl, brh);
                 FCX_MF(re[c], aih, bil);
@@ -243,10 +269,13 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, in
 {
     constexpr bool BFP = PREC != FCX_GRAM_FP32_ID;
     constexpr int NPL = PREC == FCX_GRAM_BF16X3_ID ? 4 : 2;
-    // Xs: FP32 values, rows 0..63 then (FP32 Gram only) columns 64..127
-    __shared__ float2 Xs[(BFP ? 64 : 128) * PB_LD];
-    __shared__ double2 Xd[VS ? 64 * PB_LD : 1];        // columns in FP64 (vector sums)
-    __shared__ float2 Us[BFP ? 1 : 128 * PB_LD];       // FP32 unit phasors
+    constexpr bool XR = VS;                 // rows in FP64 (vector sums; FP32 Gram A operand)
+    constexpr bool XF = !VS && !BFP;        // rows in FP32 (FP32 Gram without vector sums)
+    constexpr bool XC = VS || !BFP;         // columns in FP32
+    __shared__ double2 Xr[XR ? 64 * PB_LD : 1];
+    __shared__ float2 Xf[XF ? 64 * PB_LD : 1];
+    __shared__ float2 Xc[XC ? 64 * PB_LD : 1];
+    __shared__ float2 Us[BFP ? 1 : 128 * PB_LD];       // FP32 unit phasors, rows then columns
     __shared__ __attribute__((aligned(16))) __bf16 Xh[BFP ? NPL * PB_PLANE : 8];
     __shared__ __attribute__((aligned(16))) __bf16 Uh[BFP ? NPL * PB_PLANE : 8];
     __shared__ double SR[128];                          // 1/sqrt(P) of the staged nodes
@@ -257,9 +286,9 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, in
     const int N = s.N, B = s.B;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
     const int wr = w >> 1, wc = w & 1;
-    const int arow = 16 * wr + lr;            // Gram A operand: a row node
-    const int bcol0 = 64 + 32 * wc + lr;      // Gram B operand of block 0: a column node
-    const int rbase = 16 * wr + 4 * lg;       // the lane's pair rows rbase + k (tile rows)
+    const int arow = 16 * wr + pb_perm(lr);   // Gram A operand: the row node of MFMA row lr
+    const int bcol0 = 32 * wc + lr;           // Gram B operand of block 0: a column node
+    const int rbase = 16 * wr + lg;           // the lane's pair rows rbase + 4k (tile rows)
     const int cbase = 32 * wc + lr;           // the lane's pair columns cbase + 16c (tile columns)
     const uint32_t mm = s.metrics;
     const bool needU = mm & M_PLV;
@@ -267,22 +296,24 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, in
     const int nch = (K + PB_CC - 1) / PB_CC, total = B * nch;
     const float invK = 1.0f / (float)K;
     const float invKm1 = K >= 2 ? 1.0f / (float)(K - 1) : 0.f;
+    const float Kf = (float)K;
 
     // staged value v of this thread: node e & 127 (64 rows, then 64 columns),
-    // trial column e >> 7 of the chunk
-    int gnode[PB_PER];
-#pragma unroll
-    for (int v = 0; v < PB_PER; ++v) {
-        const int node = (tid + PB_THREADS * v) & 127;
-        gnode[v] = node < 64 ? R0 + node : C0 + node - 64;
-    }
+    // trial column (e >> 7) of the chunk, e = tid + PB_THREADS v
+    const int snode = tid & 127, scol = tid >> 7;
+    const int gnode = snode < 64 ? R0 + snode : C0 + snode - 64;
+    const bool nodeok = gnode < N;
+    const int gn = nodeok ? gnode : 0;
     auto fetch = [&](int cc, float2 (&dst)[PB_PER]) {
-        const int b = cc / nch, t0 = (cc - b * nch) * PB_CC;
+        const int b = cc / nch, t0 = (cc - b * nch) * PB_CC + scol;
+        const bool ok = cc < total && nodeok;
+        const float2 *base = ring + (size_t)b * N + gn;
 #pragma unroll
         for (int v = 0; v < PB_PER; ++v) {
-            const int t = t0 + ((tid + PB_THREADS * v) >> 7);
-            dst[v] = (cc < total && t < K && gnode[v] < N) ? ring[((size_t)t * B + b) * N + gnode[v]]
-                                                          : make_float2(0.f, 0.f);
+            const int t = t0 + 4 * v;
+            const bool live = ok && t < K;
+            const float2 x = base[(size_t)(live ? t : 0) * B * N];
+            dst[v] = live ? x : make_float2(0.f, 0.f);
         }
     };
     float2 pre[PB_PER];
@@ -311,25 +342,19 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, in
             __syncthreads();   // the previous chunk's readers are done
 #pragma unroll
             for (int v = 0; v < PB_PER; ++v) {
-                const int e = tid + PB_THREADS * v, node = e & 127, col = e >> 7;
+                const int col = scol + 4 * v;
                 const float2 x = pre[v];
-                float2 u = make_float2(0.f, 0.f);
-                if (needU) {
-                    // unit phasor X / |X| (0 for X = 0), magnitude formed in FP64
-                    const double m2 = (double)x.x * x.x + (double)x.y * x.y;
-                    const double r = m2 > 0.0 ? __builtin_amdgcn_rsq(m2) : 0.0;
-                    u.x = (float)(x.x * r);
-                    u.y = (float)(x.y * r);
-                }
-                if (!BFP || node < 64) Xs[node * PB_LD + col] = x;
-                if constexpr (VS) {
-                    if (node >= 64) Xd[(node - 64) * PB_LD + col] = make_double2(x.x, x.y);
+                if (snode < 64) {
+                    if constexpr (XR) Xr[snode * PB_LD + col] = make_double2(x.x, x.y);
+                    if constexpr (XF) Xf[snode * PB_LD + col] = x;
+                } else {
+                    if constexpr (XC) Xc[(snode - 64) * PB_LD + col] = x;
                 }
                 if constexpr (BFP) {
-                    pb_stage<PREC>(Xh, node, col, x);
-                    if (needU) pb_stage<PREC>(Uh, node, col, u);
+                    pb_stage<PREC>(Xh, snode, col, x);
+                    if (needU) pb_stage<PREC>(Uh, snode, col, pb_phasor(x));
                 } else {
-                    if (needU) Us[node * PB_LD + col] = u;
+                    if (needU) Us[snode * PB_LD + col] = pb_phasor(x);
                 }
             }
             if (ch == 0 && tid < 128) {
@@ -344,23 +369,23 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, in
             __syncthreads();
             fetch(cc + 1, pre);   // the next chunk is on its way while this one is computed
 
-            pb_gram<PREC, !VS>(Xs, Xh, arow, bcol0, lg, sre, sim);
-            if (needU) pb_gram<PREC, true>(Us, Uh, arow, bcol0, lg, ure, uim);
+            pb_gram<PREC, !VS>(XR ? Xr : nullptr, Xf, Xc, Xh, arow, bcol0, arow, 64 + bcol0, lg, sre, sim);
+            if (needU)
+                pb_gram<PREC, true>(nullptr, Us, Us + 64 * PB_LD, Uh, arow, bcol0, arow, 64 + bcol0, lg, ure, uim);
             if constexpr (VS) {
                 for (int t4 = 0; t4 < nk; t4 += 4) {   // columns past the trials are 0 and add nothing
 #pragma unroll
                     for (int tq = 0; tq < 4; ++tq) {
                         const int t = t4 + tq;
-                        const double2 xj0 = Xd[cbase * PB_LD + t];
-                        const double2 xj1 = Xd[(cbase + 16) * PB_LD + t];
+                        const float2 y0 = Xc[cbase * PB_LD + t];
+                        const float2 y1 = Xc[(cbase + 16) * PB_LD + t];
+                        const double jx[2] = {y0.x, y1.x}, jy[2] = {y0.y, y1.y};
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            const float2 xf = Xs[(rbase + k) * PB_LD + t];
-                            const double xr = xf.x, xi = xf.y;
+                            const double2 xi = Xr[(rbase + 4 * k) * PB_LD + t];
 #pragma unroll
                             for (int c = 0; c < 2; ++c) {
-                                const double2 xj = c ? xj1 : xj0;
-                                const double v = __builtin_fma(xi, xj.x, __builtin_fma(-xr, xj.y, 0.0));
+                                const double v = __builtin_fma(xi.y, jx[c], __builtin_fma(-xi.x, jy[c], 0.0));
                                 const int p = 2 * k + c;
                                 G[p] += sign_of_f64(v);
                                 Av[p] = Av[p] + fabs(v);
@@ -373,17 +398,20 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, in
             }
         }
         // metrics of this bin for the lane's pairs, into the band means
+        // (computed for every lane; only pairs i < j < N are stored)
+        double srr[4], src[2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) srr[k] = SR[rbase + 4 * k];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) src[c] = SR[64 + cbase + 16 * c];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const int p = 2 * k + c;
-                const int ri = rbase + k, cj = cbase + 16 * c;
-                const int i = R0 + ri, j = C0 + cj;
-                if (!(i < j && j < N)) continue;
                 const double Sr = sre[c][k];
                 const double Si = VS ? Sv[p] : (double)sim[c][k];
-                const double srij = SR[ri] * SR[64 + cj];
+                const double srij = srr[k] * src[c];
                 if (mm & M_COH) acc[p][0] += sqrt_ratio<float>((Sr * Sr + Si * Si) * srij * srij);
                 if (mm & M_IMCOH) acc[p][1] += (float)(Si * srij);
                 if (mm & M_PLV) {
@@ -393,7 +421,7 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, in
                 if constexpr (VS) {
                     const float pli = (float)abs(G[p]) * invK;
                     if (mm & M_PLI) acc[p][3] += pli;
-                    if (mm & M_USPLI) acc[p][5] += K >= 2 ? ((float)K * pli * pli - 1.0f) * invKm1 : NAN;
+                    if (mm & M_USPLI) acc[p][5] += K >= 2 ? (Kf * pli * pli - 1.0f) * invKm1 : NAN;
                     if (mm & M_WPLI) acc[p][4] += Av[p] > 0.0 ? ratio_t<float>(fabs(Si), Av[p]) : 0.f;
                     if (mm & M_DSWPLI) {
                         const double dd = Av[p] * Av[p] - Qv[p];
@@ -408,7 +436,7 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, in
     for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const int i = R0 + rbase + k, j = C0 + cbase + 16 * c;
+            const int i = R0 + rbase + 4 * k, j = C0 + cbase + 16 * c;
             if (!(i < j && j < N)) continue;
             const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
 #pragma unroll
