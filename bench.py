@@ -294,7 +294,7 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
     torch.cuda.synchronize()
 
     # (b) server, continuous batching
-    srv = fcx.Server(int(fp * 1.2))
+    srv = fcx.Server(int(sum(fcx.server_footprint_bytes(c) for c, _ in sess) * 1.05))
     served = []
     for c, _ in sess:
         st, h = srv.open(c)
@@ -317,17 +317,29 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
     out["server"] = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                          updates_per_s=float(sum(upd[k] for k in ss) / wall_b), wall_s=wall_b,
                          hbm_frac=offered / wall_b / (HBM_PEAK_GBS * 1e9))
-    # (c) burst: every session submits `burst` trials at once; time to drain
+    # (c) burst: every session has `burst` trials queued (submitted while the
+    # server is held, host copies outside the timed drain); time to drain.
+    # Each session's queued trials are coalesced into one pass over its sums.
     burst = 8
-    t0 = time.perf_counter()
+    fcx.check(srv.hold(True), "hold")
     for r in range(burst):
         for k, h in enumerate(served):
             srv.submit(h, trials[k][r % pool_per_session])
+    ticks0, trials0, _, busy0 = srv.counts()
+    t0 = time.perf_counter()
+    fcx.check(srv.hold(False), "release")
     srv.drain()
     wall_c = time.perf_counter() - t0
+    ticks1, trials1, group, busy1 = srv.counts()
+    dev_s = (busy1 - busy0) * 1e-3
     out["server_burst"] = dict(trials=burst * len(sess), wall_s=wall_c,
                                updates_per_s=float(burst * sum(upd) / wall_c),
-                               hbm_frac=burst * sum(pbytes) / wall_c / (HBM_PEAK_GBS * 1e9))
+                               hbm_frac=burst * sum(pbytes) / wall_c / (HBM_PEAK_GBS * 1e9),
+                               ticks=ticks1 - ticks0, largest_group=group,
+                               device_s=dev_s,
+                               device_updates_per_s=float(burst * sum(upd) / dev_s) if dev_s > 0 else None,
+                               device_hbm_frac=(burst * sum(pbytes) / dev_s / (HBM_PEAK_GBS * 1e9)
+                                                if dev_s > 0 else None))
     for h in served:
         h.close()
     srv.destroy()
@@ -337,13 +349,19 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
             fcx.check(p.push_host(trials[k][t % pool_per_session]))
     for p in plain:
         fcx.check(p.sync())
+    # the same burst from device-resident trials (uploaded before the timed
+    # region, as the held server's are), one push per trial per session
+    dev = [[torch.from_numpy(np.ascontiguousarray(trials[k][r % pool_per_session])).cuda() for r in range(burst)]
+           for k in range(len(plain))]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in range(burst):
         for k, p in enumerate(plain):
-            fcx.check(p.push_host(trials[k][r % pool_per_session]))
+            fcx.check(p.push_device(dev[k][r].data_ptr(), sess[k][0]["n_samples"]))
     for p in plain:
         fcx.check(p.sync())
     wall_d = time.perf_counter() - t0
+    del dev
     out["plain_burst"] = dict(trials=burst * len(sess), wall_s=wall_d,
                               updates_per_s=float(burst * sum(upd) / wall_d),
                               hbm_frac=burst * sum(pbytes) / wall_d / (HBM_PEAK_GBS * 1e9))

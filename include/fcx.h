@@ -416,21 +416,37 @@ fcx_status fcx_hilbert_run(fcx_hilbert *h, const float *x, int64_t ld, float *ou
 fcx_status fcx_hilbert_close(fcx_hilbert *h);
 
 /* ------------------------------------------------------------------------
- * Serving: many concurrent sessions, continuous batching.
+ * Serving: many concurrent sessions, continuous batching (the online
+ * pipeline's plug-ins joined by buffers, Sec. 2.5, for many sessions at once;
+ * the batching itself is not in the paper).
  *
  * A server owns an HBM budget.  fcx_server_open admits a session only if its
  * footprint fits what is left (FCX_E_BUSY otherwise; retry after another
- * session closes).  A served session's footprint is fcx_footprint_bytes plus
- * one more N x M float32 input buffer (256-byte aligned): the uploads of one
- * tick run on a copy stream while the previous tick computes.  Submitted
- * trials of all sessions are gathered by a server thread into ticks: one
- * tick runs the spectra, power and pair-update work of every session with
- * pending trials as a few batched launches whose workgroups drain a shared
- * list of (session, tile) items, so sessions of different N and W overlap
- * on the device.  Per session, trials are applied in submission order.  Each
- * result equals the same session run alone.  Served sessions compute in
- * float32 and without XCOR (FCX_E_INVAL otherwise).
+ * session closes).  A served session's footprint is
+ * fcx_server_footprint_bytes: the plain session's buffers with
+ * FCX_SERVER_MAX_GROUP - 1 more ring slots, plus two input buffers of
+ * FCX_SERVER_MAX_GROUP trials (the uploads of one tick run on a copy stream
+ * while the previous tick computes).  Submitted trials of all sessions are gathered by a
+ * server thread into ticks: one tick runs the spectra, power and pair-update
+ * work of every session with pending trials as a few batched launches whose
+ * workgroups drain a shared list of (session, tile) items, so sessions of
+ * different N and W overlap on the device.  A session's queued trials (up to
+ * FCX_SERVER_MAX_GROUP finite ones) are coalesced into one pass over its
+ * running sums, read once and written once, the trials applied in
+ * submission order with the single push's arithmetic; a non-finite trial
+ * goes alone and is rejected as by fcx_push_trial.  Each result equals the
+ * same session run alone, bit for bit.  fcx_read_network, fcx_sync and
+ * fcx_resync on a served session first wait until every trial submitted
+ * before them is applied (a session is used from one thread at a time).
+ * Served sessions compute in float32 and without XCOR (FCX_E_INVAL
+ * otherwise).
  * ------------------------------------------------------------------------ */
+#define FCX_SERVER_MAX_GROUP 8
+/* Device bytes a session with this configuration holds when served (its
+ * ring has W + FCX_SERVER_MAX_GROUP slots, so a coalesced group never
+ * overwrites a trial it still evicts; plus the two tick input buffers).
+ * Returns -1 for a configuration the server does not take. */
+int64_t fcx_server_footprint_bytes(const fcx_config *cfg);
 fcx_status fcx_server_create(int64_t hbm_budget_bytes, fcx_server **out);
 fcx_status fcx_server_open(fcx_server *srv, const fcx_config *cfg, fcx_session **out);
 /* Copy x (host, [N][M] with row stride ld) and queue it; *ticket identifies it. */
@@ -443,6 +459,18 @@ fcx_status fcx_server_poll(fcx_server *srv, uint64_t ticket, int *done, double *
 fcx_status fcx_server_drain(fcx_server *srv);
 /* Budget accounting: bytes admitted, bytes left, sessions open. */
 fcx_status fcx_server_usage(fcx_server *srv, int64_t *used, int64_t *left, int32_t *n_sessions);
+/* hold = 1: submissions are queued but no tick is formed (the queues fill,
+ * so the next ticks coalesce whole bursts); hold = 0 lets the server thread
+ * run again.  fcx_server_drain returns FCX_E_BUSY while held with trials
+ * pending; reading, syncing or closing a served session and
+ * fcx_server_destroy release the hold (they need the trials applied). */
+fcx_status fcx_server_hold(fcx_server *srv, int hold);
+/* Ticks run, trials applied, the largest coalesced group and the summed
+ * device time of the finished ticks (ms; from the tick's first kernel being
+ * able to start to its last one finishing, on the server's stream) so far.
+ * Any pointer may be NULL. */
+fcx_status fcx_server_counts(fcx_server *srv, int64_t *ticks, int64_t *trials, int64_t *max_group,
+                             double *busy_ms);
 /* Close a session opened on this server (drains its pending trials). */
 fcx_status fcx_server_close_session(fcx_server *srv, fcx_session *s);
 fcx_status fcx_server_destroy(fcx_server *srv);

@@ -116,6 +116,7 @@ PP = ctypes.POINTER(ctypes.c_void_p)
 _SIGS = {
     "fcx_config_init": (None, [PCFG]),
     "fcx_footprint_bytes": (I64, [PCFG]),
+    "fcx_server_footprint_bytes": (I64, [PCFG]),
     "fcx_pair_update_bytes": (I64, [PCFG]),
     "fcx_band_bins": (I32, [PCFG, PI32, PI32]),
     "fcx_open": (ctypes.c_int, [PCFG, P, PP]),
@@ -150,6 +151,8 @@ _SIGS = {
     "fcx_server_poll": (ctypes.c_int, [P, U64, ctypes.POINTER(ctypes.c_int), PD]),
     "fcx_server_drain": (ctypes.c_int, [P]),
     "fcx_server_usage": (ctypes.c_int, [P, PI64, PI64, PI32]),
+    "fcx_server_counts": (ctypes.c_int, [P, PI64, PI64, PI64, PD]),
+    "fcx_server_hold": (ctypes.c_int, [P, I32]),
     "fcx_server_close_session": (ctypes.c_int, [P, P]),
     "fcx_server_destroy": (ctypes.c_int, [P]),
 }
@@ -296,6 +299,11 @@ def footprint_bytes(cfg: dict) -> int:
     return int(lib.fcx_footprint_bytes(ctypes.byref(c)))
 
 
+def server_footprint_bytes(cfg: dict) -> int:
+    c = make_config(cfg)
+    return int(lib.fcx_server_footprint_bytes(ctypes.byref(c)))
+
+
 def pair_update_bytes(cfg: dict) -> int:
     c = make_config(cfg)
     return int(lib.fcx_pair_update_bytes(ctypes.byref(c)))
@@ -439,6 +447,16 @@ class Server:
         u, l, n = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
         check(lib.fcx_server_usage(self.h, ctypes.byref(u), ctypes.byref(l), ctypes.byref(n)), "fcx_server_usage")
         return int(u.value), int(l.value), int(n.value)
+
+    def hold(self, on: bool) -> int:
+        return lib.fcx_server_hold(self.h, 1 if on else 0)
+
+    def counts(self):
+        """(ticks run, trials applied, largest coalesced group, device ms of the ticks)."""
+        t, n, g, ms = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        check(lib.fcx_server_counts(self.h, ctypes.byref(t), ctypes.byref(n), ctypes.byref(g), ctypes.byref(ms)),
+              "server_counts")
+        return t.value, n.value, g.value, ms.value
 
     def close_session(self, sess) -> int:
         st = lib.fcx_server_close_session(self.h, sess.h)

@@ -433,6 +433,8 @@ fcx_status fcx_hilbert_open(const fcx_hilbert_config *cfg, void *hip_stream, fcx
     d.lamw = s->lamw;
     d.ctl = s->ctl;
     d.kbase = 0;
+    d.nt = 1;
+    d.R = K + 1;
     std::lock_guard<std::mutex> lk(g_h_mu);
     const uint64_t id = g_h_next++;
     g_hilberts[id] = s;

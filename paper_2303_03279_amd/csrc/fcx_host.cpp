@@ -60,6 +60,7 @@ fcx_status make_geometry(const fcx_config *c, Geometry *g)
     g->N = c->n_nodes;
     g->M = c->n_samples;
     g->W = c->window_trials;
+    g->R = g->W + 1;
     g->F = c->n_fft;
     g->klo = lo;
     g->khi = hi;
@@ -107,7 +108,7 @@ BufferPlan make_plan(const fcx_config &c, const Geometry &g)
 {
     BufferPlan p;
     const uint32_t m = c.metrics;
-    const size_t slots = (size_t)g.W + 1;
+    const size_t slots = (size_t)g.R;
     const size_t elems = (size_t)g.ntiles * g.B * TILE_PAIRS;
     const bool spectral = (m & 0x7Fu) != 0;
     if (spectral) {
@@ -522,6 +523,8 @@ template <typename T> SessDev<T> session_dev(const Session *s, const void *x, lo
     d.zring = s->zring;
     d.rsum = s->rsum;
     d.kbase = -1;
+    d.nt = 1;
+    d.R = g.R;
     d.xL = g.xL;
     d.xF = g.xF;
     d.xtw = s->xtw;
@@ -689,6 +692,11 @@ template <typename T> static fcx_status rebuild_window(Session *s, long long pus
 
 static fcx_status read_ctl(Session *s, DevCtl *c)
 {
+    if (s->server) {
+        // a served session: every trial submitted so far is applied first
+        const fcx_status st = server_wait_idle(s);
+        if (st != FCX_OK) return st;
+    }
     HIP_OK(hipStreamSynchronize(s->stream));
     HIP_OK(hipMemcpy(c, s->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost));
     return FCX_OK;

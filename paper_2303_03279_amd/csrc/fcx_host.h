@@ -29,6 +29,8 @@ struct BufferPlan {
 struct Geometry {
     int N = 0, M = 0, W = 0, F = 0, B = 0, L = 0, klo = 0, khi = 0, nT = 0, ntiles = 0, Mz = 0;
     int xL = 0, xF = 0;   // XCOR lag limit and FFT length
+    int R = 0;            // ring slots: W + 1 (a served session: W + FCX_SERVER_MAX_GROUP, so a
+                          // coalesced group never overwrites a slot it still evicts)
     bool f64 = false;
     size_t esz = 4;
     size_t P = 0;
@@ -61,7 +63,8 @@ struct Session {
     float *zring = nullptr;
     double *rsum = nullptr;
     void *xbuf = nullptr;
-    void *xbuf2 = nullptr;   // served sessions: input of the other tick buffer
+    void *xtick[2] = {nullptr, nullptr};   // served sessions: each tick buffer's input of up to
+                                           // FCX_SERVER_MAX_GROUP trials
     float2 *xtw = nullptr;
     float2 *xspec = nullptr;
     float *xsuf = nullptr, *xval = nullptr;
@@ -97,6 +100,10 @@ fcx_status session_alloc(Session *s);  // allocates per plan, uploads tables
 void session_free(Session *s);
 template <typename T> SessDev<T> session_dev(const Session *s, const void *x, long long ldx);
 fcx_status session_enqueue_push(Session *s, const void *xdev, long long ldx);
+
+// served sessions: wait until the session has no queued or unfinished trial
+// (fcx_server.cpp)
+fcx_status server_wait_idle(Session *s);
 
 // handle table
 uint64_t register_session(Session *s);

@@ -63,6 +63,10 @@ struct SessDev {
     double *rsum;           // [ntiles][TILE_PAIRS] running sum of per-trial r (COR)
     long long kbase;        // -1: sliding push; >= 0: replay of a cached window
                             // (add only, K = pushed - kbase + 1)
+    int R;                  // ring slots (>= W + 1); trial tp sits in slot tp mod R
+    int nt;                 // trials one pass applies, in order (1 except for a
+                            // served session's coalesced group; x then holds nt
+                            // trials, N x ldx elements apart)
     int xL, xF;             // XCOR: lags -xL..xL, FFT length (power of 2 >= M + xL)
     const float2 *xtw;      // [xF] exp(-2 pi i m / xF)
     float2 *xspec;          // [N][xF/2+1] spectrum of the trial's z-scored samples
@@ -91,8 +95,8 @@ __host__ __device__ inline PushView push_view(const SessDev<T> &s, long long tp)
         v.has_old = tp >= s.W;
         v.K = v.has_old ? s.W : (int)tp + 1;
     }
-    v.slot_new = (int)(tp % (long long)(s.W + 1));
-    v.slot_old = v.has_old ? (int)((tp - s.W) % (long long)(s.W + 1)) : 0;
+    v.slot_new = (int)(tp % (long long)s.R);
+    v.slot_old = v.has_old ? (int)((tp - s.W) % (long long)s.R) : 0;
     return v;
 }
 
@@ -135,6 +139,21 @@ template <typename T> hipError_t launch_xcor(const SessDev<T> &s, hipStream_t st
 __host__ __device__ int pair_node_bytes(int L, int elem_bytes, uint32_t metrics);
 __host__ __device__ int pair_chunk_bins(int B, int L, int elem_bytes, uint32_t metrics);
 __host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes, uint32_t metrics);
+// A served session's coalesced group of nt trials stages every trial's node
+// data per bin: at most pair_group_max trials fit the pair kernel's LDS with
+// one bin, and pair_chunk_bins_mt bins are staged per chunk (its LDS is
+// nt * pair_lds_bytes(chunk, ...) at most).
+__host__ __device__ inline int pair_group_max(int L, int elem_bytes, uint32_t metrics)
+{
+    const int g = PAIR_LDS_BYTES / (PAIR_NODES * pair_node_bytes(L, elem_bytes, metrics));
+    return g < 1 ? 1 : g;
+}
+__host__ __device__ inline int pair_chunk_bins_mt(int B, int L, int elem_bytes, uint32_t metrics, int nt)
+{
+    int cb = PAIR_LDS_BYTES / (PAIR_NODES * pair_node_bytes(L, elem_bytes, metrics) * (nt > 0 ? nt : 1));
+    if (cb < 1) cb = 1;
+    return cb < B ? cb : B;
+}
 
 // batched launches of the serving path (float sessions); items are
 // (session index, a, b, 0) with a/b the block coordinates of the kernel

@@ -101,7 +101,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_spectra(SessDev<T> s)
 {
     __shared__ T xs[SP_NODES][SP_CH + 1];
-    spectra_body(s, blockIdx.x, blockIdx.y, xs, (int)(s.ctl->pushed % (long long)(s.W + 1)));
+    spectra_body(s, blockIdx.x, blockIdx.y, xs, (int)(s.ctl->pushed % (long long)s.R));
 }
 
 // a batch of trials resident on the device: trial blockIdx.z (at x + z * stride
@@ -200,7 +200,7 @@ __device__ __forceinline__ void znorm_body(const SessDev<T> &s, int bx, int slot
 template <typename T>
 __global__ __launch_bounds__(256) void k_znorm(SessDev<T> s)
 {
-    znorm_body(s, blockIdx.x, (int)(s.ctl->pushed % (long long)(s.W + 1)));
+    znorm_body(s, blockIdx.x, (int)(s.ctl->pushed % (long long)s.R));
 }
 
 template <typename T>
@@ -247,10 +247,12 @@ __device__ __forceinline__ void psd_body(const SessDev<T> &s, int bx)
     const int e = bx * 256 + threadIdx.x;
     if (e >= s.B * s.N) return;
     const int b = e / s.N, i = e % s.N;
-    const PushView pv = push_view(s, s.ctl->pushed);
     double v = s.psd[e];
-    v = v + trial_psd(s, pv.slot_new, b, i);
-    if (pv.has_old) v = v - trial_psd(s, pv.slot_old, b, i);
+    for (int t = 0; t < s.nt; ++t) {   // a coalesced group: its trials in order
+        const PushView pv = push_view(s, s.ctl->pushed + t);
+        v = v + trial_psd(s, pv.slot_new, b, i);
+        if (pv.has_old) v = v - trial_psd(s, pv.slot_old, b, i);
+    }
     s.psd[e] = v;
 }
 
@@ -319,6 +321,41 @@ __host__ __device__ size_t pair_lds_bytes(int CB, int L, int elem_bytes, uint32_
 #define FCX_COR_DEPTH 2
 #endif
 constexpr int COR_DEPTH = FCX_COR_DEPTH;
+
+// one trial's r block of a 16x16 COR block: the MFMA chain of cor_block over
+// the z-scored samples (steps in order, components x, y, z, w), so the
+// result is the bits cor_block adds for that trial
+template <typename T>
+__device__ __forceinline__ floatx4 cor_chain(const SessDev<T> &s, int slot, int row, int col, int lg, int steps)
+{
+    const int N = s.N, Mz = s.Mz;
+    const float4 *rn = (const float4 *)(s.zring + ((size_t)slot * N + row) * Mz) + lg;
+    const float4 *cn = (const float4 *)(s.zring + ((size_t)slot * N + col) * Mz) + lg;
+    floatx4 an = {0.f, 0.f, 0.f, 0.f};
+    float4 a[COR_DEPTH], b[COR_DEPTH];
+#pragma unroll
+    for (int d = 0; d < COR_DEPTH; ++d) {
+        const int o = 4 * min(d, steps - 1);
+        a[d] = rn[o];
+        b[d] = cn[o];
+    }
+    for (int st = 0; st < steps; st += COR_DEPTH) {
+#pragma unroll
+        for (int d = 0; d < COR_DEPTH; ++d) {
+            if (st + d >= steps) break;
+            const float4 x = a[d], y = b[d];
+            const int o = 4 * min(st + d + COR_DEPTH, steps - 1);
+            a[d] = rn[o];
+            b[d] = cn[o];
+            an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, y.x, an, 0, 0, 0);
+            an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, y.y, an, 0, 0, 0);
+            an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, y.z, an, 0, 0, 0);
+            an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, y.w, an, 0, 0, 0);
+        }
+    }
+    return an;
+}
+
 
 template <typename T>
 __device__ __forceinline__ void cor_block(const SessDev<T> &s, const PushView &pv, int tile, int sub, int J0,
@@ -741,6 +778,264 @@ __device__ __forceinline__ void pair_item(const SessDev<T> &s, int item, long lo
         pair_slice_body<T, SPEC, LT, COR, UG, false>(s, pv, item, CB, lds);
 }
 
+// ---------------------------------------------------------------------------
+// A served session's coalesced group: the s.nt trials queued behind each
+// other are applied in one pass over the state, in submission order, with
+// the per-trial terms and the add-then-remove order of the single push, so
+// the sums equal those of pushing the trials one by one; every state element
+// is read and written once per group and the networks are finalised once,
+// after the last trial.  Bins are staged in chunks of CB with all nt trials
+// (new and evicted spectra, unit phasors).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void cor_block_mt(const SessDev<T> &s, long long tp0, int tile, int sub, int J0, int R0,
+                                             int w)
+{
+    const int N = s.N, Mz = s.Mz;
+    const int C0 = J0 + 16 * w;
+    if (R0 >= N || C0 >= N || R0 >= C0 + 15) return;   // no pair i < j < N in this block
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int row = R0 + lr, col = C0 + lr;
+    const int rr = row < N ? row : 0, cc = col < N ? col : 0;
+    const int steps = Mz / 16;
+    const size_t P = (size_t)N * (N - 1) / 2;
+    double R[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int ri = 16 * sub + 4 * lg + k, cj = 16 * w + lr;
+        const int i = R0 + 4 * lg + k, j = C0 + lr;
+        R[k] = (i < j && j < N) ? s.rsum[(size_t)tile * TILE_PAIRS + (size_t)ri * TILE + cj] : 0.0;
+    }
+    int K = 0;
+    for (int t = 0; t < s.nt; ++t) {
+        const PushView pv = push_view(s, tp0 + t);
+        const floatx4 an = cor_chain(s, pv.slot_new, rr, cc, lg, steps);
+        floatx4 ao = {0.f, 0.f, 0.f, 0.f};
+        if (pv.has_old) ao = cor_chain(s, pv.slot_old, rr, cc, lg, steps);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            R[k] = R[k] + (double)an[k];
+            if (pv.has_old) R[k] = R[k] - (double)ao[k];
+        }
+        K = pv.K;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int ri = 16 * sub + 4 * lg + k, cj = 16 * w + lr;
+        const int i = R0 + 4 * lg + k, j = C0 + lr;
+        if (!(i < j && j < N)) continue;
+        s.rsum[(size_t)tile * TILE_PAIRS + (size_t)ri * TILE + cj] = R[k];
+        const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+        s.out[7 * P + idx] = (T)(R[k] / (double)K);
+    }
+}
+
+template <typename T, uint32_t SPEC, int LT, int COR, int UG>
+__device__ __forceinline__ void pair_slice_mt(const SessDev<T> &s, long long tp0, int item, int CB, char *lds)
+{
+    typedef typename V2<T>::t T2;
+    const int tile = item / SLICES, sub = item % SLICES;
+    const int tid = threadIdx.x, c = tid & (TILE - 1), w = tid >> 6;
+    const int2 tt = s.tiles[tile];
+    const int J0 = tt.y * TILE, R0 = tt.x * TILE + SLICE_ROWS * sub;
+    const int N = s.N, B = s.B, L = LT ? LT : s.L, nt = s.nt;
+    const uint32_t mm = SPEC ? SPEC : (s.metrics & 0x7Fu);
+    const bool needSre = mm & M_COH;
+    const bool needSim = mm & (M_COH | M_IMCOH | M_WPLI | M_DSWPLI);
+    const bool needU = mm & M_PLV;
+    const bool needG = mm & (M_PLI | M_USPLI);
+    const bool needA = mm & (M_WPLI | M_DSWPLI);
+    const bool needQ = mm & M_DSWPLI;
+    const bool ufix = UG >= 0 ? (UG & 1) != 0 : s.u_fixed != 0;
+    const bool g8 = UG >= 0 ? (UG & 2) != 0 : s.g_narrow != 0;
+    const float uscale = ldexpf(1.0f, s.ufix_bits);
+    const T uinvT = (T)ldexp(1.0, -s.ufix_bits);
+    const bool with_cor = COR > 0 || (COR < 0 && (s.metrics & M_COR));
+    const bool stageU = L == 1 && needU;
+    const T2 *ring = (const T2 *)s.ring;
+    const size_t P = (size_t)N * (N - 1) / 2;
+    const int K = push_view(s, tp0 + nt - 1).K;
+    if (!mm) {
+        if (with_cor) cor_block_mt(s, tp0, tile, sub, J0, R0, w);
+        return;
+    }
+    const size_t tb = (size_t)tile * B * TILE_PAIRS;
+    const int usz = ufix ? 4 : 8, gsz = g8 ? 1 : 2;
+    const uint32_t tpairs = (uint32_t)B * TILE_PAIRS;
+    auto plane_rsrc = [&](bool need, void *plane, int esz) {
+        return tile_rsrc(need ? (char *)plane + tb * esz : nullptr, need ? tpairs * (uint32_t)esz : 0u);
+    };
+    const Rsrc rSre = plane_rsrc(needSre, s.plane[P_SRE], 8);
+    const Rsrc rSim = plane_rsrc(needSim, s.plane[P_SIM], 8);
+    const Rsrc rUre = plane_rsrc(needU, s.plane[P_URE], usz);
+    const Rsrc rUim = plane_rsrc(needU, s.plane[P_UIM], usz);
+    const Rsrc rA = plane_rsrc(needA, s.plane[P_A], 8);
+    const Rsrc rQ = plane_rsrc(needQ, s.plane[P_Q], 8);
+    const Rsrc rG = plane_rsrc(needG, s.gsum, gsz);
+    // LDS: new and evicted spectra [nt][CB][L][nodes], their unit phasors
+    // [nt][CB][nodes], 1/sqrt(P) [CB][nodes]
+    T2 *Xn = (T2 *)lds;
+    T2 *Xo = Xn + (size_t)nt * CB * L * PAIR_NODES;
+    T2 *Un = Xo + (size_t)nt * CB * L * PAIR_NODES;
+    T2 *Uo = Un + (stageU ? (size_t)nt * CB * PAIR_NODES : 0);
+    double *SR = (double *)(Uo + (stageU ? (size_t)nt * CB * PAIR_NODES : 0));
+    int ci = 0;
+    for (int b0 = 0; b0 < B; b0 += CB, ++ci) {
+        const int nb = min(CB, B - b0);
+        const bool last_chunk = b0 + CB >= B;
+        const int per = nb * L * PAIR_NODES;
+        for (int e = tid; e < nt * per; e += PAIR_THREADS) {
+            const int t = e / per, r = e % per;
+            const int nl = r % PAIR_NODES, bl = r / PAIR_NODES;
+            const int l = bl % L, bb = bl / L;
+            const int node = nl < SLICE_ROWS ? R0 + nl : J0 + nl - SLICE_ROWS;
+            const PushView pv = push_view(s, tp0 + t);
+            T2 xn, xo;
+            xn.x = xn.y = xo.x = xo.y = 0;
+            if (node < N) {
+                xn = ring[(((size_t)pv.slot_new * B + b0 + bb) * L + l) * N + node];
+                if (pv.has_old) xo = ring[(((size_t)pv.slot_old * B + b0 + bb) * L + l) * N + node];
+            }
+            Xn[((size_t)t * nb * L + bl) * PAIR_NODES + nl] = xn;
+            Xo[((size_t)t * nb * L + bl) * PAIR_NODES + nl] = xo;
+            if (stageU) {
+                Un[((size_t)t * nb + bb) * PAIR_NODES + nl] = unit_phasor<T>(xn);
+                Uo[((size_t)t * nb + bb) * PAIR_NODES + nl] = unit_phasor<T>(xo);
+            }
+        }
+        if (mm & (M_COH | M_IMCOH)) {
+            for (int e = tid; e < nb * PAIR_NODES; e += PAIR_THREADS) {
+                const int nl = e % PAIR_NODES, bb = e / PAIR_NODES;
+                const int node = nl < SLICE_ROWS ? R0 + nl : J0 + nl - SLICE_ROWS;
+                double sr = 0.0;
+                if (node < N) {
+                    const double p = s.psd[(size_t)(b0 + bb) * N + node];
+                    sr = p > 0.0 ? rsqrt(p) : 0.0;
+                }
+                SR[e] = sr;
+            }
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int q = 0; q < SLICE_ROWS / 4; ++q) {
+            const int r = 4 * q + w, rt = SLICE_ROWS * sub + r;
+            const int i = R0 + r, j = J0 + c;
+            if (!(i < j && j < N)) continue;
+            const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+            T acc[7];
+#pragma unroll
+            for (int m = 0; m < 7; ++m) acc[m] = (ci > 0 && (mm & (1u << m))) ? s.out[(size_t)m * P + idx] : (T)0;
+            // the state loads of MT_GROUP bins go out together before their
+            // trials are applied (their latency overlaps)
+            constexpr int MT_GROUP = 4;
+            for (int g0 = 0; g0 < nb; g0 += MT_GROUP) {
+            PairState sg[MT_GROUP];
+#pragma unroll
+            for (int k = 0; k < MT_GROUP; ++k) {
+                if (g0 + k >= nb) break;
+                const uint32_t e = (uint32_t)(((b0 + g0 + k) * TILE + rt) * TILE + c);
+                PairState &st = sg[k];
+                st.sre = needSre ? buf_ld_f64(rSre, e * 8u) : 0.0;
+                st.sim = needSim ? buf_ld_f64(rSim, e * 8u) : 0.0;
+                st.ure = (needU && !ufix) ? buf_ld_f64(rUre, e * 8u) : 0.0;
+                st.uim = (needU && !ufix) ? buf_ld_f64(rUim, e * 8u) : 0.0;
+                st.uqr = (needU && ufix) ? buf_ld_i32(rUre, e * 4u) : 0;
+                st.uqi = (needU && ufix) ? buf_ld_i32(rUim, e * 4u) : 0;
+                st.a = needA ? buf_ld_f64(rA, e * 8u) : 0.0;
+                st.q = needQ ? buf_ld_f64(rQ, e * 8u) : 0.0;
+                st.g = needG ? (g8 ? buf_ld_i8(rG, e) : buf_ld_i16(rG, e * 2u)) : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < MT_GROUP; ++k) {
+                const int bb = g0 + k;
+                if (bb >= nb) break;
+                const uint32_t e = (uint32_t)(((b0 + bb) * TILE + rt) * TILE + c);
+                PairState &st = sg[k];
+                for (int t = 0; t < nt; ++t) {
+                    const bool old = push_view(s, tp0 + t).has_old;
+                    const size_t xo = ((size_t)t * nb * L + (size_t)bb * L) * PAIR_NODES;
+                    const size_t uo = ((size_t)t * nb + bb) * PAIR_NODES;
+                    double cnr, cni, cor_ = 0.0, coi = 0.0;
+                    trial_csd<T>(Xn + xo, r, c, L, s.lamw, cnr, cni);
+                    if (old) trial_csd<T>(Xo + xo, r, c, L, s.lamw, cor_, coi);
+                    if (needSre) {
+                        st.sre = st.sre + cnr;
+                        if (old) st.sre = st.sre - cor_;
+                    }
+                    if (needSim) {
+                        st.sim = st.sim + cni;
+                        if (old) st.sim = st.sim - coi;
+                    }
+                    if (needU) {
+                        double unr, uni, uor = 0.0, uoi = 0.0;
+                        trial_uprod<T>(Un + uo, r, c, L, cnr, cni, unr, uni);
+                        if (old) trial_uprod<T>(Uo + uo, r, c, L, cor_, coi, uor, uoi);
+                        if (ufix) {
+                            st.uqr += ufix_of(unr, uscale);
+                            st.uqi += ufix_of(uni, uscale);
+                            if (old) {
+                                st.uqr -= ufix_of(uor, uscale);
+                                st.uqi -= ufix_of(uoi, uscale);
+                            }
+                        } else {
+                            st.ure = st.ure + unr;
+                            st.uim = st.uim + uni;
+                            if (old) {
+                                st.ure = st.ure - uor;
+                                st.uim = st.uim - uoi;
+                            }
+                        }
+                    }
+                    if (needG) {
+                        st.g = st.g + sgn_of(cni);
+                        if (old) st.g -= sgn_of(coi);
+                    }
+                    if (needA) {
+                        st.a = st.a + fabs(cni);
+                        if (old) st.a = st.a - fabs(coi);
+                    }
+                    if (needQ) {
+                        st.q = st.q + cni * cni;
+                        if (old) st.q = st.q - coi * coi;
+                    }
+                }
+                if (needSre) buf_st_f64(rSre, e * 8u, st.sre);
+                if (needSim) buf_st_f64(rSim, e * 8u, st.sim);
+                if (needU) {
+                    if (ufix) {
+                        buf_st_i32(rUre, e * 4u, st.uqr);
+                        buf_st_i32(rUim, e * 4u, st.uqi);
+                    } else {
+                        buf_st_f64(rUre, e * 8u, st.ure);
+                        buf_st_f64(rUim, e * 8u, st.uim);
+                    }
+                }
+                if (needG) {
+                    if (g8)
+                        buf_st_i8(rG, e, st.g);
+                    else
+                        buf_st_i16(rG, e * 2u, st.g);
+                }
+                if (needA) buf_st_f64(rA, e * 8u, st.a);
+                if (needQ) buf_st_f64(rQ, e * 8u, st.q);
+                const double srij = (mm & (M_COH | M_IMCOH))
+                                        ? SR[bb * PAIR_NODES + r] * SR[bb * PAIR_NODES + SLICE_ROWS + c] : 0.0;
+                const T ur = ufix ? (T)st.uqr * uinvT : (T)st.ure;
+                const T ui = ufix ? (T)st.uqi * uinvT : (T)st.uim;
+                bin_metrics<T>(mm, st, srij, ur, ui, K, acc);
+            }
+            }
+#pragma unroll
+            for (int m = 0; m < 7; ++m) {
+                if (!(mm & (1u << m))) continue;
+                s.out[(size_t)m * P + idx] = last_chunk ? acc[m] / (T)B : acc[m];
+            }
+        }
+        __syncthreads();
+    }
+    if (with_cor) cor_block_mt(s, tp0, tile, sub, J0, R0, w);
+}
+
 template <typename T, uint32_t SPEC, int LT, int COR, int UG>
 __global__ __launch_bounds__(PAIR_THREADS) void k_pair_update(SessDev<T> s, int CB)
 {
@@ -849,7 +1144,7 @@ __global__ __launch_bounds__(256) void k_psd_rebuild(SessDev<T> s, long long fir
     if (e >= s.B * s.N) return;
     const int b = e / s.N, i = e % s.N;
     double v = 0.0;
-    for (int t = 0; t < K; ++t) v = v + trial_psd(s, (int)((first + t) % (long long)(s.W + 1)), b, i);
+    for (int t = 0; t < K; ++t) v = v + trial_psd(s, (int)((first + t) % (long long)s.R), b, i);
     s.psd[e] = v;
 }
 
@@ -875,31 +1170,8 @@ __device__ __forceinline__ void cor_rebuild(const SessDev<T> &s, long long first
     const int steps = Mz / 16;
     double R[4] = {0.0, 0.0, 0.0, 0.0};
     for (int t = 0; t < K; ++t) {
-        const int slot = (int)((first + t) % (long long)(s.W + 1));
-        const float4 *rn = (const float4 *)(s.zring + ((size_t)slot * N + (rv ? row : 0)) * Mz) + lg;
-        const float4 *cn = (const float4 *)(s.zring + ((size_t)slot * N + (cv ? col : 0)) * Mz) + lg;
-        floatx4 an = {0.f, 0.f, 0.f, 0.f};
-        float4 a[COR_DEPTH], b[COR_DEPTH];
-#pragma unroll
-        for (int d = 0; d < COR_DEPTH; ++d) {
-            const int o = 4 * min(d, steps - 1);
-            a[d] = rn[o];
-            b[d] = cn[o];
-        }
-        for (int st = 0; st < steps; st += COR_DEPTH) {
-#pragma unroll
-            for (int d = 0; d < COR_DEPTH; ++d) {
-                if (st + d >= steps) break;
-                const float4 x = a[d], y = b[d];
-                const int o = 4 * min(st + d + COR_DEPTH, steps - 1);
-                a[d] = rn[o];
-                b[d] = cn[o];
-                an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, y.x, an, 0, 0, 0);
-                an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, y.y, an, 0, 0, 0);
-                an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, y.z, an, 0, 0, 0);
-                an = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, y.w, an, 0, 0, 0);
-            }
-        }
+        const int slot = (int)((first + t) % (long long)s.R);
+        const floatx4 an = cor_chain(s, slot, rv ? row : 0, cv ? col : 0, lg, steps);
 #pragma unroll
         for (int k = 0; k < 4; ++k) R[k] = R[k] + (double)an[k];
     }
@@ -972,7 +1244,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_rebuild(SessDev<T> s, lon
                     const int nl = e % PAIR_NODES, tl = e / PAIR_NODES;
                     const int l = tl % L, t = tl / L;
                     const int node = nl < SLICE_ROWS ? R0 + nl : J0 + nl - SLICE_ROWS;
-                    const long long slot = (first + t0 + t) % (long long)(s.W + 1);
+                    const long long slot = (first + t0 + t) % (long long)s.R;
                     T2 x;
                     x.x = x.y = 0;
                     if (node < N) x = ring[(((size_t)slot * B + b) * L + l) * N + node];
@@ -1212,8 +1484,11 @@ __global__ __launch_bounds__(256) void kb_spectra(const SessDev<float> *S, const
     __shared__ float xs[SP_NODES][SP_CH + 1];
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
-        const SessDev<float> &d = S[w.x];
-        spectra_body(d, w.y, w.z, xs, (int)(d.ctl->pushed % (long long)(d.W + 1)));
+        SessDev<float> d = S[w.x];
+        // trial w.w of the session's group: input rows N x ldx apart, ring slot
+        // of that trial
+        d.x = (const float *)d.x + (size_t)w.w * d.N * d.ldx;
+        spectra_body(d, w.y, w.z, xs, (int)((d.ctl->pushed + w.w) % (long long)d.R));
         __syncthreads();
     }
 }
@@ -1222,8 +1497,9 @@ __global__ __launch_bounds__(256) void kb_znorm(const SessDev<float> *S, const i
 {
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 w = items[it];
-        const SessDev<float> &d = S[w.x];
-        znorm_body(d, w.y, (int)(d.ctl->pushed % (long long)(d.W + 1)));
+        SessDev<float> d = S[w.x];
+        d.x = (const float *)d.x + (size_t)w.w * d.N * d.ldx;
+        znorm_body(d, w.y, (int)((d.ctl->pushed + w.w) % (long long)d.R));
     }
 }
 
@@ -1243,8 +1519,17 @@ __global__ __launch_bounds__(PAIR_THREADS) void kb_pair_update(const SessDev<flo
         const int4 w = items[it];
         const SessDev<float> &s = S[w.x];
         if (s.ctl->bad) continue;
-        pair_item<float, SPEC, LT, COR, UG>(s, w.y, s.ctl->pushed, pair_chunk_bins(s.B, s.L, 4, s.metrics & 0x7Fu),
-                                            lds);
+        if (s.nt > 1) {
+            const int tile = w.y / SLICES, sub = w.y % SLICES;
+            const int2 tt = s.tiles[tile];
+            const int R0 = tt.x * TILE + SLICE_ROWS * sub, J0 = tt.y * TILE;
+            if (!(R0 >= s.N || R0 >= min(J0 + TILE - 1, s.N - 1)))
+                pair_slice_mt<float, SPEC, LT, COR, UG>(
+                    s, s.ctl->pushed, w.y, pair_chunk_bins_mt(s.B, s.L, 4, s.metrics & 0x7Fu, s.nt), lds);
+        } else {
+            pair_item<float, SPEC, LT, COR, UG>(s, w.y, s.ctl->pushed,
+                                                pair_chunk_bins(s.B, s.L, 4, s.metrics & 0x7Fu), lds);
+        }
         __syncthreads();
     }
 }
@@ -1257,7 +1542,7 @@ __global__ void kb_commit(const SessDev<float> *S, int n)
         if (c->bad)
             c->rejected = c->rejected + 1;
         else
-            c->pushed = c->pushed + 1;
+            c->pushed = c->pushed + S[i].nt;
         c->bad = 0;
     }
 }

@@ -2,15 +2,20 @@
 //
 // Admission: a session is opened only if its device footprint fits the
 // server's HBM budget (FCX_E_BUSY otherwise).  Submission copies the trial
-// into pinned host memory and queues it on its session.  A builder thread
-// forms ticks: every session with a queued trial contributes its oldest one;
-// the tick uploads those trials and runs the whole update of all of them as
-// five batched launches (spectra, z-scores, power sums, pair update
-// with its COR blocks, commit) whose workgroups drain a shared list of (session, block) items.
-// Trials that arrive while a tick runs go into the next tick, which is queued
-// behind it on the stream (at most two ticks in flight), so the device is
-// never idle while work is waiting.  A completion thread waits for each
-// tick's event and stamps its trials done.
+// into pinned host memory (checking it is finite in the same pass) and
+// queues it on its session.  A builder thread forms ticks: every session with
+// queued trials contributes its oldest ones -- up to FCX_SERVER_MAX_GROUP
+// finite trials in submission order, coalesced into one pass over the
+// session's running sums (read once, the trials applied in order, written
+// once), or a non-finite trial alone, which the device then rejects as a
+// plain push would.  The tick uploads those trials and runs the whole update
+// of all of them as five batched launches (spectra, z-scores, power sums,
+// pair update with its COR blocks, commit) whose workgroups drain a shared
+// list of (session, block) items.  Trials that arrive while a tick runs go
+// into the next tick, which is queued behind it on the stream (at most two
+// ticks in flight), so the device is never idle while work is waiting.  A
+// completion thread waits for each tick's event and stamps its trials done.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <new>
@@ -37,6 +42,13 @@ struct Submission {
     void *pinned;
     size_t bytes;
     double t_submit;
+    bool finite;     // checked on the host while copying
+};
+
+// one session's share of a tick: its trials, applied in order in one pass
+struct Group {
+    Session *s;
+    std::vector<Submission> subs;
 };
 
 struct TickBuffers {
@@ -45,11 +57,12 @@ struct TickBuffers {
     int4 *h_items = nullptr, *d_items = nullptr;
     size_t desc_cap = 0, item_cap = 0;
     hipEvent_t uploaded = nullptr;   // inputs, descriptors and items of the tick are on the device
-    hipEvent_t done = nullptr;
+    hipEvent_t started = nullptr;    // the tick's first kernel may start (timing)
+    hipEvent_t done = nullptr;       // its last kernel finished (timing)
 };
 
 struct Tick {
-    std::vector<Submission> subs;
+    std::vector<Group> groups;
     int buf = 0;
 };
 
@@ -73,13 +86,19 @@ struct Server {
     bool failed = false;
     std::multimap<size_t, void *> pinned_pool;
     std::thread builder, completer;
+    bool hold = false;      // fcx_server_hold: queue submissions, form no tick
+    int64_t n_ticks = 0, n_trials = 0, max_group = 0;   // statistics
+    double busy_ms = 0.0;   // summed device time of the ticks (start to done, one stream)
 };
 
-// device bytes a served session holds: the plain session plus a second
-// input buffer (uploads of one tick overlap the other tick's kernels)
+// device bytes a served session holds: the plain session plus one input
+// buffer of FCX_SERVER_MAX_GROUP trials per tick buffer (uploads of one tick
+// overlap the other tick's kernels)
+static size_t tick_input_bytes(const BufferPlan &p) { return p.xbuf * (size_t)FCX_SERVER_MAX_GROUP; }
+
 static int64_t served_footprint(const BufferPlan &p)
 {
-    return (int64_t)p.total() + (int64_t)p.xbuf;
+    return (int64_t)p.total() + 2 * (int64_t)tick_input_bytes(p);
 }
 
 static std::mutex g_srv_mu;
@@ -97,8 +116,13 @@ static hipError_t ensure_capacity(TickBuffers &b, size_t ndesc, size_t nitems)
 {
     hipError_t e = hipSuccess;
     if (ndesc > b.desc_cap) {
+        // freed and cleared first, so a failed allocation leaves nothing to
+        // free twice
         if (b.h_desc) hipHostFree(b.h_desc);
         if (b.d_desc) hipFree(b.d_desc);
+        b.h_desc = nullptr;
+        b.d_desc = nullptr;
+        b.desc_cap = 0;
         size_t cap = ndesc * 2;
         if ((e = hipHostMalloc((void **)&b.h_desc, cap * sizeof(SessDev<float>), hipHostMallocDefault)) != hipSuccess)
             return e;
@@ -108,6 +132,9 @@ static hipError_t ensure_capacity(TickBuffers &b, size_t ndesc, size_t nitems)
     if (nitems > b.item_cap) {
         if (b.h_items) hipHostFree(b.h_items);
         if (b.d_items) hipFree(b.d_items);
+        b.h_items = nullptr;
+        b.d_items = nullptr;
+        b.item_cap = 0;
         size_t cap = nitems * 2;
         if ((e = hipHostMalloc((void **)&b.h_items, cap * sizeof(int4), hipHostMallocDefault)) != hipSuccess)
             return e;
@@ -121,7 +148,7 @@ static hipError_t ensure_capacity(TickBuffers &b, size_t ndesc, size_t nitems)
 static hipError_t run_tick(Server *sv, Tick &tk)
 {
     TickBuffers &b = sv->bufs[tk.buf];
-    const int ns = (int)tk.subs.size();
+    const int ns = (int)tk.groups.size();
     // item counts per kernel
     size_t n_sp = 0, n_zn = 0, n_psd = 0, n_pair = 0;
     // pair items are grouped by the session's kernel class: one batched
@@ -129,17 +156,19 @@ static hipError_t run_tick(Server *sv, Tick &tk)
     std::vector<int> cls(ns);
     size_t cls_n[PAIR_CLASSES] = {}, cls_lds[PAIR_CLASSES] = {};
     for (int k = 0; k < ns; ++k) {
-        Session *s = tk.subs[k].s;
+        Session *s = tk.groups[k].s;
+        const int nt = (int)tk.groups[k].subs.size();
         const Geometry &g = s->g;
         cls[k] = pair_kernel_class(session_dev<float>(s, s->xbuf, g.M));
         const uint32_t sm = s->cfg.metrics & 0x7Fu;
         if (sm) {
-            n_sp += (size_t)((g.N + 15) / 16) * ((g.B * g.L + 15) / 16);
+            n_sp += (size_t)nt * ((g.N + 15) / 16) * ((g.B * g.L + 15) / 16);
             n_psd += (size_t)(g.B * g.N + 255) / 256;
-            const size_t l = pair_lds_bytes(pair_chunk_bins(g.B, g.L, 4, sm), g.L, 4, sm);
+            const size_t l = nt > 1 ? (size_t)nt * pair_lds_bytes(pair_chunk_bins_mt(g.B, g.L, 4, sm, nt), g.L, 4, sm)
+                                    : pair_lds_bytes(pair_chunk_bins(g.B, g.L, 4, sm), g.L, 4, sm);
             if (l > cls_lds[cls[k]]) cls_lds[cls[k]] = l;
         }
-        if (s->cfg.metrics & M_COR) n_zn += (size_t)(g.N + 3) / 4;
+        if (s->cfg.metrics & M_COR) n_zn += (size_t)nt * ((g.N + 3) / 4);
         const size_t np = (size_t)g.ntiles * SLICES;  // spectral sums and COR blocks of every tile slice
         cls_n[cls[k]] += np;
         n_pair += np;
@@ -154,23 +183,32 @@ static hipError_t run_tick(Server *sv, Tick &tk)
     for (int c = 0; c < PAIR_CLASSES; ++c) cls_fill[c] = cls_off[c];
     size_t a = 0, z = 0, p = 0;
     for (int k = 0; k < ns; ++k) {
-        Session *s = tk.subs[k].s;
+        Session *s = tk.groups[k].s;
+        const int nt = (int)tk.groups[k].subs.size();
         const Geometry &g = s->g;
         // each tick buffer has its own device input per session; the last
         // tick that used this buffer has finished, so the upload can run
-        // while the other buffer's tick computes
-        void *xb = tk.buf ? s->xbuf2 : s->xbuf;
-        e = hipMemcpyAsync(xb, tk.subs[k].pinned, tk.subs[k].bytes, hipMemcpyHostToDevice, sv->copy_stream);
-        if (e != hipSuccess) return e;
+        // while the other buffer's tick computes.  Trial t of the group at
+        // t * N * M floats.
+        char *xb = (char *)s->xtick[tk.buf];
+        for (int t = 0; t < nt; ++t) {
+            const Submission &sb = tk.groups[k].subs[t];
+            e = hipMemcpyAsync(xb + (size_t)t * sb.bytes, sb.pinned, sb.bytes, hipMemcpyHostToDevice,
+                               sv->copy_stream);
+            if (e != hipSuccess) return e;
+        }
         b.h_desc[k] = session_dev<float>(s, xb, g.M);
+        b.h_desc[k].nt = nt;
         const bool spectral = (s->cfg.metrics & 0x7Fu) != 0;
         if (spectral) {
-            for (int by = 0; by < (g.B * g.L + 15) / 16; ++by)
-                for (int bx = 0; bx < (g.N + 15) / 16; ++bx) it_sp[a++] = make_int4(k, bx, by, 0);
+            for (int t = 0; t < nt; ++t)
+                for (int by = 0; by < (g.B * g.L + 15) / 16; ++by)
+                    for (int bx = 0; bx < (g.N + 15) / 16; ++bx) it_sp[a++] = make_int4(k, bx, by, t);
             for (int bx = 0; bx < (g.B * g.N + 255) / 256; ++bx) it_psd[p++] = make_int4(k, bx, 0, 0);
         }
         if (s->cfg.metrics & M_COR)
-            for (int bx = 0; bx < (g.N + 3) / 4; ++bx) it_zn[z++] = make_int4(k, bx, 0, 0);
+            for (int t = 0; t < nt; ++t)
+                for (int bx = 0; bx < (g.N + 3) / 4; ++bx) it_zn[z++] = make_int4(k, bx, 0, t);
         for (int t = 0; t < g.ntiles * SLICES; ++t) it_pair[cls_fill[cls[k]]++] = make_int4(k, t, 0, 0);
     }
     if ((e = hipMemcpyAsync(b.d_desc, b.h_desc, ns * sizeof(SessDev<float>), hipMemcpyHostToDevice,
@@ -181,6 +219,7 @@ static hipError_t run_tick(Server *sv, Tick &tk)
         return e;
     if ((e = hipEventRecord(b.uploaded, sv->copy_stream)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(sv->stream, b.uploaded, 0)) != hipSuccess) return e;
+    if ((e = hipEventRecord(b.started, sv->stream)) != hipSuccess) return e;
     const int4 *d_sp = b.d_items, *d_zn = d_sp + n_sp, *d_psd = d_zn + n_zn, *d_pair = d_psd + n_psd;
     if ((e = launch_batched(FCX_B_SPECTRA, b.d_desc, d_sp, (int)n_sp, 0, sv->stream)) != hipSuccess) return e;
     if ((e = launch_batched(FCX_B_ZNORM, b.d_desc, d_zn, (int)n_zn, 0, sv->stream)) != hipSuccess) return e;
@@ -201,7 +240,7 @@ static void builder_main(Server *sv)
     for (;;) {
         sv->cv_work.wait(lk, [&] {
             if (sv->stop) return true;
-            if (sv->buf_busy[0] && sv->buf_busy[1]) return false;
+            if (sv->hold || (sv->buf_busy[0] && sv->buf_busy[1])) return false;
             for (auto &kv : sv->queues)
                 if (!kv.second.empty()) return true;
             return false;
@@ -212,9 +251,28 @@ static void builder_main(Server *sv)
         for (auto &kv : sv->sessions) {  // deterministic order: by session id
             auto qit = sv->queues.find(kv.second);
             if (qit == sv->queues.end() || qit->second.empty()) continue;
-            tk.subs.push_back(qit->second.front());
-            qit->second.pop_front();
+            auto &q = qit->second;
+            Group gr;
+            gr.s = kv.second;
+            // the oldest trials, in order: a run of finite ones, or a
+            // non-finite one alone (the device rejects it)
+            if (!q.front().finite) {
+                gr.subs.push_back(q.front());
+                q.pop_front();
+            } else {
+                const Session *ss = kv.second;
+                const int lim = std::min(FCX_SERVER_MAX_GROUP,
+                                         pair_group_max(ss->g.L, 4, ss->cfg.metrics & 0x7Fu));
+                while (!q.empty() && q.front().finite && (int)gr.subs.size() < lim) {
+                    gr.subs.push_back(q.front());
+                    q.pop_front();
+                }
+            }
+            sv->n_trials += (int64_t)gr.subs.size();
+            if ((int64_t)gr.subs.size() > sv->max_group) sv->max_group = (int64_t)gr.subs.size();
+            tk.groups.push_back(std::move(gr));
         }
+        sv->n_ticks += 1;
         sv->buf_busy[tk.buf] = true;
         lk.unlock();
         const hipError_t e = run_tick(sv, tk);
@@ -237,13 +295,17 @@ static void completer_main(Server *sv)
         lk.unlock();
         hipEventSynchronize(sv->bufs[tk.buf].done);
         const double t = now_s();
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, sv->bufs[tk.buf].started, sv->bufs[tk.buf].done) != hipSuccess) ms = 0.f;
         lk.lock();
-        for (auto &sb : tk.subs) {
-            sv->latency[sb.ticket] = t - sb.t_submit;
-            sv->pending_tickets.erase(sb.ticket);
-            sv->pinned_pool.insert({sb.bytes, sb.pinned});
-            sv->outstanding -= 1;
-        }
+        sv->busy_ms += ms;
+        for (auto &gr : tk.groups)
+            for (auto &sb : gr.subs) {
+                sv->latency[sb.ticket] = t - sb.t_submit;
+                sv->pending_tickets.erase(sb.ticket);
+                sv->pinned_pool.insert({sb.bytes, sb.pinned});
+                sv->outstanding -= 1;
+            }
         sv->buf_busy[tk.buf] = false;
         sv->cv_work.notify_all();
         sv->cv_slot.notify_all();
@@ -255,16 +317,43 @@ static bool session_idle(Server *sv, Session *s)
     auto it = sv->queues.find(s);
     if (it != sv->queues.end() && !it->second.empty()) return false;
     for (auto &tk : sv->inflight)
-        for (auto &sb : tk.subs)
-            if (sb.s == s) return false;
+        for (auto &gr : tk.groups)
+            if (gr.s == s) return false;
     return true;
 }
+
+}  // namespace fcx
+
+// Wait until a served session has no queued or unfinished trial, so a read
+// of its state sees every trial submitted before it (the builder thread
+// enqueues the session's next tick only for trials submitted after that).
+fcx_status fcx::server_wait_idle(Session *s)
+{
+    Server *sv = (Server *)s->server;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    if (sv->hold) {   // the caller needs the session's trials applied
+        sv->hold = false;
+        sv->cv_work.notify_all();
+    }
+    sv->cv_slot.wait(lk, [&] { return session_idle(sv, s) || sv->failed; });
+    return sv->failed ? FCX_E_DEVICE : FCX_OK;
+}
+
+namespace fcx {
 
 }  // namespace fcx
 
 using namespace fcx;
 
 extern "C" {
+
+int64_t fcx_server_footprint_bytes(const fcx_config *cfg)
+{
+    Geometry g;
+    if (make_geometry(cfg, &g) != FCX_OK || g.f64 || (cfg->metrics & M_XCOR)) return -1;
+    g.R = g.W + FCX_SERVER_MAX_GROUP;
+    return served_footprint(make_plan(*cfg, g));
+}
 
 fcx_status fcx_server_create(int64_t hbm_budget_bytes, fcx_server **out)
 {
@@ -284,9 +373,19 @@ fcx_status fcx_server_create(int64_t hbm_budget_bytes, fcx_server **out)
         return FCX_E_DEVICE;
     }
     for (auto &b : sv->bufs)
-        if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&b.uploaded, hipEventDisableTiming) != hipSuccess)
+        if (hipEventCreateWithFlags(&b.done, hipEventDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&b.started, hipEventDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&b.uploaded, hipEventDisableTiming) != hipSuccess) {
+            for (auto &c : sv->bufs) {
+                if (c.done) (void)hipEventDestroy(c.done);
+                if (c.started) (void)hipEventDestroy(c.started);
+                if (c.uploaded) (void)hipEventDestroy(c.uploaded);
+            }
+            (void)hipStreamDestroy(sv->copy_stream);
+            (void)hipStreamDestroy(sv->stream);
+            delete sv;
             return FCX_E_DEVICE;
+        }
     sv->builder = std::thread(builder_main, sv);
     sv->completer = std::thread(completer_main, sv);
     std::lock_guard<std::mutex> lk(g_srv_mu);
@@ -305,6 +404,7 @@ fcx_status fcx_server_open(fcx_server *h, const fcx_config *cfg, fcx_session **o
     fcx_status st = make_geometry(cfg, &g);
     if (st != FCX_OK) return st;
     if (g.f64 || (cfg->metrics & M_XCOR)) return FCX_E_INVAL;  // served sessions: float32, no XCOR
+    g.R = g.W + FCX_SERVER_MAX_GROUP;   // room for a coalesced group's new trials
     const int64_t fp = served_footprint(make_plan(*cfg, g));
     {
         std::lock_guard<std::mutex> lk(sv->mu);
@@ -325,9 +425,9 @@ fcx_status fcx_server_open(fcx_server *h, const fcx_config *cfg, fcx_session **o
     s->device = sv->device;
     s->server = sv;
     st = session_alloc(s);
-    if (st == FCX_OK) {
-        if (hipMalloc(&s->xbuf2, s->plan.xbuf) == hipSuccess)
-            s->allocs.push_back(s->xbuf2);
+    for (int k = 0; k < 2 && st == FCX_OK; ++k) {
+        if (hipMalloc(&s->xtick[k], tick_input_bytes(s->plan)) == hipSuccess)
+            s->allocs.push_back(s->xtick[k]);
         else
             st = FCX_E_NOMEM;
     }
@@ -375,9 +475,15 @@ fcx_status fcx_server_submit(fcx_server *h, fcx_session *hs, const void *x, int6
     } else {
         for (int i = 0; i < s->g.N; ++i) memcpy((char *)pin + i * row, src + (size_t)i * ld * 4, row);
     }
+    // Inf or NaN anywhere: exponent bits all ones (an integer OR-reduction
+    // over the copy, which is still in cache)
+    uint32_t allones = 0;
+    const uint32_t *w = (const uint32_t *)pin;
+    const size_t n = bytes / 4;
+    for (size_t k = 0; k < n; ++k) allones |= (uint32_t)((w[k] & 0x7f800000u) == 0x7f800000u);
     std::lock_guard<std::mutex> lk(sv->mu);
     const uint64_t t = sv->next_ticket++;
-    sv->queues[s].push_back({t, s, pin, bytes, now_s()});
+    sv->queues[s].push_back({t, s, pin, bytes, now_s(), allones == 0});
     sv->pending_tickets[t] = true;
     sv->outstanding += 1;
     *ticket = t;
@@ -409,6 +515,7 @@ fcx_status fcx_server_drain(fcx_server *h)
     Server *sv = lookup_server(h);
     if (!sv) return FCX_E_INVAL;
     std::unique_lock<std::mutex> lk(sv->mu);
+    if (sv->hold && sv->outstanding > 0) return FCX_E_BUSY;   // would never finish
     sv->cv_slot.wait(lk, [&] { return sv->outstanding == 0 || sv->failed; });
     return sv->failed ? FCX_E_DEVICE : FCX_OK;
 }
@@ -424,6 +531,28 @@ fcx_status fcx_server_usage(fcx_server *h, int64_t *used, int64_t *left, int32_t
     return FCX_OK;
 }
 
+fcx_status fcx_server_hold(fcx_server *h, int hold)
+{
+    Server *sv = lookup_server(h);
+    if (!sv) return FCX_E_INVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->hold = hold != 0;
+    sv->cv_work.notify_all();
+    return FCX_OK;
+}
+
+fcx_status fcx_server_counts(fcx_server *h, int64_t *ticks, int64_t *trials, int64_t *max_group, double *busy_ms)
+{
+    Server *sv = lookup_server(h);
+    if (!sv) return FCX_E_INVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (ticks) *ticks = sv->n_ticks;
+    if (trials) *trials = sv->n_trials;
+    if (max_group) *max_group = sv->max_group;
+    if (busy_ms) *busy_ms = sv->busy_ms;
+    return FCX_OK;
+}
+
 fcx_status fcx_server_close_session(fcx_server *h, fcx_session *hs)
 {
     Server *sv = lookup_server(h);
@@ -434,6 +563,10 @@ fcx_status fcx_server_close_session(fcx_server *h, fcx_session *hs)
     if (s->server != sv) return FCX_E_INVAL;
     {
         std::unique_lock<std::mutex> lk(sv->mu);
+        if (sv->hold) {
+            sv->hold = false;
+            sv->cv_work.notify_all();
+        }
         sv->cv_slot.wait(lk, [&] { return session_idle(sv, s) || sv->failed; });
         sv->sessions.erase(s->id);
         sv->queues.erase(s);
@@ -460,6 +593,8 @@ fcx_status fcx_server_destroy(fcx_server *h)
     }
     {
         std::unique_lock<std::mutex> lk(sv->mu);
+        sv->hold = false;
+        sv->cv_work.notify_all();
         sv->cv_slot.wait(lk, [&] { return sv->outstanding == 0 || sv->failed; });
         sv->stop = true;
         sv->cv_work.notify_all();
@@ -484,6 +619,7 @@ fcx_status fcx_server_destroy(fcx_server *h)
         if (b.h_items) hipHostFree(b.h_items);
         if (b.d_items) hipFree(b.d_items);
         if (b.done) (void)hipEventDestroy(b.done);
+        if (b.started) (void)hipEventDestroy(b.started);
         if (b.uploaded) (void)hipEventDestroy(b.uploaded);
     }
     (void)hipStreamDestroy(sv->copy_stream);

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(XT) void k_xcor_node(SessDev<T> s)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 
 // A transform buffer holds element m at m + m / 32: the pad after every 32
@@ -325,8 +325,8 @@ void k_xcor_pair(SessDev<T> s)
     };
     // Z = H1 + i H2 over the full circle, H = X_i conj(X_j) (Hermitian)
     auto put = [&](int f, float2 a, float2 c1, float2 c2) {
-        const float h1r = a.x * c1.x + a.y * c1.y, h1i = a.y * c1.x - a.x * c1.y;
-        const float h2r = a.x * c2.x + a.y * c2.y, h2i = a.y * c2.x - a.x * c2.y;
+        const float h1r = __builtin_fmaf(a.x, c1.x, a.y * c1.y), h1i = __builtin_fmaf(a.y, c1.x, -(a.x * c1.y));
+        const float h2r = __builtin_fmaf(a.x, c2.x, a.y * c2.y), h2i = __builtin_fmaf(a.y, c2.x, -(a.x * c2.y));
         Z[xpad(f)] = make_float2(h1r - h2i, h1i + h2r);
         if (f > 0 && f < F / 2) Z[xpad(F - f)] = make_float2(h1r + h2i, h2r - h1i);
     };

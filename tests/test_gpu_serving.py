@@ -2,7 +2,9 @@
 
 Each session's networks must be identical (bit for bit) whether it runs
 alone through the plain push path or mixed with other sessions in the
-server's batched launches; admission must respect the HBM budget."""
+server's batched launches, with its queued trials coalesced into one pass
+over its running sums; admission must respect the HBM budget; a read waits
+for every trial submitted before it."""
 import numpy as np
 import pytest
 
@@ -60,22 +62,31 @@ def test_alone_equals_mix(fcx):
         st, ss = srv.open(c)
         fcx.check(st)
         sess.append(ss)
-    # interleave submissions across sessions (per-session order preserved)
+    # interleave submissions across sessions (per-session order preserved);
+    # the first 200 are queued while the server is held, so the first ticks
+    # coalesce full groups, the rest run as they arrive
     rng = np.random.default_rng(0)
     cursor = [0] * len(cfgs)
     tickets = []
+    fcx.check(srv.hold(True))
     while any(cursor[k] < T[k] for k in range(len(cfgs))):
         k = int(rng.integers(len(cfgs)))
         if cursor[k] < T[k]:
             tickets.append(srv.submit(sess[k], np.ascontiguousarray(xs[k][cursor[k]])))
             cursor[k] += 1
+            if len(tickets) == 200:
+                fcx.check(srv.hold(False))
     srv.drain()
     lat = []
     for t in tickets:
         done, l = srv.poll(t)
         assert done and l > 0
         lat.append(l)
-    log(f"served {len(tickets)} trials, latency p50 {1e3 * np.median(lat):.2f} ms")
+    ticks, trials, group, busy = srv.counts()
+    log(f"served {len(tickets)} trials in {ticks} ticks (largest coalesced group {group}), "
+        f"latency p50 {1e3 * np.median(lat):.2f} ms")
+    assert trials == len(tickets)
+    assert group == 8         # the held submissions were coalesced in full groups
     for k, c in enumerate(cfgs):
         for m, ref in alone[k].items():
             st, out, K = sess[k].read(m)
@@ -93,10 +104,24 @@ def test_alone_equals_mix(fcx):
 
 
 def _served_bytes(fcx, c):
-    # a served session holds the plain session's buffers plus a second
-    # device input buffer (N x M float32, 256-byte aligned)
-    xb = c["n_nodes"] * c["n_samples"] * 4
-    return fcx.footprint_bytes(c) + (xb + 255) // 256 * 256
+    # a served session holds the plain session's buffers with 7 more ring
+    # slots plus two device input buffers of 8 trials (256-byte aligned)
+    N, M, W = c["n_nodes"], c["n_samples"], c["window_trials"]
+    xb = (N * M * 4 + 255) // 256 * 256
+    spectral = c["metrics"] & 0x7F
+    B = fcx.band_bins(c)[0]
+    L = c.get("dpss_k", 1) if c.get("taper") == "dpss" else 1
+    mz = (M + 31) // 32 * 32
+    def al(v):
+        return (v + 255) // 256 * 256
+    extra = 0
+    if spectral:
+        extra += al((W + 8) * B * L * N * 8) - al((W + 1) * B * L * N * 8)
+    if c["metrics"] & 128:
+        extra += al((W + 8) * N * mz * 4) - al((W + 1) * N * mz * 4)
+    fp = fcx.footprint_bytes(c) + extra + 2 * 8 * xb
+    assert fp == fcx.server_footprint_bytes(c)
+    return fp
 
 
 def test_admission_by_hbm_budget(fcx):
@@ -128,9 +153,12 @@ def test_admission_by_hbm_budget(fcx):
 
 
 def test_served_nonfinite_rejected(fcx):
+    """A non-finite trial in the middle of a burst: the finite ones around it
+    are coalesced, it goes alone and is rejected, the window holds the
+    accepted trials in order."""
     c = synth.base_config(n_nodes=64, n_samples=500, window_trials=4, n_fft=512, f_lo_hz=8, f_hi_hz=30,
                           metrics=synth.ALL8)
-    x = synth.c4_trials(c, 9, 6).astype(np.float32)
+    x = synth.c4_trials(c, 9, 8).astype(np.float32)
     srv = fcx.Server(1 << 34)
     st, s = srv.open(c)
     fcx.check(st)
@@ -139,9 +167,38 @@ def test_served_nonfinite_rejected(fcx):
     bad = x[5].copy()
     bad[3, 7] = np.nan
     srv.submit(s, bad)
+    for k in (6, 7):
+        srv.submit(s, np.ascontiguousarray(x[k]))
     srv.drain()
     assert s.sync() == fcx.FCX_E_NONFINITE
-    ref = oracle.network(x[1:5].astype(np.float64), c)
+    assert s.counts() == (7, 1)
+    ref = oracle.network(x[[3, 4, 6, 7]].astype(np.float64), c)
     compare_network(s, ref, c, ALL, label="served after rejection")
+    fcx.check(s.close())
+    fcx.check(srv.destroy())
+
+
+def test_read_waits_for_queued_trials(fcx):
+    """Reads issued right after submissions (no drain) see every trial
+    submitted before them: K and the networks are those of the whole
+    submitted window, against the oracle; a read of a held server releases
+    the hold, and a drain while held is refused."""
+    c = synth.base_config(n_nodes=300, n_samples=500, window_trials=6, n_fft=512, f_lo_hz=8, f_hi_hz=30,
+                          metrics=synth.ALL8)
+    x = synth.c4_trials(c, 21, 17).astype(np.float32)
+    srv = fcx.Server(1 << 36)
+    st, s = srv.open(c)
+    fcx.check(st)
+    done = 0
+    for burst in (3, 9, 5):
+        fcx.check(srv.hold(burst == 9))     # the 9 are queued while held: the read releases the hold
+        for k in range(done, done + burst):
+            srv.submit(s, np.ascontiguousarray(x[k]))
+        done += burst
+        if burst == 9:
+            assert fcx.lib.fcx_server_drain(srv.h) == fcx.FCX_E_BUSY   # held with trials pending
+        W = c["window_trials"]
+        ref = oracle.network(x[max(0, done - W):done].astype(np.float64), c)
+        compare_network(s, ref, c, ALL, label=f"read after {done} submitted")
     fcx.check(s.close())
     fcx.check(srv.destroy())
