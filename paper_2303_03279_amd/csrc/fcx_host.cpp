@@ -86,7 +86,7 @@ fcx_status make_geometry(const fcx_config *c, Geometry *g)
 size_t BufferPlan::total() const
 {
     size_t t = ring + psd + gsum + out + ctl + wtw + lamw + tiles + zring + rsum + xbuf;
-    t += xtw + xspec + xsuf + xval + xsum;
+    t += xtw + xtwi + xspec + xpair + xrho + xval + xsum;
     for (int i = 0; i < NPLANES; ++i)
         if (planes_used[i]) t += (i == P_URE || i == P_UIM) ? uplane : plane;
     return t;
@@ -137,9 +137,12 @@ BufferPlan make_plan(const fcx_config &c, const Geometry &g)
     if (m & (M_COR | M_XCOR)) p.zring = align256(slots * g.N * g.Mz * 4);
     if (m & M_COR) p.rsum = align256((size_t)g.ntiles * TILE_PAIRS * 8);
     if (m & M_XCOR) {
-        p.xtw = align256((size_t)g.xF * 8);
-        p.xspec = align256((size_t)g.N * (g.xF / 2 + 1) * 8);
-        p.xsuf = align256((size_t)g.N * (g.xL + 1) * 4);
+        const size_t np = (size_t)(g.N + 1) / 2;   // node pairs (2p, 2p + 1)
+        p.xtw = align256((size_t)g.xF * 16);
+        p.xtwi = align256((size_t)xcor_tw_len(g.xF) * 8);
+        p.xspec = align256(2 * np * (g.xF / 2 + 1) * 8);
+        p.xpair = align256(np * g.xF * 8);
+        p.xrho = align256(2 * np * g.xF * 4);
         p.xval = align256(slots * g.ntiles * TILE_PAIRS * 4);
         p.xsum = align256((size_t)g.ntiles * TILE_PAIRS * 8);
     }
@@ -449,19 +452,32 @@ fcx_status session_alloc(Session *s)
     ALLOC(rsum, p.rsum);
     ALLOC(xbuf, p.xbuf);
     ALLOC(xtw, p.xtw);
+    ALLOC(xtwi, p.xtwi);
     ALLOC(xspec, p.xspec);
-    ALLOC(xsuf, p.xsuf);
+    ALLOC(xpair, p.xpair);
+    ALLOC(xrho, p.xrho);
     ALLOC(xval, p.xval);
     ALLOC(xsum, p.xsum);
 #undef ALLOC
     if (p.xtw) {
-        std::vector<float2> tw(g.xF);
+        std::vector<double2> tw(g.xF);
         for (int m = 0; m < g.xF; ++m) {
             double c, sn;
             unit_root(m, g.xF, &c, &sn);
-            tw[m] = make_float2((float)c, (float)sn);
+            tw[m] = make_double2(c, sn);
         }
-        HIP_OK(hipMemcpyAsync(s->xtw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, s->stream));
+        HIP_OK(hipMemcpyAsync(s->xtw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, s->stream));
+        // inverse-FFT pass twiddles exp(+2 pi i r k / (R NS)) = conj(exp(-2 pi i r k (F / (R NS)) / F))
+        std::vector<float2> twi;
+        for (int i = 0; i < xcor_npass(g.xF); ++i) {
+            const int R = xcor_pass_r(g.xF, i), NS = xcor_pass_ns(g.xF, i);
+            for (int r = 1; r < R; ++r)
+                for (int k = 0; k < NS; ++k) {
+                    const double2 w = tw[(size_t)r * k * (g.xF / (R * NS))];
+                    twi.push_back(make_float2((float)w.x, (float)-w.y));
+                }
+        }
+        HIP_OK(hipMemcpyAsync(s->xtwi, twi.data(), twi.size() * sizeof(float2), hipMemcpyHostToDevice, s->stream));
         HIP_OK(hipMemsetAsync(s->xsum, 0, p.xsum, s->stream));
         HIP_OK(hipStreamSynchronize(s->stream));
     }
@@ -528,8 +544,10 @@ template <typename T> SessDev<T> session_dev(const Session *s, const void *x, lo
     d.xL = g.xL;
     d.xF = g.xF;
     d.xtw = s->xtw;
+    d.xtwi = s->xtwi;
     d.xspec = s->xspec;
-    d.xsuf = s->xsuf;
+    d.xpair = s->xpair;
+    d.xrho = s->xrho;
     d.xval = s->xval;
     d.xsum = s->xsum;
     return d;

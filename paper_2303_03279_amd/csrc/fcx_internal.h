@@ -29,6 +29,28 @@ enum : uint32_t { M_COH = 1, M_IMCOH = 2, M_PLV = 4, M_PLI = 8, M_WPLI = 16, M_U
 // XCOR: largest FFT length (LDS of one wavefront's transform)
 constexpr int XCOR_MAX_F = 2048;
 
+// XCOR inverse FFT of length F (256..2048) by one wavefront: a first pass of
+// radix xcor_r1(F), then xcor_npass(F) passes of radix xcor_pass_r(F, i) over
+// strides xcor_pass_ns(F, i) (product of the radices before it).  The
+// twiddles of those passes, exp(+2 pi i r k / (R NS)) for r = 1..R-1 and
+// k < NS, are stored pass after pass, [r - 1][k] within a pass, in a table of
+// xcor_tw_len(F) entries.
+__host__ __device__ constexpr int xcor_r1(int F) { return F >= 1024 ? 16 : F / 64; }
+__host__ __device__ constexpr int xcor_npass(int F) { return F == 256 ? 3 : 2; }
+__host__ __device__ constexpr int xcor_pass_r(int F, int i)
+{
+    return F == 256 ? 4 : F == 512 ? 8 : i == 0 ? 16 : F / 256;
+}
+__host__ __device__ constexpr int xcor_pass_ns(int F, int i)
+{
+    return F == 256 ? (i == 0 ? 4 : i == 1 ? 16 : 64) : F == 512 ? (i == 0 ? 8 : 64) : (i == 0 ? 16 : 256);
+}
+__host__ __device__ constexpr int xcor_tw_off(int F, int i)
+{
+    return i == 0 ? 0 : xcor_tw_off(F, i - 1) + (xcor_pass_r(F, i - 1) - 1) * xcor_pass_ns(F, i - 1);
+}
+__host__ __device__ constexpr int xcor_tw_len(int F) { return xcor_tw_off(F, xcor_npass(F)); }
+
 // Device-resident push control.  Every kernel of a push reads it; only the
 // commit kernel advances it, so a rejected (non-finite) trial changes nothing.
 struct DevCtl {
@@ -68,9 +90,16 @@ struct SessDev {
                             // served session's coalesced group; x then holds nt
                             // trials, N x ldx elements apart)
     int xL, xF;             // XCOR: lags -xL..xL, FFT length (power of 2 >= M + xL)
-    const float2 *xtw;      // [xF] exp(-2 pi i m / xF)
-    float2 *xspec;          // [N][xF/2+1] spectrum of the trial's z-scored samples
-    float *xsuf;            // [N][xL+1] 1/sqrt(energy of the z-scored samples from tau on)
+    const double2 *xtw;     // [xF] exp(-2 pi i m / xF)
+    const float2 *xtwi;     // [xcor_tw_len(xF)] twiddles of the inverse FFT's passes
+    // the trial's z-scored samples of node n scaled to unit energy (u = z / sqrt(E),
+    // E = sum z^2; u = 0 if E = 0), for N rounded up to even (a missing last
+    // node is 0):
+    float2 *xspec;          // [N][xF/2+1] U(f) / xF, f = 0..xF/2
+    float2 *xpair;          // [N/2][xF] U_2p(f) - i U_2p+1(f) over the full circle
+    float *xrho;            // [N][xF] lag factor sqrt(E / S(tau)), S(tau) = sum_{t >= tau} z^2,
+                            // at index tau (tau <= xL) and xF - tau (1 <= tau <= xL);
+                            // 0 where S = 0, NaN at the indices of no lag
     float *xval;            // [(W+1)][ntiles][TILE_PAIRS] per-trial XCOR maxima
     double *xsum;           // [ntiles][TILE_PAIRS] their running sum over the window
 };

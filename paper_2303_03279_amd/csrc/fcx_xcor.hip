@@ -3,30 +3,35 @@
 // their product, back to the time domain, then the largest correlation over
 // the lags.  Per push, for the trial at the push's ring slot:
 //
-//   k_xcor_node   per node, from its z-scored samples z (zero mean, unit
-//                 energy, already in the COR sample ring): the energies
-//                 S(tau) = sum_{t >= tau} z(t)^2 for tau = 0..L (FP64 sums),
-//                 stored as 1/sqrt(S(tau)) in FP32 (0 for S = 0), and the
-//                 spectrum Z(f) = sum_t z(t) e^{-2 pi i f t/F}, f = 0..F/2,
-//                 F a power of two >= M + L (FP64 sums and phasors, FP32 out)
-//   k_xcor_pair   per pair tile row: for two columns at a time, the product
-//                 spectra of the pairs are packed as H1 + i H2 (both
-//                 Hermitian), one in-LDS inverse FFT of length F yields both
-//                 circular correlations c1 = Re, c2 = Im, which equal the
-//                 linear ones at lags -L..L since F >= M + L; then
-//                   XCOR(tau)  = c(tau) / sqrt(S_i(tau) E_j)        tau = 0..L
-//                   XCOR(-tau) = c(F - tau) / sqrt(S_j(tau) E_i)    tau = 1..L
-//                 (0 where the product of energies is 0), the maximum over
-//                 the 2L+1 lags, and the window sum: + this trial's maximum,
-//                 - the evicted trial's maximum kept in a ring of per-trial
-//                 values, so add and remove cancel exactly.
+//   k_xcor_node   per node pair (2p, 2p + 1), from the z-scored samples z
+//                 (already in the COR sample ring): the suffix energies
+//                 S(tau) = sum_{t >= tau} z(t)^2 in FP64, E = S(0), the lag
+//                 factors rho(tau) = sqrt(E / S(tau)), and the spectra of the
+//                 unit-energy samples u = z / sqrt(E) from one FP64 FFT of
+//                 length F (a power of two >= M + L) of u_2p + i u_2p+1:
+//                 each node's U(f) / F for f = 0..F/2 (row operand) and the
+//                 pair's D(f) = U_2p(f) - i U_2p+1(f) over the full circle
+//                 (column operand), each rounded to FP32 once
+//   k_xcor_pair   per pair-tile row i and column pair (j, j + 1): one
+//                 inverse FFT of A(f) conj(D(f)), A(f) = U_i(f) / F, gives
+//                 c_ij(tau) + i c_i,j+1(tau), the circular correlations of the
+//                 unit-energy samples, equal to the linear ones at lags -L..L
+//                 since F >= M + L; then
+//                   XCOR(tau)  = c(tau) rho_i(tau)        tau = 0..L
+//                   XCOR(-tau) = c(F - tau) rho_j(tau)    tau = 1..L
+//                 which is c / sqrt(S_i(tau) E_j), resp. c / sqrt(E_i S_j(tau)),
+//                 of the z-scored samples (0 where an energy is 0); the maximum
+//                 over the 2L + 1 lags, and the window sum: + this trial's
+//                 maximum, - the evicted trial's maximum kept in a ring of
+//                 per-trial values, so add and remove cancel exactly.
 //
 // The inverse FFT is a mixed-radix Stockham (autosorting) transform done by
-// one wavefront in its own LDS buffer: three passes of radix 16, 16 and 4 at
-// F = 1024 (radix-16 butterflies in registers), each loading its
-// butterflies' inputs, then storing the outputs in place; the wavefronts of
-// a workgroup share the row node's data and the twiddles and never wait for
-// each other.
+// one wavefront in its own LDS buffer, radix 16, 16 and 4 at F = 1024 with
+// the butterflies in registers.  Its first pass takes its inputs straight
+// from the operands (A in LDS, D in registers, loaded while the previous
+// transform ran), and its last pass hands its outputs to the maximum in
+// registers, so a transform makes two trips through LDS.  The lag factors
+// carry NaN at the output indices that are no lag, which the maximum skips.
 #include "fcx_device.h"
 
 #include <math.h>
@@ -35,96 +40,98 @@
 
 namespace fcx {
 
-constexpr int XT = 256;   // threads of both XCOR kernels
+constexpr int XT = 256;   // threads of the node kernel
 
 // ---------------------------------------------------------------------------
-// node pass: one workgroup per node
+// node pass: one workgroup per node pair
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int F>
 __global__ __launch_bounds__(XT) void k_xcor_node(SessDev<T> s)
 {
-    __shared__ float z[XCOR_MAX_F];
-    __shared__ double suf[XCOR_MAX_F];
+    __shared__ double2 buf[2][F];
+    __shared__ float z[2][F];
     if (s.ctl->bad) return;
-    const int node = blockIdx.x, tid = threadIdx.x;
-    const int M = s.M, L = s.xL, F = s.xF;
+    const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int N = s.N, M = s.M, L = s.xL;
+    const int n0 = 2 * p;
+    const bool has1 = n0 + 1 < N;
     const PushView pv = push_view(s, s.ctl->pushed);
-    const float *zr = s.zring + ((size_t)pv.slot_new * s.N + node) * s.Mz;
-    for (int t = tid; t < M; t += XT) z[t] = zr[t];
-    __syncthreads();
-    // bin f: sum_t z(t) exp(-2 pi i f t / F), the phasor advanced by one
-    // FP64 rotation per sample and restarted from its exact value at the
-    // start of each of XSEG segments (independent chains; the rounding of
-    // the rotation grows by at most a few hundred FP64 ulps).  The bins
-    // 1..F/2-1 go round the threads; f = 0 and f = F/2, whose phasors are
-    // exactly +-1, are plain sums over the same segments, taken by the last
-    // thread, which has the fewest rotating bins
-    constexpr int XSEG = 4;
-    float2 *xo = s.xspec + (size_t)node * (F / 2 + 1);
-    const int seg = (M + XSEG - 1) / XSEG;
-    for (int f = 1 + tid; f < F / 2; f += XT) {
-        double sr, ci0;
-        sincospi(-2.0 * (double)f / (double)F, &sr, &ci0);   // one-sample rotation (cos ci0, sin sr)
-        double re[XSEG], im[XSEG], cr[XSEG], cs[XSEG];
-#pragma unroll
-        for (int g = 0; g < XSEG; ++g) {
-            const int m = (int)(((long long)f * (long long)(g * seg)) % F);
-            sincospi(-2.0 * (double)m / (double)F, &cs[g], &cr[g]);
-            re[g] = 0.0;
-            im[g] = 0.0;
-        }
-        for (int u = 0; u < seg; ++u) {
-#pragma unroll
-            for (int g = 0; g < XSEG; ++g) {
-                const int t = g * seg + u;
-                if (t < M) {
-                    const double v = (double)z[t];
-                    re[g] += v * cr[g];
-                    im[g] += v * cs[g];
-                    const double nr = cr[g] * ci0 - cs[g] * sr;
-                    cs[g] = cr[g] * sr + cs[g] * ci0;
-                    cr[g] = nr;
-                }
-            }
-        }
-        double tr = 0.0, ti = 0.0;
-#pragma unroll
-        for (int g = 0; g < XSEG; ++g) {
-            tr += re[g];
-            ti += im[g];
-        }
-        xo[f] = make_float2((float)tr, (float)ti);
+    const float *zr = s.zring + ((size_t)pv.slot_new * N + n0) * s.Mz;
+    for (int t = tid; t < M; t += XT) {
+        z[0][t] = zr[t];
+        z[1][t] = has1 ? zr[s.Mz + t] : 0.f;
     }
-    if (tid == XT - 1) {
-        double d[XSEG], q[XSEG];   // f = 0: sum z(t); f = F/2: sum (-1)^t z(t)
-#pragma unroll
-        for (int g = 0; g < XSEG; ++g) {
-            d[g] = 0.0;
-            q[g] = 0.0;
-            for (int t = g * seg; t < min(M, (g + 1) * seg); ++t) {
-                const double v = (double)z[t];
-                d[g] += v;
-                q[g] += (t & 1) ? -v : v;
-            }
+    __syncthreads();
+    // suffix energies, FP64, wavefront h for node h: lane l sums its segment
+    // of samples from the top, the sum of the segments above it comes from a
+    // scan over the lanes (fixed order), then the lane writes its segment's
+    // suffix sums
+    double *suf = reinterpret_cast<double *>(buf[1]);   // [2][F]
+    if (wv < 2) {
+        const int h = wv;
+        const int seg = (M + 63) / 64;
+        const int t0 = lane * seg, t1 = min(M, t0 + seg);
+        double part = 0.0;
+        for (int t = t1 - 1; t >= t0; --t) part += (double)z[h][t] * (double)z[h][t];
+        double above = __shfl_down(part, 1, 64);
+        if (lane == 63) above = 0.0;
+        for (int off = 1; off < 64; off <<= 1) {
+            const double o = __shfl_down(above, off, 64);
+            if (lane + off < 64) above += o;
         }
-        double td = 0.0, tq = 0.0;
-#pragma unroll
-        for (int g = 0; g < XSEG; ++g) {
-            td += d[g];
-            tq += q[g];
-        }
-        xo[0] = make_float2((float)td, 0.f);
-        xo[F / 2] = make_float2((float)tq, 0.f);
-        // suffix energies, FP64, one thread (deterministic order)
-        double acc = 0.0;
-        for (int t = M - 1; t >= 0; --t) {
-            acc += (double)z[t] * (double)z[t];
-            suf[t] = acc;
+        double acc = above;
+        for (int t = t1 - 1; t >= t0; --t) {
+            acc += (double)z[h][t] * (double)z[h][t];
+            suf[h * F + t] = acc;
         }
     }
     __syncthreads();
-    float *so = s.xsuf + (size_t)node * (L + 1);
-    for (int t = tid; t <= L; t += XT) so[t] = suf[t] > 0.0 ? (float)(1.0 / sqrt(suf[t])) : 0.f;
+    const double E0 = suf[0], E1 = suf[F];
+    // lag factors: index tau < F/2 for lag tau, index F - tau for lag -tau
+    for (int e = tid; e < 2 * F; e += XT) {
+        const int h = e / F, id = e - h * F;
+        const int tau = id < F / 2 ? id : F - id;
+        float v = __builtin_nanf("");
+        if (tau <= L) {
+            const double S = suf[h * F + tau];
+            v = S > 0.0 ? (float)sqrt(suf[h * F] / S) : 0.f;
+        }
+        s.xrho[(size_t)(n0 + h) * F + id] = v;
+    }
+    const double r0 = E0 > 0.0 ? 1.0 / sqrt(E0) : 0.0, r1 = E1 > 0.0 ? 1.0 / sqrt(E1) : 0.0;
+    for (int t = tid; t < F; t += XT)
+        buf[0][t] = t < M ? make_double2(r0 * (double)z[0][t], r1 * (double)z[1][t]) : make_double2(0.0, 0.0);
+    __syncthreads();
+    // forward FFT, radix-2 Stockham passes between the two buffers
+    int src = 0;
+    for (int ns = 1; ns < F; ns *= 2) {
+        const double2 *in = buf[src];
+        double2 *out = buf[src ^ 1];
+        for (int j = tid; j < F / 2; j += XT) {
+            const int k = j & (ns - 1);
+            const double2 a0 = in[j], b = in[j + F / 2];
+            const double2 w = s.xtw[k * (F / (2 * ns))];   // exp(-2 pi i k / (2 ns))
+            const double2 a1 = make_double2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
+            const int o = 2 * (j - k) + k;                  // (j / ns) 2 ns + k
+            out[o] = make_double2(a0.x + a1.x, a0.y + a1.y);
+            out[o + ns] = make_double2(a0.x - a1.x, a0.y - a1.y);
+        }
+        __syncthreads();
+        src ^= 1;
+    }
+    // Y = U0 + i U1: D(f) = U0(f) - i U1(f) = conj(Y(F - f)),
+    // U0(f) = (Y(f) + conj(Y(F - f))) / 2, U1(f) = (Y(f) - conj(Y(F - f))) / 2i
+    const double2 *Y = buf[src];
+    const double sc = 0.5 / (double)F;
+    float2 *x0 = s.xspec + (size_t)n0 * (F / 2 + 1), *x1 = x0 + (F / 2 + 1);
+    for (int f = tid; f < F; f += XT) {
+        const double2 y = Y[f], ym = Y[(F - f) & (F - 1)];
+        s.xpair[(size_t)p * F + f] = make_float2((float)ym.x, (float)-ym.y);
+        if (f <= F / 2) {
+            x0[f] = make_float2((float)((y.x + ym.x) * sc), (float)((y.y - ym.y) * sc));
+            x1[f] = make_float2((float)((y.y + ym.y) * sc), (float)((ym.x - y.x) * sc));
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -135,9 +142,14 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
     return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 
+// a conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b)
+{
+    return make_float2(__builtin_fmaf(a.x, b.x, a.y * b.y), __builtin_fmaf(a.y, b.x, -(a.x * b.y)));
+}
+
 // A transform buffer holds element m at m + m / 32: the pad after every 32
-// elements (256 bytes) spreads the strided stores of the early passes over
-// the LDS banks.
+// elements (256 bytes) spreads the strided stores over the LDS banks.
 constexpr int XPAD_SHIFT = 5;
 __host__ __device__ constexpr int xpad(int m) { return m + (m >> XPAD_SHIFT); }
 template <int F> constexpr int xbuf_len() { return F + (F >> XPAD_SHIFT); }
@@ -147,6 +159,17 @@ __constant__ const float W16_RE[8] = {1.0f, 0.92387953251128674f, 0.707106781186
                                       0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f};
 __constant__ const float W16_IM[8] = {0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f,
                                       1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f};
+
+// o exp(+2 pi i m / R), m < R / 2 known at compile time after unrolling:
+// no arithmetic for m = 0 and for the quarter turn
+template <int R>
+__device__ __forceinline__ float2 wrot(float2 o, int m)
+{
+    if (m == 0) return o;
+    if (4 * m == R) return make_float2(-o.y, o.x);
+    const int w = m * (16 / R);
+    return cmul(o, make_float2(W16_RE[w], W16_IM[w]));
+}
 
 // In-register inverse DFT of R = 4, 8 or 16 points: y_m = sum_r v_r
 // exp(+2 pi i r m / R), split into even and odd halves down to radix 4.
@@ -175,31 +198,28 @@ __device__ __forceinline__ void idft_reg(float2 (&v)[R])
         idft_reg<H>(o);
 #pragma unroll
         for (int m = 0; m < H; ++m) {
-            const int w = m * (16 / R);                  // exp(+2 pi i m / R) = W16^(16 m / R)
-            const float2 t = cmul(o[m], make_float2(W16_RE[w], W16_IM[w]));
+            const float2 t = wrot<R>(o[m], m);
             v[m] = make_float2(e[m].x + t.x, e[m].y + t.y);
             v[m + H] = make_float2(e[m].x - t.x, e[m].y - t.y);
         }
     }
 }
 
-// One pass of radix R of the in-place Stockham (autosorting) inverse FFT by
-// one wavefront; NS = product of the radices before it.  Butterfly j takes
-// Z[j + r F/R] (times exp(+2 pi i r k / (R NS)), k = j mod NS) and writes
-// its R-point DFT to Z[(j / NS) NS R + k + m NS].  A wavefront's LDS
-// operations are performed in order, so all loads of the pass precede its
-// stores; the wave barriers keep the compiler from moving LDS accesses
-// across the phase boundaries.  With the pad every 32 elements both address
-// patterns are one base plus constants (F / R and NS are multiples of 32, or
-// NS < 32 with k + (m NS mod 32) < 32).
+// Stockham pass of radix R over stride NS (product of the radices before it):
+// butterfly j takes Z[j + r F / R] (times exp(+2 pi i r k / (R NS)),
+// k = j mod NS, from the table T laid out [r - 1][k]) and its R-point DFT
+// goes to Z[(j / NS) NS R + k + m NS].  Loads: xpass_load; the DFT and the
+// stores: xpass_store.  A wavefront's LDS operations are performed in order,
+// so all loads of a pass precede its stores; the wave barriers keep the
+// compiler from moving LDS accesses across the phase boundaries.  With the
+// pad every 32 elements both address patterns are one base plus constants
+// (F / R and NS are multiples of 32, or NS < 32 with k + (m NS mod 32) < 32).
 template <int F, int R, int NS>
-__device__ __forceinline__ void xpass(float2 *Z, const float2 *tw, int lane)
+__device__ __forceinline__ void xpass_load(const float2 *Z, const float2 *T, int lane,
+                                           float2 (&v)[F / R / 64][R])
 {
-    constexpr int NB = F / R;                   // butterflies
-    constexpr int PER = NB / 64;                // per lane
-    constexpr int STEP = F / (R * NS);          // twiddle stride
+    constexpr int NB = F / R, PER = NB / 64;
     static_assert(NB % 64 == 0 && NB % 32 == 0, "butterflies per lane");
-    float2 v[PER][R];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int j = lane + 64 * q;
@@ -208,15 +228,16 @@ __device__ __forceinline__ void xpass(float2 *Z, const float2 *tw, int lane)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             float2 a = zi[r * NB + ((r * NB) >> XPAD_SHIFT)];
-            if (NS > 1 && r) {
-                float2 w = tw[r * k * STEP];
-                w.y = -w.y;                             // inverse: exp(+2 pi i m / F)
-                a = cmul(a, w);
-            }
+            if (NS > 1 && r) a = cmul(a, T[(r - 1) * NS + k]);
             v[q][r] = a;
         }
     }
-    __builtin_amdgcn_wave_barrier();
+}
+
+template <int F, int R, int NS>
+__device__ __forceinline__ void xpass_store(float2 *Z, int lane, float2 (&v)[F / R / 64][R])
+{
+    constexpr int PER = F / R / 64;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int j = lane + 64 * q;
@@ -226,33 +247,16 @@ __device__ __forceinline__ void xpass(float2 *Z, const float2 *tw, int lane)
 #pragma unroll
         for (int m = 0; m < R; ++m) zo[m * NS + ((m * NS) >> XPAD_SHIFT)] = v[q][m];
     }
-    __builtin_amdgcn_wave_barrier();
 }
 
-// In-place inverse DFT (no 1/F) of the padded Z[F] in LDS by one wavefront:
-// radices 4-4-4-4 (F = 256), 8-8-8 (512), 16-16-4 (1024), 16-16-8 (2048).
-template <int F>
-__device__ __forceinline__ void ifft_wave(float2 *Z, const float2 *tw, int lane)
+template <int F, int R, int NS>
+__device__ __forceinline__ void xpass(float2 *Z, const float2 *T, int lane)
 {
-    if constexpr (F == 256) {
-        xpass<F, 4, 1>(Z, tw, lane);
-        xpass<F, 4, 4>(Z, tw, lane);
-        xpass<F, 4, 16>(Z, tw, lane);
-        xpass<F, 4, 64>(Z, tw, lane);
-    } else if constexpr (F == 512) {
-        xpass<F, 8, 1>(Z, tw, lane);
-        xpass<F, 8, 8>(Z, tw, lane);
-        xpass<F, 8, 64>(Z, tw, lane);
-    } else if constexpr (F == 1024) {
-        xpass<F, 16, 1>(Z, tw, lane);
-        xpass<F, 16, 16>(Z, tw, lane);
-        xpass<F, 4, 256>(Z, tw, lane);
-    } else {
-        static_assert(F == 2048, "transform length");
-        xpass<F, 16, 1>(Z, tw, lane);
-        xpass<F, 16, 16>(Z, tw, lane);
-        xpass<F, 8, 256>(Z, tw, lane);
-    }
+    float2 v[F / R / 64][R];
+    xpass_load<F, R, NS>(Z, T, lane, v);
+    __builtin_amdgcn_wave_barrier();
+    xpass_store<F, R, NS>(Z, lane, v);
+    __builtin_amdgcn_wave_barrier();
 }
 
 __device__ __forceinline__ float wave_max(float v)
@@ -261,141 +265,130 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
-// waves per workgroup of the pair kernel (each has its own transform
-// buffer), and whether the twiddles are staged in LDS (up to F = 1024; the
-// 2048-point kernel reads them from the cache to keep three workgroups per CU)
+// waves per workgroup of the pair kernel (each has its own transform buffer)
 template <int F> constexpr int xcor_waves() { return F >= 2048 ? 2 : 4; }
-template <int F> constexpr bool xcor_tw_lds() { return F <= 1024; }
 
 // One workgroup per (tile, row of the tile): row node i against the tile's
-// columns j > i.  The row's spectrum, energies and the twiddles are shared in
-// LDS; each wavefront takes two columns at a time into its own transform.
-// Up to F = 1024 the global loads of a job are issued early: this job's
-// column energies and the next job's column spectra go into registers before
-// the transform, so their latency overlaps it.  NL = F / 128 lag registers
-// per lane (L + 1 <= F / 2).
-template <int F> constexpr bool xcor_prefetch() { return F <= 1024; }
-
-template <typename T, int F, int NL>
+// columns j > i, two columns (a node pair 2p, 2p + 1) per transform.  The
+// row operand A (full circle), the twiddles and the row's lag factors are
+// set up once; each wavefront takes column pairs in turn into its own
+// transform buffer, loading the next pair's D into registers while it
+// transforms the current one.
+template <typename T, int F>
 __global__ __launch_bounds__(64 * xcor_waves<F>()) __attribute__((amdgpu_waves_per_eu(F == 1024 ? 3 : 1)))
 void k_xcor_pair(SessDev<T> s)
 {
     constexpr int NW = xcor_waves<F>();
-    constexpr int NF = (F / 2 + 1 + 63) / 64;   // spectrum bins per lane
+    constexpr int R1 = xcor_r1(F), NB1 = F / R1, PER1 = NB1 / 64;
+    constexpr int NP = xcor_npass(F);
+    constexpr int RL = xcor_pass_r(F, NP - 1), NSL = xcor_pass_ns(F, NP - 1), PERL = NSL / 64;
+    constexpr int HL = RL / 2;   // outputs m < HL of the last pass are lags >= 0, the rest lags < 0
+    static_assert(NSL * RL == F, "last pass");
     __shared__ float2 Zw[NW][xbuf_len<F>()];
-    __shared__ float2 Rsp[F / 2 + 1];
-    __shared__ float Rsuf[F];
-    __shared__ float2 tws[xcor_tw_lds<F>() ? F : 1];
+    __shared__ float2 A[F];
+    __shared__ float2 tws[xcor_tw_len(F)];
     if (s.ctl->bad) return;
     const int item = xcd_item(blockIdx.x, gridDim.x);
     const int tile = item / TILE, r = item % TILE;
     const int2 tt = s.tiles[tile];
-    const int N = s.N, L = s.xL, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int N = s.N, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int i = tt.x * TILE + r, J0 = tt.y * TILE;
     if (i >= N) return;
-    const int jlo = max(J0, i + 1), jhi = min(J0 + TILE, N);
-    if (jlo >= jhi) return;
+    // column pairs (J0 + 2p, J0 + 2p + 1) that hold a column j > i, j < N
+    const int jend = min(J0 + TILE, N);
+    const int plo = (max(J0, i + 1) - J0) >> 1, phi = (jend - J0 + 1) >> 1;
+    if (plo >= phi) return;
     const PushView pv = push_view(s, s.ctl->pushed);
-    for (int f = tid; f <= F / 2; f += 64 * NW) Rsp[f] = s.xspec[(size_t)i * (F / 2 + 1) + f];
-    for (int t = tid; t <= L; t += 64 * NW) Rsuf[t] = s.xsuf[(size_t)i * (L + 1) + t];
-    if constexpr (xcor_tw_lds<F>())
-        for (int m = tid; m < F; m += 64 * NW) tws[m] = s.xtw[m];
+    {
+        const float2 *xs = s.xspec + (size_t)i * (F / 2 + 1);
+        for (int f = tid; f < F; f += 64 * NW) {
+            const float2 a = xs[f <= F / 2 ? f : F - f];
+            A[f] = f <= F / 2 ? a : make_float2(a.x, -a.y);
+        }
+        for (int e = tid; e < xcor_tw_len(F); e += 64 * NW) tws[e] = s.xtwi[e];
+    }
+    // the row's lag factors at this lane's outputs of lags >= 0
+    float rowf[PERL][HL];
+    {
+        const float *rho = s.xrho + (size_t)i * F;
+#pragma unroll
+        for (int q = 0; q < PERL; ++q)
+#pragma unroll
+            for (int m = 0; m < HL; ++m) rowf[q][m] = rho[lane + 64 * q + NSL * m];
+    }
     __syncthreads();
     float2 *Z = Zw[wv];
-    const float rEi = Rsuf[0];   // 1/sqrt of node i's energy (0 if none)
-    const float invF = 1.0f / (float)F;
     const size_t TP = (size_t)s.ntiles * TILE_PAIRS;
     const size_t P = (size_t)N * (N - 1) / 2;
-    // column spectra of a job (j, j + 1 or none) into registers
-    float2 b1[xcor_prefetch<F>() ? NF : 1], b2[xcor_prefetch<F>() ? NF : 1];
-    auto load_spec = [&](int j) {
-        const int j2 = j + 1 < jhi ? j + 1 : -1;
-        const float2 *c1p = s.xspec + (size_t)j * (F / 2 + 1);
-        const float2 *c2p = s.xspec + (size_t)(j2 >= 0 ? j2 : j) * (F / 2 + 1);
+    const int c0 = (J0 >> 1);   // node pair index of column J0
+    float2 d[PER1][R1];
+    auto load_d = [&](int pp) {
+        const float2 *dp = s.xpair + (size_t)(c0 + pp) * F;
 #pragma unroll
-        for (int q = 0; q < NF; ++q) {
-            const int f = lane + 64 * q;
-            b1[q] = make_float2(0.f, 0.f);
-            b2[q] = b1[q];
-            if (f <= F / 2) {
-                b1[q] = c1p[f];
-                if (j2 >= 0) b2[q] = c2p[f];
-            }
-        }
+        for (int q = 0; q < PER1; ++q)
+#pragma unroll
+            for (int rr = 0; rr < R1; ++rr) d[q][rr] = dp[lane + 64 * q + NB1 * rr];
     };
-    // Z = H1 + i H2 over the full circle, H = X_i conj(X_j) (Hermitian)
-    auto put = [&](int f, float2 a, float2 c1, float2 c2) {
-        const float h1r = __builtin_fmaf(a.x, c1.x, a.y * c1.y), h1i = __builtin_fmaf(a.y, c1.x, -(a.x * c1.y));
-        const float h2r = __builtin_fmaf(a.x, c2.x, a.y * c2.y), h2i = __builtin_fmaf(a.y, c2.x, -(a.x * c2.y));
-        Z[xpad(f)] = make_float2(h1r - h2i, h1i + h2r);
-        if (f > 0 && f < F / 2) Z[xpad(F - f)] = make_float2(h1r + h2i, h2r - h1i);
-    };
-    int j = jlo + 2 * wv;
-    if constexpr (xcor_prefetch<F>())
-        if (j < jhi) load_spec(j);
-    for (; j < jhi; j += 2 * NW) {
-        const int j2 = j + 1 < jhi ? j + 1 : -1;
-        if constexpr (xcor_prefetch<F>()) {
+    int pp = plo + wv;
+    if (pp < phi) load_d(pp);
+    for (; pp < phi; pp += NW) {
+        const int j1 = J0 + 2 * pp, j2 = j1 + 1;
+        // this job's column lag factors (lags < 0), used after the transform
+        float cf1[PERL][HL], cf2[PERL][HL];
+        {
+            const float *r1p = s.xrho + (size_t)j1 * F, *r2p = r1p + F;
 #pragma unroll
-            for (int q = 0; q < NF; ++q) {
-                const int f = lane + 64 * q;
-                if (f <= F / 2) put(f, Rsp[f], b1[q], b2[q]);
-            }
-        } else {
-            const float2 *c1p = s.xspec + (size_t)j * (F / 2 + 1);
-            const float2 *c2p = s.xspec + (size_t)(j2 >= 0 ? j2 : j) * (F / 2 + 1);
-            for (int f = lane; f <= F / 2; f += 64)
-                put(f, Rsp[f], c1p[f], j2 >= 0 ? c2p[f] : make_float2(0.f, 0.f));
-        }
-        // this job's column energies, then the next job's spectra
-        const float *s1 = s.xsuf + (size_t)j * (L + 1);
-        const float *s2 = s.xsuf + (size_t)(j2 >= 0 ? j2 : j) * (L + 1);
-        const float rE1 = s1[0], rE2 = j2 >= 0 ? s2[0] : 0.f;
-        float e1[xcor_prefetch<F>() ? NL : 1], e2[xcor_prefetch<F>() ? NL : 1];
-        if constexpr (xcor_prefetch<F>()) {
+            for (int q = 0; q < PERL; ++q)
 #pragma unroll
-            for (int q = 0; q < NL; ++q) {
-                const int tau = lane + 64 * q;
-                e1[q] = tau <= L ? s1[tau] : 0.f;
-                e2[q] = tau <= L && j2 >= 0 ? s2[tau] : 0.f;
-            }
+                for (int m = 0; m < HL; ++m) {
+                    cf1[q][m] = r1p[lane + 64 * q + NSL * (m + HL)];
+                    cf2[q][m] = r2p[lane + 64 * q + NSL * (m + HL)];
+                }
         }
-        if constexpr (xcor_prefetch<F>())
-            if (j + 2 * NW < jhi) load_spec(j + 2 * NW);
+        // first pass: inputs A(f) conj(D(f)) at f = b + NB1 r
+        {
+            float2 v[PER1][R1];
+#pragma unroll
+            for (int q = 0; q < PER1; ++q)
+#pragma unroll
+                for (int rr = 0; rr < R1; ++rr) v[q][rr] = cmulc(A[lane + 64 * q + NB1 * rr], d[q][rr]);
+            if (pp + NW < phi) load_d(pp + NW);
+            xpass_store<F, R1, 1>(Z, lane, v);
+            __builtin_amdgcn_wave_barrier();
+        }
+        // middle passes
+        if constexpr (NP == 3) xpass<F, xcor_pass_r(F, 0), xcor_pass_ns(F, 0)>(Z, tws + xcor_tw_off(F, 0), lane);
+        if constexpr (NP == 3) xpass<F, xcor_pass_r(F, 1), xcor_pass_ns(F, 1)>(Z, tws + xcor_tw_off(F, 1), lane);
+        if constexpr (NP == 2) xpass<F, xcor_pass_r(F, 0), xcor_pass_ns(F, 0)>(Z, tws + xcor_tw_off(F, 0), lane);
+        // last pass: its outputs j + NSL m (j = lane + 64 q) stay in registers
+        float2 y[PERL][RL];
+        xpass_load<F, RL, NSL>(Z, tws + xcor_tw_off(F, NP - 1), lane, y);
         __builtin_amdgcn_wave_barrier();
-        ifft_wave<F>(Z, xcor_tw_lds<F>() ? tws : s.xtw, lane);
-        // largest XCOR over the lags, both pairs
-        // XCOR = c / F * (1/sqrt S_advanced(tau)) * (1/sqrt E_other)
-        float best1 = -INFINITY, best2 = -INFINITY;
 #pragma unroll
-        for (int q = 0; q < NL; ++q) {
-            const int tau = lane + 64 * q;
-            if (tau <= L) {
-                const float2 p = Z[xpad(tau)];
-                const float ri = Rsuf[tau];
-                best1 = fmaxf(best1, p.x * invF * ri * rE1);
-                best2 = fmaxf(best2, p.y * invF * ri * rE2);
-                if (tau > 0) {
-                    const float2 qv = Z[xpad(F - tau)];
-                    float f1, f2;
-                    if constexpr (xcor_prefetch<F>()) {
-                        f1 = e1[q];
-                        f2 = e2[q];
-                    } else {
-                        f1 = s1[tau];
-                        f2 = j2 >= 0 ? s2[tau] : 0.f;
-                    }
-                    best1 = fmaxf(best1, qv.x * invF * f1 * rEi);
-                    if (j2 >= 0) best2 = fmaxf(best2, qv.y * invF * f2 * rEi);
+        for (int q = 0; q < PERL; ++q) idft_reg<RL>(y[q]);
+        // largest XCOR over the lags of both pairs (the factors are NaN at
+        // indices of no lag, which fmaxf skips)
+        float b1 = -INFINITY, b2 = -INFINITY, e1 = -INFINITY, e2 = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < PERL; ++q)
+#pragma unroll
+            for (int m = 0; m < RL; ++m) {
+                const float f1 = m < HL ? rowf[q][m] : cf1[q][m - HL];
+                const float f2 = m < HL ? rowf[q][m] : cf2[q][m - HL];
+                if (m & 1) {
+                    e1 = fmaxf(e1, y[q][m].x * f1);
+                    e2 = fmaxf(e2, y[q][m].y * f2);
+                } else {
+                    b1 = fmaxf(b1, y[q][m].x * f1);
+                    b2 = fmaxf(b2, y[q][m].y * f2);
                 }
             }
-        }
-        best1 = wave_max(best1);
-        best2 = wave_max(best2);
+        b1 = wave_max(fmaxf(b1, e1));
+        b2 = wave_max(fmaxf(b2, e2));
         if (lane < 2) {
-            const int jj = lane == 0 ? j : j2;
-            if (jj >= 0) {
-                const float v = lane == 0 ? best1 : best2;
+            const int jj = lane == 0 ? j1 : j2;
+            if (jj > i && jj < N) {
+                const float v = lane == 0 ? b1 : b2;
                 const size_t e = (size_t)tile * TILE_PAIRS + (size_t)r * TILE + (jj - J0);
                 double sum = s.xsum[e] + (double)v;
                 if (pv.has_old) sum = sum - (double)s.xval[(size_t)pv.slot_old * TP + e];
@@ -409,17 +402,22 @@ void k_xcor_pair(SessDev<T> s)
     }
 }
 
+template <typename T, int F> static void launch_xcor_f(const SessDev<T> &s, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_xcor_node<T, F>), dim3((s.N + 1) / 2), dim3(XT), 0, st, s);
+    hipLaunchKernelGGL((k_xcor_pair<T, F>), dim3((unsigned)(s.ntiles * TILE)), dim3(64 * xcor_waves<F>()), 0, st,
+                       s);
+}
+
 template <typename T> hipError_t launch_xcor(const SessDev<T> &s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_xcor_node<T>, dim3(s.N), dim3(XT), 0, st, s);
-    const dim3 grid((unsigned)(s.ntiles * TILE));
-    // lag registers: L <= M - 1 and M + L <= F give L + 1 <= F / 2
-    if (2 * (s.xL + 1) > s.xF) return hipErrorInvalidValue;
+    // the lag ranges of the last pass's output halves: L < F / 2
+    if (2 * s.xL >= s.xF) return hipErrorInvalidValue;
     switch (s.xF) {
-    case 256: hipLaunchKernelGGL((k_xcor_pair<T, 256, 2>), grid, dim3(64 * xcor_waves<256>()), 0, st, s); break;
-    case 512: hipLaunchKernelGGL((k_xcor_pair<T, 512, 4>), grid, dim3(64 * xcor_waves<512>()), 0, st, s); break;
-    case 1024: hipLaunchKernelGGL((k_xcor_pair<T, 1024, 8>), grid, dim3(64 * xcor_waves<1024>()), 0, st, s); break;
-    case 2048: hipLaunchKernelGGL((k_xcor_pair<T, 2048, 16>), grid, dim3(64 * xcor_waves<2048>()), 0, st, s); break;
+    case 256: launch_xcor_f<T, 256>(s, st); break;
+    case 512: launch_xcor_f<T, 512>(s, st); break;
+    case 1024: launch_xcor_f<T, 1024>(s, st); break;
+    case 2048: launch_xcor_f<T, 2048>(s, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
