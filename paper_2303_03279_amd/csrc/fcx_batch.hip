@@ -373,27 +373,39 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, in
             if (needU)
                 pb_gram<PREC, true>(nullptr, Us, Us + 64 * PB_LD, Uh, arow, bcol0, arow, 64 + bcol0, lg, ure, uim);
             if constexpr (VS) {
-                for (int t4 = 0; t4 < nk; t4 += 4) {   // columns past the trials are 0 and add nothing
+                // trial t's operands are loaded while trial t - 1 is summed;
+                // columns past the trials are 0 and add nothing, and the pad
+                // column PB_CC is loaded but never summed
+                const double2 *xrp = Xr + rbase * PB_LD;
+                const float2 *ycp = Xc + cbase * PB_LD;
+                auto ldt = [&](int t, double2 (&xr)[4], float2 (&yc)[2]) {
 #pragma unroll
-                    for (int tq = 0; tq < 4; ++tq) {
-                        const int t = t4 + tq;
-                        const float2 y0 = Xc[cbase * PB_LD + t];
-                        const float2 y1 = Xc[(cbase + 16) * PB_LD + t];
-                        const double jx[2] = {y0.x, y1.x}, jy[2] = {y0.y, y1.y};
+                    for (int k = 0; k < 4; ++k) xr[k] = xrp[4 * k * PB_LD + t];
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const double2 xi = Xr[(rbase + 4 * k) * PB_LD + t];
+                    for (int c = 0; c < 2; ++c) yc[c] = ycp[16 * c * PB_LD + t];
+                };
+                auto sum_t = [&](const double2 (&xr)[4], const float2 (&yc)[2]) {
+                    const double jx[2] = {yc[0].x, yc[1].x}, jy[2] = {yc[0].y, yc[1].y};
 #pragma unroll
-                            for (int c = 0; c < 2; ++c) {
-                                const double v = __builtin_fma(xi.y, jx[c], __builtin_fma(-xi.x, jy[c], 0.0));
-                                const int p = 2 * k + c;
-                                G[p] += sign_of_f64(v);
-                                Av[p] = Av[p] + fabs(v);
-                                Qv[p] = __builtin_fma(v, v, Qv[p]);
-                                Sv[p] = Sv[p] + v;
-                            }
+                    for (int k = 0; k < 4; ++k)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const double v = __builtin_fma(xr[k].y, jx[c], __builtin_fma(-xr[k].x, jy[c], 0.0));
+                            const int p = 2 * k + c;
+                            G[p] += sign_of_f64(v);
+                            Av[p] = Av[p] + fabs(v);
+                            Qv[p] = __builtin_fma(v, v, Qv[p]);
+                            Sv[p] = Sv[p] + v;
                         }
-                    }
+                };
+                double2 ra[4], rb[4];
+                float2 ca[2], cb[2];
+                ldt(0, ra, ca);
+                for (int t = 0; t < nk; t += 2) {
+                    ldt(t + 1, rb, cb);
+                    sum_t(ra, ca);
+                    ldt(min(t + 2, PB_CC), ra, ca);
+                    sum_t(rb, cb);
                 }
             }
         }

@@ -196,11 +196,25 @@ __device__ __forceinline__ void idft_reg(float2 (&v)[R])
         }
         idft_reg<H>(e);
         idft_reg<H>(o);
+        constexpr float C = 0.70710678118654752f;   // sqrt(1/2)
 #pragma unroll
         for (int m = 0; m < H; ++m) {
-            const float2 t = wrot<R>(o[m], m);
-            v[m] = make_float2(e[m].x + t.x, e[m].y + t.y);
-            v[m + H] = make_float2(e[m].x - t.x, e[m].y - t.y);
+            if (8 * m == R || 8 * m == 3 * R) {
+                // exp(+2 pi i m / R) = (+-C, C): e +- o w from o.x - o.y and
+                // o.x + o.y by fused multiply-adds
+                const float dx = o[m].x - o[m].y, sx = o[m].x + o[m].y;
+                if (8 * m == R) {   // w = (C, C): o w = (C dx, C sx)
+                    v[m] = make_float2(__builtin_fmaf(C, dx, e[m].x), __builtin_fmaf(C, sx, e[m].y));
+                    v[m + H] = make_float2(__builtin_fmaf(-C, dx, e[m].x), __builtin_fmaf(-C, sx, e[m].y));
+                } else {            // w = (-C, C): o w = (-C sx, C dx)
+                    v[m] = make_float2(__builtin_fmaf(-C, sx, e[m].x), __builtin_fmaf(C, dx, e[m].y));
+                    v[m + H] = make_float2(__builtin_fmaf(C, sx, e[m].x), __builtin_fmaf(-C, dx, e[m].y));
+                }
+            } else {
+                const float2 t = wrot<R>(o[m], m);
+                v[m] = make_float2(e[m].x + t.x, e[m].y + t.y);
+                v[m + H] = make_float2(e[m].x - t.x, e[m].y - t.y);
+            }
         }
     }
 }
@@ -291,7 +305,8 @@ void k_xcor_pair(SessDev<T> s)
     const int item = xcd_item(blockIdx.x, gridDim.x);
     const int tile = item / TILE, r = item % TILE;
     const int2 tt = s.tiles[tile];
-    const int N = s.N, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int N = s.N, tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: job indices live in scalar registers
     const int i = tt.x * TILE + r, J0 = tt.y * TILE;
     if (i >= N) return;
     // column pairs (J0 + 2p, J0 + 2p + 1) that hold a column j > i, j < N
@@ -307,44 +322,49 @@ void k_xcor_pair(SessDev<T> s)
         }
         for (int e = tid; e < xcor_tw_len(F); e += 64 * NW) tws[e] = s.xtwi[e];
     }
+    // the column operands and lag factors through buffer resources: a uniform
+    // job offset in a scalar register, the lane's offset, constants
+    const int np = (N + 1) / 2;
+    const Rsrc dres = tile_rsrc(s.xpair, (uint32_t)((size_t)np * F * 8));
+    const Rsrc rres = tile_rsrc(s.xrho, (uint32_t)((size_t)2 * np * F * 4));
     // the row's lag factors at this lane's outputs of lags >= 0
     float rowf[PERL][HL];
-    {
-        const float *rho = s.xrho + (size_t)i * F;
 #pragma unroll
-        for (int q = 0; q < PERL; ++q)
+    for (int q = 0; q < PERL; ++q)
 #pragma unroll
-            for (int m = 0; m < HL; ++m) rowf[q][m] = rho[lane + 64 * q + NSL * m];
-    }
+        for (int m = 0; m < HL; ++m)
+            rowf[q][m] = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(rres, 4 * (lane + 64 * q + NSL * m), i * F * 4, 0));
     __syncthreads();
     float2 *Z = Zw[wv];
     const size_t TP = (size_t)s.ntiles * TILE_PAIRS;
     const size_t P = (size_t)N * (N - 1) / 2;
+    const double invK = 1.0 / (double)pv.K;
     const int c0 = (J0 >> 1);   // node pair index of column J0
-    float2 d[PER1][R1];
-    auto load_d = [&](int pp) {
-        const float2 *dp = s.xpair + (size_t)(c0 + pp) * F;
+    auto load_d = [&](int pp, float2 (&d)[PER1][R1]) {
 #pragma unroll
         for (int q = 0; q < PER1; ++q)
 #pragma unroll
-            for (int rr = 0; rr < R1; ++rr) d[q][rr] = dp[lane + 64 * q + NB1 * rr];
+            for (int rr = 0; rr < R1; ++rr)
+                d[q][rr] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(
+                                                          dres, 8 * (lane + 64 * q), ((c0 + pp) * F + NB1 * rr) * 8, 0));
     };
-    int pp = plo + wv;
-    if (pp < phi) load_d(pp);
-    for (; pp < phi; pp += NW) {
+    // one column pair: transform with operand d, loading the operand of pair
+    // pn (if any) into dn once d is consumed
+    auto job = [&](int pp, float2 (&d)[PER1][R1], int pn, float2 (&dn)[PER1][R1]) {
         const int j1 = J0 + 2 * pp, j2 = j1 + 1;
         // this job's column lag factors (lags < 0), used after the transform
         float cf1[PERL][HL], cf2[PERL][HL];
-        {
-            const float *r1p = s.xrho + (size_t)j1 * F, *r2p = r1p + F;
 #pragma unroll
-            for (int q = 0; q < PERL; ++q)
+        for (int q = 0; q < PERL; ++q)
 #pragma unroll
-                for (int m = 0; m < HL; ++m) {
-                    cf1[q][m] = r1p[lane + 64 * q + NSL * (m + HL)];
-                    cf2[q][m] = r2p[lane + 64 * q + NSL * (m + HL)];
-                }
-        }
+            for (int m = 0; m < HL; ++m) {
+                const int o = 4 * (lane + 64 * q);
+                cf1[q][m] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(rres, o, (j1 * F + NSL * (m + HL)) * 4, 0));
+                cf2[q][m] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(rres, o, (j2 * F + NSL * (m + HL)) * 4, 0));
+            }
         // first pass: inputs A(f) conj(D(f)) at f = b + NB1 r
         {
             float2 v[PER1][R1];
@@ -352,7 +372,7 @@ void k_xcor_pair(SessDev<T> s)
             for (int q = 0; q < PER1; ++q)
 #pragma unroll
                 for (int rr = 0; rr < R1; ++rr) v[q][rr] = cmulc(A[lane + 64 * q + NB1 * rr], d[q][rr]);
-            if (pp + NW < phi) load_d(pp + NW);
+            if (pn < phi) load_d(pn, dn);
             xpass_store<F, R1, 1>(Z, lane, v);
             __builtin_amdgcn_wave_barrier();
         }
@@ -395,10 +415,20 @@ void k_xcor_pair(SessDev<T> s)
                 s.xsum[e] = sum;
                 s.xval[(size_t)pv.slot_new * TP + e] = v;
                 const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(jj - i - 1);
-                s.out[8 * P + idx] = (T)(sum / (double)pv.K);
+                s.out[8 * P + idx] = (T)(sum * invK);
             }
         }
         __builtin_amdgcn_wave_barrier();   // Z is rebuilt for the next columns
+    };
+    // the jobs of this wavefront two at a time, the operand registers
+    // alternating, so the loads of the next operand need no copies
+    float2 d0[PER1][R1], d1[PER1][R1];
+    int pp = plo + wv;
+    if (pp < phi) load_d(pp, d0);
+    for (; pp < phi; pp += 2 * NW) {
+        job(pp, d0, pp + NW, d1);
+        if (pp + NW >= phi) break;
+        job(pp + NW, d1, pp + 2 * NW, d0);
     }
 }
 
