@@ -244,11 +244,12 @@ def _wait_until(t0, t_arr):
             time.sleep(dt - 0.0004)
 
 
-def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
+def run_serving(fcx, torch, duration_s, plain_s=16.0, seed=4, pool_per_session=6):
     """The serving mix: 64 sessions (N in {60,128,306,1000,2000}, W ~U{10..100},
     random metric subsets), Poisson arrivals at 10 trials/s per session.  The
-    same arrival trace runs through (a) the plain path, one stream and one
-    push per trial per session, and (b) the server's continuous batching.
+    arrival trace runs through (a) the plain path, one stream and one push
+    per trial per session, over its first plain_s seconds, and (b) the
+    server's continuous batching, over all duration_s seconds.
     Latency = submit -> update finished on the device (host clock)."""
     import synth
     sys.setswitchinterval(1e-4)
@@ -272,8 +273,9 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
         fcx.check(p.sync())
     comp = _Completion()
     cursor = [0] * len(sess)
+    na = int(np.searchsorted(ts, min(plain_s, duration_s)))
     t0 = time.perf_counter()
-    for t_arr, k in zip(ts, ss):
+    for t_arr, k in zip(ts[:na], ss[:na]):
         _wait_until(t0, t_arr)
         ts_sub = time.perf_counter()
         fcx.check(plain[k].push_host(trials[k][cursor[k] % pool_per_session]))
@@ -286,9 +288,10 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
     wall_a = time.perf_counter() - t0
     comp.close()
     lat = np.array([d for d, _ in comp.done]) * 1e3
-    out["plain"] = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                        updates_per_s=float(sum(upd[k] for k in ss) / wall_a), wall_s=wall_a,
-                        hbm_frac=offered / wall_a / (HBM_PEAK_GBS * 1e9))
+    offered_a = float(sum(pbytes[k] for k in ss[:na]))
+    out["plain"] = dict(arrivals=na, p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                        updates_per_s=float(sum(upd[k] for k in ss[:na]) / wall_a), wall_s=wall_a,
+                        hbm_frac=offered_a / wall_a / (HBM_PEAK_GBS * 1e9))
     for p in plain:
         p.close()
     torch.cuda.synchronize()
@@ -314,7 +317,7 @@ def run_serving(fcx, torch, duration_s, seed=4, pool_per_session=6):
     srv.drain()
     wall_b = time.perf_counter() - t0
     lat = np.array([srv.poll(t)[1] for t in tickets]) * 1e3
-    out["server"] = dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+    out["server"] = dict(arrivals=int(ts.size), p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                          updates_per_s=float(sum(upd[k] for k in ss) / wall_b), wall_s=wall_b,
                          hbm_frac=offered / wall_b / (HBM_PEAK_GBS * 1e9))
     # (c) burst: every session has `burst` trials queued (submitted while the
@@ -600,8 +603,10 @@ def main():
     ap.add_argument("--resync-reps", type=int, default=2,
                     help="timed one-pass rebuilds of the running sums (fcx_resync) of the 5000-node and "
                          "10000-node windows, 0 to skip")
-    ap.add_argument("--serving-seconds", type=float, default=16.0,
-                    help="serving-mix arrival window (about 650 arrivals/s), 0 to skip")
+    ap.add_argument("--serving-seconds", type=float, default=60.0,
+                    help="serving-mix arrival window of the server (about 650 arrivals/s), 0 to skip")
+    ap.add_argument("--serving-plain-seconds", type=float, default=16.0,
+                    help="the prefix of the same arrivals run through the plain per-session path")
     ap.add_argument("--sensor-pushes", type=int, default=300,
                     help="latency pushes of the 306-sensor session (host input), 0 to skip")
     ap.add_argument("--xcor-steps", type=int, default=5,
@@ -776,7 +781,8 @@ def main():
         pl = kl.get("pair_update", {})
         gl = algorithmic_bytes(fcx, cl) / (pl["avg_ms"] * 1e-3) / 1e9 if pl else None
         large = dict(workload="N=10000 (50M pairs), DPSS NW=2 x 3 tapers, 4-40 Hz (37 bins), W=200 x 1000 "
-                              "samples, all 8 metrics, one push per step",
+                              "samples, all 8 metrics, one push per step; signals: 250 coupled AR(2) generators "
+                              "(20% directed density, lags 1-50 ms) mixed into the 10000 nodes plus white noise",
                      value=Pl * Bl * args.large_steps / wl, ms_per_step=wl * 1e3 / args.large_steps,
                      pair_update_avg_ms=pl.get("avg_ms"), pair_update_gbs=gl, resync_ms=kl.get("resync_ms"),
                      hbm_frac=(gl / HBM_PEAK_GBS) if gl else None,
@@ -792,7 +798,7 @@ def main():
     serving = None
     if args.serving_seconds > 0:
         print("[bench] serving mix", file=sys.stderr, flush=True)
-        serving = run_serving(fcx, torch, args.serving_seconds)
+        serving = run_serving(fcx, torch, args.serving_seconds, args.serving_plain_seconds)
 
     base = None
     if not args.no_cpu_baseline:
