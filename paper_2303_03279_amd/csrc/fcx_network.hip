@@ -5,11 +5,12 @@
 // network).
 //
 // On a packed upper-triangle FP32 network w[P]:
-//   k_sel_scan    max |w| over the finite edges and their count
-//   k_sel_init    k = min(ceil(f P), finite edges)
-//   k_sel_hist    \  three passes (11, 10, 10 bits) of a radix select on the
-//   k_sel_pick    /  bits of |w| (monotone for non-negative floats): the
-//                    exact key T of the k-th strongest edge
+//   k_sel_scan    max |w| over the finite edges, their count, and the
+//                 histogram of the first digit of the radix select below
+//   k_sel_pick    (first) k = min(ceil(f P), finite edges); then for each of
+//   k_sel_hist    the three digits (11, 10, 10 bits) of a radix select on the
+//                 bits of |w| (monotone for non-negative floats), the digit
+//                 of the k-th strongest edge: the exact key T
 //   k_sel_rows    one wavefront per row of the triangle: w / max, the
 //                 selected flags (|w| >= T), their count, and the degree and
 //                 strength of both ends of every selected edge
@@ -112,12 +113,18 @@ __device__ __forceinline__ void sel_for_each(const float *__restrict__ w, long l
     }
 }
 
+// The scan also takes the histogram of the first digit (bits 30..20 of
+// every finite key: no prefix yet), so the first select pass needs no read
+// of its own.
 template <bool VEC>
 __global__ __launch_bounds__(SEL_THREADS) void k_sel_scan(const float *__restrict__ w, long long P, int N, SelCtl *c)
 {
     for (int i = blockIdx.x * SEL_THREADS + threadIdx.x; i < N; i += gridDim.x * SEL_THREADS) c->node[i] = 0;
     __shared__ unsigned int smax[SEL_THREADS / 64];
     __shared__ unsigned long long scnt[SEL_THREADS / 64];
+    __shared__ unsigned int h[SEL_BINS];
+    for (int d = threadIdx.x; d < SEL_BINS; d += SEL_THREADS) h[d] = 0;
+    __syncthreads();
     unsigned int mx = 0;
     unsigned long long nf = 0;
     sel_for_each<VEC>(w, P, [&](long long, float v) {
@@ -125,6 +132,7 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_scan(const float *__restric
         if (sel_key(v, key)) {
             mx = max(mx, key);
             ++nf;
+            atomicAdd(&h[key >> 20], 1u);
         }
     });
     for (int o = 32; o > 0; o >>= 1) {
@@ -145,10 +153,14 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_scan(const float *__restric
         c->blk_max[blockIdx.x] = mx;
         c->blk_nf[blockIdx.x] = nf;
     }
+    unsigned int *g = c->hist[blockIdx.x % SEL_SLOTS];
+    for (int d = threadIdx.x; d < SEL_BINS; d += SEL_THREADS)
+        if (h[d]) atomicAdd(&g[d], h[d]);
 }
 
-// folds the scan blocks' partials (nblk of them) and sets up the selection
-__global__ __launch_bounds__(SEL_THREADS) void k_sel_init(SelCtl *c, int nblk, double fraction, long long P)
+// folds the scan blocks' partials (nblk of them) and sets up the selection;
+// called by every thread of the single-block pick kernel of the first pass
+__device__ __forceinline__ void sel_init(SelCtl *c, int nblk, double fraction, long long P)
 {
     __shared__ unsigned int smax[SEL_THREADS / 64];
     __shared__ unsigned long long scnt[SEL_THREADS / 64];
@@ -183,6 +195,7 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_init(SelCtl *c, int nblk, d
         c->h.prefix = 0;
         c->h.mask = 0;
     }
+    __syncthreads();
 }
 
 // LDS histogram of the digit (key >> shift) & (nb - 1) of the keys that
@@ -211,10 +224,12 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_hist(const float *__restric
 // picks the digit of the k_left-th largest key among those with the prefix
 // (each thread sums a run of nb / 256 bins, then one thread walks the runs
 // from the top), then clears the histograms for the next pass
-__global__ __launch_bounds__(SEL_THREADS) void k_sel_pick(SelCtl *c, int shift, int nb)
+__global__ __launch_bounds__(SEL_THREADS) void k_sel_pick(SelCtl *c, int shift, int nb, int nblk, double fraction,
+                                                        long long P)
 {
     __shared__ unsigned int tot[SEL_BINS];
     __shared__ unsigned long long run[SEL_THREADS];
+    if (nblk > 0) sel_init(c, nblk, fraction, P);   // first pass: the scan's partials
     const int per = nb / SEL_THREADS;
     // read before any barrier: one thread rewrites k_left at the end
     const bool none = c->h.none;
@@ -287,7 +302,10 @@ __device__ __forceinline__ float sel_norm(float v, float m)
 // over the wavefront; the partners' shares go straight to their counters.
 // A selected edge adds one edge and its |w_norm| in units of 2^-32 (exact
 // for |w_norm| >= 2^-9) to one 64-bit counter per end, so the sums do not
-// depend on the order of the atomics.
+// depend on the order of the atomics.  VEC: the row's aligned body is read
+// and written four edges per lane (w and w_norm 16-byte aligned, the flags
+// 4-byte aligned); the edges before and after it one per lane.
+template <bool VEC>
 __global__ __launch_bounds__(SEL_THREADS) void k_sel_rows(const float *w, int N, SelCtl *c, float *w_norm,
                                                         unsigned char *selected, int nodes)
 {
@@ -301,22 +319,48 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_rows(const float *w, int N,
         const long long r0 = (long long)i * (2LL * N - i - 1) / 2 - (i + 1);   // e = r0 + j
         int deg = 0;
         double str = 0.0;
-        for (int j = i + 1 + lane; j < N; j += 64) {
-            const long long e = r0 + j;
-            const float v = w[e];
-            const bool t = sel_take(v, *c, T);
-            const float nv = sel_norm(v, m);
-            if (selected) selected[e] = t;
-            if (w_norm) w_norm[e] = nv;
+        // edge e with its value v: the flag, the normalised value, the counters
+        auto edge = [&](long long e, float v, bool &t, float &nv) {
+            t = sel_take(v, *c, T);
+            nv = sel_norm(v, m);
             if (t) {
                 ++ns;
                 if (nodes) {
                     ++deg;
                     const float a = fabsf(nv);
                     str += (double)a;
-                    atomicAdd(&c->node[j], SEL_DEG1 + (unsigned long long)rint((double)a * SEL_FIX));
+                    atomicAdd(&c->node[(int)(e - r0)], SEL_DEG1 + (unsigned long long)rint((double)a * SEL_FIX));
                 }
             }
+        };
+        auto one = [&](long long e) {
+            bool t;
+            float nv;
+            edge(e, w[e], t, nv);
+            if (selected) selected[e] = t;
+            if (w_norm) w_norm[e] = nv;
+        };
+        const long long e0 = r0 + i + 1, e1 = r0 + N;   // the row's edges [e0, e1)
+        if (VEC) {
+            const long long a0 = min((e0 + 3) & ~3LL, e1);          // aligned body [a0, a1)
+            const long long a1 = a0 + ((e1 - a0) & ~3LL);
+            if (e0 + lane < a0) one(e0 + lane);
+            if (a1 + lane < e1) one(a1 + lane);
+            for (long long q = a0 + 4 * lane; q < a1; q += 256) {
+                const float4 v = *(const float4 *)(w + q);
+                bool t0, t1, t2, t3;
+                float4 nv;
+                edge(q, v.x, t0, nv.x);
+                edge(q + 1, v.y, t1, nv.y);
+                edge(q + 2, v.z, t2, nv.z);
+                edge(q + 3, v.w, t3, nv.w);
+                if (selected)
+                    *(unsigned int *)(selected + q) = (unsigned)t0 | ((unsigned)t1 << 8) | ((unsigned)t2 << 16) |
+                                                      ((unsigned)t3 << 24);
+                if (w_norm) *(float4 *)(w_norm + q) = nv;
+            }
+        } else {
+            for (long long e = e0 + lane; e < e1; e += 64) one(e);
         }
         if (nodes) {
             for (int o = 32; o > 0; o >>= 1) {
@@ -387,19 +431,28 @@ fcx_status sel_run(SelCtl *c, int32_t n_nodes, const float *w, double fraction, 
         hipLaunchKernelGGL(k_sel_scan<true>, grid, blk, 0, st, w, P, (int)n_nodes, c);
     else
         hipLaunchKernelGGL(k_sel_scan<false>, grid, blk, 0, st, w, P, (int)n_nodes, c);
-    hipLaunchKernelGGL(k_sel_init, dim3(1), blk, 0, st, c, (int)blocks, fraction, P);
-    // digits of 11, 10 and 10 bits (bits 30..20, 19..10, 9..0)
+    // digits of 11, 10 and 10 bits (bits 30..20, 19..10, 9..0); the scan
+    // took the first digit's histogram, and the first pick also sets up k
     const int shifts[3] = {20, 10, 0}, bins[3] = {2048, 1024, 1024};
     for (int pass = 0; pass < 3; ++pass) {
-        if (vec)
-            hipLaunchKernelGGL(k_sel_hist<true>, grid, blk, 0, st, w, P, c, shifts[pass], bins[pass]);
-        else
-            hipLaunchKernelGGL(k_sel_hist<false>, grid, blk, 0, st, w, P, c, shifts[pass], bins[pass]);
-        hipLaunchKernelGGL(k_sel_pick, dim3(1), blk, 0, st, c, shifts[pass], bins[pass]);
+        if (pass > 0) {
+            if (vec)
+                hipLaunchKernelGGL(k_sel_hist<true>, grid, blk, 0, st, w, P, c, shifts[pass], bins[pass]);
+            else
+                hipLaunchKernelGGL(k_sel_hist<false>, grid, blk, 0, st, w, P, c, shifts[pass], bins[pass]);
+        }
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), blk, 0, st, c, shifts[pass], bins[pass], pass == 0 ? (int)blocks : 0,
+                           fraction, P);
     }
     // last: w_norm may overwrite w
     const int nodes = degree || strength;
-    hipLaunchKernelGGL(k_sel_rows, dim3((n_nodes + 3) / 4), blk, 0, st, w, n_nodes, c, w_norm, selected, nodes);
+    const bool rvec = vec && ((uintptr_t)w_norm & 15) == 0 && ((uintptr_t)selected & 3) == 0;
+    if (rvec)
+        hipLaunchKernelGGL(k_sel_rows<true>, dim3((n_nodes + 3) / 4), blk, 0, st, w, n_nodes, c, w_norm, selected,
+                           nodes);
+    else
+        hipLaunchKernelGGL(k_sel_rows<false>, dim3((n_nodes + 3) / 4), blk, 0, st, w, n_nodes, c, w_norm, selected,
+                           nodes);
     if (nodes)
         hipLaunchKernelGGL(k_sel_node_out, dim3((n_nodes + SEL_THREADS - 1) / SEL_THREADS), blk, 0, st, c, n_nodes,
                            degree, strength);
