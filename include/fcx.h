@@ -154,7 +154,11 @@ fcx_status fcx_push_trial(fcx_session *s, const void *x, int64_t ld, int x_on_de
  * launch per kernel; host trials are uploaded one at a time.  The batch
  * writes the band-mean networks directly; the running sums (which the batch
  * pass uses as scratch) are rebuilt from the cached window, in one pass, by
- * the next sliding push, per-bin read or fcx_resync.
+ * the next sliding push, per-bin read or fcx_resync.  A session with COR and
+ * gram_precision FCX_GRAM_BF16 allocates, on its first batch call, a BF16
+ * copy of a window of z-scored samples (W * N * Mz * 2 bytes, Mz = M rounded
+ * up to a multiple of 32; not counted by fcx_footprint_bytes), kept until
+ * fcx_close; FCX_E_NOMEM if that allocation fails.
  */
 fcx_status fcx_push_batch(fcx_session *s, const void *x, int64_t n_trials, int64_t trial_stride,
                           int64_t ld, int x_on_device);

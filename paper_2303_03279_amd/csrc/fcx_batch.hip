@@ -649,14 +649,18 @@ __device__ __forceinline__ float cor_pick(float4 v, int e)
     return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
 }
 
-template <int PREC, int WR, int WC, int PF>
+// PRE (BF16 only): the samples come already rounded to BF16 (s.zbf, by
+// k_z_bf16 with the same rounding), so a chunk moves half the bytes.
+template <int PREC, int WR, int WC, int PF, bool PRE = false>
 __global__ __launch_bounds__(64 * (CR_T / (16 * WR)) * (CR_T / (16 * WC))) void k_cor_batch(SessDev<float> s, int K,
                                                                                   int G, double *scratch, int *count)
 {
+    static_assert(!PRE || PREC == FCX_GRAM_BF16_ID, "pre-rounded samples feed the BF16 Gram only");
     constexpr int WAVES_C = CR_T / (16 * WC);
     constexpr int NT = 64 * (CR_T / (16 * WR)) * WAVES_C;
-    constexpr int V4 = 2 * CR_T * (CR_CH / 4) / NT;  // float4 staged per thread and chunk
-    static_assert(V4 * NT == 2 * CR_T * (CR_CH / 4), "staging must cover the chunk");
+    constexpr int SPV = PRE ? 8 : 4;                  // samples per staged 16-byte vector
+    constexpr int V4 = 2 * CR_T * (CR_CH / SPV) / NT;  // vectors staged per thread and chunk
+    static_assert(V4 * NT == 2 * CR_T * (CR_CH / SPV), "staging must cover the chunk");
     // one buffer: FP32 rows of CR_LD floats, or BF16 rows of CR_LDH (hi, then for
     // BF16x3 a plane of lo parts)
     constexpr int ZBUF = PREC == FCX_GRAM_FP32_ID ? 2 * CR_T * CR_LD
@@ -697,34 +701,41 @@ __global__ __launch_bounds__(64 * (CR_T / (16 * WR)) * (CR_T / (16 * WC))) void 
         const int2 tt = cor_tile(lin, T);
         const int I0 = tt.x * CR_T, J0 = tt.y * CR_T;
 
-        // staging: float4 number e = tid + NT v of a chunk is node e / (CR_CH / 4)
-        // (the 128 row nodes, then the 128 column nodes), samples 4 (e % (CR_CH / 4))
-        // .. + 3; rows past N read node N - 1 and only feed outputs never written
+        // staging: vector number e = tid + NT v of a chunk is node e / (CR_CH / SPV)
+        // (the 128 row nodes, then the 128 column nodes), samples SPV (e % (CR_CH / SPV))
+        // .. + SPV - 1; rows past N read node N - 1 and only feed outputs never written
         unsigned off[V4];
         int lds[V4];
 #pragma unroll
         for (int v = 0; v < V4; ++v) {
-            const int e = tid + NT * v, node = e / (CR_CH / 4), q4 = e % (CR_CH / 4);
+            const int e = tid + NT * v, node = e / (CR_CH / SPV), q4 = e % (CR_CH / SPV);
             const int g = min(node < CR_T ? I0 + node : J0 + node - CR_T, N - 1);
-            off[v] = (unsigned)g * (unsigned)Mz + 4u * (unsigned)q4;
-            lds[v] = node * (PREC == FCX_GRAM_FP32_ID ? CR_LD : CR_LDH) + 4 * q4;
+            off[v] = (unsigned)g * (unsigned)Mz + (unsigned)(SPV * q4);
+            lds[v] = node * (PREC == FCX_GRAM_FP32_ID ? CR_LD : CR_LDH) + SPV * q4;
         }
         const int nch = Mz / CR_CH, cbeg = t0 * nch, total = t1 * nch;
         const size_t trial = (size_t)N * Mz;
         // chunk cc = trial * nch + chunk within the trial; chunks past the
         // segment's last load that one again (never used)
-        auto chunk_base = [&](int cc) {
+        // (element offset of the chunk; elements are floats, or BF16 with PRE)
+        auto chunk_at = [&](int cc) {
             cc = min(cc, total - 1);
             const int tq = cc / nch;
-            return s.zring + (size_t)tq * trial + (cc - tq * nch) * CR_CH;
+            return (size_t)tq * trial + (size_t)(cc - tq * nch) * CR_CH;
+        };
+        auto load_chunk = [&](int cc, floatx4 (&dst)[V4]) {
+            const size_t b = chunk_at(cc);
+#pragma unroll
+            for (int v = 0; v < V4; ++v) {
+                if constexpr (PRE)
+                    dst[v] = *(const floatx4 *)((const __bf16 *)s.zbf + b + off[v]);
+                else
+                    dst[v] = *(const floatx4 *)(s.zring + b + off[v]);
+            }
         };
         floatx4 pre[PF][V4];
 #pragma unroll
-        for (int p = 0; p < PF; ++p) {
-            const float *base = chunk_base(cbeg + p);
-#pragma unroll
-            for (int v = 0; v < V4; ++v) pre[p][v] = *(const floatx4 *)(base + off[v]);
-        }
+        for (int p = 0; p < PF; ++p) load_chunk(cbeg + p, pre[p]);
         floatx4 acc[WR][WC];
         double R[WR][WC][4];
 #pragma unroll
@@ -746,6 +757,8 @@ __global__ __launch_bounds__(64 * (CR_T / (16 * WR)) * (CR_T / (16 * WC))) void 
                     const floatx4 x = pre[p][v];
                     if (PREC == FCX_GRAM_FP32_ID) {
                         *(floatx4 *)(Zb + lds[v]) = x;
+                    } else if (PRE) {  // 8 samples already in BF16
+                        *(floatx4 *)((__bf16 *)Zb + lds[v]) = x;
                     } else {  // rounded once here, for every wavefront that reads it
                         __bf16 *Zh = (__bf16 *)Zb;
                         const bf16x4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
@@ -757,11 +770,7 @@ __global__ __launch_bounds__(64 * (CR_T / (16 * WR)) * (CR_T / (16 * WC))) void 
                     }
                 }
                 __syncthreads();
-                {   // chunk c + PF into the registers just emptied
-                    const float *base = chunk_base(c + PF);
-#pragma unroll
-                    for (int v = 0; v < V4; ++v) pre[p][v] = *(const floatx4 *)(base + off[v]);
-                }
+                load_chunk(c + PF, pre[p]);   // chunk c + PF into the registers just emptied
                 __builtin_amdgcn_sched_barrier(0);  // the loads go out before the chunk's LDS reads and MFMAs
 #pragma unroll
                 for (int sub = 0; sub < CR_CH / 32; ++sub) {
@@ -864,6 +873,16 @@ __global__ __launch_bounds__(64 * (CR_T / (16 * WR)) * (CR_T / (16 * WC))) void 
                     }
         }
         __syncthreads();  // LDS buffers and `last` are reused by the next segment
+    }
+}
+
+// The K trials' z-scored samples (ring slots 0..K-1) rounded to BF16, four
+// per thread and step, with the rounding the BF16 COR staging applies.
+__global__ __launch_bounds__(256) void k_z_bf16(const float *__restrict__ z, __bf16 *__restrict__ zb, long long n4)
+{
+    for (long long q = blockIdx.x * 256LL + threadIdx.x; q < n4; q += (long long)gridDim.x * 256) {
+        const floatx4 x = ((const floatx4 *)z)[q];
+        ((bf16x4 *)zb)[q] = (bf16x4){(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
     }
 }
 
@@ -970,8 +989,15 @@ hipError_t launch_cor_batch(const SessDev<float> &s, int K, int prec, hipStream_
     const dim3 grid(G), blk(NT);
     switch (prec) {
     case FCX_GRAM_BF16_ID:
-        hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16_ID, WR, WC, FCX_COR_PF16>), grid, blk, 0, st, s, K, G, scratch,
-                           count);
+        if (s.zbf) {   // the window in BF16 once, then half the bytes per tile
+            const long long n4 = (long long)K * s.N * s.Mz / 4;
+            hipLaunchKernelGGL(k_z_bf16, dim3(2048), dim3(256), 0, st, s.zring, (__bf16 *)s.zbf, n4);
+            hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16_ID, WR, WC, FCX_COR_PF16, true>), grid, blk, 0, st, s, K, G,
+                               scratch, count);
+        } else {
+            hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16_ID, WR, WC, FCX_COR_PF16>), grid, blk, 0, st, s, K, G,
+                               scratch, count);
+        }
         break;
     case FCX_GRAM_BF16X3_ID:
         hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16X3_ID, WR, WC, FCX_COR_PF16>), grid, blk, 0, st, s, K, G,

@@ -537,6 +537,7 @@ template <typename T> SessDev<T> session_dev(const Session *s, const void *x, lo
     d.x = x;
     d.ldx = ldx;
     d.zring = s->zring;
+    d.zbf = s->zbf;
     d.rsum = s->rsum;
     d.kbase = -1;
     d.nt = 1;
@@ -911,6 +912,9 @@ fcx_status fcx_push_batch(fcx_session *h, const void *x, int64_t n_trials, int64
     }
     // FP32 sessions: spectra of every trial into the ring, then one batch
     // pass with the Gram sums on the matrix cores
+    if ((s->cfg.metrics & M_COR) && s->cfg.gram_precision == FCX_GRAM_BF16 && !s->zbf &&
+        (st = dalloc(s, (size_t)g.W * g.N * g.Mz * 2, &s->zbf)) != FCX_OK)
+        return st;
     SessDev<float> d = session_dev<float>(s, nullptr, 0);
     const bool spectral = (s->cfg.metrics & 0x7Fu) != 0, cor = (s->cfg.metrics & M_COR) != 0;
     const bool zneed = (s->cfg.metrics & (M_COR | M_XCOR)) != 0;   // XCOR comes from the rebuild

@@ -61,6 +61,7 @@ struct Session {
     double *lamw = nullptr;
     int2 *tiles = nullptr;
     float *zring = nullptr;
+    void *zbf = nullptr;   // BF16 z-scored window of the BF16 COR batch, allocated on first use
     double *rsum = nullptr;
     void *xbuf = nullptr;
     void *xtick[2] = {nullptr, nullptr};   // served sessions: each tick buffer's input of up to

@@ -82,6 +82,8 @@ struct SessDev {
     const void *x;          // current trial input [N][ldx] (T)
     long long ldx;
     float *zring;           // [(W+1)][N][Mz] z-scored samples (COR)
+    void *zbf;              // [W][N][Mz] BF16 copy of a batch window's z-scored samples
+                            // (BF16 COR batch), or null
     double *rsum;           // [ntiles][TILE_PAIRS] running sum of per-trial r (COR)
     long long kbase;        // -1: sliding push; >= 0: replay of a cached window
                             // (add only, K = pushed - kbase + 1)
