@@ -158,15 +158,18 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_scan(const float *__restric
         if (h[d]) atomicAdd(&g[d], h[d]);
 }
 
+// the single-block kernel that folds the histograms and picks a digit
+constexpr int PICK_THREADS = 1024;
+
 // folds the scan blocks' partials (nblk of them) and sets up the selection;
-// called by every thread of the single-block pick kernel of the first pass
+// called by every thread of the pick kernel of the first pass
 __device__ __forceinline__ void sel_init(SelCtl *c, int nblk, double fraction, long long P)
 {
-    __shared__ unsigned int smax[SEL_THREADS / 64];
-    __shared__ unsigned long long scnt[SEL_THREADS / 64];
+    __shared__ unsigned int smax[PICK_THREADS / 64];
+    __shared__ unsigned long long scnt[PICK_THREADS / 64];
     unsigned int mx = 0;
     unsigned long long nf = 0;
-    for (int b = threadIdx.x; b < nblk; b += SEL_THREADS) {
+    for (int b = threadIdx.x; b < nblk; b += PICK_THREADS) {
         mx = max(mx, c->blk_max[b]);
         nf += c->blk_nf[b];
     }
@@ -180,7 +183,7 @@ __device__ __forceinline__ void sel_init(SelCtl *c, int nblk, double fraction, l
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int q = 1; q < SEL_THREADS / 64; ++q) {
+        for (int q = 1; q < PICK_THREADS / 64; ++q) {
             mx = max(mx, smax[q]);
             nf += scnt[q];
         }
@@ -221,45 +224,48 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_hist(const float *__restric
         if (h[d]) atomicAdd(&g[d], h[d]);
 }
 
-// picks the digit of the k_left-th largest key among those with the prefix
-// (each thread sums a run of nb / 256 bins, then one thread walks the runs
-// from the top), then clears the histograms for the next pass
-__global__ __launch_bounds__(SEL_THREADS) void k_sel_pick(SelCtl *c, int shift, int nb, int nblk, double fraction,
-                                                        long long P)
+// picks the digit of the k_left-th largest key among those with the prefix:
+// thread t sums the slots of its run of nb / PICK_THREADS bins, a suffix
+// scan over the runs (within each wavefront by shuffles, then over the
+// wavefront totals) finds the run that holds the k_left-th key, whose
+// thread walks its bins from the top; then the histograms are cleared for
+// the next pass
+__global__ __launch_bounds__(PICK_THREADS) void k_sel_pick(SelCtl *c, int shift, int nb, int nblk, double fraction,
+                                                         long long P)
 {
-    __shared__ unsigned int tot[SEL_BINS];
-    __shared__ unsigned long long run[SEL_THREADS];
+    __shared__ unsigned long long wsum[PICK_THREADS / 64];
     if (nblk > 0) sel_init(c, nblk, fraction, P);   // first pass: the scan's partials
-    const int per = nb / SEL_THREADS;
-    // read before any barrier: one thread rewrites k_left at the end
+    const int per = nb / PICK_THREADS, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // read before any later barrier: one thread rewrites k_left at the end
     const bool none = c->h.none;
     const long long kl = c->h.k_left;
-    for (int d = threadIdx.x; d < nb; d += SEL_THREADS) {
+    unsigned int tot[SEL_BINS / PICK_THREADS];
+    unsigned long long r = 0;
+    for (int q = 0; q < per; ++q) {
+        const int d = threadIdx.x * per + q;
         unsigned int t = 0;
 #pragma unroll
         for (int sl = 0; sl < SEL_SLOTS; ++sl) t += c->hist[sl][d];
-        tot[d] = t;
+        tot[q] = t;
+        r += t;
     }
-    __syncthreads();
-    // run q = bins q*per .. q*per + per - 1; above[q] = keys in the runs above q
-    unsigned long long r = 0;
-    for (int q = 0; q < per; ++q) r += tot[threadIdx.x * per + q];
-    run[threadIdx.x] = r;
-    __syncthreads();
-    for (int o = 1; o < SEL_THREADS; o <<= 1) {   // inclusive suffix sums over the runs
-        const unsigned long long add = threadIdx.x + o < SEL_THREADS ? run[threadIdx.x + o] : 0ull;
-        __syncthreads();
-        run[threadIdx.x] += add;
-        __syncthreads();
+    // inclusive suffix sum over the threads (runs in ascending bin order)
+    unsigned long long incl = r;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long v = __shfl_down(incl, o, 64);
+        if (lane + o < 64) incl += v;
     }
+    if (lane == 0) wsum[wv] = incl;   // the wavefront's total
+    __syncthreads();
+    for (int q = wv + 1; q < PICK_THREADS / 64; ++q) incl += wsum[q];
     if (!none) {
-        const long long incl = (long long)run[threadIdx.x];
-        const long long above = incl - (long long)r;
-        if (above < kl && incl >= kl) {   // exactly one run holds the k_left-th key
+        const long long above = (long long)(incl - r);
+        if (above < kl && (long long)incl >= kl) {   // exactly one run holds the k_left-th key
             long long cum = above;
-            for (int d = threadIdx.x * per + per - 1; d >= threadIdx.x * per; --d) {
-                const long long hd = tot[d];
+            for (int q = per - 1; q >= 0; --q) {
+                const long long hd = tot[q];
                 if (cum + hd >= kl) {
+                    const int d = threadIdx.x * per + q;
                     c->h.prefix |= (unsigned int)d << shift;
                     c->h.mask |= (unsigned int)(nb - 1) << shift;
                     c->h.k_left = kl - cum;
@@ -270,7 +276,7 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_pick(SelCtl *c, int shift, 
         }
     }
     for (int sl = 0; sl < SEL_SLOTS; ++sl)
-        for (int d = threadIdx.x; d < nb; d += SEL_THREADS) c->hist[sl][d] = 0;
+        for (int d = threadIdx.x; d < nb; d += PICK_THREADS) c->hist[sl][d] = 0;
 }
 
 // zero the part of a control block that must start at zero (everything but
@@ -302,10 +308,7 @@ __device__ __forceinline__ float sel_norm(float v, float m)
 // over the wavefront; the partners' shares go straight to their counters.
 // A selected edge adds one edge and its |w_norm| in units of 2^-32 (exact
 // for |w_norm| >= 2^-9) to one 64-bit counter per end, so the sums do not
-// depend on the order of the atomics.  VEC: the row's aligned body is read
-// and written four edges per lane (w and w_norm 16-byte aligned, the flags
-// 4-byte aligned); the edges before and after it one per lane.
-template <bool VEC>
+// depend on the order of the atomics.
 __global__ __launch_bounds__(SEL_THREADS) void k_sel_rows(const float *w, int N, SelCtl *c, float *w_norm,
                                                         unsigned char *selected, int nodes)
 {
@@ -319,48 +322,22 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_rows(const float *w, int N,
         const long long r0 = (long long)i * (2LL * N - i - 1) / 2 - (i + 1);   // e = r0 + j
         int deg = 0;
         double str = 0.0;
-        // edge e with its value v: the flag, the normalised value, the counters
-        auto edge = [&](long long e, float v, bool &t, float &nv) {
-            t = sel_take(v, *c, T);
-            nv = sel_norm(v, m);
+        for (int j = i + 1 + lane; j < N; j += 64) {
+            const long long e = r0 + j;
+            const float v = w[e];
+            const bool t = sel_take(v, *c, T);
+            const float nv = sel_norm(v, m);
+            if (selected) selected[e] = t;
+            if (w_norm) w_norm[e] = nv;
             if (t) {
                 ++ns;
                 if (nodes) {
                     ++deg;
                     const float a = fabsf(nv);
                     str += (double)a;
-                    atomicAdd(&c->node[(int)(e - r0)], SEL_DEG1 + (unsigned long long)rint((double)a * SEL_FIX));
+                    atomicAdd(&c->node[j], SEL_DEG1 + (unsigned long long)rint((double)a * SEL_FIX));
                 }
             }
-        };
-        auto one = [&](long long e) {
-            bool t;
-            float nv;
-            edge(e, w[e], t, nv);
-            if (selected) selected[e] = t;
-            if (w_norm) w_norm[e] = nv;
-        };
-        const long long e0 = r0 + i + 1, e1 = r0 + N;   // the row's edges [e0, e1)
-        if (VEC) {
-            const long long a0 = min((e0 + 3) & ~3LL, e1);          // aligned body [a0, a1)
-            const long long a1 = a0 + ((e1 - a0) & ~3LL);
-            if (e0 + lane < a0) one(e0 + lane);
-            if (a1 + lane < e1) one(a1 + lane);
-            for (long long q = a0 + 4 * lane; q < a1; q += 256) {
-                const float4 v = *(const float4 *)(w + q);
-                bool t0, t1, t2, t3;
-                float4 nv;
-                edge(q, v.x, t0, nv.x);
-                edge(q + 1, v.y, t1, nv.y);
-                edge(q + 2, v.z, t2, nv.z);
-                edge(q + 3, v.w, t3, nv.w);
-                if (selected)
-                    *(unsigned int *)(selected + q) = (unsigned)t0 | ((unsigned)t1 << 8) | ((unsigned)t2 << 16) |
-                                                      ((unsigned)t3 << 24);
-                if (w_norm) *(float4 *)(w_norm + q) = nv;
-            }
-        } else {
-            for (long long e = e0 + lane; e < e1; e += 64) one(e);
         }
         if (nodes) {
             for (int o = 32; o > 0; o >>= 1) {
@@ -441,18 +418,12 @@ fcx_status sel_run(SelCtl *c, int32_t n_nodes, const float *w, double fraction, 
             else
                 hipLaunchKernelGGL(k_sel_hist<false>, grid, blk, 0, st, w, P, c, shifts[pass], bins[pass]);
         }
-        hipLaunchKernelGGL(k_sel_pick, dim3(1), blk, 0, st, c, shifts[pass], bins[pass], pass == 0 ? (int)blocks : 0,
-                           fraction, P);
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(PICK_THREADS), 0, st, c, shifts[pass], bins[pass],
+                           pass == 0 ? (int)blocks : 0, fraction, P);
     }
     // last: w_norm may overwrite w
     const int nodes = degree || strength;
-    const bool rvec = vec && ((uintptr_t)w_norm & 15) == 0 && ((uintptr_t)selected & 3) == 0;
-    if (rvec)
-        hipLaunchKernelGGL(k_sel_rows<true>, dim3((n_nodes + 3) / 4), blk, 0, st, w, n_nodes, c, w_norm, selected,
-                           nodes);
-    else
-        hipLaunchKernelGGL(k_sel_rows<false>, dim3((n_nodes + 3) / 4), blk, 0, st, w, n_nodes, c, w_norm, selected,
-                           nodes);
+    hipLaunchKernelGGL(k_sel_rows, dim3((n_nodes + 3) / 4), blk, 0, st, w, n_nodes, c, w_norm, selected, nodes);
     if (nodes)
         hipLaunchKernelGGL(k_sel_node_out, dim3((n_nodes + SEL_THREADS - 1) / SEL_THREADS), blk, 0, st, c, n_nodes,
                            degree, strength);
