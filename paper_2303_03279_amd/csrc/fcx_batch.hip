@@ -649,13 +649,14 @@ __device__ __forceinline__ float cor_pick(float4 v, int e)
     return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
 }
 
-// PRE (BF16 only): the samples come already rounded to BF16 (s.zbf, by
-// k_z_bf16 with the same rounding), so a chunk moves half the bytes.
-template <int PREC, int WR, int WC, int PF, bool PRE = false>
+// The BF16 form reads the samples already rounded to BF16 (s.zbf, by
+// k_z_bf16, the rounding the other forms apply as they stage), so a chunk
+// moves half the bytes; FP32 and BF16x3 read the FP32 samples.
+template <int PREC, int WR, int WC, int PF>
 __global__ __launch_bounds__(64 * (CR_T / (16 * WR)) * (CR_T / (16 * WC))) void k_cor_batch(SessDev<float> s, int K,
                                                                                   int G, double *scratch, int *count)
 {
-    static_assert(!PRE || PREC == FCX_GRAM_BF16_ID, "pre-rounded samples feed the BF16 Gram only");
+    constexpr bool PRE = PREC == FCX_GRAM_BF16_ID;
     constexpr int WAVES_C = CR_T / (16 * WC);
     constexpr int NT = 64 * (CR_T / (16 * WR)) * WAVES_C;
     constexpr int SPV = PRE ? 8 : 4;                  // samples per staged 16-byte vector
@@ -988,17 +989,14 @@ hipError_t launch_cor_batch(const SessDev<float> &s, int K, int prec, hipStream_
     }
     const dim3 grid(G), blk(NT);
     switch (prec) {
-    case FCX_GRAM_BF16_ID:
-        if (s.zbf) {   // the window in BF16 once, then half the bytes per tile
-            const long long n4 = (long long)K * s.N * s.Mz / 4;
-            hipLaunchKernelGGL(k_z_bf16, dim3(2048), dim3(256), 0, st, s.zring, (__bf16 *)s.zbf, n4);
-            hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16_ID, WR, WC, FCX_COR_PF16, true>), grid, blk, 0, st, s, K, G,
-                               scratch, count);
-        } else {
-            hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16_ID, WR, WC, FCX_COR_PF16>), grid, blk, 0, st, s, K, G,
-                               scratch, count);
-        }
+    case FCX_GRAM_BF16_ID: {   // the window in BF16 once, then half the bytes per tile
+        if (!s.zbf) return hipErrorInvalidValue;
+        const long long n4 = (long long)K * s.N * s.Mz / 4;
+        hipLaunchKernelGGL(k_z_bf16, dim3(2048), dim3(256), 0, st, s.zring, (__bf16 *)s.zbf, n4);
+        hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16_ID, WR, WC, FCX_COR_PF16>), grid, blk, 0, st, s, K, G, scratch,
+                           count);
         break;
+    }
     case FCX_GRAM_BF16X3_ID:
         hipLaunchKernelGGL((k_cor_batch<FCX_GRAM_BF16X3_ID, WR, WC, FCX_COR_PF16>), grid, blk, 0, st, s, K, G,
                            scratch, count);

@@ -123,11 +123,12 @@ __global__ __launch_bounds__(256) void k_window_psd(const float2 *__restrict__ z
 }
 
 template <int NWO>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NWO == 2 ? 3 : 1))) void k_hilbert_windows(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NWO == 2 ? 2 : 1))) void k_hilbert_windows(
     SessDev<float> s, HWin hw)
 {
     __shared__ float2 Xs[64 * HW_LD];
     __shared__ float2 Us[64 * HW_LD];
+    __shared__ double2 Xd[32 * HW_LD];   // the row nodes again in FP64, for the vector sums
     const int tile = blockIdx.x >> 2, qd = blockIdx.x & 3;
     const int2 tt = s.tiles[tile];
     const int R0 = tt.x * TILE + 32 * (qd >> 1), C0 = tt.y * TILE + 32 * (qd & 1);
@@ -193,13 +194,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NWO == 2 ? 
                     }
                 }
                 Xs[node * HW_LD + col] = v;
+                if (node < 32) Xd[node * HW_LD + col] = make_double2(v.x, v.y);
                 if (needU) Us[node * HW_LD + col] = u;
             }
             __syncthreads();
-            // each MFMA step (4 samples) is followed by the vector sums of
-            // the same samples
-#pragma unroll
-            for (int st = 0; st < HW_CC / 4; ++st) {
+            // each MFMA step (4 samples) is followed by the vector sums of the
+            // same samples; sample t's operands are loaded while sample t - 1
+            // is summed (columns past the samples are 0 and add nothing; the
+            // pad column HW_CC is loaded but never summed)
+            auto mfma_step = [&](int st) {
                 {
                     const float2 a = Xs[arow * HW_LD + 4 * st + lg];
                     const float2 bb = Xs[bcol * HW_LD + 4 * st + lg];
@@ -214,23 +217,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NWO == 2 ? 
                     uim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, uim, 0, 0, 0);
                     uim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, bb.y, uim, 0, 0, 0);
                 }
+            };
+            auto ldt = [&](int t, double2 (&xr)[4], float2 &xc) {
 #pragma unroll
-                for (int t4 = 0; t4 < 4; ++t4) {
-                    const int t = 4 * st + t4;
-                    if (t < nk) {
-                        const float2 xj = Xs[bcol * HW_LD + t];
-                        const double jx = xj.x, jy = xj.y;
+                for (int k = 0; k < 4; ++k) xr[k] = Xd[rows[k] * HW_LD + t];
+                xc = Xs[bcol * HW_LD + t];
+            };
+            auto sum_t = [&](const double2 (&xr)[4], float2 xc) {
+                const double jx = xc.x, jy = xc.y;
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            // Im(z_i conj z_j) exact-rounded in FP64; sums in FP64
-                            const double ci = im_cross(Xs[rows[k] * HW_LD + t], jx, jy);
-                            G[k] += sign_of_f64(ci);
-                            Ab[k] = Ab[k] + fabs(ci);
-                            Qb[k] = __builtin_fma(ci, ci, Qb[k]);
-                            Sb[k] = Sb[k] + ci;
-                        }
-                    }
+                for (int k = 0; k < 4; ++k) {
+                    // Im(z_i conj z_j) exact-rounded in FP64 (both products exact; never -0); sums in FP64
+                    const double ci = __builtin_fma(xr[k].y, jx, __builtin_fma(-xr[k].x, jy, 0.0));
+                    G[k] += sign_of_f64(ci);
+                    Ab[k] = Ab[k] + fabs(ci);
+                    Qb[k] = __builtin_fma(ci, ci, Qb[k]);
+                    Sb[k] = Sb[k] + ci;
                 }
+            };
+            double2 ra[4], rb[4];
+            float2 ca, cb;
+            ldt(0, ra, ca);
+            for (int t = 0; t < nk; t += 2) {
+                if ((t & 3) == 0) mfma_step(t >> 2);
+                ldt(t + 1, rb, cb);
+                sum_t(ra, ca);
+                ldt(min(t + 2, HW_CC), ra, ca);
+                sum_t(rb, cb);
             }
         }
         // the block into every open window, then the windows that end here
