@@ -100,18 +100,22 @@ def test_batch_then_slide(fcx, mid):
     s.close()
 
 
-def test_batch_multitaper(fcx):
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+def test_batch_multitaper(fcx, prec):
+    """DPSS with three tapers (the taper-weighted Gram columns), per Gram
+    precision at its stated bounds."""
     rng = np.random.default_rng(8)
     N, M, K = 90, 200, 12
     x = rng.standard_normal((K, N, M))
     x[:, 1, 3:] += 0.9 * x[:, 0, :-3]
     cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=K, n_fft=256, f_lo_hz=4, f_hi_hz=120,
-                            taper="dpss", dpss_nw=2.0, dpss_k=3, metrics=synth.ALL8, gram="fp32")
+                            taper="dpss", dpss_nw=2.0, dpss_k=3, metrics=synth.ALL8, gram=prec)
     s, _ = _batch(fcx, cfg, x)
     ref = oracle.network(oracle.as_device_input(x, cfg), cfg)
     err = _errors(s, ref, ALL)
-    log("batch dpss L=3 fp32: " + json.dumps({k: f"{v:.2e}" for k, v in err.items()}))
-    assert max(err.values()) <= TOL
+    log(f"batch dpss L=3 {prec}: " + json.dumps({k: f"{v:.2e}" for k, v in err.items()}))
+    for m in ALL:
+        assert err[m] <= BOUND[prec][m], (prec, m, err[m])
     s.close()
 
 
