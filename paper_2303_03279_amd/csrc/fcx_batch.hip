@@ -464,18 +464,19 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, in
 // taper-combined CSD c = sum_l w_l X_il conj(X_jl) with each taper's products
 // exact in FP64 (so Im c of a zero-lag pair is an exact 0), its sign, |Im c|,
 // (Im c)^2 and Im c summed in FP64, and the unit phasor of c for PLV.
-template <int PREC>
+// LT: the number of tapers when fixed at compile time (0: s.L at run time).
+template <int PREC, int LT>
 __global__ __launch_bounds__(BT_THREADS) void k_pair_batchL(SessDev<float> s, int K)
 {
     constexpr bool BFP = PREC != FCX_GRAM_FP32_ID;
     constexpr int NPL = PREC == FCX_GRAM_BF16X3_ID ? 4 : 2;   // BF16 planes per operand
-    __shared__ float2 Xs[64 * BT_LD];                         // FP32 values (the vector sums read them)
+    __shared__ float2 Xs[64 * BT_LD];                         // FP32 values (Gram operands, column nodes)
     __shared__ __attribute__((aligned(16))) __bf16 Xh[BFP ? NPL * BT_PLANE : 8];
     if (s.ctl->bad) return;
     const int tile = blockIdx.x >> 2, qd = blockIdx.x & 3;
     const int2 tt = s.tiles[tile];
     const int R0 = tt.x * TILE + 32 * (qd >> 1), C0 = tt.y * TILE + 32 * (qd & 1);
-    const int N = s.N, B = s.B, L = s.L;
+    const int N = s.N, B = s.B, L = LT ? LT : s.L;
     if (R0 >= N || R0 >= min(C0 + 31, N - 1)) return;   // no pair i < j < N here
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
     const int wr = w >> 1, wc = w & 1;
@@ -530,27 +531,31 @@ __global__ __launch_bounds__(BT_THREADS) void k_pair_batchL(SessDev<float> s, in
                 Gram<PREC>::chunk(Xs, arow, bcol, lg, sre, sdum);
             }
             for (int t = 0; t < nk; ++t) {
+                double cr[4] = {0.0, 0.0, 0.0, 0.0}, ci[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll(LT ? LT : 1)
+                for (int l = 0; l < L; ++l) {
+                    const float2 xj = Xs[bcol * BT_LD + t * L + l];
+                    const double jx = xj.x, jy = xj.y;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float2 xf = Xs[rows[k] * BT_LD + t * L + l];
+                        const double2 xi = make_double2(xf.x, xf.y);
+                        // each taper's Im exact-rounded in FP64 (both products exact; the
+                        // +0 keeps an exact zero positive), then summed over the tapers
+                        ci[k] = ci[k] + __builtin_fma(xi.y, jx, __builtin_fma(-xi.x, jy, 0.0));
+                        if (needU) cr[k] = __builtin_fma(xi.x, jx, __builtin_fma(xi.y, jy, cr[k]));
+                    }
+                }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    double cr = 0.0, ci = 0.0;
-                    for (int l = 0; l < L; ++l) {
-                        const float2 xi = Xs[rows[k] * BT_LD + t * L + l];
-                        const float2 xj = Xs[bcol * BT_LD + t * L + l];
-                        // exact FP64 products; the +0 keeps an exact zero positive
-                        ci = ci + im_cross(xi, xj.x, xj.y);
-                        if (needU) cr = cr + ((double)xi.x * xj.x + (double)xi.y * xj.y);
-                    }
-                    G[k] += sign_of_f64(ci);
-                    A[k] = A[k] + fabs(ci);
-                    Q[k] = __builtin_fma(ci, ci, Q[k]);
-                    S[k] = S[k] + ci;
-                    if (needU) {
-                        const double m2 = cr * cr + ci * ci;
-                        if (m2 > 0.0) {
-                            const double rm = rsqrt(m2);
-                            VUr[k] += cr * rm;
-                            VUi[k] += ci * rm;
-                        }
+                    G[k] += sign_of_f64(ci[k]);
+                    A[k] = A[k] + fabs(ci[k]);
+                    Q[k] = __builtin_fma(ci[k], ci[k], Q[k]);
+                    S[k] = S[k] + ci[k];
+                    if (needU) {   // the unit phasor of the taper-combined CSD
+                        const float2 u = pb_phasor(make_float2((float)cr[k], (float)ci[k]));
+                        VUr[k] += (double)u.x;
+                        VUi[k] += (double)u.y;
                     }
                 }
             }
@@ -945,12 +950,21 @@ hipError_t launch_pair_batch(const SessDev<float> &s, int K, int prec, hipStream
             launch_pair_batch1<false>(s, K, prec, st);
     } else {
         const dim3 grid(s.ntiles * 4), blk(BT_THREADS);
+        // three tapers (the common DPSS choice) with the taper loop unrolled
+        const bool l3 = s.L == 3;
         switch (prec) {
-        case FCX_GRAM_BF16_ID: hipLaunchKernelGGL((k_pair_batchL<FCX_GRAM_BF16_ID>), grid, blk, 0, st, s, K); break;
-        case FCX_GRAM_BF16X3_ID:
-            hipLaunchKernelGGL((k_pair_batchL<FCX_GRAM_BF16X3_ID>), grid, blk, 0, st, s, K);
+        case FCX_GRAM_BF16_ID:
+            if (l3) hipLaunchKernelGGL((k_pair_batchL<FCX_GRAM_BF16_ID, 3>), grid, blk, 0, st, s, K);
+            else hipLaunchKernelGGL((k_pair_batchL<FCX_GRAM_BF16_ID, 0>), grid, blk, 0, st, s, K);
             break;
-        default: hipLaunchKernelGGL((k_pair_batchL<FCX_GRAM_FP32_ID>), grid, blk, 0, st, s, K); break;
+        case FCX_GRAM_BF16X3_ID:
+            if (l3) hipLaunchKernelGGL((k_pair_batchL<FCX_GRAM_BF16X3_ID, 3>), grid, blk, 0, st, s, K);
+            else hipLaunchKernelGGL((k_pair_batchL<FCX_GRAM_BF16X3_ID, 0>), grid, blk, 0, st, s, K);
+            break;
+        default:
+            if (l3) hipLaunchKernelGGL((k_pair_batchL<FCX_GRAM_FP32_ID, 3>), grid, blk, 0, st, s, K);
+            else hipLaunchKernelGGL((k_pair_batchL<FCX_GRAM_FP32_ID, 0>), grid, blk, 0, st, s, K);
+            break;
         }
     }
     return hipGetLastError();
