@@ -1263,12 +1263,14 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_rebuild(SessDev<T> s, lon
                     }
                 }
                 __syncthreads();
+                // trial by trial, the lane's four pairs side by side (each pair's
+                // sums still in trial order); pairs outside i < j < N are summed
+                // too, from staged values (zeros past N), and never written
+                for (int t = 0; t < nt; ++t) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = 4 * q + w, i = R0 + r, j = J0 + c;
-                    if (!(i < j && j < N)) continue;
-                    PairState &z = st[q];
-                    for (int t = 0; t < nt; ++t) {
+                    for (int q = 0; q < 4; ++q) {
+                        const int r = 4 * q + w;
+                        PairState &z = st[q];
                         double cnr, cni;
                         trial_csd<T>(X + (size_t)t * L * PAIR_NODES, r, c, L, s.lamw, cnr, cni);
                         if (needSre) z.sre = z.sre + cnr;
