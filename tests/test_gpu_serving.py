@@ -202,3 +202,59 @@ def test_read_waits_for_queued_trials(fcx):
         compare_network(s, ref, c, ALL, label=f"read after {done} submitted")
     fcx.check(s.close())
     fcx.check(srv.destroy())
+
+
+def test_full_serving_mix_against_oracle(fcx):
+    """The serving mix at its full shape (64 sessions, N in {60, 128, 306,
+    1000, 2000}, W ~ U{10..100}, seeded metric subsets): every session's
+    window filled and slid through the server (all trials queued while the
+    server is held, so they are coalesced in groups of 8), then checked
+    against the FP64 oracle: the largest sessions on sampled rows against
+    sampled columns, a few small ones in full."""
+    sess = synth.c4_sessions(4)
+    pool = 6                                   # distinct trials per session, reused in order
+    xs = [np.ascontiguousarray(synth.c4_trials(c, sd, pool), dtype=np.float32) for c, sd in sess]
+    srv = fcx.Server(int(sum(fcx.server_footprint_bytes(c) for c, _ in sess) * 1.05))
+    served = []
+    for c, _ in sess:
+        st, h = srv.open(c)
+        fcx.check(st, "open")
+        served.append(h)
+    # W + 3 trials per session: the window fills and slides past its first trials
+    T = [c["window_trials"] + 3 for c, _ in sess]
+    fcx.check(srv.hold(True))
+    for r in range(max(T)):
+        for k, h in enumerate(served):
+            if r < T[k]:
+                srv.submit(h, xs[k][r % pool])
+    fcx.check(srv.hold(False))
+    srv.drain()
+    ticks, trials, group, busy = srv.counts()
+    log(f"full serving mix: {trials} trials in {ticks} ticks, largest group {group}")
+    assert trials == sum(T) and group == 8
+    Ns = [c["n_nodes"] for c, _ in sess]
+    big = sorted(range(len(sess)), key=lambda k: -Ns[k])[:2]
+    small = sorted(range(len(sess)), key=lambda k: Ns[k])[:3]
+    rng = np.random.default_rng(11)
+    for k in big + small:
+        c = sess[k][0]
+        N, W = c["n_nodes"], c["window_trials"]
+        names = [m for m in ALL if c["metrics"] & synth.METRIC_BITS[m]]
+        window = [r % pool for r in range(T[k] - W, T[k])]
+        if N > 500:
+            rows = [0, 1, N // 2, N - 2]
+            cols = sorted(set(rng.choice(N, 64, replace=False).tolist()) | {2, N - 1})
+            pi, pj = oracle.row_pairs(rows, N, cols)
+            nodes = np.unique(np.concatenate([pi, pj]))
+            local = np.full(N, -1, dtype=np.int64)
+            local[nodes] = np.arange(nodes.size)
+            sub = xs[k][window][:, nodes, :].astype(np.float64)
+            ref = oracle.network(sub, dict(c, n_nodes=int(nodes.size)), local[pi], local[pj])
+            compare_network(served[k], ref, c, names, idx=oracle.packed_index(pi, pj, N),
+                            label=f"served N={N} W={W} (sampled)")
+        else:
+            ref = oracle.network(xs[k][window].astype(np.float64), c)
+            compare_network(served[k], ref, c, names, label=f"served N={N} W={W}")
+    for h in served:
+        fcx.check(h.close())
+    fcx.check(srv.destroy())
