@@ -86,7 +86,7 @@ fcx_status make_geometry(const fcx_config *c, Geometry *g)
 size_t BufferPlan::total() const
 {
     size_t t = ring + psd + gsum + out + ctl + wtw + lamw + tiles + zring + rsum + xbuf;
-    t += xtw + xtwi + xspec + xpair + xrho + xval + xsum;
+    t += xtw + xtwi + xspec + xpair + xrho + xtail + xg + xtm + xval + xsum;
     for (int i = 0; i < NPLANES; ++i)
         if (planes_used[i]) t += (i == P_URE || i == P_UIM) ? uplane : plane;
     return t;
@@ -143,6 +143,9 @@ BufferPlan make_plan(const fcx_config &c, const Geometry &g)
         p.xspec = align256(2 * np * (g.xF / 2 + 1) * 8);
         p.xpair = align256(np * g.xF * 8);
         p.xrho = align256(2 * np * g.xF * 4);
+        p.xtail = align256(2 * np * 8);
+        p.xg = align256(2 * np * g.Mz * 8);
+        p.xtm = align256((size_t)g.ntiles * TILE_PAIRS * 4);
         p.xval = align256(slots * g.ntiles * TILE_PAIRS * 4);
         p.xsum = align256((size_t)g.ntiles * TILE_PAIRS * 8);
     }
@@ -456,6 +459,9 @@ fcx_status session_alloc(Session *s)
     ALLOC(xspec, p.xspec);
     ALLOC(xpair, p.xpair);
     ALLOC(xrho, p.xrho);
+    ALLOC(xtail, p.xtail);
+    ALLOC(xg, p.xg);
+    ALLOC(xtm, p.xtm);
     ALLOC(xval, p.xval);
     ALLOC(xsum, p.xsum);
 #undef ALLOC
@@ -549,6 +555,9 @@ template <typename T> SessDev<T> session_dev(const Session *s, const void *x, lo
     d.xspec = s->xspec;
     d.xpair = s->xpair;
     d.xrho = s->xrho;
+    d.xtail = s->xtail;
+    d.xg = s->xg;
+    d.xtm = s->xtm;
     d.xval = s->xval;
     d.xsum = s->xsum;
     return d;

@@ -16,7 +16,8 @@ struct BufferPlan {
     // device byte sizes of every buffer a session allocates
     size_t ring = 0, psd = 0, plane = 0, gsum = 0, out = 0, ctl = 0, wtw = 0, lamw = 0, tiles = 0;
     size_t zring = 0, rsum = 0, xbuf = 0;
-    size_t xtw = 0, xtwi = 0, xspec = 0, xpair = 0, xrho = 0, xval = 0, xsum = 0;   // XCOR
+    size_t xtw = 0, xtwi = 0, xspec = 0, xpair = 0, xrho = 0, xtail = 0, xg = 0, xtm = 0, xval = 0,
+           xsum = 0;   // XCOR
     int nplanes = 0;
     bool planes_used[NPLANES] = {false, false, false, false, false, false};
     bool g_used = false;
@@ -69,7 +70,9 @@ struct Session {
     double2 *xtw = nullptr;
     float2 *xtwi = nullptr;
     float2 *xspec = nullptr, *xpair = nullptr;
-    float *xrho = nullptr, *xval = nullptr;
+    float *xrho = nullptr, *xval = nullptr, *xtm = nullptr;
+    int2 *xtail = nullptr;
+    double *xg = nullptr;
     double *xsum = nullptr;
     std::vector<void *> allocs;
 

@@ -28,6 +28,11 @@ enum : uint32_t { M_COH = 1, M_IMCOH = 2, M_PLV = 4, M_PLI = 8, M_WPLI = 16, M_U
 
 // XCOR: largest FFT length (LDS of one wavefront's transform)
 constexpr int XCOR_MAX_F = 2048;
+// XCOR tail lags: the lags tau of a node whose suffix energy S(tau) is below
+// E / XCOR_TAIL_RHO2 (lag factor sqrt(E / S(tau)) above 32).  The FP32 FFT's
+// absolute error in the unit-energy correlation, about 1e-7, grows by that
+// factor, so these lags are summed directly in FP64 instead.
+constexpr double XCOR_TAIL_RHO2 = 1024.0;
 
 // XCOR inverse FFT of length F (256..2048) by one wavefront: a first pass of
 // radix xcor_r1(F), then xcor_npass(F) passes of radix xcor_pass_r(F, i) over
@@ -101,7 +106,12 @@ struct SessDev {
     float2 *xpair;          // [N/2][xF] U_2p(f) - i U_2p+1(f) over the full circle
     float *xrho;            // [N][xF] lag factor sqrt(E / S(tau)), S(tau) = sum_{t >= tau} z^2,
                             // at index tau (tau <= xL) and xF - tau (1 <= tau <= xL);
-                            // 0 where S = 0, NaN at the indices of no lag
+                            // 0 where S = 0, NaN at the indices of no lag and of tail lags
+    int2 *xtail;            // [N] (a, e): the node's tail lags are a <= tau < min(e, xL + 1),
+                            // e = 1 + its last nonzero sample; (0, 0): none
+    double *xg;             // [N][Mz] 1 / sqrt(S(tau)) (0 where S = 0)
+    float *xtm;             // [ntiles][TILE_PAIRS] largest XCOR over the tail lags of both
+                            // nodes of the pair (NaN: no tail lag)
     float *xval;            // [(W+1)][ntiles][TILE_PAIRS] per-trial XCOR maxima
     double *xsum;           // [ntiles][TILE_PAIRS] their running sum over the window
 };

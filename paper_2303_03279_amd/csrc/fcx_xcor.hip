@@ -11,7 +11,13 @@
 //                 length F (a power of two >= M + L) of u_2p + i u_2p+1:
 //                 each node's U(f) / F for f = 0..F/2 (row operand) and the
 //                 pair's D(f) = U_2p(f) - i U_2p+1(f) over the full circle
-//                 (column operand), each rounded to FP32 once
+//                 (column operand), each rounded to FP32 once; the node's
+//                 tail lags (below) and 1 / sqrt(S(tau))
+//   k_xcor_tail   per pair: the largest XCOR over the tail lags of both
+//                 nodes, summed directly in FP64.  A tail lag has
+//                 S(tau) < E / 1024: there the lag factor (> 32) would
+//                 magnify the FFT's rounding error beyond 1e-5, so the
+//                 transform's value is not used (its lag factor is NaN)
 //   k_xcor_pair   per pair-tile row i and column pair (j, j + 1): one
 //                 inverse FFT of A(f) conj(D(f)), A(f) = U_i(f) / F, gives
 //                 c_ij(tau) + i c_i,j+1(tau), the circular correlations of the
@@ -21,7 +27,8 @@
 //                   XCOR(-tau) = c(F - tau) rho_j(tau)    tau = 1..L
 //                 which is c / sqrt(S_i(tau) E_j), resp. c / sqrt(E_i S_j(tau)),
 //                 of the z-scored samples (0 where an energy is 0); the maximum
-//                 over the 2L + 1 lags, and the window sum: + this trial's
+//                 over the 2L + 1 lags (with the tail lags' maximum), and the
+//                 window sum: + this trial's
 //                 maximum, - the evicted trial's maximum kept in a ring of
 //                 per-trial values, so add and remove cancel exactly.
 //
@@ -57,11 +64,21 @@ __global__ __launch_bounds__(XT) void k_xcor_node(SessDev<T> s)
     const bool has1 = n0 + 1 < N;
     const PushView pv = push_view(s, s.ctl->pushed);
     const float *zr = s.zring + ((size_t)pv.slot_new * N + n0) * s.Mz;
+    // per node: the first tail lag (M: none) and 1 + the last nonzero sample
+    __shared__ int tail_lo[2], tail_end[2];
+    if (tid < 2) {
+        tail_lo[tid] = M;
+        tail_end[tid] = 0;
+    }
     for (int t = tid; t < M; t += XT) {
         z[0][t] = zr[t];
         z[1][t] = has1 ? zr[s.Mz + t] : 0.f;
     }
     __syncthreads();
+    for (int t = tid; t < M; t += XT) {
+        if (z[0][t] != 0.f) atomicMax(&tail_end[0], t + 1);
+        if (z[1][t] != 0.f) atomicMax(&tail_end[1], t + 1);
+    }
     // suffix energies, FP64, wavefront h for node h: lane l sums its segment
     // of samples from the top, the sum of the segments above it comes from a
     // scan over the lanes (fixed order), then the lane writes its segment's
@@ -87,12 +104,30 @@ __global__ __launch_bounds__(XT) void k_xcor_node(SessDev<T> s)
     }
     __syncthreads();
     const double E0 = suf[0], E1 = suf[F];
+    // tail lags: 1 <= tau <= L with 0 < S(tau) < E / XCOR_TAIL_RHO2; S does
+    // not increase with tau, so they run from the first such lag to the
+    // last lag with S > 0 (tau < tail_end)
+    for (int e = tid; e < 2 * M; e += XT) {
+        const int h = e >= M, tau = e - h * M;
+        if (tau >= 1 && tau <= L && tau < tail_end[h] && suf[h * F + tau] * XCOR_TAIL_RHO2 < suf[h * F])
+            atomicMin(&tail_lo[h], tau);
+    }
+    __syncthreads();
+    if (tid < 2) {
+        const int a = tail_lo[tid], e = tail_end[tid];
+        s.xtail[n0 + tid] = a < min(e, L + 1) ? make_int2(a, e) : make_int2(0, 0);
+    }
+    for (int e = tid; e < 2 * s.Mz; e += XT) {
+        const int h = e >= s.Mz, t = e - h * s.Mz;
+        const double S = t < M ? suf[h * F + t] : 0.0;
+        s.xg[(size_t)(n0 + h) * s.Mz + t] = S > 0.0 ? 1.0 / sqrt(S) : 0.0;
+    }
     // lag factors: index tau < F/2 for lag tau, index F - tau for lag -tau
     for (int e = tid; e < 2 * F; e += XT) {
         const int h = e / F, id = e - h * F;
         const int tau = id < F / 2 ? id : F - id;
         float v = __builtin_nanf("");
-        if (tau <= L) {
+        if (tau <= L && !(tau >= tail_lo[h] && tau < tail_end[h])) {
             const double S = suf[h * F + tau];
             v = S > 0.0 ? (float)sqrt(suf[h * F] / S) : 0.f;
         }
@@ -132,6 +167,48 @@ __global__ __launch_bounds__(XT) void k_xcor_node(SessDev<T> s)
             x1[f] = make_float2((float)((y.y + ym.y) * sc), (float)((ym.x - y.x) * sc));
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// tail lags: one wavefront per (tile, row), one lane per column
+// ---------------------------------------------------------------------------
+// The largest XCOR over the tail lags of the pair (i, j): lags tau of row
+// node i's tail, sum_t z_i(t + tau) z_j(t) / sqrt(S_i(tau) E_j), and lags
+// -tau of column node j's tail, sum_t z_i(t) z_j(t + tau) / sqrt(E_i S_j(tau)),
+// summed in FP64 from the trial's z-scored samples (products of FP32 values
+// are exact in FP64).  The sums stop at the node's last nonzero sample.
+constexpr int XTAIL_ROWS = 4;   // rows (wavefronts) per workgroup
+
+template <typename T>
+__global__ __launch_bounds__(64 * XTAIL_ROWS) void k_xcor_tail(SessDev<T> s)
+{
+    if (s.ctl->bad) return;
+    const int tile = blockIdx.x / (TILE / XTAIL_ROWS);
+    const int r = (blockIdx.x % (TILE / XTAIL_ROWS)) * XTAIL_ROWS +
+                  (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int2 tt = s.tiles[tile];
+    const int N = s.N, L = s.xL, Mz = s.Mz;
+    const int i = tt.x * TILE + r, j = tt.y * TILE + lane;
+    float best = __builtin_nanf("");
+    if (i < N && j > i && j < N) {
+        const PushView pv = push_view(s, s.ctl->pushed);
+        const float *zs = s.zring + (size_t)pv.slot_new * N * Mz;
+        const float *zi = zs + (size_t)i * Mz, *zj = zs + (size_t)j * Mz;
+        const double *gi = s.xg + (size_t)i * Mz, *gj = s.xg + (size_t)j * Mz;
+        const int2 ti = s.xtail[i], tj = s.xtail[j];
+        for (int tau = ti.x; tau < min(ti.y, L + 1); ++tau) {
+            double acc = 0.0;
+            for (int t = 0; t < ti.y - tau; ++t) acc = __builtin_fma((double)zi[t + tau], (double)zj[t], acc);
+            best = fmaxf(best, (float)(acc * gi[tau] * gj[0]));
+        }
+        for (int tau = tj.x; tau < min(tj.y, L + 1); ++tau) {
+            double acc = 0.0;
+            for (int t = 0; t < tj.y - tau; ++t) acc = __builtin_fma((double)zi[t], (double)zj[t + tau], acc);
+            best = fmaxf(best, (float)(acc * gj[tau] * gi[0]));
+        }
+    }
+    s.xtm[(size_t)tile * TILE_PAIRS + (size_t)r * TILE + lane] = best;
 }
 
 // ---------------------------------------------------------------------------
@@ -353,6 +430,9 @@ void k_xcor_pair(SessDev<T> s)
     // pn (if any) into dn once d is consumed
     auto job = [&](int pp, float2 (&d)[PER1][R1], int pn, float2 (&dn)[PER1][R1]) {
         const int j1 = J0 + 2 * pp, j2 = j1 + 1;
+        // the tail lags' maximum of this lane's pair (lanes 0 and 1), used at the end
+        const float tm = lane < 2 ? s.xtm[(size_t)tile * TILE_PAIRS + (size_t)r * TILE + (j1 + lane - J0)]
+                                  : 0.f;
         // this job's column lag factors (lags < 0), used after the transform
         float cf1[PERL][HL], cf2[PERL][HL];
 #pragma unroll
@@ -408,8 +488,8 @@ void k_xcor_pair(SessDev<T> s)
         if (lane < 2) {
             const int jj = lane == 0 ? j1 : j2;
             if (jj > i && jj < N) {
-                const float v = lane == 0 ? b1 : b2;
                 const size_t e = (size_t)tile * TILE_PAIRS + (size_t)r * TILE + (jj - J0);
+                const float v = fmaxf(lane == 0 ? b1 : b2, tm);   // the tail lags (NaN: none)
                 double sum = s.xsum[e] + (double)v;
                 if (pv.has_old) sum = sum - (double)s.xval[(size_t)pv.slot_old * TP + e];
                 s.xsum[e] = sum;
@@ -435,6 +515,8 @@ void k_xcor_pair(SessDev<T> s)
 template <typename T, int F> static void launch_xcor_f(const SessDev<T> &s, hipStream_t st)
 {
     hipLaunchKernelGGL((k_xcor_node<T, F>), dim3((s.N + 1) / 2), dim3(XT), 0, st, s);
+    hipLaunchKernelGGL((k_xcor_tail<T>), dim3((unsigned)(s.ntiles * (TILE / XTAIL_ROWS))), dim3(64 * XTAIL_ROWS),
+                       0, st, s);
     hipLaunchKernelGGL((k_xcor_pair<T, F>), dim3((unsigned)(s.ntiles * TILE)), dim3(64 * xcor_waves<F>()), 0, st,
                        s);
 }

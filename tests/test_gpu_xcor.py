@@ -85,6 +85,45 @@ def test_degenerate_rows_and_transients(fcx):
     s.close()
 
 
+@pytest.mark.parametrize("N", [2, 3, 5, 63, 64, 65, 129])
+def test_node_counts_and_tile_edges(fcx, N):
+    """The smallest networks (one pair; an odd count, so the last column pair
+    holds a missing node) and counts at and around the 64-node tile edge,
+    with a lagged copy between the first two nodes."""
+    M, W, T = 120, 3, 5
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=W, n_fft=128, f_lo_hz=8, f_hi_hz=30,
+                            metrics=synth.XCOR)
+    rng = np.random.default_rng(100 + N)
+    x = rng.standard_normal((T, N, M)).astype(np.float32)
+    x[:, 1, 7:] += 0.8 * x[:, 0, :-7]
+    s = run_pushes(fcx, cfg, x)
+    _check(s, x, cfg, T - W, T, f"N={N}")
+    s.close()
+
+
+@pytest.mark.parametrize("L", [0, 50])
+def test_tail_lags(fcx, L):
+    """Lags whose overlap holds under 1/1024 of the advanced node's energy
+    (summed directly): white noise (short tails at the last samples), a
+    decaying transient (a tail of most lags), and a node of zero-mean
+    integers followed by exact zeros (zero suffix energy from sample 80 on,
+    so its XCOR there is 0 and its sums stop at sample 80)."""
+    N, M, W, T = 10, 200, 3, 4
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=W, n_fft=256, f_lo_hz=8, f_hi_hz=30,
+                            metrics=synth.XCOR, xcor_max_lag=L)
+    rng = np.random.default_rng(31 + L)
+    x = rng.standard_normal((T, N, M)).astype(np.float32)
+    h = rng.integers(-5, 6, size=(T, 80))
+    h[:, -1] -= h.sum(axis=1)
+    x[:, 4] = 0.0
+    x[:, 4, :80] = h
+    x[:, 5] *= np.exp(-np.arange(M) / 15.0).astype(np.float32)
+    x[:, 6, 9:] += 0.7 * x[:, 5, :-9]
+    s = run_pushes(fcx, cfg, x)
+    _check(s, x, cfg, T - W, T, f"tails L={L}")
+    s.close()
+
+
 def test_batch_then_read(fcx):
     """After a batch pass the XCOR sums come from the replay of the window."""
     N, M, W = 60, 300, 5
