@@ -369,9 +369,39 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, in
             __syncthreads();
             fetch(cc + 1, pre);   // the next chunk is on its way while this one is computed
 
-            pb_gram<PREC, !VS>(XR ? Xr : nullptr, Xf, Xc, Xh, arow, bcol0, arow, 64 + bcol0, lg, sre, sim);
-            if (needU)
-                pb_gram<PREC, true>(nullptr, Us, Us + 64 * PB_LD, Uh, arow, bcol0, arow, 64 + bcol0, lg, ure, uim);
+            // FP32 Gram with vector sums: its steps (4 trials each) are
+            // interleaved with the vector sums of the same trials below, so
+            // the matrix cores work while the vector units sum
+            constexpr bool MIX = VS && PREC == FCX_GRAM_FP32_ID;
+            if constexpr (!MIX) {
+                pb_gram<PREC, !VS>(XR ? Xr : nullptr, Xf, Xc, Xh, arow, bcol0, arow, 64 + bcol0, lg, sre, sim);
+                if (needU)
+                    pb_gram<PREC, true>(nullptr, Us, Us + 64 * PB_LD, Uh, arow, bcol0, arow, 64 + bcol0, lg, ure,
+                                        uim);
+            }
+            // one FP32 Gram step: trials 4 st + lg of the chunk (Re S, and the
+            // unit-phasor Gram); steps past the chunk's trials would add zeros
+            auto gram_step = [&](int st) {
+                const double2 ad = Xr[arow * PB_LD + 4 * st + lg];
+                const float2 a = make_float2((float)ad.x, (float)ad.y);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const float2 bb = Xc[(bcol0 + 16 * c) * PB_LD + 4 * st + lg];
+                    sre[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, sre[c], 0, 0, 0);
+                    sre[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, sre[c], 0, 0, 0);
+                }
+                if (needU) {
+                    const float2 ua = Us[arow * PB_LD + 4 * st + lg];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const float2 ub = Us[(64 + bcol0 + 16 * c) * PB_LD + 4 * st + lg];
+                        ure[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua.x, ub.x, ure[c], 0, 0, 0);
+                        ure[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua.y, ub.y, ure[c], 0, 0, 0);
+                        uim[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua.y, ub.x, uim[c], 0, 0, 0);
+                        uim[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ua.x, ub.y, uim[c], 0, 0, 0);
+                    }
+                }
+            };
             if constexpr (VS) {
                 // trial t's operands are loaded while trial t - 1 is summed;
                 // columns past the trials are 0 and add nothing, and the pad
@@ -401,11 +431,25 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_batch1(SessDev<float> s, in
                 double2 ra[4], rb[4];
                 float2 ca[2], cb[2];
                 ldt(0, ra, ca);
-                for (int t = 0; t < nk; t += 2) {
-                    ldt(t + 1, rb, cb);
-                    sum_t(ra, ca);
-                    ldt(min(t + 2, PB_CC), ra, ca);
-                    sum_t(rb, cb);
+                if constexpr (MIX) {
+                    for (int t = 0; t < nk; t += 4) {
+                        gram_step(t >> 2);
+                        ldt(t + 1, rb, cb);
+                        sum_t(ra, ca);
+                        ldt(t + 2, ra, ca);
+                        sum_t(rb, cb);
+                        ldt(t + 3, rb, cb);
+                        sum_t(ra, ca);
+                        ldt(min(t + 4, PB_CC), ra, ca);
+                        sum_t(rb, cb);
+                    }
+                } else {
+                    for (int t = 0; t < nk; t += 2) {
+                        ldt(t + 1, rb, cb);
+                        sum_t(ra, ca);
+                        ldt(min(t + 2, PB_CC), ra, ca);
+                        sum_t(rb, cb);
+                    }
                 }
             }
         }
