@@ -290,10 +290,10 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_clear(SelCtl *c)
         p[i] = 0ull;
 }
 
-__device__ __forceinline__ bool sel_take(float v, const SelCtl &c, unsigned int T)
+__device__ __forceinline__ bool sel_take(float v, bool none, unsigned int T)
 {
     unsigned int key;
-    return sel_key(v, key) && !c.h.none && key >= T;
+    return sel_key(v, key) && !none && key >= T;
 }
 
 __device__ __forceinline__ float sel_norm(float v, float m)
@@ -315,27 +315,40 @@ __global__ __launch_bounds__(SEL_THREADS) void k_sel_rows(const float *w, int N,
     __shared__ unsigned long long scnt[SEL_THREADS / 64];
     const int i = blockIdx.x * (SEL_THREADS / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    // the selection state is read once: the byte stores below may alias it
     const unsigned int T = c->h.prefix;
     const float m = __uint_as_float(c->h.maxbits);
+    const bool none = c->h.none;
     unsigned long long ns = 0;
     if (i < N - 1) {
         const long long r0 = (long long)i * (2LL * N - i - 1) / 2 - (i + 1);   // e = r0 + j
         int deg = 0;
         double str = 0.0;
-        for (int j = i + 1 + lane; j < N; j += 64) {
-            const long long e = r0 + j;
-            const float v = w[e];
-            const bool t = sel_take(v, *c, T);
-            const float nv = sel_norm(v, m);
-            if (selected) selected[e] = t;
-            if (w_norm) w_norm[e] = nv;
-            if (t) {
-                ++ns;
-                if (nodes) {
-                    ++deg;
-                    const float a = fabsf(nv);
-                    str += (double)a;
-                    atomicAdd(&c->node[j], SEL_DEG1 + (unsigned long long)rint((double)a * SEL_FIX));
+        // eight loads in flight per lane (the edges are visited in the same order)
+        for (int j0 = i + 1 + lane; j0 < N; j0 += 8 * 64) {
+            float v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int j = j0 + 64 * q;
+                v[q] = j < N ? w[r0 + j] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int j = j0 + 64 * q;
+                if (j >= N) break;
+                const long long e = r0 + j;
+                const bool t = sel_take(v[q], none, T);
+                const float nv = sel_norm(v[q], m);
+                if (selected) selected[e] = t;
+                if (w_norm) w_norm[e] = nv;
+                if (t) {
+                    ++ns;
+                    if (nodes) {
+                        ++deg;
+                        const float a = fabsf(nv);
+                        str += (double)a;
+                        atomicAdd(&c->node[j], SEL_DEG1 + (unsigned long long)rint((double)a * SEL_FIX));
+                    }
                 }
             }
         }
