@@ -75,9 +75,20 @@ __global__ __launch_bounds__(XT) void k_xcor_node(SessDev<T> s)
         z[1][t] = has1 ? zr[s.Mz + t] : 0.f;
     }
     __syncthreads();
-    for (int t = tid; t < M; t += XT) {
-        if (z[0][t] != 0.f) atomicMax(&tail_end[0], t + 1);
-        if (z[1][t] != 0.f) atomicMax(&tail_end[1], t + 1);
+    {
+        int e0 = 0, e1 = 0;
+        for (int t = tid; t < M; t += XT) {
+            if (z[0][t] != 0.f) e0 = t + 1;
+            if (z[1][t] != 0.f) e1 = t + 1;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            e0 = max(e0, __shfl_xor(e0, o, 64));
+            e1 = max(e1, __shfl_xor(e1, o, 64));
+        }
+        if (lane == 0) {
+            if (e0) atomicMax(&tail_end[0], e0);
+            if (e1) atomicMax(&tail_end[1], e1);
+        }
     }
     // suffix energies, FP64, wavefront h for node h: lane l sums its segment
     // of samples from the top, the sum of the segments above it comes from a
@@ -107,10 +118,20 @@ __global__ __launch_bounds__(XT) void k_xcor_node(SessDev<T> s)
     // tail lags: 1 <= tau <= L with 0 < S(tau) < E / XCOR_TAIL_RHO2; S does
     // not increase with tau, so they run from the first such lag to the
     // last lag with S > 0 (tau < tail_end)
-    for (int e = tid; e < 2 * M; e += XT) {
-        const int h = e >= M, tau = e - h * M;
-        if (tau >= 1 && tau <= L && tau < tail_end[h] && suf[h * F + tau] * XCOR_TAIL_RHO2 < suf[h * F])
-            atomicMin(&tail_lo[h], tau);
+    {
+        int a0 = M, a1 = M;
+        for (int tau = 1 + tid; tau <= min(L, M - 1); tau += XT) {
+            if (tau < a0 && tau < tail_end[0] && suf[tau] * XCOR_TAIL_RHO2 < suf[0]) a0 = tau;
+            if (tau < a1 && tau < tail_end[1] && suf[F + tau] * XCOR_TAIL_RHO2 < suf[F]) a1 = tau;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            a0 = min(a0, __shfl_xor(a0, o, 64));
+            a1 = min(a1, __shfl_xor(a1, o, 64));
+        }
+        if (lane == 0) {
+            if (a0 < M) atomicMin(&tail_lo[0], a0);
+            if (a1 < M) atomicMin(&tail_lo[1], a1);
+        }
     }
     __syncthreads();
     if (tid < 2) {
