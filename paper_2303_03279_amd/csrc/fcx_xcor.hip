@@ -191,45 +191,76 @@ __global__ __launch_bounds__(XT) void k_xcor_node(SessDev<T> s)
 }
 
 // ---------------------------------------------------------------------------
-// tail lags: one wavefront per (tile, row), one lane per column
+// tail lags: one lane per column, four rows of a tile per wavefront
 // ---------------------------------------------------------------------------
 // The largest XCOR over the tail lags of the pair (i, j): lags tau of row
 // node i's tail, sum_t z_i(t + tau) z_j(t) / sqrt(S_i(tau) E_j), and lags
 // -tau of column node j's tail, sum_t z_i(t) z_j(t + tau) / sqrt(E_i S_j(tau)),
 // summed in FP64 from the trial's z-scored samples (products of FP32 values
-// are exact in FP64).  The sums stop at the node's last nonzero sample.
-constexpr int XTAIL_ROWS = 4;   // rows (wavefronts) per workgroup
+// are exact in FP64).  The sums stop at the node's last nonzero sample.  A
+// wavefront takes four rows, so one column's samples serve four pairs.
+constexpr int XTAIL_RPW = 4;                      // rows per wavefront
+constexpr int XTAIL_WAVES = 4;                    // wavefronts per workgroup
+constexpr int XTAIL_ROWS = XTAIL_RPW * XTAIL_WAVES;   // rows per workgroup
 
 template <typename T>
-__global__ __launch_bounds__(64 * XTAIL_ROWS) void k_xcor_tail(SessDev<T> s)
+__global__ __launch_bounds__(64 * XTAIL_WAVES) void k_xcor_tail(SessDev<T> s)
 {
     if (s.ctl->bad) return;
     const int tile = blockIdx.x / (TILE / XTAIL_ROWS);
-    const int r = (blockIdx.x % (TILE / XTAIL_ROWS)) * XTAIL_ROWS +
-                  (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r0 = (blockIdx.x % (TILE / XTAIL_ROWS)) * XTAIL_ROWS +
+                   XTAIL_RPW * (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int2 tt = s.tiles[tile];
     const int N = s.N, L = s.xL, Mz = s.Mz;
-    const int i = tt.x * TILE + r, j = tt.y * TILE + lane;
-    float best = __builtin_nanf("");
-    if (i < N && j > i && j < N) {
+    const int i0 = tt.x * TILE + r0, j = tt.y * TILE + lane;
+    float best[XTAIL_RPW];
+#pragma unroll
+    for (int k = 0; k < XTAIL_RPW; ++k) best[k] = __builtin_nanf("");
+    if (i0 < N && j > i0 && j < N) {
         const PushView pv = push_view(s, s.ctl->pushed);
         const float *zs = s.zring + (size_t)pv.slot_new * N * Mz;
-        const float *zi = zs + (size_t)i * Mz, *zj = zs + (size_t)j * Mz;
-        const double *gi = s.xg + (size_t)i * Mz, *gj = s.xg + (size_t)j * Mz;
-        const int2 ti = s.xtail[i], tj = s.xtail[j];
-        for (int tau = ti.x; tau < min(ti.y, L + 1); ++tau) {
-            double acc = 0.0;
-            for (int t = 0; t < ti.y - tau; ++t) acc = __builtin_fma((double)zi[t + tau], (double)zj[t], acc);
-            best = fmaxf(best, (float)(acc * gi[tau] * gj[0]));
+        const float *zj = zs + (size_t)j * Mz;
+        const double *gj = s.xg + (size_t)j * Mz;
+        const double gj0 = gj[0];
+        const int2 tj = s.xtail[j];
+        const int nr = min(XTAIL_RPW, N - i0);   // rows of this wavefront below N
+        // lags tau >= 0 in each row's tail
+#pragma unroll
+        for (int k = 0; k < XTAIL_RPW; ++k) {
+            if (k >= nr) break;
+            const int i = i0 + k;
+            if (j <= i) continue;
+            const float *zi = zs + (size_t)i * Mz;
+            const double *gi = s.xg + (size_t)i * Mz;
+            const int2 ti = s.xtail[i];
+            for (int tau = ti.x; tau < min(ti.y, L + 1); ++tau) {
+                double acc = 0.0;
+                for (int t = 0; t < ti.y - tau; ++t) acc = __builtin_fma((double)zi[t + tau], (double)zj[t], acc);
+                best[k] = fmaxf(best[k], (float)(acc * gi[tau] * gj0));
+            }
         }
+        // lags -tau in the column's tail, for the four rows at once
         for (int tau = tj.x; tau < min(tj.y, L + 1); ++tau) {
-            double acc = 0.0;
-            for (int t = 0; t < tj.y - tau; ++t) acc = __builtin_fma((double)zi[t], (double)zj[t + tau], acc);
-            best = fmaxf(best, (float)(acc * gj[tau] * gi[0]));
+            double acc[XTAIL_RPW];
+#pragma unroll
+            for (int k = 0; k < XTAIL_RPW; ++k) acc[k] = 0.0;
+            for (int t = 0; t < tj.y - tau; ++t) {
+                const double v = (double)zj[t + tau];
+#pragma unroll
+                for (int k = 0; k < XTAIL_RPW; ++k)
+                    if (k < nr) acc[k] = __builtin_fma((double)zs[(size_t)(i0 + k) * Mz + t], v, acc[k]);
+            }
+            const double g = gj[tau];
+#pragma unroll
+            for (int k = 0; k < XTAIL_RPW; ++k)
+                if (k < nr && j > i0 + k)
+                    best[k] = fmaxf(best[k], (float)(acc[k] * g * s.xg[(size_t)(i0 + k) * Mz]));
         }
     }
-    s.xtm[(size_t)tile * TILE_PAIRS + (size_t)r * TILE + lane] = best;
+#pragma unroll
+    for (int k = 0; k < XTAIL_RPW; ++k)
+        s.xtm[(size_t)tile * TILE_PAIRS + (size_t)(r0 + k) * TILE + lane] = best[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -536,7 +567,7 @@ void k_xcor_pair(SessDev<T> s)
 template <typename T, int F> static void launch_xcor_f(const SessDev<T> &s, hipStream_t st)
 {
     hipLaunchKernelGGL((k_xcor_node<T, F>), dim3((s.N + 1) / 2), dim3(XT), 0, st, s);
-    hipLaunchKernelGGL((k_xcor_tail<T>), dim3((unsigned)(s.ntiles * (TILE / XTAIL_ROWS))), dim3(64 * XTAIL_ROWS),
+    hipLaunchKernelGGL((k_xcor_tail<T>), dim3((unsigned)(s.ntiles * (TILE / XTAIL_ROWS))), dim3(64 * XTAIL_WAVES),
                        0, st, s);
     hipLaunchKernelGGL((k_xcor_pair<T, F>), dim3((unsigned)(s.ntiles * TILE)), dim3(64 * xcor_waves<F>()), 0, st,
                        s);
