@@ -169,7 +169,9 @@ fcx_status fcx_push_batch(fcx_session *s, const void *x, int64_t n_trials, int64
  * averaged).
  * per_bin = 0: band mean, out_len >= P.  per_bin = 1: [B][P], out_len >= B*P
  * (COR and XCOR are broadband and always [P]).  Element type follows
- * cfg.elem; XCOR is computed in FP32 (an FP32 FFT per pair) for both.
+ * cfg.elem; XCOR is computed in FP32 (an FP32 FFT per pair) for both,
+ * except at the lags where the overlap holds under 1/1024 of the advanced
+ * node's energy, which are summed directly in FP64.
  * *k_trials_out (may be NULL) receives K, the trials in the window.
  * Synchronous.  Returns FCX_E_NOTREADY (and fills NaN) for USPLI/DSWPLI
  * while K < 2 and when no trial was pushed; FCX_E_NONFINITE once after a
