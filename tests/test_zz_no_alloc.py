@@ -78,3 +78,43 @@ def test_noalloc_rejects_oversize(fcx):
     assert st == fcx.FCX_E_INVAL
     st, _ = fcx.network_select_noalloc(1, w.data_ptr(), 0.05)
     assert st == fcx.FCX_E_INVAL
+
+
+def test_noalloc_under_graph_capture(fcx):
+    """The enqueue-only form (no info) captured in a HIP graph through
+    torch.cuda.graph and replayed three times, the network rewritten eagerly
+    in the same buffer before each replay and the allocating call run eagerly
+    after it: every replay's outputs equal that call's, bit for bit."""
+    import torch
+    N, frac = 900, 0.05
+    P = N * (N - 1) // 2
+    w = torch.from_numpy(_network(N, 11)).cuda()
+    w_norm = torch.empty(P, dtype=torch.float32, device="cuda")
+    sel = torch.empty(P, dtype=torch.uint8, device="cuda")
+    deg = torch.empty(N, dtype=torch.int32, device="cuda")
+    stren = torch.empty(N, dtype=torch.float32, device="cuda")
+    args = (N, w.data_ptr(), frac, w_norm.data_ptr(), sel.data_ptr(), deg.data_ptr(), stren.data_ptr())
+    # eager warm-up on a side stream: the first call on the device looks up the array
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fcx.check(fcx.network_select_noalloc(*args, stream=side.cuda_stream, want_info=False)[0], "warm-up")
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        st, _ = fcx.network_select_noalloc(*args, stream=torch.cuda.current_stream().cuda_stream, want_info=False)
+    fcx.check(st, "capture")
+    torch.cuda.synchronize()
+    for rep in range(3):
+        log(f"graph replay {rep}")
+        data = _network(N, 20 + rep) * np.float32(rep + 1)
+        w.copy_(torch.from_numpy(data))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = (None, w_norm.cpu().numpy(), sel.cpu().numpy(), deg.cpu().numpy(), stren.cpu().numpy())
+        ref = _select(fcx, "select", data, N, frac)
+        _same(got, ref, f"replay {rep}")
+        assert int(got[2].sum()) == ref[0]["n_selected"] > 0
+    del g
