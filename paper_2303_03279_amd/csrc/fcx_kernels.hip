@@ -1154,36 +1154,115 @@ template <typename T> hipError_t launch_psd_rebuild(const SessDev<T> &s, long lo
     return hipGetLastError();
 }
 
-// the COR sums of a slice: per trial the same 16x16 MFMA chain over the
-// z-scored samples as cor_block (steps in order, components x, y, z, w),
-// each trial's block added to the FP64 sums in trial order
+// the COR sums of a whole 64x64 tile rebuilt from the window's cached
+// z-scored samples: per 16x16 block and trial the same MFMA chain as the
+// sliding update (cor_chain: steps in order, components x, y, z, w, the same
+// lane layout), each trial's block added to the FP64 sums in trial order, so
+// the sums are bit for bit those of a replay.  The tile's 64 row nodes are
+// staged in LDS CRB_CH samples at a time (the next chunk loaded into
+// registers meanwhile); wavefront w reads its 16 column nodes once per step,
+// two steps ahead, for the tile's four row blocks, whose four chains run side
+// by side.  Each trial's samples are read once per tile instead of once per
+// 16x16 block.
+constexpr int CRB_CH = 128;             // samples per staged chunk
+constexpr int CRB_LD = CRB_CH + 4;     // LDS row stride in floats
+
 template <typename T>
-__device__ __forceinline__ void cor_rebuild(const SessDev<T> &s, long long first, int K, int tile, int sub, int J0,
-                                            int R0, int w)
+__global__ __launch_bounds__(256) void k_cor_rebuild(SessDev<T> s, long long first, int K)
 {
+    __shared__ __align__(16) float Zr[TILE * CRB_LD];
+    const int tile = xcd_item(blockIdx.x, gridDim.x);
+    const int2 tt = s.tiles[tile];
     const int N = s.N, Mz = s.Mz;
-    const int C0 = J0 + 16 * w;
-    if (R0 >= N || C0 >= N || R0 >= C0 + 15) return;
-    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-    const int row = R0 + lr, col = C0 + lr;
-    const bool rv = row < N, cv = col < N;
-    const int steps = Mz / 16;
-    double R[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int t = 0; t < K; ++t) {
-        const int slot = (int)((first + t) % (long long)s.R);
-        const floatx4 an = cor_chain(s, slot, rv ? row : 0, cv ? col : 0, lg, steps);
+    const int R0 = tt.x * TILE, J0 = tt.y * TILE;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+    const int C0 = J0 + 16 * w, col = C0 + lr;
+    // row block b (tile rows 16b..16b+15) holds a pair i < j < N with these columns
+    bool act[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) R[k] = R[k] + (double)an[k];
+    for (int b = 0; b < 4; ++b) {
+        const int Rb = R0 + 16 * b;
+        act[b] = !(Rb >= N || C0 >= N || Rb >= C0 + 15);
+    }
+    double R[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) R[b][k] = 0.0;
+    // the (trial, chunk) sequence; the next chunk's rows are loaded into
+    // registers while the current one is contracted, and a chunk's column
+    // values are loaded before its rows are stored
+    const int nch = (Mz + CRB_CH - 1) / CRB_CH, total = K * nch;
+    // thread tid stages float4 q = tid mod QPR of rows tid / QPR + u RPR
+    // (u < RPT); float4s past the row's Mz samples are 0
+    constexpr int QPR = CRB_CH / 4, RPR = 256 / QPR, RPT = TILE / RPR;
+    const int sq = tid % QPR, sr = tid / QPR;
+    auto zslot = [&](int t) { return s.zring + (size_t)((first + t) % (long long)s.R) * N * Mz; };
+    auto load_rows = [&](int ix, float4 (&v)[RPT]) {
+        const int t = ix / nch, c0 = (ix - t * nch) * CRB_CH;
+        const bool ok = ix < total && c0 + 4 * sq < Mz;
+        const float *zs = zslot(ok ? t : 0) + c0 + 4 * sq;
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            const int g = R0 + sr + RPR * u;
+            v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (ok && g < N) v[u] = *(const float4 *)(zs + (size_t)g * Mz);
+        }
+    };
+    float4 rows[RPT];
+    load_rows(0, rows);
+    floatx4 an[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) an[b] = (floatx4){0.f, 0.f, 0.f, 0.f};
+    for (int ix = 0; ix < total; ++ix) {
+        const int t = ix / nch, ci = ix - t * nch, c0 = ci * CRB_CH, nq = min(CRB_CH, Mz - c0) / 4;
+        // a lane past N reads column 0, which only feeds columns never stored
+        const float4 *cn = (const float4 *)(zslot(t) + (size_t)(col < N ? col : 0) * Mz + c0) + lg;
+        const int ns = nq / 4;   // 16-sample steps in this chunk
+        // the column values two steps ahead are in flight while a step's MFMAs issue
+        float4 y0 = cn[0], y1 = cn[4 * min(1, ns - 1)];
+        __syncthreads();   // the previous chunk's readers are done
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) *(float4 *)(Zr + (sr + RPR * u) * CRB_LD + 4 * sq) = rows[u];
+        __syncthreads();
+        load_rows(ix + 1, rows);
+        for (int st = 0; st < ns; ++st) {
+            const float4 y = y0, y2 = cn[4 * min(st + 2, ns - 1)];
+            y0 = y1;
+            y1 = y2;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if (!act[b]) continue;
+                const float4 x = *(const float4 *)(Zr + (16 * b + lr) * CRB_LD + 16 * st + 4 * lg);
+                an[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, y.x, an[b], 0, 0, 0);
+                an[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, y.y, an[b], 0, 0, 0);
+                an[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, y.z, an[b], 0, 0, 0);
+                an[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, y.w, an[b], 0, 0, 0);
+            }
+        }
+        if (ci == nch - 1) {   // the trial's blocks, into the sums in trial order
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) R[b][k] = R[b][k] + (double)an[b][k];
+                an[b] = (floatx4){0.f, 0.f, 0.f, 0.f};
+            }
+        }
     }
     const size_t P = (size_t)N * (N - 1) / 2;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int ri = 16 * sub + 4 * lg + k, cj = 16 * w + lr;
-        const int i = R0 + 4 * lg + k, j = C0 + lr;
-        if (!(i < j && j < N)) continue;
-        s.rsum[(size_t)tile * TILE_PAIRS + (size_t)ri * TILE + cj] = R[k];
-        const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
-        s.out[7 * P + idx] = (T)(R[k] / (double)K);
+    for (int b = 0; b < 4; ++b) {
+        if (!act[b]) continue;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            // accumulator element k of lane l: row 4*(l>>4)+k, column l&15 of the block
+            const int ri = 16 * b + 4 * lg + k, cj = 16 * w + lr;
+            const int i = R0 + ri, j = C0 + lr;
+            if (!(i < j && j < N)) continue;
+            s.rsum[(size_t)tile * TILE_PAIRS + (size_t)ri * TILE + cj] = R[b][k];
+            const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(j - i - 1);
+            s.out[7 * P + idx] = (T)(R[b][k] / (double)K);
+        }
     }
 }
 
@@ -1217,7 +1296,6 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_rebuild(SessDev<T> s, lon
     const bool g8 = UG >= 0 ? (UG & 2) != 0 : s.g_narrow != 0;
     const float uscale = ldexpf(1.0f, s.ufix_bits);
     const T uinvT = (T)ldexp(1.0, -s.ufix_bits);
-    const bool with_cor = COR > 0 || (COR < 0 && (s.metrics & M_COR));
     const bool stageU = L == 1 && needU;
     const T2 *ring = (const T2 *)s.ring;
     const size_t P = (size_t)N * (N - 1) / 2;
@@ -1335,7 +1413,6 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_rebuild(SessDev<T> s, lon
                 if (mm & (1u << m)) s.out[(size_t)m * P + idx] = acc[q][m] / (T)B;
         }
     }
-    if (with_cor) cor_rebuild(s, first, K, tile, sub, J0, R0, w);
 }
 
 template <typename T> hipError_t launch_pair_rebuild(const SessDev<T> &s, long long first, int K, hipStream_t st)
@@ -1345,20 +1422,20 @@ template <typename T> hipError_t launch_pair_rebuild(const SessDev<T> &s, long l
     const int per = rebuild_trial_bytes(s.L, (int)sizeof(T), spec);
     int TT = (PAIR_LDS_BYTES - PAIR_NODES * 8) / per;
     TT = TT < 1 ? 1 : (TT > K ? K : TT);
-    const size_t lds = spec ? (size_t)TT * per + PAIR_NODES * 8 : 0;
+    const size_t lds = (size_t)TT * per + PAIR_NODES * 8;
     const dim3 grid(s.ntiles * SLICES), blk(PAIR_THREADS);
-    if constexpr (sizeof(T) == 4) {
-        dispatch_pair_class(pair_kernel_class(s), [&](auto v) {
-            using V = decltype(v);
-            hipLaunchKernelGGL((k_pair_rebuild<float, V::spec, V::lt, V::cor, V::ug>), grid, blk, lds, st, s,
-                               first, K, TT);
-        });
-    } else {
-        if (s.metrics & M_COR)
-            hipLaunchKernelGGL((k_pair_rebuild<T, 0u, 0, 1, -1>), grid, blk, lds, st, s, first, K, TT);
-        else
+    if (spec) {
+        if constexpr (sizeof(T) == 4) {
+            dispatch_pair_class(pair_kernel_class(s), [&](auto v) {
+                using V = decltype(v);
+                hipLaunchKernelGGL((k_pair_rebuild<float, V::spec, V::lt, V::cor, V::ug>), grid, blk, lds, st, s,
+                                   first, K, TT);
+            });
+        } else {
             hipLaunchKernelGGL((k_pair_rebuild<T, 0u, 0, 0, -1>), grid, blk, lds, st, s, first, K, TT);
+        }
     }
+    if (s.metrics & M_COR) hipLaunchKernelGGL(k_cor_rebuild<T>, dim3(s.ntiles), dim3(256), 0, st, s, first, K);
     return hipGetLastError();
 }
 

@@ -109,3 +109,27 @@ def test_batch_then_slide_equals_fresh_window(fcx, case):
     _same(_networks(c), _networks(b), f"{case} batch then {x.shape[0] - T} pushes")
     c.close()
     b.close()
+
+
+def test_resync_cor_only(fcx):
+    """A session with COR alone (only the COR rebuild runs), ragged tiles and
+    a last sample chunk shorter than the others: resync equals the fresh
+    window bit for bit, before and after more pushes."""
+    rng = np.random.default_rng(23)
+    N, M, W, T = 130, 300, 5, 12
+    x = rng.standard_normal((T + 3, N, M))
+    x[:, 5, 2:] += 0.7 * x[:, 4, :-2]
+    cfg = synth.base_config(n_nodes=N, n_samples=M, window_trials=W, n_fft=512, f_lo_hz=8, f_hi_hz=30,
+                            metrics=synth.COR)
+    log(f"rebuild cor only: N={N} M={M} W={W}")
+    a = run_pushes(fcx, cfg, x, 0, T)
+    fcx.check(a.resync(), "resync")
+    b = run_pushes(fcx, cfg, x, T - W, T)
+    assert np.array_equal(a.read("cor")[1], b.read("cor")[1])
+    ref = oracle.network(oracle.as_device_input(x[T - W:T], cfg), cfg)
+    compare_network(a, ref, cfg, ["cor"], label="cor only resync")
+    run_pushes(fcx, cfg, x, T, x.shape[0], session=a)
+    run_pushes(fcx, cfg, x, T, x.shape[0], session=b)
+    assert np.array_equal(a.read("cor")[1], b.read("cor")[1])
+    a.close()
+    b.close()
