@@ -482,9 +482,17 @@ void k_xcor_pair(SessDev<T> s)
     // pn (if any) into dn once d is consumed
     auto job = [&](int pp, float2 (&d)[PER1][R1], int pn, float2 (&dn)[PER1][R1]) {
         const int j1 = J0 + 2 * pp, j2 = j1 + 1;
-        // the tail lags' maximum of this lane's pair (lanes 0 and 1), used at the end
-        const float tm = lane < 2 ? s.xtm[(size_t)tile * TILE_PAIRS + (size_t)r * TILE + (j1 + lane - J0)]
-                                  : 0.f;
+        // lanes 0 and 1 (pairs (i, j1), (i, j2)): the tail lags' maximum, the
+        // window sum and the evicted trial's maximum, loaded now and used at
+        // the end of the job
+        const size_t e = (size_t)tile * TILE_PAIRS + (size_t)r * TILE + (j1 + lane - J0);
+        float tm = 0.f, vold = 0.f;
+        double sum0 = 0.0;
+        if (lane < 2 && j1 + lane > i && j1 + lane < N) {
+            tm = s.xtm[e];
+            sum0 = s.xsum[e];
+            if (pv.has_old) vold = s.xval[(size_t)pv.slot_old * TP + e];
+        }
         // this job's column lag factors (lags < 0), used after the transform
         float cf1[PERL][HL], cf2[PERL][HL];
 #pragma unroll
@@ -540,10 +548,9 @@ void k_xcor_pair(SessDev<T> s)
         if (lane < 2) {
             const int jj = lane == 0 ? j1 : j2;
             if (jj > i && jj < N) {
-                const size_t e = (size_t)tile * TILE_PAIRS + (size_t)r * TILE + (jj - J0);
                 const float v = fmaxf(lane == 0 ? b1 : b2, tm);   // the tail lags (NaN: none)
-                double sum = s.xsum[e] + (double)v;
-                if (pv.has_old) sum = sum - (double)s.xval[(size_t)pv.slot_old * TP + e];
+                double sum = sum0 + (double)v;
+                if (pv.has_old) sum = sum - (double)vold;
                 s.xsum[e] = sum;
                 s.xval[(size_t)pv.slot_new * TP + e] = v;
                 const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(jj - i - 1);
