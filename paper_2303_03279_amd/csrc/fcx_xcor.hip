@@ -402,10 +402,26 @@ __device__ __forceinline__ void xpass(float2 *Z, const float2 *T, int lane)
     __builtin_amdgcn_wave_barrier();
 }
 
+// Largest value over the wavefront (no NaN in v), the same in every lane:
+// within each 16-lane row by DPP rotations (8, 4, 2, 1), then the four rows'
+// maxima read from lanes 0, 16, 32 and 48
+template <int CTRL> __device__ __forceinline__ float dpp_f(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf,
+                                                                 false));
+}
 __device__ __forceinline__ float wave_max(float v)
 {
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-    return v;
+    v = fmaxf(v, dpp_f<0x128>(v));   // row_ror:8
+    v = fmaxf(v, dpp_f<0x124>(v));   // row_ror:4
+    v = fmaxf(v, dpp_f<0x122>(v));   // row_ror:2
+    v = fmaxf(v, dpp_f<0x121>(v));   // row_ror:1
+    const int b = __builtin_bit_cast(int, v);
+    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 0));
+    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 16));
+    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 32));
+    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 48));
+    return fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
 }
 
 // waves per workgroup of the pair kernel (each has its own transform buffer)
