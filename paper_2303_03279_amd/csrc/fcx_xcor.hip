@@ -403,20 +403,26 @@ __device__ __forceinline__ void xpass(float2 *Z, const float2 *T, int lane)
 }
 
 // Largest value over the wavefront (no NaN in v), the same in every lane:
-// within each 16-lane row by DPP rotations (8, 4, 2, 1), then the four rows'
-// maxima read from lanes 0, 16, 32 and 48
-template <int CTRL> __device__ __forceinline__ float dpp_f(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf,
-                                                                 false));
-}
+// within each 16-lane row by v_max_f32 with DPP rotations of its first
+// operand (8, 4, 2, 1; two wait states before each DPP read of a VGPR the
+// previous instruction wrote, and before the value leaves the block), then
+// the four rows' maxima read from lanes 0, 16, 32 and 48
 __device__ __forceinline__ float wave_max(float v)
 {
-    v = fmaxf(v, dpp_f<0x128>(v));   // row_ror:8
-    v = fmaxf(v, dpp_f<0x124>(v));   // row_ror:4
-    v = fmaxf(v, dpp_f<0x122>(v));   // row_ror:2
-    v = fmaxf(v, dpp_f<0x121>(v));   // row_ror:1
-    const int b = __builtin_bit_cast(int, v);
+    float r;
+    asm volatile(
+        "s_nop 1\n"
+        "v_max_f32_dpp %0, %1, %1 row_ror:8 row_mask:0xf bank_mask:0xf\n"
+        "s_nop 1\n"
+        "v_max_f32_dpp %0, %0, %0 row_ror:4 row_mask:0xf bank_mask:0xf\n"
+        "s_nop 1\n"
+        "v_max_f32_dpp %0, %0, %0 row_ror:2 row_mask:0xf bank_mask:0xf\n"
+        "s_nop 1\n"
+        "v_max_f32_dpp %0, %0, %0 row_ror:1 row_mask:0xf bank_mask:0xf\n"
+        "s_nop 1"
+        : "=&v"(r)
+        : "v"(v));
+    const int b = __builtin_bit_cast(int, r);
     const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 0));
     const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 16));
     const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 32));
