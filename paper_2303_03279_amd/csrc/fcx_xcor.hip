@@ -277,9 +277,10 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b)
     return make_float2(__builtin_fmaf(a.x, b.x, a.y * b.y), __builtin_fmaf(a.y, b.x, -(a.x * b.y)));
 }
 
-// A transform buffer holds element m at m + m / 32: the pad after every 32
-// elements (256 bytes) spreads the strided stores over the LDS banks.
-constexpr int XPAD_SHIFT = 5;
+// A transform buffer holds element m at m + m / 16: the pad after every 16
+// elements (128 bytes) spreads the strided loads and stores over the LDS
+// banks (measured: fewer conflicts than a pad every 8, 32 or 64 elements).
+constexpr int XPAD_SHIFT = 4;
 __host__ __device__ constexpr int xpad(int m) { return m + (m >> XPAD_SHIFT); }
 template <int F> constexpr int xbuf_len() { return F + (F >> XPAD_SHIFT); }
 
@@ -355,8 +356,8 @@ __device__ __forceinline__ void idft_reg(float2 (&v)[R])
 // stores: xpass_store.  A wavefront's LDS operations are performed in order,
 // so all loads of a pass precede its stores; the wave barriers keep the
 // compiler from moving LDS accesses across the phase boundaries.  With the
-// pad every 32 elements both address patterns are one base plus constants
-// (F / R and NS are multiples of 32, or NS < 32 with k + (m NS mod 32) < 32).
+// pad every 16 elements both address patterns are one base plus constants
+// (F / R and NS are multiples of 16, or NS < 16 with k + (m NS mod 16) < 16).
 template <int F, int R, int NS>
 __device__ __forceinline__ void xpass_load(const float2 *Z, const float2 *T, int lane,
                                            float2 (&v)[F / R / 64][R])
