@@ -453,6 +453,10 @@ void k_xcor_pair(SessDev<T> s)
     __shared__ float2 Zw[NW][xbuf_len<F>()];
     __shared__ float2 A[F];
     __shared__ float2 tws[xcor_tw_len(F)];
+    // the row's 64 pairs of this tile: window sum, evicted trial's maximum,
+    // tail lags' maximum (loaded with the row operand, read by the jobs)
+    __shared__ double wsum[TILE];
+    __shared__ float wold[TILE], wtm[TILE];
     if (s.ctl->bad) return;
     const int item = xcd_item(blockIdx.x, gridDim.x);
     const int tile = item / TILE, r = item % TILE;
@@ -473,6 +477,20 @@ void k_xcor_pair(SessDev<T> s)
             A[f] = f <= F / 2 ? a : make_float2(a.x, -a.y);
         }
         for (int e = tid; e < xcor_tw_len(F); e += 64 * NW) tws[e] = s.xtwi[e];
+        if (tid < TILE) {
+            const int jj = J0 + tid;
+            const size_t e = (size_t)tile * TILE_PAIRS + (size_t)r * TILE + tid;
+            double sm = 0.0;
+            float vo = 0.f, tm = 0.f;
+            if (jj > i && jj < N) {
+                sm = s.xsum[e];
+                if (pv.has_old) vo = s.xval[(size_t)pv.slot_old * s.ntiles * TILE_PAIRS + e];
+                tm = s.xtm[e];
+            }
+            wsum[tid] = sm;
+            wold[tid] = vo;
+            wtm[tid] = tm;
+        }
     }
     // the column operands and lag factors through buffer resources: a uniform
     // job offset in a scalar register, the lane's offset, constants
@@ -505,17 +523,8 @@ void k_xcor_pair(SessDev<T> s)
     // pn (if any) into dn once d is consumed
     auto job = [&](int pp, float2 (&d)[PER1][R1], int pn, float2 (&dn)[PER1][R1]) {
         const int j1 = J0 + 2 * pp, j2 = j1 + 1;
-        // lanes 0 and 1 (pairs (i, j1), (i, j2)): the tail lags' maximum, the
-        // window sum and the evicted trial's maximum, loaded now and used at
-        // the end of the job
+        // lanes 0 and 1: pairs (i, j1) and (i, j2)
         const size_t e = (size_t)tile * TILE_PAIRS + (size_t)r * TILE + (j1 + lane - J0);
-        float tm = 0.f, vold = 0.f;
-        double sum0 = 0.0;
-        if (lane < 2 && j1 + lane > i && j1 + lane < N) {
-            tm = s.xtm[e];
-            sum0 = s.xsum[e];
-            if (pv.has_old) vold = s.xval[(size_t)pv.slot_old * TP + e];
-        }
         // this job's column lag factors (lags < 0), used after the transform
         float cf1[PERL][HL], cf2[PERL][HL];
 #pragma unroll
@@ -571,9 +580,10 @@ void k_xcor_pair(SessDev<T> s)
         if (lane < 2) {
             const int jj = lane == 0 ? j1 : j2;
             if (jj > i && jj < N) {
-                const float v = fmaxf(lane == 0 ? b1 : b2, tm);   // the tail lags (NaN: none)
-                double sum = sum0 + (double)v;
-                if (pv.has_old) sum = sum - (double)vold;
+                const int c = jj - J0;
+                const float v = fmaxf(lane == 0 ? b1 : b2, wtm[c]);   // the tail lags (NaN: none)
+                double sum = wsum[c] + (double)v;
+                if (pv.has_old) sum = sum - (double)wold[c];
                 s.xsum[e] = sum;
                 s.xval[(size_t)pv.slot_new * TP + e] = v;
                 const size_t idx = (size_t)i * (2 * (size_t)N - i - 1) / 2 + (size_t)(jj - i - 1);
